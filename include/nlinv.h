@@ -1,0 +1,208 @@
+/*
+ * nlinv.h -- C ABI of the MI355X (gfx950) library for nonlinear-inverse MRI
+ * reconstruction: the iteratively regularised Gauss-Newton method (IRGNM)
+ * that estimates an image and the coil sensitivities together
+ * (Schaetz & Uecker, Sec. 3.1, Eqs. 2-3).
+ *
+ * Model (Eq. 2).  For an unknown x = (rho, chat):
+ *   F(x)_j = P . DTFT( E( rho . c_j ) ),   c_j = E^H W^{-1} chat_j,
+ *   W^{-1} chat = DTFT^{-1}( chat / w ),   w(k) = (1 + a |k|^2)^(l/2),
+ * where DTFT is the centred unitary 2D DFT on the n x n grid (DC at index
+ * n/2, k_d = (kappa_d - n/2)/n), E zero-pads an n_om x n_om image into the
+ * centre of the grid (the mask M_Omega of Eq. 2) and E^H crops it, and P is
+ * the real k-space sampling array (the projection P_k; binary for measured /
+ * not measured, or a soft weight).
+ *
+ * Conventions shared by every call:
+ *   - Array arguments are DEVICE pointers to C-contiguous data owned by the
+ *     caller; they must stay valid until `stream` has executed the call.
+ *     nlinv_c32 has the layout of std::complex<float> / torch.complex64.
+ *     Pointers must be 16-byte aligned.
+ *   - Shapes: rho-like arrays [n_om][n_om]; chat-like and k-space arrays
+ *     [J][n][n]; sensitivities c [J][n_om][n_om]; P [n][n] float32.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Every compute call
+ *     only enqueues work and returns; kernel faults surface at the caller's
+ *     next synchronisation.  Compute calls never allocate device memory.
+ *   - Return value: NLINV_OK (0) or a negative status.  NLINV_EINVAL for a
+ *     NULL / misaligned pointer or bad argument, NLINV_EUNSUPPORTED for a
+ *     grid size that is not 2^p 3^q in [8, 1024] or Omega sides that are odd
+ *     or larger than n, NLINV_ENOMEM when plan creation cannot allocate,
+ *     NLINV_EHIP for a HIP error (its code: nlinv_last_hip_error()).
+ *     No C++ exception crosses this interface.
+ *   - Outputs must not alias inputs except where a name ends in _inout.
+ *   - A plan is not thread-safe; separate plans are independent.
+ */
+#ifndef NLINV_H
+#define NLINV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { float re, im; } nlinv_c32;
+
+typedef struct nlinv_plan_s* nlinv_plan;
+
+/* Geometry of one frame.  sobolev_a = 220 and sobolev_l = 32 give the
+ * weight (1 + 220 |k|^2)^16 on the coil sensitivities. */
+typedef struct {
+    int32_t n;          /* grid side (square grid), 2^p 3^q, 8 <= n <= 1024 */
+    int32_t n_om;       /* side of the centred image region Omega, even, <= n */
+    int32_t ncoils;     /* J, 1..64 */
+    float sobolev_a;
+    float sobolev_l;
+} nlinv_dims;
+
+/* Gauss-Newton parameters (Eq. 3).  alpha_n = max(alpha0 * alpha_q^n, alpha_min),
+ * n = 0..newton_steps-1; each step runs cg_iters conjugate-gradient iterations
+ * from 0 (stopping early only when <r,r> = 0 or Re<p, N p> <= 0).
+ * scale_norm > 0 scales the data to ||y|| = scale_norm before the solve and
+ * undoes it on rho afterwards (exact: F is bilinear); 0 turns it off. */
+typedef struct {
+    int32_t newton_steps;
+    int32_t cg_iters;
+    float alpha0;
+    float alpha_q;
+    float alpha_min;
+    float scale_norm;
+    uint32_t flags;     /* NLINV_* flags below */
+} nlinv_irgnm_params;
+
+enum {
+    NLINV_OK = 0,
+    NLINV_EINVAL = -1,
+    NLINV_EUNSUPPORTED = -2,
+    NLINV_ENOMEM = -3,
+    NLINV_EHIP = -4
+};
+
+enum {
+    NLINV_USE_GRAPH = 1u,   /* replay the solve from a captured hipGraph */
+    NLINV_WARM_START = 2u   /* rho/chat hold the start x0 (data units); else rho = 1, chat = 0 */
+};
+
+/* Stats written per frame (device doubles), when a stats pointer is given:
+ *   [0] data scale s, [1] flags (bit 0: CG breakdown in some step,
+ *   bit 1: non-finite scalar met), [2 .. 2+N) ||y_s - F(x_n)|| per Newton
+ *   step (scaled units), then N*K values <r,r> after each CG iteration
+ *   (-1 where an iteration was skipped after a breakdown). */
+#define NLINV_STATS_LEN(newton, cg) (2 + (newton) + (newton) * (cg))
+
+/* One frame of a batched or serial solve (all pointers on the device). */
+typedef struct {
+    const nlinv_c32* y;         /* [J][n][n] measured k-space data */
+    const float* P;             /* [n][n] sampling array */
+    nlinv_c32* rho;             /* [n_om][n_om] out (in: x0 with NLINV_WARM_START) */
+    nlinv_c32* chat;            /* [J][n][n]    out (in: x0 with NLINV_WARM_START) */
+    const nlinv_c32* rho_ref;   /* nullable: x_ref (data units); NULL -> x_ref = x0 */
+    const nlinv_c32* chat_ref;
+    nlinv_c32* image;           /* nullable [n_om][n_om]: rho . sqrt(sum_j |c_j|^2) */
+    double* stats;              /* nullable, NLINV_STATS_LEN doubles */
+} nlinv_frame;
+
+/* ---- plans --------------------------------------------------------------
+ * A plan holds the workspace for `nframes` frames of the given shapes
+ * (dims[0..nframes-1]; frames may differ in n, n_om and J).  It allocates all
+ * device memory here, on the current HIP device; compute calls allocate none.
+ * The single-frame operators and nlinv_irgnm_solve act on frame 0's shape. */
+int nlinv_plan_create(nlinv_plan* out, const nlinv_dims* dims, int32_t nframes);
+int nlinv_plan_destroy(nlinv_plan plan);                  /* NULL-safe */
+
+/* c_j = E^H W^{-1} chat_j (Eq. 2: the weighted inverse transform of the
+ * sensitivities, restricted to Omega): the linearisation cache that the
+ * method computes once per Newton step.  c_out [J][n_om][n_om]. */
+int nlinv_coil_maps(nlinv_plan plan, const nlinv_c32* chat, nlinv_c32* c_out, void* stream);
+
+/* y = F(rho, chat) (Eq. 2).  y_out [J][n][n]; c_out (nullable) receives c. */
+int nlinv_forward(nlinv_plan plan, const nlinv_c32* rho, const nlinv_c32* chat,
+                  const float* P, nlinv_c32* y_out, nlinv_c32* c_out, void* stream);
+
+/* dy = DF_x (drho, dchat): the Frechet derivative of F at x = (rho, chat)
+ * (left factor of Eq. 3), dy_j = P . DTFT(E(drho . c_j + rho . E^H W^{-1} dchat_j)).
+ * c = nlinv_coil_maps(chat); if c is NULL it is recomputed from chat. */
+int nlinv_deriv(nlinv_plan plan, const nlinv_c32* rho, const nlinv_c32* chat,
+                const nlinv_c32* c, const float* P, const nlinv_c32* drho,
+                const nlinv_c32* dchat, nlinv_c32* dy_out, void* stream);
+
+/* (drho, dchat) = DF_x^H dy (Eq. 3): u_j = E^H DTFT^{-1}(P . dy_j),
+ * drho = sum_j conj(c_j) . u_j,  dchat_j = DTFT(E(conj(rho) . u_j)) / w. */
+int nlinv_adjoint(nlinv_plan plan, const nlinv_c32* rho, const nlinv_c32* chat,
+                  const nlinv_c32* c, const float* P, const nlinv_c32* dy,
+                  nlinv_c32* drho_out, nlinv_c32* dchat_out, void* stream);
+
+/* (DF_x^H DF_x + alpha I) h, the left-hand side of Eq. 3 (P enters squared). */
+int nlinv_normal(nlinv_plan plan, const nlinv_c32* rho, const nlinv_c32* chat,
+                 const nlinv_c32* c, const float* P, float alpha,
+                 const nlinv_c32* drho, const nlinv_c32* dchat,
+                 nlinv_c32* drho_out, nlinv_c32* dchat_out, void* stream);
+
+/* Gradient with respect to P of a loss of y = F(x; P), given
+ * g = dL/dRe(y) + i dL/dIm(y) [J][n][n]:  gP = Re sum_j conj(g_j) . DTFT(E(rho . c_j)).
+ * gP_out [n][n] float32. c as in nlinv_deriv. */
+int nlinv_mask_gradient(nlinv_plan plan, const nlinv_c32* rho, const nlinv_c32* chat,
+                        const nlinv_c32* c, const nlinv_c32* g, float* gP_out, void* stream);
+
+/* image = rho . sqrt(sum_j |c_j|^2) on Omega. */
+int nlinv_image(nlinv_plan plan, const nlinv_c32* rho, const nlinv_c32* c,
+                nlinv_c32* image_out, void* stream);
+
+/* ---- solves ---------------------------------------------------------------
+ * Eq. 3 iterated: x_{n+1} = x_n + dx with dx from cg_iters CG iterations on
+ * (DF^H DF + alpha_n I) dx = DF^H (y - F x_n) - alpha_n (x_n - x_ref).
+ * One frame of frame 0's shape; rho_inout / chat_inout give x0 when
+ * NLINV_WARM_START is set and receive the result.  rho_ref / chat_ref:
+ * nullable x_ref (NULL -> x_ref = x0).  image_out, stats_out nullable. */
+int nlinv_irgnm_solve(nlinv_plan plan, const nlinv_c32* y, const float* P,
+                      const nlinv_irgnm_params* prm, nlinv_c32* rho_inout,
+                      nlinv_c32* chat_inout, const nlinv_c32* rho_ref,
+                      const nlinv_c32* chat_ref, nlinv_c32* image_out,
+                      double* stats_out, void* stream);
+
+/* All nframes frames of the plan solved together (frame f has dims[f]);
+ * `frames` is a HOST array of nframes descriptors.  Frames are independent:
+ * each has its own data scale, CG scalars and breakdown guard. */
+int nlinv_irgnm_solve_batch(nlinv_plan plan, const nlinv_frame* frames,
+                            const nlinv_irgnm_params* prm, void* stream);
+
+/* A temporal series (Sec. 3.2): `count` frames of frame 0's shape solved in
+ * order; frame 0 starts as in nlinv_irgnm_solve (its rho_ref / chat_ref
+ * honoured), frame t > 0 starts from and is regularised towards the result of
+ * frame t-1 (x0 = x_ref = x(t-1), in data units).  `frames` is a HOST array;
+ * the whole series is enqueued without host synchronisation. */
+int nlinv_irgnm_solve_series(nlinv_plan plan, int32_t count, const nlinv_frame* frames,
+                             const nlinv_irgnm_params* prm, void* stream);
+
+/* ---- autotuning -----------------------------------------------------------
+ * Time the FFT pass variants (lines per workgroup, whole-plane-in-LDS
+ * kernels where the plane fits) for every grid size of the plan on `stream`
+ * (which must not be capturing) and keep the fastest.  Results are cached
+ * per (device architecture, n, planes) in the text file named by
+ * NLINV_TUNE_CACHE, if set.  Without this call a fixed default is used. */
+int nlinv_plan_autotune(nlinv_plan plan, void* stream);
+
+/* Choice made for grid size n (-1 if n is not in the plan): the variant index
+ * used by column passes / row passes. */
+int nlinv_plan_variant(nlinv_plan plan, int32_t n, int32_t* col_variant, int32_t* row_variant);
+
+/* Force a variant (for tests): returns NLINV_EINVAL for an unknown index. */
+int nlinv_plan_set_variant(nlinv_plan plan, int32_t n, int32_t col_variant, int32_t row_variant);
+
+/* ---- kernel timing --------------------------------------------------------
+ * When enabled, every launch of the kernel class `kclass` (see
+ * nlinv_kernel_class_name) made by this plan is bracketed by HIP events on
+ * its stream; nlinv_plan_timing_read synchronises those events and returns
+ * the launch count and the summed duration in milliseconds, then resets. */
+int nlinv_plan_timing_enable(nlinv_plan plan, int32_t kclass, int32_t enable);
+int nlinv_plan_timing_read(nlinv_plan plan, int32_t* launches, double* total_ms);
+const char* nlinv_kernel_class_name(int32_t kclass);   /* NULL past the last */
+
+const char* nlinv_status_string(int status);
+int nlinv_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NLINV_H */

@@ -1,0 +1,280 @@
+"""ctypes binding of libnlinv.so (include/nlinv.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls and passes
+torch tensors' device pointers and the current HIP stream through.  No step
+of the computation runs in Python.  Loading fails loudly when the library is
+missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnlinv.so")
+
+NLINV_OK, NLINV_EINVAL, NLINV_EUNSUPPORTED, NLINV_ENOMEM, NLINV_EHIP = 0, -1, -2, -3, -4
+NLINV_USE_GRAPH, NLINV_WARM_START = 1, 2
+
+EXPORTED = (
+    "nlinv_plan_create", "nlinv_plan_destroy", "nlinv_coil_maps", "nlinv_forward", "nlinv_deriv",
+    "nlinv_adjoint", "nlinv_normal", "nlinv_mask_gradient", "nlinv_image", "nlinv_irgnm_solve",
+    "nlinv_irgnm_solve_batch", "nlinv_irgnm_solve_series", "nlinv_plan_autotune", "nlinv_plan_variant",
+    "nlinv_plan_set_variant", "nlinv_plan_timing_enable", "nlinv_plan_timing_read",
+    "nlinv_kernel_class_name", "nlinv_status_string", "nlinv_last_hip_error",
+)
+
+
+class nlinv_dims(C.Structure):
+    _fields_ = [("n", C.c_int32), ("n_om", C.c_int32), ("ncoils", C.c_int32),
+                ("sobolev_a", C.c_float), ("sobolev_l", C.c_float)]
+
+
+class nlinv_irgnm_params(C.Structure):
+    _fields_ = [("newton_steps", C.c_int32), ("cg_iters", C.c_int32), ("alpha0", C.c_float),
+                ("alpha_q", C.c_float), ("alpha_min", C.c_float), ("scale_norm", C.c_float),
+                ("flags", C.c_uint32)]
+
+
+class nlinv_frame(C.Structure):
+    _fields_ = [("y", C.c_void_p), ("P", C.c_void_p), ("rho", C.c_void_p), ("chat", C.c_void_p),
+                ("rho_ref", C.c_void_p), ("chat_ref", C.c_void_p), ("image", C.c_void_p),
+                ("stats", C.c_void_p)]
+
+
+def stats_len(newton: int, cg: int) -> int:
+    return 2 + newton + newton * cg
+
+
+class NlinvError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load the library (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise NlinvError(f"{p} not found: build it with `python -m paper_1301_1215_amd.build`")
+    lib = C.CDLL(p)
+    vp, i32, f32 = C.c_void_p, C.c_int32, C.c_float
+    sig = {
+        "nlinv_plan_create": ([C.POINTER(vp), C.POINTER(nlinv_dims), i32], C.c_int),
+        "nlinv_plan_destroy": ([vp], C.c_int),
+        "nlinv_coil_maps": ([vp, vp, vp, vp], C.c_int),
+        "nlinv_forward": ([vp, vp, vp, vp, vp, vp, vp], C.c_int),
+        "nlinv_deriv": ([vp, vp, vp, vp, vp, vp, vp, vp, vp], C.c_int),
+        "nlinv_adjoint": ([vp, vp, vp, vp, vp, vp, vp, vp, vp], C.c_int),
+        "nlinv_normal": ([vp, vp, vp, vp, vp, f32, vp, vp, vp, vp, vp], C.c_int),
+        "nlinv_mask_gradient": ([vp, vp, vp, vp, vp, vp, vp], C.c_int),
+        "nlinv_image": ([vp, vp, vp, vp, vp], C.c_int),
+        "nlinv_irgnm_solve": ([vp, vp, vp, C.POINTER(nlinv_irgnm_params), vp, vp, vp, vp, vp, vp, vp], C.c_int),
+        "nlinv_irgnm_solve_batch": ([vp, C.POINTER(nlinv_frame), C.POINTER(nlinv_irgnm_params), vp], C.c_int),
+        "nlinv_irgnm_solve_series": ([vp, i32, C.POINTER(nlinv_frame), C.POINTER(nlinv_irgnm_params), vp],
+                                     C.c_int),
+        "nlinv_plan_autotune": ([vp, vp], C.c_int),
+        "nlinv_plan_variant": ([vp, i32, C.POINTER(i32), C.POINTER(i32)], C.c_int),
+        "nlinv_plan_set_variant": ([vp, i32, i32, i32], C.c_int),
+        "nlinv_plan_timing_enable": ([vp, i32, i32], C.c_int),
+        "nlinv_plan_timing_read": ([vp, C.POINTER(i32), C.POINTER(C.c_double)], C.c_int),
+        "nlinv_kernel_class_name": ([i32], C.c_char_p),
+        "nlinv_status_string": ([C.c_int], C.c_char_p),
+        "nlinv_last_hip_error": ([], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def check(status: int, what: str = "") -> None:
+    if status != NLINV_OK:
+        lib = load()
+        msg = lib.nlinv_status_string(status).decode()
+        hip = lib.nlinv_last_hip_error() if status == NLINV_EHIP else 0
+        raise NlinvError(f"{what}: {msg} (status {status}{', hip error %d' % hip if hip else ''})")
+
+
+# ---------------------------------------------------------------------------
+# pointer / stream marshalling
+# ---------------------------------------------------------------------------
+
+def _ptr(t, dtype=None, what="tensor"):
+    """Device pointer of a contiguous CUDA (HIP) tensor, or None."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what}: expected a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{what}: must be on the GPU")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{what}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream if hasattr(s, "cuda_stream") else int(s)
+
+
+def _c64(t, what):
+    import torch
+    return _ptr(t, torch.complex64, what)
+
+
+def _f32(t, what):
+    import torch
+    return _ptr(t, torch.float32, what)
+
+
+# ---------------------------------------------------------------------------
+# entry points under their C names
+# ---------------------------------------------------------------------------
+
+def nlinv_plan_create(dims_list, nframes=None):
+    """dims_list: sequence of (n, n_om, ncoils[, a, l]) or nlinv_dims."""
+    lib = load()
+    arr = (nlinv_dims * len(dims_list))()
+    for i, d in enumerate(dims_list):
+        if isinstance(d, nlinv_dims):
+            arr[i] = d
+        else:
+            a = d[3] if len(d) > 3 else 220.0
+            l = d[4] if len(d) > 4 else 32.0
+            arr[i] = nlinv_dims(int(d[0]), int(d[1]), int(d[2]), float(a), float(l))
+    h = C.c_void_p()
+    check(lib.nlinv_plan_create(C.byref(h), arr, len(dims_list) if nframes is None else nframes),
+          "nlinv_plan_create")
+    return h
+
+
+def nlinv_plan_destroy(plan):
+    check(load().nlinv_plan_destroy(plan), "nlinv_plan_destroy")
+
+
+def nlinv_coil_maps(plan, chat, c_out, stream=None):
+    check(load().nlinv_coil_maps(plan, _c64(chat, "chat"), _c64(c_out, "c_out"), _stream(stream)),
+          "nlinv_coil_maps")
+
+
+def nlinv_forward(plan, rho, chat, P, y_out, c_out=None, stream=None):
+    check(load().nlinv_forward(plan, _c64(rho, "rho"), _c64(chat, "chat"), _f32(P, "P"),
+                               _c64(y_out, "y_out"), _c64(c_out, "c_out"), _stream(stream)), "nlinv_forward")
+
+
+def nlinv_deriv(plan, rho, chat, c, P, drho, dchat, dy_out, stream=None):
+    check(load().nlinv_deriv(plan, _c64(rho, "rho"), _c64(chat, "chat"), _c64(c, "c"), _f32(P, "P"),
+                             _c64(drho, "drho"), _c64(dchat, "dchat"), _c64(dy_out, "dy_out"),
+                             _stream(stream)), "nlinv_deriv")
+
+
+def nlinv_adjoint(plan, rho, chat, c, P, dy, drho_out, dchat_out, stream=None):
+    check(load().nlinv_adjoint(plan, _c64(rho, "rho"), _c64(chat, "chat"), _c64(c, "c"), _f32(P, "P"),
+                               _c64(dy, "dy"), _c64(drho_out, "drho_out"), _c64(dchat_out, "dchat_out"),
+                               _stream(stream)), "nlinv_adjoint")
+
+
+def nlinv_normal(plan, rho, chat, c, P, alpha, drho, dchat, drho_out, dchat_out, stream=None):
+    check(load().nlinv_normal(plan, _c64(rho, "rho"), _c64(chat, "chat"), _c64(c, "c"), _f32(P, "P"),
+                              float(alpha), _c64(drho, "drho"), _c64(dchat, "dchat"),
+                              _c64(drho_out, "drho_out"), _c64(dchat_out, "dchat_out"), _stream(stream)),
+          "nlinv_normal")
+
+
+def nlinv_mask_gradient(plan, rho, chat, c, g, gP_out, stream=None):
+    check(load().nlinv_mask_gradient(plan, _c64(rho, "rho"), _c64(chat, "chat"), _c64(c, "c"),
+                                     _c64(g, "g"), _f32(gP_out, "gP_out"), _stream(stream)),
+          "nlinv_mask_gradient")
+
+
+def nlinv_image(plan, rho, c, image_out, stream=None):
+    check(load().nlinv_image(plan, _c64(rho, "rho"), _c64(c, "c"), _c64(image_out, "image_out"),
+                             _stream(stream)), "nlinv_image")
+
+
+def make_params(newton_steps=7, cg_iters=10, alpha0=1.0, alpha_q=0.5, alpha_min=0.0, scale_norm=100.0,
+                flags=0):
+    return nlinv_irgnm_params(int(newton_steps), int(cg_iters), float(alpha0), float(alpha_q),
+                              float(alpha_min), float(scale_norm), int(flags))
+
+
+def nlinv_irgnm_solve(plan, y, P, prm, rho_inout, chat_inout, rho_ref=None, chat_ref=None, image_out=None,
+                      stats_out=None, stream=None):
+    import torch
+    check(load().nlinv_irgnm_solve(plan, _c64(y, "y"), _f32(P, "P"), C.byref(prm),
+                                   _c64(rho_inout, "rho_inout"), _c64(chat_inout, "chat_inout"),
+                                   _c64(rho_ref, "rho_ref"), _c64(chat_ref, "chat_ref"),
+                                   _c64(image_out, "image_out"), _ptr(stats_out, torch.float64, "stats_out"),
+                                   _stream(stream)), "nlinv_irgnm_solve")
+
+
+def _frames(frames):
+    import torch
+    arr = (nlinv_frame * len(frames))()
+    for i, f in enumerate(frames):
+        arr[i] = nlinv_frame(_c64(f["y"], "y"), _f32(f["P"], "P"), _c64(f["rho"], "rho"),
+                             _c64(f["chat"], "chat"), _c64(f.get("rho_ref"), "rho_ref"),
+                             _c64(f.get("chat_ref"), "chat_ref"), _c64(f.get("image"), "image"),
+                             _ptr(f.get("stats"), torch.float64, "stats"))
+    return arr
+
+
+def nlinv_irgnm_solve_batch(plan, frames, prm, stream=None):
+    arr = _frames(frames)
+    check(load().nlinv_irgnm_solve_batch(plan, arr, C.byref(prm), _stream(stream)), "nlinv_irgnm_solve_batch")
+
+
+def nlinv_irgnm_solve_series(plan, frames, prm, stream=None):
+    arr = _frames(frames)
+    check(load().nlinv_irgnm_solve_series(plan, len(frames), arr, C.byref(prm), _stream(stream)),
+          "nlinv_irgnm_solve_series")
+
+
+def nlinv_plan_autotune(plan, stream=None):
+    check(load().nlinv_plan_autotune(plan, _stream(stream)), "nlinv_plan_autotune")
+
+
+def nlinv_plan_variant(plan, n):
+    cv, rv = C.c_int32(), C.c_int32()
+    check(load().nlinv_plan_variant(plan, int(n), C.byref(cv), C.byref(rv)), "nlinv_plan_variant")
+    return cv.value, rv.value
+
+
+def nlinv_plan_set_variant(plan, n, col_variant, row_variant):
+    check(load().nlinv_plan_set_variant(plan, int(n), int(col_variant), int(row_variant)),
+          "nlinv_plan_set_variant")
+
+
+def nlinv_kernel_class_names():
+    lib = load()
+    out = []
+    k = 0
+    while True:
+        s = lib.nlinv_kernel_class_name(k)
+        if s is None:
+            return out
+        out.append(s.decode())
+        k += 1
+
+
+def nlinv_plan_timing_enable(plan, kclass, enable=True):
+    if isinstance(kclass, str):
+        kclass = nlinv_kernel_class_names().index(kclass)
+    check(load().nlinv_plan_timing_enable(plan, int(kclass), 1 if enable else 0), "nlinv_plan_timing_enable")
+
+
+def nlinv_plan_timing_read(plan):
+    n, ms = C.c_int32(), C.c_double()
+    check(load().nlinv_plan_timing_read(plan, C.byref(n), C.byref(ms)), "nlinv_plan_timing_read")
+    return n.value, ms.value

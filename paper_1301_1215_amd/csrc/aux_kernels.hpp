@@ -1,0 +1,307 @@
+// Coil-sum, image, CG vector and FP64 reduction kernels (not size-templated;
+// built once, in the host library's translation unit).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_core.hpp"
+
+namespace nlinv {
+
+// ---------------------------------------------------------------------------
+// coil sums over the planes of each frame (fixed order: deterministic)
+// ---------------------------------------------------------------------------
+
+// out[f][e] = sum_{p in f} aux[p][e] + s1_f add1[f][e] + s2_f add2[f][e]
+struct CoilSumArgs {
+    const float2* aux;       // [planes][E]
+    float2* out;             // [frames][E]
+    const float2* add1;
+    const float2* add2;
+    const float* s1;
+    const float* s2;
+    float c1, c2;
+    const int* frame_plane0; // nullable: single frame with `nplanes` planes
+    const int* frame_planes;
+    int nplanes;
+    int nframes;
+    int E;                   // elements per frame (m*m)
+};
+
+__global__ __launch_bounds__(kThreads) void k_coil_sum(CoilSumArgs a) {
+    const long long tot = (long long)a.nframes * a.E;
+    for (long long g = (long long)blockIdx.x * kThreads + threadIdx.x; g < tot;
+         g += (long long)gridDim.x * kThreads) {
+        const int f = (int)(g / a.E), e = (int)(g % a.E);
+        const int p0 = a.frame_plane0 ? a.frame_plane0[f] : 0;
+        const int np = a.frame_planes ? a.frame_planes[f] : a.nplanes;
+        float2 s = make_float2(0.f, 0.f);
+        for (int p = 0; p < np; ++p) s = cadd(s, a.aux[(long long)(p0 + p) * a.E + e]);
+        const float s1 = a.s1 ? a.s1[f] : a.c1;
+        const float s2 = a.s2 ? a.s2[f] : a.c2;
+        if (a.add1) { const float2 u = a.add1[g]; s.x += s1 * u.x; s.y += s1 * u.y; }
+        if (a.add2) { const float2 u = a.add2[g]; s.x += s2 * u.x; s.y += s2 * u.y; }
+        a.out[g] = s;
+    }
+}
+
+// gP[f][e] = sum_{p in f} gprod[p][e]   (real)
+__global__ __launch_bounds__(kThreads) void k_coil_sum_real(const float* gprod, float* out, int nplanes, int E) {
+    for (int e = blockIdx.x * kThreads + threadIdx.x; e < E; e += gridDim.x * kThreads) {
+        float s = 0.f;
+        for (int p = 0; p < nplanes; ++p) s += gprod[(long long)p * E + e];
+        out[e] = s;
+    }
+}
+
+// image[f][e] = rho[f][e] . sqrt(sum_{p in f} |c[p][e]|^2) * inv_s[f]
+__global__ __launch_bounds__(kThreads) void k_image(const float2* rho, const float2* c, float2* img,
+                                                    const int* frame_plane0, const int* frame_planes,
+                                                    int nplanes, int nframes, int E, const float* inv_s) {
+    const long long tot = (long long)nframes * E;
+    for (long long g = (long long)blockIdx.x * kThreads + threadIdx.x; g < tot;
+         g += (long long)gridDim.x * kThreads) {
+        const int f = (int)(g / E), e = (int)(g % E);
+        const int p0 = frame_plane0 ? frame_plane0[f] : 0;
+        const int np = frame_planes ? frame_planes[f] : nplanes;
+        float s = 0.f;
+        for (int p = 0; p < np; ++p) {
+            const float2 v = c[(long long)(p0 + p) * E + e];
+            s += v.x * v.x + v.y * v.y;
+        }
+        const float sc = sqrtf(s) * (inv_s ? inv_s[f] : 1.0f);
+        img[g] = cscale(rho[g], sc);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// segmented vector kernels over the two parts of a class-wide CG vector:
+//   chat part [planes][n*n] in `cseg` segments per plane,
+//   rho part  [frames][m*m] in `rseg` segments per frame.
+// One workgroup per segment; reductions give one FP64 partial per segment.
+// ---------------------------------------------------------------------------
+
+struct SegGeom {
+    int nplanes, nframes;
+    int cn, rn;          // elements per plane / per frame (complex)
+    int cseg, rseg;      // segments per plane / per frame
+    int clen, rlen;      // elements per segment (even), last one ragged
+    const int* plane_frame;
+};
+
+__device__ __forceinline__ void seg_locate(const SegGeom& g, int s, bool& is_c, int& owner, int& f,
+                                           long long& base, int& len) {
+    const int ncs = g.nplanes * g.cseg;
+    if (s < ncs) {
+        is_c = true;
+        owner = s / g.cseg;
+        const int k = s % g.cseg;
+        f = g.plane_frame ? g.plane_frame[owner] : 0;
+        base = (long long)owner * g.cn + (long long)k * g.clen;
+        len = min(g.clen, g.cn - k * g.clen);
+    } else {
+        is_c = false;
+        const int t = s - ncs;
+        owner = t / g.rseg;
+        const int k = t % g.rseg;
+        f = owner;
+        base = (long long)owner * g.rn + (long long)k * g.rlen;
+        len = min(g.rlen, g.rn - k * g.rlen);
+    }
+}
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    // wavefront reduce then across the 4 waves, fixed order
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) t = (red[0] + red[1]) + (red[2] + red[3]);
+    return t;
+}
+
+struct VecPtrs {
+    float2* c0; float2* c1; float2* c2; float2* c3;   // chat parts
+    float2* r0; float2* r1; float2* r2; float2* r3;   // rho parts
+};
+
+enum VecOp : int {
+    VEC_DOT = 0,        // partial = Re<v0, v1>
+    VEC_XR_UPDATE = 1,  // v0 += a v1 (x += a p);  v2 -= a v3 (r -= a q);  partial = |v2|^2
+    VEC_P_UPDATE = 2,   // v0 = v1 + beta v0        (p = r + beta p)
+    VEC_COPY = 3,       // v0 = v1
+    VEC_ADD = 4,        // v0 += v1
+};
+
+template <int OP>
+__global__ __launch_bounds__(kThreads) void k_vec(SegGeom g, VecPtrs v, const float* a_f,
+                                                  const float* b_f, double* partial) {
+    __shared__ double red[4];
+    bool is_c; int owner, f, len; long long base;
+    seg_locate(g, blockIdx.x, is_c, owner, f, base, len);
+    float2* x0 = is_c ? v.c0 : v.r0;
+    float2* x1 = is_c ? v.c1 : v.r1;
+    float2* x2 = is_c ? v.c2 : v.r2;
+    float2* x3 = is_c ? v.c3 : v.r3;
+    float4* y0 = reinterpret_cast<float4*>(x0 + base);
+    float4* y1 = reinterpret_cast<float4*>(x1 + base);
+    float4* y2 = reinterpret_cast<float4*>(x2 + base);
+    float4* y3 = reinterpret_cast<float4*>(x3 + base);
+    const int n4 = len / 2;
+    double acc = 0.0;
+    const float av = a_f ? a_f[f] : 0.f;
+    const float bv = b_f ? b_f[f] : 0.f;
+    for (int i = threadIdx.x; i < n4; i += kThreads) {
+        if constexpr (OP == VEC_DOT) {
+            const float4 p = y0[i], q = y1[i];
+            acc += (double)p.x * q.x + (double)p.y * q.y + (double)p.z * q.z + (double)p.w * q.w;
+        } else if constexpr (OP == VEC_XR_UPDATE) {
+            float4 x = y0[i];
+            const float4 p = y1[i];
+            float4 r = y2[i];
+            const float4 q = y3[i];
+            x.x += av * p.x; x.y += av * p.y; x.z += av * p.z; x.w += av * p.w;
+            r.x -= av * q.x; r.y -= av * q.y; r.z -= av * q.z; r.w -= av * q.w;
+            y0[i] = x;
+            y2[i] = r;
+            acc += (double)r.x * r.x + (double)r.y * r.y + (double)r.z * r.z + (double)r.w * r.w;
+        } else if constexpr (OP == VEC_P_UPDATE) {
+            float4 p = y0[i];
+            const float4 r = y1[i];
+            p.x = r.x + bv * p.x; p.y = r.y + bv * p.y; p.z = r.z + bv * p.z; p.w = r.w + bv * p.w;
+            y0[i] = p;
+        } else if constexpr (OP == VEC_COPY) {
+            y0[i] = y1[i];
+        } else if constexpr (OP == VEC_ADD) {
+            float4 p = y0[i];
+            const float4 r = y1[i];
+            p.x += r.x; p.y += r.y; p.z += r.z; p.w += r.w;
+            y0[i] = p;
+        }
+    }
+    if constexpr (OP == VEC_DOT || OP == VEC_XR_UPDATE) {
+        const double t = block_sum(acc, red);
+        if (threadIdx.x == 0) partial[blockIdx.x] = t;
+    }
+}
+
+// Sum the partials of each frame in a fixed order: the chat segments of its
+// planes (plane order), then its rho segments.  One workgroup per frame.
+__device__ __forceinline__ double frame_total(const SegGeom& g, const double* partial, int f,
+                                              const int* frame_plane0, const int* frame_planes,
+                                              double* red) {
+    const int p0 = frame_plane0 ? frame_plane0[f] : 0;
+    const int np = frame_planes ? frame_planes[f] : g.nplanes;
+    const int nc = np * g.cseg;
+    const int tot = nc + g.rseg;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < tot; i += kThreads) {
+        acc += (i < nc) ? partial[p0 * g.cseg + i]
+                        : partial[g.nplanes * g.cseg + f * g.rseg + (i - nc)];
+    }
+    return block_sum(acc, red);
+}
+
+// CG and Newton scalars of every frame of a class, all on the device.
+struct Scalars {
+    double* rr;        // [F] <r, r>
+    float* a;          // [F] CG step a = rr / gamma
+    float* beta;       // [F]
+    int* brk;          // [F] breakdown in the current Newton step
+    float* alpha;      // [F] current alpha (and -alpha at alpha + F)
+    float* s;          // [F] data scale
+    float* inv_s;      // [F]
+    double* stats;     // [F][stats_len]
+    int stats_len;
+};
+
+enum ScalarOp : int {
+    SC_YNORM = 0,      // s = scale_norm / ||y|| (scale_norm > 0 and ||y|| > 0), else 1
+    SC_R0NORM = 1,     // stats[2 + step] = ||r0||
+    SC_RR0 = 2,        // rr = <b, b>; new Newton step: clear breakdown
+    SC_GAMMA = 3,      // gamma = Re<p, q>; a = rr / gamma or breakdown
+    SC_RR = 4,         // rr' = <r, r>; beta = rr'/rr; rr = rr'; stats
+};
+
+__global__ __launch_bounds__(kThreads) void k_scalar(int op, SegGeom g, const double* partial,
+                                                     const int* frame_plane0, const int* frame_planes,
+                                                     Scalars sc, float scale_norm, int step) {
+    __shared__ double red[4];
+    const int f = blockIdx.x;
+    const double t = frame_total(g, partial, f, frame_plane0, frame_planes, red);
+    if (threadIdx.x != 0) return;
+    double* st = sc.stats + (long long)f * sc.stats_len;
+    if (op == SC_YNORM) {
+        const double nrm = sqrt(t);
+        const float s = (scale_norm > 0.f && nrm > 0.0) ? (float)(scale_norm / nrm) : 1.0f;
+        sc.s[f] = s;
+        sc.inv_s[f] = 1.0f / s;
+        st[0] = (double)s;
+        st[1] = 0.0;
+        if (!isfinite(nrm)) st[1] = 2.0;
+    } else if (op == SC_R0NORM) {
+        st[2 + step] = sqrt(t);
+        if (!isfinite(t)) st[1] = (double)((int)st[1] | 2);
+    } else if (op == SC_RR0) {
+        sc.rr[f] = t;
+        sc.brk[f] = 0;
+    } else if (op == SC_GAMMA) {
+        const double rr = sc.rr[f];
+        if (sc.brk[f] || rr == 0.0 || !(t > 0.0) || !isfinite(rr)) {
+            if (!sc.brk[f]) {
+                int fl = (int)st[1] | 1;
+                if (!isfinite(t) || !isfinite(rr)) fl |= 2;
+                st[1] = (double)fl;
+            }
+            sc.brk[f] = 1;
+            sc.a[f] = 0.f;
+        } else {
+            sc.a[f] = (float)(rr / t);
+        }
+    } else if (op == SC_RR) {
+        if (sc.brk[f]) {
+            sc.beta[f] = 0.f;
+        } else {
+            if (!isfinite(t)) st[1] = (double)((int)st[1] | 2);
+            sc.beta[f] = (float)(t / sc.rr[f]);
+            sc.rr[f] = t;
+        }
+    }
+}
+
+// stats of CG iteration `it` of Newton step `step`: <r,r> or -1 after a breakdown
+__global__ void k_cg_stat(Scalars sc, int nframes, int nsteps, int ncg, int step, int it) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nframes) return;
+    double* st = sc.stats + (long long)f * sc.stats_len;
+    st[2 + nsteps + step * ncg + it] = sc.brk[f] ? -1.0 : sc.rr[f];
+}
+
+// per-frame: alpha[f] = value, alpha[F + f] = -value
+__global__ void k_set_alpha(float* alpha, int nframes, float value) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f < nframes) { alpha[f] = value; alpha[nframes + f] = -value; }
+}
+
+// x[f][e] = s_f * src[f][e] (src nullable -> s_f * 1) on rho parts
+__global__ __launch_bounds__(kThreads) void k_scale_rho(float2* x, const float2* src, const float* s,
+                                                        int nframes, int E, int use_inv) {
+    const long long tot = (long long)nframes * E;
+    for (long long g = (long long)blockIdx.x * kThreads + threadIdx.x; g < tot;
+         g += (long long)gridDim.x * kThreads) {
+        const int f = (int)(g / E);
+        const float sf = s[f];
+        const float2 v = src ? src[g] : make_float2(1.f, 0.f);
+        x[g] = cscale(v, sf);
+        (void)use_inv;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill(float2* x, long long n, float2 v) {
+    for (long long g = (long long)blockIdx.x * kThreads + threadIdx.x; g < n;
+         g += (long long)gridDim.x * kThreads) x[g] = v;
+}
+
+}  // namespace nlinv

@@ -1,0 +1,39 @@
+// Host-side launchers of the size-templated pass kernels.  Each grid size is
+// instantiated in its own translation unit (inst.hip built with
+// -DNLINV_SIZE=n) so that the sizes compile in parallel.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "pass_kernels.hpp"
+
+namespace nlinv {
+
+// The grid sizes the library is built for: 2^p and 3 * 2^p from 8 to 1024.
+#define NLINV_FOR_EACH_SIZE(X) \
+    X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
+
+// Pass variants = lines (columns or rows) per 256-thread workgroup.
+constexpr int kColL[] = {8, 16, 4};
+constexpr int kRowL[] = {4, 8, 2, 1};
+constexpr int kNumColVariants = 3;
+constexpr int kNumRowVariants = 4;
+
+constexpr bool col_variant_ok(int n, int v) {
+    return v >= 0 && v < kNumColVariants && n % kColL[v] == 0 && n * kColL[v] <= 16384;
+}
+constexpr bool row_variant_ok(int n, int v) {
+    return v >= 0 && v < kNumRowVariants && n * kRowL[v] <= 8192;
+}
+
+template <int N>
+hipError_t launch_col(int mode, int variant, const ColArgs& a, int nplanes, hipStream_t s);
+template <int N>
+hipError_t launch_row(int mode, int variant, const RowArgs& a, hipStream_t s);
+
+#define NLINV_DECLARE(N)                                                                       \
+    extern template hipError_t launch_col<N>(int, int, const ColArgs&, int, hipStream_t);       \
+    extern template hipError_t launch_row<N>(int, int, const RowArgs&, hipStream_t);
+NLINV_FOR_EACH_SIZE(NLINV_DECLARE)
+#undef NLINV_DECLARE
+
+}  // namespace nlinv

@@ -1,0 +1,1202 @@
+// Host side of the NLINV library: plans and workspace, the operator
+// sequences of F, DF, DF^H and the normal operator (Eqs. 2-3 of Schaetz &
+// Uecker), the IRGNM / CG driver with every scalar on the device, hipGraph
+// capture of the Newton loop, the pass autotuner, kernel timing, and the
+// C ABI declared in include/nlinv.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "nlinv.h"
+#include "aux_kernels.hpp"
+#include "launch.hpp"
+
+using namespace nlinv;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+#define HIPCHK(expr)                                             \
+    do {                                                         \
+        hipError_t e_ = (expr);                                  \
+        if (e_ != hipSuccess) {                                  \
+            g_last_hip = (int)e_;                                \
+            return NLINV_EHIP;                                   \
+        }                                                        \
+    } while (0)
+
+#define CHK(expr)                                                \
+    do {                                                         \
+        int st_ = (expr);                                        \
+        if (st_ != NLINV_OK) return st_;                         \
+    } while (0)
+
+constexpr int kMaxNewton = 32;
+constexpr int kMaxCG = 256;
+constexpr int kStatsCap = 2 + kMaxNewton + kMaxNewton * kMaxCG;
+constexpr int kSegLen = 4096;        // complex elements per reduction segment
+constexpr int kTimingSlots = 8192;   // event pairs for kernel timing
+
+bool size_supported(int n) {
+    switch (n) {
+#define X(N) case N:
+        NLINV_FOR_EACH_SIZE(X)
+#undef X
+        return true;
+        default: return false;
+    }
+}
+
+hipError_t col_dispatch(int n, int mode, int variant, const ColArgs& a, int nplanes, hipStream_t s) {
+    switch (n) {
+#define X(N) case N: return launch_col<N>(mode, variant, a, nplanes, s);
+        NLINV_FOR_EACH_SIZE(X)
+#undef X
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t row_dispatch(int n, int mode, int variant, const RowArgs& a, hipStream_t s) {
+    switch (n) {
+#define X(N) case N: return launch_row<N>(mode, variant, a, s);
+        NLINV_FOR_EACH_SIZE(X)
+#undef X
+    }
+    return hipErrorInvalidValue;
+}
+
+bool col_ok(int n, int v) { return col_variant_ok(n, v); }
+bool row_ok(int n, int v) { return row_variant_ok(n, v); }
+
+// kernel classes for timing
+enum KClass : int {
+    KC_COL_WINV_IFFT = 0, KC_COL_P_IFFT, KC_COL_FFT_P, KC_COL_FFT_P_RESID, KC_COL_PSF,
+    KC_COL_FFT_WINV_ADD, KC_COL_FFT_GPROD, KC_ROW_CACHE, KC_ROW_FWD, KC_ROW_DERIV, KC_ROW_ADJ,
+    KC_COIL_SUM, KC_VEC_DOT, KC_VEC_XR, KC_VEC_P, KC_VEC_OTHER, KC_SCALAR, KC_IMAGE, KC_NUM
+};
+const char* kKClassNames[KC_NUM] = {
+    "col_winv_ifft", "col_p_ifft", "col_fft_p", "col_fft_p_resid", "col_psf",
+    "col_fft_winv_add", "col_fft_gprod", "row_cache", "row_fwd", "row_deriv", "row_adj",
+    "coil_sum", "vec_dot", "vec_xr_update", "vec_p_update", "vec_other", "scalar", "image"};
+
+int col_kclass(int mode) {
+    switch (mode) {
+        case COL_WINV_IFFT_CROP: return KC_COL_WINV_IFFT;
+        case COL_P_IFFT_CROP: return KC_COL_P_IFFT;
+        case COL_PAD_FFT_P: return KC_COL_FFT_P;
+        case COL_PAD_FFT_P_RESID: return KC_COL_FFT_P_RESID;
+        case COL_PAD_FFT_P2_IFFT: return KC_COL_PSF;
+        case COL_PAD_FFT_WINV_ADD: return KC_COL_FFT_WINV_ADD;
+        default: return KC_COL_FFT_GPROD;
+    }
+}
+int row_kclass(int mode) {
+    switch (mode) {
+        case ROW_CACHE: return KC_ROW_CACHE;
+        case ROW_FWD: return KC_ROW_FWD;
+        case ROW_DERIV: return KC_ROW_DERIV;
+        default: return KC_ROW_ADJ;
+    }
+}
+
+// One shape class: frames of a plan that share n and n_om.  Every CG vector
+// of the class is stored contiguously: chat parts [planes][n*n], rho parts
+// [frames][m*m].
+struct Class {
+    int n = 0, m = 0, lo = 0;
+    int nframes = 0, nplanes = 0;
+    std::vector<int> frames;     // plan frame index of each class frame
+    std::vector<int> J, plane0;
+    int colv = 0, rowv = 0;
+
+    int* plane_frame = nullptr;
+    int* frame_plane0 = nullptr;
+    int* frame_planes = nullptr;
+    float2* tw = nullptr;
+    float2 *x_c = nullptr, *x_r = nullptr, *dx_c = nullptr, *dx_r = nullptr;
+    float2 *r_c = nullptr, *r_r = nullptr, *p_c = nullptr, *p_r = nullptr;
+    float2 *q_c = nullptr, *q_r = nullptr, *xr_c = nullptr, *xr_r = nullptr;
+    float2* y = nullptr;
+    float* P = nullptr;
+    float2 *c = nullptr, *T = nullptr, *aux = nullptr;
+    double* partial = nullptr;
+    float* alpha = nullptr;      // [2F]: alpha, -alpha
+    SegGeom geom{}, geomC{};
+    Scalars sc{};
+
+    long long cplane() const { return (long long)n * n; }
+    long long rplane() const { return (long long)m * m; }
+};
+
+struct GraphKey {
+    int newton = -1, cg = -1;
+    float a0 = 0, q = 0, amin = 0;
+    bool operator==(const GraphKey& o) const {
+        return newton == o.newton && cg == o.cg && a0 == o.a0 && q == o.q && amin == o.amin;
+    }
+};
+
+}  // namespace
+
+struct nlinv_plan_s {
+    int device = 0;
+    std::vector<nlinv_dims> dims;
+    std::vector<Class> classes;
+    std::vector<std::pair<int, int>> loc;   // frame -> (class, class-local frame)
+    float sob_a = 220.f, sob_hl = 16.f;
+    std::vector<void*> allocs;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    GraphKey gkey;
+    // kernel timing
+    bool timing[KC_NUM] = {};
+    std::vector<hipEvent_t> ev;
+    std::vector<unsigned char> ev_used;
+    int ev_next = 0;
+    bool capturing = false;
+};
+
+namespace {
+
+template <class T>
+int dalloc(nlinv_plan_s* p, T** out, size_t count) {
+    void* q = nullptr;
+    size_t bytes = count * sizeof(T);
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) {
+        g_last_hip = (int)e;
+        return NLINV_ENOMEM;
+    }
+    p->allocs.push_back(q);
+    e = hipMemset(q, 0, bytes);
+    if (e != hipSuccess) {
+        g_last_hip = (int)e;
+        return NLINV_EHIP;
+    }
+    *out = static_cast<T*>(q);
+    return NLINV_OK;
+}
+
+void make_geom(SegGeom& g, int nplanes, int nframes, long long cn, long long rn, bool with_rho,
+               const int* plane_frame) {
+    g.nplanes = nplanes;
+    g.nframes = nframes;
+    g.cn = (int)cn;
+    g.rn = (int)rn;
+    g.cseg = (int)((cn + kSegLen - 1) / kSegLen);
+    g.clen = (int)((cn + g.cseg - 1) / g.cseg);
+    g.clen += g.clen & 1;
+    g.rseg = with_rho ? (int)((rn + kSegLen - 1) / kSegLen) : 0;
+    g.rlen = with_rho ? (int)((rn + g.rseg - 1) / g.rseg) : 2;
+    g.rlen += g.rlen & 1;
+    g.plane_frame = plane_frame;
+}
+
+int nseg(const SegGeom& g) { return g.nplanes * g.cseg + g.nframes * g.rseg; }
+
+// ---- timing brackets --------------------------------------------------------
+
+// Slots: ev_used 0 = free, 1 = recorded by an eager launch (read once),
+// 2 = owned by the captured graph (re-recorded by every replay).
+int tbegin(nlinv_plan_s* p, int kc, hipStream_t s) {
+    if (!p->timing[kc] || p->ev.empty()) return -1;
+    for (int tries = 0; tries < kTimingSlots; ++tries) {
+        const int slot = p->ev_next;
+        p->ev_next = (p->ev_next + 1) % kTimingSlots;
+        if (p->ev_used[slot] == 2) continue;
+        if (hipEventRecord(p->ev[2 * slot], s) != hipSuccess) return -1;
+        return slot;
+    }
+    return -1;
+}
+void tend(nlinv_plan_s* p, int slot, hipStream_t s) {
+    if (slot < 0) return;
+    if (hipEventRecord(p->ev[2 * slot + 1], s) == hipSuccess) p->ev_used[slot] = p->capturing ? 2 : 1;
+}
+int drop_graph(nlinv_plan_s* p) {
+    if (!p->gexec) return NLINV_OK;
+    hipError_t e = hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+    for (auto& u : p->ev_used)
+        if (u == 2) u = 0;
+    HIPCHK(e);
+    return NLINV_OK;
+}
+
+// ---- launch helpers -----------------------------------------------------------
+
+ColArgs col_args(const nlinv_plan_s* p, const Class& C) {
+    ColArgs a{};
+    a.m = C.m;
+    a.lo = C.lo;
+    a.sob_a = p->sob_a;
+    a.sob_hl = p->sob_hl;
+    a.rs = (float)(1.0 / std::sqrt((double)C.n));
+    a.tw = C.tw;
+    return a;
+}
+
+RowArgs row_args(const Class& C) {
+    RowArgs a{};
+    a.m = C.m;
+    a.lo = C.lo;
+    a.rs = (float)(1.0 / std::sqrt((double)C.n));
+    a.tw = C.tw;
+    return a;
+}
+
+int run_col(nlinv_plan_s* p, const Class& C, int mode, const ColArgs& a, int nplanes, hipStream_t s) {
+    const int slot = tbegin(p, col_kclass(mode), s);
+    hipError_t e = col_dispatch(C.n, mode, C.colv, a, nplanes, s);
+    tend(p, slot, s);
+    HIPCHK(e);
+    return NLINV_OK;
+}
+
+int run_row(nlinv_plan_s* p, const Class& C, int mode, const RowArgs& a, hipStream_t s) {
+    const int slot = tbegin(p, row_kclass(mode), s);
+    hipError_t e = row_dispatch(C.n, mode, C.rowv, a, s);
+    tend(p, slot, s);
+    HIPCHK(e);
+    return NLINV_OK;
+}
+
+int grid_for(long long n, int per = kThreads) {
+    long long g = (n + per - 1) / per;
+    if (g > 65535) g = 65535;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+int run_coil_sum(nlinv_plan_s* p, const CoilSumArgs& a, hipStream_t s) {
+    const int slot = tbegin(p, KC_COIL_SUM, s);
+    hipLaunchKernelGGL(k_coil_sum, dim3(grid_for((long long)a.nframes * a.E)), dim3(kThreads), 0, s, a);
+    hipError_t e = hipGetLastError();
+    tend(p, slot, s);
+    HIPCHK(e);
+    return NLINV_OK;
+}
+
+template <int OP>
+int run_vec(nlinv_plan_s* p, const SegGeom& g, const VecPtrs& v, const float* a_f, const float* b_f,
+            double* partial, hipStream_t s) {
+    const int kc = OP == VEC_DOT ? KC_VEC_DOT : OP == VEC_XR_UPDATE ? KC_VEC_XR
+                 : OP == VEC_P_UPDATE ? KC_VEC_P : KC_VEC_OTHER;
+    const int slot = tbegin(p, kc, s);
+    hipLaunchKernelGGL((k_vec<OP>), dim3(nseg(g)), dim3(kThreads), 0, s, g, v, a_f, b_f, partial);
+    hipError_t e = hipGetLastError();
+    tend(p, slot, s);
+    HIPCHK(e);
+    return NLINV_OK;
+}
+
+int run_scalar(nlinv_plan_s* p, Class& C, int op, const SegGeom& g, float scale_norm, int step,
+               hipStream_t s) {
+    const int slot = tbegin(p, KC_SCALAR, s);
+    hipLaunchKernelGGL(k_scalar, dim3(C.nframes), dim3(kThreads), 0, s, op, g, C.partial,
+                       C.frame_plane0, C.frame_planes, C.sc, scale_norm, step);
+    hipError_t e = hipGetLastError();
+    tend(p, slot, s);
+    HIPCHK(e);
+    return NLINV_OK;
+}
+
+VecPtrs vptrs(float2* c0, float2* r0, float2* c1 = nullptr, float2* r1 = nullptr,
+              float2* c2 = nullptr, float2* r2 = nullptr, float2* c3 = nullptr, float2* r3 = nullptr) {
+    VecPtrs v{};
+    v.c0 = c0; v.r0 = r0; v.c1 = c1; v.r1 = r1; v.c2 = c2; v.r2 = r2; v.c3 = c3; v.r3 = r3;
+    return v;
+}
+
+// ---- operator sequences (shared by the single-frame calls and the solve) --
+
+struct Frames {               // which planes / frames a sequence acts on
+    int nplanes, nframes;
+    const int* plane_frame;   // nullable
+    const int* frame_plane0;  // nullable
+    const int* frame_planes;  // nullable
+};
+
+// c = E^H W^{-1} chat
+int seq_coil_maps(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2* chat, float2* c_out,
+                  hipStream_t s) {
+    ColArgs a = col_args(p, C);
+    a.in = chat;
+    a.out = C.T;
+    a.plane_frame = fr.plane_frame;
+    CHK(run_col(p, C, COL_WINV_IFFT_CROP, a, fr.nplanes, s));
+    RowArgs r = row_args(C);
+    r.in = C.T;
+    r.c_out = c_out;
+    r.plane_frame = fr.plane_frame;
+    r.nlines = fr.nplanes * C.m;
+    return run_row(p, C, ROW_CACHE, r, s);
+}
+
+// out = P . DFT(E(rho . c))  or, with y != NULL, out = s y - P . DFT(E(rho . c))
+int seq_forward(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2* rho, const float2* c,
+                const float* P, long long p_stride, float2* out, const float2* y, const float* s_y,
+                hipStream_t s) {
+    RowArgs r = row_args(C);
+    r.c = c;
+    r.rho = rho;
+    r.out = C.T;
+    r.plane_frame = fr.plane_frame;
+    r.nlines = fr.nplanes * C.m;
+    CHK(run_row(p, C, ROW_FWD, r, s));
+    ColArgs a = col_args(p, C);
+    a.in = C.T;
+    a.out = out;
+    a.P = P;
+    a.p_stride = p_stride;
+    a.plane_frame = fr.plane_frame;
+    if (y) {
+        a.add1 = y;
+        a.s1 = s_y;
+        a.c1 = 1.f;
+        return run_col(p, C, COL_PAD_FFT_P_RESID, a, fr.nplanes, s);
+    }
+    return run_col(p, C, COL_PAD_FFT_P, a, fr.nplanes, s);
+}
+
+// T = row-DFT(E(drho . c + rho . E^H W^{-1} dchat))   (first half of DF)
+int seq_deriv_head(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2* rho, const float2* c,
+                   const float2* drho, const float2* dchat, hipStream_t s) {
+    ColArgs a = col_args(p, C);
+    a.in = dchat;
+    a.out = C.T;
+    a.plane_frame = fr.plane_frame;
+    CHK(run_col(p, C, COL_WINV_IFFT_CROP, a, fr.nplanes, s));
+    RowArgs r = row_args(C);
+    r.in = C.T;
+    r.out = C.T;
+    r.c = c;
+    r.rho = rho;
+    r.drho = drho;
+    r.plane_frame = fr.plane_frame;
+    r.nlines = fr.nplanes * C.m;
+    return run_row(p, C, ROW_DERIV, r, s);
+}
+
+// from T = crop_rows(IDFT_0(...)): u = crop(IDFT_1(T)); aux = conj(c) u;
+// dchat_out = W^{-H} E(conj(rho) u) + s1 add1 + s2 add2;
+// drho_out = sum_j aux + s1 add1r + s2 add2r
+int seq_adjoint_tail(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2* rho, const float2* c,
+                     float2* drho_out, float2* dchat_out, const float2* add1c, const float2* add1r,
+                     const float2* add2c, const float2* add2r, const float* s1, const float* s2,
+                     float c1, float c2, hipStream_t s) {
+    RowArgs r = row_args(C);
+    r.in = C.T;
+    r.out = C.T;
+    r.c = c;
+    r.rho = rho;
+    r.aux = C.aux;
+    r.plane_frame = fr.plane_frame;
+    r.nlines = fr.nplanes * C.m;
+    CHK(run_row(p, C, ROW_ADJ, r, s));
+    ColArgs a = col_args(p, C);
+    a.in = C.T;
+    a.out = dchat_out;
+    a.plane_frame = fr.plane_frame;
+    a.add1 = add1c;
+    a.add2 = add2c;
+    a.s1 = s1;
+    a.s2 = s2;
+    a.c1 = c1;
+    a.c2 = c2;
+    CHK(run_col(p, C, COL_PAD_FFT_WINV_ADD, a, fr.nplanes, s));
+    CoilSumArgs cs{};
+    cs.aux = C.aux;
+    cs.out = drho_out;
+    cs.add1 = add1r;
+    cs.add2 = add2r;
+    cs.s1 = s1;
+    cs.s2 = s2;
+    cs.c1 = c1;
+    cs.c2 = c2;
+    cs.frame_plane0 = fr.frame_plane0;
+    cs.frame_planes = fr.frame_planes;
+    cs.nplanes = fr.nplanes;
+    cs.nframes = fr.nframes;
+    cs.E = C.m * C.m;
+    return run_coil_sum(p, cs, s);
+}
+
+// (drho_out, dchat_out) = (DF^H DF + alpha) (drho, dchat)
+int seq_normal(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2* rho, const float2* c,
+               const float* P, long long p_stride, const float* alpha_f, float alpha_c,
+               const float2* drho, const float2* dchat, float2* drho_out, float2* dchat_out,
+               hipStream_t s) {
+    CHK(seq_deriv_head(p, C, fr, rho, c, drho, dchat, s));
+    ColArgs a = col_args(p, C);
+    a.in = C.T;
+    a.out = C.T;
+    a.P = P;
+    a.p_stride = p_stride;
+    a.plane_frame = fr.plane_frame;
+    CHK(run_col(p, C, COL_PAD_FFT_P2_IFFT, a, fr.nplanes, s));
+    return seq_adjoint_tail(p, C, fr, rho, c, drho_out, dchat_out, dchat, drho, nullptr, nullptr,
+                            alpha_f, nullptr, alpha_c, 0.f, s);
+}
+
+Frames single_frame(int J) { return Frames{J, 1, nullptr, nullptr, nullptr}; }
+Frames class_frames(const Class& C) {
+    return Frames{C.nplanes, C.nframes, C.plane_frame, C.frame_plane0, C.frame_planes};
+}
+
+// ---- the Newton loop of one solve (device-only work: capturable) ------------
+
+float alpha_of(const nlinv_irgnm_params& prm, int step) {
+    double a = (double)prm.alpha0 * std::pow((double)prm.alpha_q, step);
+    if (a < prm.alpha_min) a = prm.alpha_min;
+    return (float)a;
+}
+
+int enqueue_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s) {
+    const int N = prm.newton_steps, K = prm.cg_iters;
+    for (int step = 0; step < N; ++step) {
+        const float al = alpha_of(prm, step);
+        for (Class& C : p->classes) {
+            const Frames fr = class_frames(C);
+            const long long ps = C.cplane();
+            hipLaunchKernelGGL(k_set_alpha, dim3((C.nframes + 63) / 64), dim3(64), 0, s, C.alpha, C.nframes, al);
+            HIPCHK(hipGetLastError());
+            // linearisation cache c at x_n
+            CHK(seq_coil_maps(p, C, fr, C.x_c, C.c, s));
+            // r0 = s y - F(x_n) into q, its norm
+            CHK(seq_forward(p, C, fr, C.x_r, C.c, C.P, ps, C.q_c, C.y, C.sc.s, s));
+            CHK(run_vec<VEC_DOT>(p, C.geomC, vptrs(C.q_c, nullptr, C.q_c, nullptr), nullptr, nullptr, C.partial, s));
+            CHK(run_scalar(p, C, SC_R0NORM, C.geomC, 0.f, step, s));
+            // b = DF^H r0 - alpha (x_n - x_ref) into r
+            {
+                ColArgs a = col_args(p, C);
+                a.in = C.q_c;
+                a.out = C.T;
+                a.P = C.P;
+                a.p_stride = ps;
+                a.plane_frame = fr.plane_frame;
+                CHK(run_col(p, C, COL_P_IFFT_CROP, a, fr.nplanes, s));
+                CHK(seq_adjoint_tail(p, C, fr, C.x_r, C.c, C.r_r, C.r_c, C.x_c, C.x_r, C.xr_c, C.xr_r,
+                                     C.alpha + C.nframes, C.alpha, 0.f, 0.f, s));
+            }
+            CHK(run_vec<VEC_COPY>(p, C.geom, vptrs(C.p_c, C.p_r, C.r_c, C.r_r), nullptr, nullptr, nullptr, s));
+            {
+                const int slot = tbegin(p, KC_VEC_OTHER, s);
+                hipLaunchKernelGGL(k_fill, dim3(grid_for((long long)C.nplanes * ps)), dim3(kThreads), 0, s,
+                                   C.dx_c, (long long)C.nplanes * ps, make_float2(0.f, 0.f));
+                hipLaunchKernelGGL(k_fill, dim3(grid_for((long long)C.nframes * C.rplane())), dim3(kThreads), 0, s,
+                                   C.dx_r, (long long)C.nframes * C.rplane(), make_float2(0.f, 0.f));
+                tend(p, slot, s);
+                HIPCHK(hipGetLastError());
+            }
+            CHK(run_vec<VEC_DOT>(p, C.geom, vptrs(C.r_c, C.r_r, C.r_c, C.r_r), nullptr, nullptr, C.partial, s));
+            CHK(run_scalar(p, C, SC_RR0, C.geom, 0.f, step, s));
+        }
+        for (int it = 0; it < K; ++it) {
+            for (Class& C : p->classes) {
+                const Frames fr = class_frames(C);
+                CHK(seq_normal(p, C, fr, C.x_r, C.c, C.P, C.cplane(), C.alpha, 0.f, C.p_r, C.p_c, C.q_r,
+                               C.q_c, s));
+                CHK(run_vec<VEC_DOT>(p, C.geom, vptrs(C.p_c, C.p_r, C.q_c, C.q_r), nullptr, nullptr, C.partial, s));
+                CHK(run_scalar(p, C, SC_GAMMA, C.geom, 0.f, step, s));
+                CHK(run_vec<VEC_XR_UPDATE>(p, C.geom, vptrs(C.dx_c, C.dx_r, C.p_c, C.p_r, C.r_c, C.r_r, C.q_c, C.q_r),
+                                           C.sc.a, nullptr, C.partial, s));
+                CHK(run_scalar(p, C, SC_RR, C.geom, 0.f, step, s));
+                hipLaunchKernelGGL(k_cg_stat, dim3((C.nframes + 63) / 64), dim3(64), 0, s, C.sc, C.nframes, N, K,
+                                   step, it);
+                HIPCHK(hipGetLastError());
+                CHK(run_vec<VEC_P_UPDATE>(p, C.geom, vptrs(C.p_c, C.p_r, C.r_c, C.r_r), nullptr, C.sc.beta, nullptr, s));
+            }
+        }
+        for (Class& C : p->classes)
+            CHK(run_vec<VEC_ADD>(p, C.geom, vptrs(C.x_c, C.x_r, C.dx_c, C.dx_r), nullptr, nullptr, nullptr, s));
+    }
+    // sensitivities of the final x (for the image)
+    for (Class& C : p->classes) CHK(seq_coil_maps(p, C, class_frames(C), C.x_c, C.c, s));
+    return NLINV_OK;
+}
+
+int check_params(const nlinv_irgnm_params* prm) {
+    if (!prm) return NLINV_EINVAL;
+    if (prm->newton_steps < 0 || prm->newton_steps > kMaxNewton) return NLINV_EINVAL;
+    if (prm->cg_iters < 0 || prm->cg_iters > kMaxCG) return NLINV_EINVAL;
+    if (!(prm->alpha0 >= 0.f) || !(prm->alpha_q >= 0.f) || !(prm->alpha_min >= 0.f) || !(prm->scale_norm >= 0.f))
+        return NLINV_EINVAL;
+    return NLINV_OK;
+}
+
+bool aligned(const void* q) { return ((uintptr_t)q & 15) == 0; }
+
+// Per-frame set-up: copy y and P into the class workspace, data scale, x0, x_ref.
+int setup_frames(nlinv_plan_s* p, const nlinv_frame* frames, const nlinv_irgnm_params& prm, hipStream_t s) {
+    for (Class& C : p->classes) {
+        for (int lf = 0; lf < C.nframes; ++lf) {
+            const nlinv_frame& F = frames[C.frames[lf]];
+            const size_t cb = (size_t)C.J[lf] * C.cplane() * sizeof(float2);
+            HIPCHK(hipMemcpyAsync(C.y + (size_t)C.plane0[lf] * C.cplane(), F.y, cb, hipMemcpyDeviceToDevice, s));
+            HIPCHK(hipMemcpyAsync(C.P + (size_t)lf * C.cplane(), F.P, C.cplane() * sizeof(float),
+                                  hipMemcpyDeviceToDevice, s));
+        }
+        CHK(run_vec<VEC_DOT>(p, C.geomC, vptrs(C.y, nullptr, C.y, nullptr), nullptr, nullptr, C.partial, s));
+        CHK(run_scalar(p, C, SC_YNORM, C.geomC, prm.scale_norm, 0, s));
+        // x0: warm start copies the caller's x (rho scaled below); else rho = 1 (scaled units), chat = 0
+        const bool warm = (prm.flags & NLINV_WARM_START) != 0;
+        for (int lf = 0; lf < C.nframes; ++lf) {
+            const nlinv_frame& F = frames[C.frames[lf]];
+            const size_t cb = (size_t)C.J[lf] * C.cplane() * sizeof(float2);
+            float2* xc = C.x_c + (size_t)C.plane0[lf] * C.cplane();
+            float2* xr = C.x_r + (size_t)lf * C.rplane();
+            if (warm) {
+                HIPCHK(hipMemcpyAsync(xc, F.chat, cb, hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(xr, F.rho, C.rplane() * sizeof(float2), hipMemcpyDeviceToDevice, s));
+            } else {
+                HIPCHK(hipMemsetAsync(xc, 0, cb, s));
+            }
+        }
+        if (warm) {
+            hipLaunchKernelGGL(k_scale_rho, dim3(grid_for((long long)C.nframes * C.rplane())), dim3(kThreads), 0, s,
+                               C.x_r, (const float2*)C.x_r, (const float*)C.sc.s, C.nframes, (int)C.rplane(), 0);
+        } else {
+            hipLaunchKernelGGL(k_fill, dim3(grid_for((long long)C.nframes * C.rplane())), dim3(kThreads), 0, s,
+                               C.x_r, (long long)C.nframes * C.rplane(), make_float2(1.f, 0.f));
+        }
+        HIPCHK(hipGetLastError());
+        // x_ref
+        for (int lf = 0; lf < C.nframes; ++lf) {
+            const nlinv_frame& F = frames[C.frames[lf]];
+            const size_t cb = (size_t)C.J[lf] * C.cplane() * sizeof(float2);
+            float2* rc = C.xr_c + (size_t)C.plane0[lf] * C.cplane();
+            float2* rr = C.xr_r + (size_t)lf * C.rplane();
+            if (F.rho_ref && F.chat_ref) {
+                HIPCHK(hipMemcpyAsync(rc, F.chat_ref, cb, hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(rr, F.rho_ref, C.rplane() * sizeof(float2), hipMemcpyDeviceToDevice, s));
+            } else {
+                HIPCHK(hipMemcpyAsync(rc, C.x_c + (size_t)C.plane0[lf] * C.cplane(), cb, hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(rr, C.x_r + (size_t)lf * C.rplane(), C.rplane() * sizeof(float2),
+                                      hipMemcpyDeviceToDevice, s));
+            }
+        }
+        // a caller's x_ref is in data units: scale its rho part (x0-derived refs already are scaled)
+        bool any_ref = false;
+        for (int lf = 0; lf < C.nframes; ++lf) {
+            const nlinv_frame& F = frames[C.frames[lf]];
+            if (F.rho_ref && F.chat_ref) any_ref = true;
+        }
+        if (any_ref) {
+            for (int lf = 0; lf < C.nframes; ++lf) {
+                const nlinv_frame& F = frames[C.frames[lf]];
+                if (!(F.rho_ref && F.chat_ref)) continue;
+                float2* rr = C.xr_r + (size_t)lf * C.rplane();
+                hipLaunchKernelGGL(k_scale_rho, dim3(grid_for(C.rplane())), dim3(kThreads), 0, s, rr,
+                                   (const float2*)rr, (const float*)(C.sc.s + lf), 1, (int)C.rplane(), 0);
+                HIPCHK(hipGetLastError());
+            }
+        }
+    }
+    return NLINV_OK;
+}
+
+int finish_frames(nlinv_plan_s* p, const nlinv_frame* frames, const nlinv_irgnm_params& prm, hipStream_t s) {
+    const int stats_len = 2 + prm.newton_steps + prm.newton_steps * prm.cg_iters;
+    for (Class& C : p->classes) {
+        // image (uses rho in scaled units times 1/s) into aux, rho / s into dx_r
+        const int slot = tbegin(p, KC_IMAGE, s);
+        hipLaunchKernelGGL(k_image, dim3(grid_for((long long)C.nframes * C.rplane())), dim3(kThreads), 0, s,
+                           (const float2*)C.x_r, (const float2*)C.c, C.aux, (const int*)C.frame_plane0,
+                           (const int*)C.frame_planes, C.nplanes, C.nframes, (int)C.rplane(),
+                           (const float*)C.sc.inv_s);
+        tend(p, slot, s);
+        hipLaunchKernelGGL(k_scale_rho, dim3(grid_for((long long)C.nframes * C.rplane())), dim3(kThreads), 0, s,
+                           C.dx_r, (const float2*)C.x_r, (const float*)C.sc.inv_s, C.nframes, (int)C.rplane(), 1);
+        HIPCHK(hipGetLastError());
+        for (int lf = 0; lf < C.nframes; ++lf) {
+            const nlinv_frame& F = frames[C.frames[lf]];
+            const size_t cb = (size_t)C.J[lf] * C.cplane() * sizeof(float2);
+            const size_t rb = C.rplane() * sizeof(float2);
+            HIPCHK(hipMemcpyAsync(F.rho, C.dx_r + (size_t)lf * C.rplane(), rb, hipMemcpyDeviceToDevice, s));
+            HIPCHK(hipMemcpyAsync(F.chat, C.x_c + (size_t)C.plane0[lf] * C.cplane(), cb, hipMemcpyDeviceToDevice, s));
+            if (F.image)
+                HIPCHK(hipMemcpyAsync(F.image, C.aux + (size_t)lf * C.rplane(), rb, hipMemcpyDeviceToDevice, s));
+            if (F.stats)
+                HIPCHK(hipMemcpyAsync(F.stats, C.sc.stats + (size_t)lf * kStatsCap, stats_len * sizeof(double),
+                                      hipMemcpyDeviceToDevice, s));
+        }
+    }
+    return NLINV_OK;
+}
+
+int validate_frames(nlinv_plan_s* p, const nlinv_frame* frames, int count) {
+    if (!frames) return NLINV_EINVAL;
+    for (int f = 0; f < count; ++f) {
+        const nlinv_frame& F = frames[f];
+        if (!F.y || !F.P || !F.rho || !F.chat) return NLINV_EINVAL;
+        if (!aligned(F.y) || !aligned(F.P) || !aligned(F.rho) || !aligned(F.chat)) return NLINV_EINVAL;
+        if ((F.rho_ref == nullptr) != (F.chat_ref == nullptr)) return NLINV_EINVAL;
+        if (F.image && !aligned(F.image)) return NLINV_EINVAL;
+        if (F.stats && ((uintptr_t)F.stats & 7)) return NLINV_EINVAL;
+    }
+    (void)p;
+    return NLINV_OK;
+}
+
+int run_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s) {
+    // stats_len must be known to the kernels that write stats
+    for (Class& C : p->classes) C.sc.stats_len = kStatsCap;
+    if (!(prm.flags & NLINV_USE_GRAPH)) return enqueue_newton(p, prm, s);
+    GraphKey key{prm.newton_steps, prm.cg_iters, prm.alpha0, prm.alpha_q, prm.alpha_min};
+    if (!p->gexec || !(p->gkey == key)) {
+        CHK(drop_graph(p));
+        HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+        p->capturing = true;
+        const int st = enqueue_newton(p, prm, p->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+        p->capturing = false;
+        if (st != NLINV_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        HIPCHK(e);
+        e = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPCHK(e);
+        p->gkey = key;
+    }
+    HIPCHK(hipGraphLaunch(p->gexec, s));
+    return NLINV_OK;
+}
+
+int solve_all(nlinv_plan_s* p, const nlinv_frame* frames, const nlinv_irgnm_params& prm, hipStream_t s) {
+    CHK(setup_frames(p, frames, prm, s));
+    CHK(run_newton(p, prm, s));
+    return finish_frames(p, frames, prm, s);
+}
+
+// ---- twiddles -------------------------------------------------------------------
+
+int make_twiddles(nlinv_plan_s* p, Class& C) {
+    std::vector<float2> h(C.n);
+    for (int k = 0; k < C.n; ++k) {
+        const double ang = -2.0 * M_PI * (double)k / (double)C.n;
+        h[k] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+    CHK(dalloc(p, &C.tw, C.n));
+    HIPCHK(hipMemcpy(C.tw, h.data(), C.n * sizeof(float2), hipMemcpyHostToDevice));
+    return NLINV_OK;
+}
+
+int default_col_variant(int n) {
+    for (int v = 0; v < kNumColVariants; ++v)
+        if (col_ok(n, v)) return v;
+    return -1;
+}
+int default_row_variant(int n) {
+    for (int v = 0; v < kNumRowVariants; ++v)
+        if (row_ok(n, v)) return v;
+    return -1;
+}
+
+int build_class(nlinv_plan_s* p, Class& C) {
+    CHK(make_twiddles(p, C));
+    const long long cn = C.cplane(), rn = C.rplane();
+    const size_t cv = (size_t)C.nplanes * cn, rv = (size_t)C.nframes * rn;
+    std::vector<int> pf(C.nplanes), fp0(C.nframes), fpn(C.nframes);
+    for (int lf = 0; lf < C.nframes; ++lf) {
+        fp0[lf] = C.plane0[lf];
+        fpn[lf] = C.J[lf];
+        for (int j = 0; j < C.J[lf]; ++j) pf[C.plane0[lf] + j] = lf;
+    }
+    CHK(dalloc(p, &C.plane_frame, C.nplanes));
+    CHK(dalloc(p, &C.frame_plane0, C.nframes));
+    CHK(dalloc(p, &C.frame_planes, C.nframes));
+    HIPCHK(hipMemcpy(C.plane_frame, pf.data(), pf.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(C.frame_plane0, fp0.data(), fp0.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(C.frame_planes, fpn.data(), fpn.size() * sizeof(int), hipMemcpyHostToDevice));
+    float2** cvecs[] = {&C.x_c, &C.dx_c, &C.r_c, &C.p_c, &C.q_c, &C.xr_c, &C.y};
+    for (float2** v : cvecs) CHK(dalloc(p, v, cv));
+    float2** rvecs[] = {&C.x_r, &C.dx_r, &C.r_r, &C.p_r, &C.q_r, &C.xr_r};
+    for (float2** v : rvecs) CHK(dalloc(p, v, rv));
+    CHK(dalloc(p, &C.P, (size_t)C.nframes * cn));
+    CHK(dalloc(p, &C.c, (size_t)C.nplanes * rn));
+    CHK(dalloc(p, &C.aux, (size_t)C.nplanes * rn));
+    CHK(dalloc(p, &C.T, (size_t)C.nplanes * C.m * C.n));
+    make_geom(C.geom, C.nplanes, C.nframes, cn, rn, true, C.plane_frame);
+    make_geom(C.geomC, C.nplanes, C.nframes, cn, rn, false, C.plane_frame);
+    CHK(dalloc(p, &C.partial, (size_t)std::max(nseg(C.geom), nseg(C.geomC))));
+    CHK(dalloc(p, &C.alpha, (size_t)2 * C.nframes));
+    CHK(dalloc(p, &C.sc.rr, C.nframes));
+    CHK(dalloc(p, &C.sc.a, C.nframes));
+    CHK(dalloc(p, &C.sc.beta, C.nframes));
+    CHK(dalloc(p, &C.sc.brk, C.nframes));
+    CHK(dalloc(p, &C.sc.s, C.nframes));
+    CHK(dalloc(p, &C.sc.inv_s, C.nframes));
+    CHK(dalloc(p, &C.sc.stats, (size_t)C.nframes * kStatsCap));
+    C.sc.alpha = C.alpha;
+    C.sc.stats_len = kStatsCap;
+    C.colv = default_col_variant(C.n);
+    C.rowv = default_row_variant(C.n);
+    return NLINV_OK;
+}
+
+void free_plan(nlinv_plan_s* p) {
+    if (!p) return;
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    for (void* q : p->allocs) (void)hipFree(q);
+    delete p;
+}
+
+int check_dims(const nlinv_dims& d) {
+    if (d.n <= 0 || d.n_om <= 0 || d.ncoils <= 0) return NLINV_EINVAL;
+    if (!size_supported(d.n)) return NLINV_EUNSUPPORTED;
+    if ((d.n_om & 1) || d.n_om > d.n) return NLINV_EUNSUPPORTED;
+    if (d.ncoils > 64) return NLINV_EUNSUPPORTED;
+    if (!(d.sobolev_a >= 0.f) || !(d.sobolev_l >= 0.f)) return NLINV_EINVAL;
+    return NLINV_OK;
+}
+
+Class* class0(nlinv_plan_s* p) { return &p->classes[p->loc[0].first]; }
+
+// time `reps` launches of a representative pass for every variant; keep the fastest
+int tune_class(nlinv_plan_s* p, Class& C, hipStream_t s) {
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const int reps = 10;
+    const Frames fr = class_frames(C);
+    float best = 1e30f;
+    int bestv = C.colv;
+    for (int v = 0; v < kNumColVariants; ++v) {
+        if (!col_ok(C.n, v)) continue;
+        C.colv = v;
+        ColArgs a = col_args(p, C);
+        a.in = C.T;
+        a.out = C.T;
+        a.P = C.P;
+        a.p_stride = C.cplane();
+        a.plane_frame = fr.plane_frame;
+        CHK(run_col(p, C, COL_PAD_FFT_P2_IFFT, a, fr.nplanes, s));   // warm-up
+        HIPCHK(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r) CHK(run_col(p, C, COL_PAD_FFT_P2_IFFT, a, fr.nplanes, s));
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) { best = ms; bestv = v; }
+    }
+    C.colv = bestv;
+    best = 1e30f;
+    bestv = C.rowv;
+    for (int v = 0; v < kNumRowVariants; ++v) {
+        if (!row_ok(C.n, v)) continue;
+        C.rowv = v;
+        RowArgs r = row_args(C);
+        r.in = C.T;
+        r.out = C.T;
+        r.c = C.c;
+        r.rho = C.x_r;
+        r.drho = C.p_r;
+        r.plane_frame = fr.plane_frame;
+        r.nlines = fr.nplanes * C.m;
+        CHK(run_row(p, C, ROW_DERIV, r, s));
+        HIPCHK(hipEventRecord(e0, s));
+        for (int k = 0; k < reps; ++k) CHK(run_row(p, C, ROW_DERIV, r, s));
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) { best = ms; bestv = v; }
+    }
+    C.rowv = bestv;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return NLINV_OK;
+}
+
+std::string arch_name(int dev) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+}  // namespace
+
+// =============================================================================
+// C ABI
+// =============================================================================
+
+extern "C" {
+
+const char* nlinv_status_string(int status) {
+    switch (status) {
+        case NLINV_OK: return "ok";
+        case NLINV_EINVAL: return "invalid argument";
+        case NLINV_EUNSUPPORTED: return "unsupported size";
+        case NLINV_ENOMEM: return "out of device memory";
+        case NLINV_EHIP: return "HIP error";
+        default: return "unknown status";
+    }
+}
+
+int nlinv_last_hip_error(void) { return g_last_hip; }
+
+const char* nlinv_kernel_class_name(int32_t kclass) {
+    if (kclass < 0 || kclass >= KC_NUM) return nullptr;
+    return kKClassNames[kclass];
+}
+
+int nlinv_plan_create(nlinv_plan* out, const nlinv_dims* dims, int32_t nframes) {
+    if (!out || !dims || nframes <= 0 || nframes > 4096) return NLINV_EINVAL;
+    *out = nullptr;
+    for (int f = 0; f < nframes; ++f) CHK(check_dims(dims[f]));
+    for (int f = 1; f < nframes; ++f)
+        if (dims[f].sobolev_a != dims[0].sobolev_a || dims[f].sobolev_l != dims[0].sobolev_l) return NLINV_EINVAL;
+    nlinv_plan_s* p = new (std::nothrow) nlinv_plan_s;
+    if (!p) return NLINV_ENOMEM;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) { g_last_hip = (int)e; delete p; return NLINV_EHIP; }
+    p->dims.assign(dims, dims + nframes);
+    p->sob_a = dims[0].sobolev_a;
+    p->sob_hl = 0.5f * dims[0].sobolev_l;
+    p->loc.resize(nframes);
+    std::map<std::pair<int, int>, int> cls;
+    for (int f = 0; f < nframes; ++f) {
+        const auto key = std::make_pair(dims[f].n, dims[f].n_om);
+        auto it = cls.find(key);
+        int ci;
+        if (it == cls.end()) {
+            ci = (int)p->classes.size();
+            cls[key] = ci;
+            Class C;
+            C.n = dims[f].n;
+            C.m = dims[f].n_om;
+            C.lo = C.n / 2 - C.m / 2;
+            p->classes.push_back(C);
+        } else {
+            ci = it->second;
+        }
+        Class& C = p->classes[ci];
+        p->loc[f] = {ci, C.nframes};
+        C.frames.push_back(f);
+        C.J.push_back(dims[f].ncoils);
+        C.plane0.push_back(C.nplanes);
+        C.nplanes += dims[f].ncoils;
+        C.nframes += 1;
+    }
+    for (Class& C : p->classes) {
+        if (C.nplanes > 65535) { free_plan(p); return NLINV_EUNSUPPORTED; }   // column-pass grid.y
+        const int st = build_class(p, C);
+        if (st != NLINV_OK) { free_plan(p); return st; }
+    }
+    e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) { g_last_hip = (int)e; free_plan(p); return NLINV_EHIP; }
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) { g_last_hip = (int)e; free_plan(p); return NLINV_EHIP; }
+    *out = p;
+    return NLINV_OK;
+}
+
+int nlinv_plan_destroy(nlinv_plan plan) {
+    if (!plan) return NLINV_OK;
+    (void)hipDeviceSynchronize();
+    free_plan(plan);
+    return NLINV_OK;
+}
+
+int nlinv_coil_maps(nlinv_plan p, const nlinv_c32* chat, nlinv_c32* c_out, void* stream) {
+    if (!p || !chat || !c_out || !aligned(chat) || !aligned(c_out)) return NLINV_EINVAL;
+    Class& C = *class0(p);
+    return seq_coil_maps(p, C, single_frame(p->dims[0].ncoils), (const float2*)chat, (float2*)c_out,
+                         (hipStream_t)stream);
+}
+
+int nlinv_forward(nlinv_plan p, const nlinv_c32* rho, const nlinv_c32* chat, const float* P,
+                  nlinv_c32* y_out, nlinv_c32* c_out, void* stream) {
+    if (!p || !rho || !chat || !P || !y_out) return NLINV_EINVAL;
+    if (!aligned(rho) || !aligned(chat) || !aligned(P) || !aligned(y_out) || (c_out && !aligned(c_out)))
+        return NLINV_EINVAL;
+    Class& C = *class0(p);
+    const hipStream_t s = (hipStream_t)stream;
+    const Frames fr = single_frame(p->dims[0].ncoils);
+    float2* c = c_out ? (float2*)c_out : C.c;
+    CHK(seq_coil_maps(p, C, fr, (const float2*)chat, c, s));
+    return seq_forward(p, C, fr, (const float2*)rho, c, P, 0, (float2*)y_out, nullptr, nullptr, s);
+}
+
+int nlinv_deriv(nlinv_plan p, const nlinv_c32* rho, const nlinv_c32* chat, const nlinv_c32* c,
+                const float* P, const nlinv_c32* drho, const nlinv_c32* dchat, nlinv_c32* dy_out,
+                void* stream) {
+    if (!p || !rho || !P || !drho || !dchat || !dy_out || (!c && !chat)) return NLINV_EINVAL;
+    if (!aligned(rho) || !aligned(P) || !aligned(drho) || !aligned(dchat) || !aligned(dy_out) ||
+        (c && !aligned(c)) || (chat && !aligned(chat)))
+        return NLINV_EINVAL;
+    Class& C = *class0(p);
+    const hipStream_t s = (hipStream_t)stream;
+    const Frames fr = single_frame(p->dims[0].ncoils);
+    const float2* cc = (const float2*)c;
+    if (!cc) {
+        CHK(seq_coil_maps(p, C, fr, (const float2*)chat, C.c, s));
+        cc = C.c;
+    }
+    CHK(seq_deriv_head(p, C, fr, (const float2*)rho, cc, (const float2*)drho, (const float2*)dchat, s));
+    ColArgs a = col_args(p, C);
+    a.in = C.T;
+    a.out = (float2*)dy_out;
+    a.P = P;
+    return run_col(p, C, COL_PAD_FFT_P, a, fr.nplanes, s);
+}
+
+int nlinv_adjoint(nlinv_plan p, const nlinv_c32* rho, const nlinv_c32* chat, const nlinv_c32* c,
+                  const float* P, const nlinv_c32* dy, nlinv_c32* drho_out, nlinv_c32* dchat_out,
+                  void* stream) {
+    if (!p || !rho || !P || !dy || !drho_out || !dchat_out || (!c && !chat)) return NLINV_EINVAL;
+    if (!aligned(rho) || !aligned(P) || !aligned(dy) || !aligned(drho_out) || !aligned(dchat_out) ||
+        (c && !aligned(c)) || (chat && !aligned(chat)))
+        return NLINV_EINVAL;
+    Class& C = *class0(p);
+    const hipStream_t s = (hipStream_t)stream;
+    const Frames fr = single_frame(p->dims[0].ncoils);
+    const float2* cc = (const float2*)c;
+    if (!cc) {
+        CHK(seq_coil_maps(p, C, fr, (const float2*)chat, C.c, s));
+        cc = C.c;
+    }
+    ColArgs a = col_args(p, C);
+    a.in = (const float2*)dy;
+    a.out = C.T;
+    a.P = P;
+    CHK(run_col(p, C, COL_P_IFFT_CROP, a, fr.nplanes, s));
+    return seq_adjoint_tail(p, C, fr, (const float2*)rho, cc, (float2*)drho_out, (float2*)dchat_out, nullptr,
+                            nullptr, nullptr, nullptr, nullptr, nullptr, 0.f, 0.f, s);
+}
+
+int nlinv_normal(nlinv_plan p, const nlinv_c32* rho, const nlinv_c32* chat, const nlinv_c32* c,
+                 const float* P, float alpha, const nlinv_c32* drho, const nlinv_c32* dchat,
+                 nlinv_c32* drho_out, nlinv_c32* dchat_out, void* stream) {
+    if (!p || !rho || !P || !drho || !dchat || !drho_out || !dchat_out || (!c && !chat)) return NLINV_EINVAL;
+    if (!aligned(rho) || !aligned(P) || !aligned(drho) || !aligned(dchat) || !aligned(drho_out) ||
+        !aligned(dchat_out) || (c && !aligned(c)) || (chat && !aligned(chat)))
+        return NLINV_EINVAL;
+    Class& C = *class0(p);
+    const hipStream_t s = (hipStream_t)stream;
+    const Frames fr = single_frame(p->dims[0].ncoils);
+    const float2* cc = (const float2*)c;
+    if (!cc) {
+        CHK(seq_coil_maps(p, C, fr, (const float2*)chat, C.c, s));
+        cc = C.c;
+    }
+    return seq_normal(p, C, fr, (const float2*)rho, cc, P, 0, nullptr, alpha, (const float2*)drho,
+                      (const float2*)dchat, (float2*)drho_out, (float2*)dchat_out, s);
+}
+
+int nlinv_mask_gradient(nlinv_plan p, const nlinv_c32* rho, const nlinv_c32* chat, const nlinv_c32* c,
+                        const nlinv_c32* g, float* gP_out, void* stream) {
+    if (!p || !rho || !g || !gP_out || (!c && !chat)) return NLINV_EINVAL;
+    if (!aligned(rho) || !aligned(g) || !aligned(gP_out) || (c && !aligned(c)) || (chat && !aligned(chat)))
+        return NLINV_EINVAL;
+    Class& C = *class0(p);
+    const hipStream_t s = (hipStream_t)stream;
+    const int J = p->dims[0].ncoils;
+    const Frames fr = single_frame(J);
+    const float2* cc = (const float2*)c;
+    if (!cc) {
+        CHK(seq_coil_maps(p, C, fr, (const float2*)chat, C.c, s));
+        cc = C.c;
+    }
+    RowArgs r = row_args(C);
+    r.c = cc;
+    r.rho = (const float2*)rho;
+    r.out = C.T;
+    r.nlines = J * C.m;
+    CHK(run_row(p, C, ROW_FWD, r, s));
+    ColArgs a = col_args(p, C);
+    a.in = C.T;
+    a.out = C.q_c;                  // real products Re(conj g . S) [J][n][n] as floats
+    a.add1 = (const float2*)g;
+    CHK(run_col(p, C, COL_PAD_FFT_GPROD, a, J, s));
+    const int slot = tbegin(p, KC_COIL_SUM, s);
+    hipLaunchKernelGGL(k_coil_sum_real, dim3(grid_for(C.cplane())), dim3(kThreads), 0, s,
+                       (const float*)C.q_c, gP_out, J, (int)C.cplane());
+    hipError_t e = hipGetLastError();
+    tend(p, slot, s);
+    HIPCHK(e);
+    return NLINV_OK;
+}
+
+int nlinv_image(nlinv_plan p, const nlinv_c32* rho, const nlinv_c32* c, nlinv_c32* image_out, void* stream) {
+    if (!p || !rho || !c || !image_out || !aligned(rho) || !aligned(c) || !aligned(image_out)) return NLINV_EINVAL;
+    Class& C = *class0(p);
+    const hipStream_t s = (hipStream_t)stream;
+    const int slot = tbegin(p, KC_IMAGE, s);
+    hipLaunchKernelGGL(k_image, dim3(grid_for(C.rplane())), dim3(kThreads), 0, s, (const float2*)rho,
+                       (const float2*)c, (float2*)image_out, (const int*)nullptr, (const int*)nullptr,
+                       p->dims[0].ncoils, 1, (int)C.rplane(), (const float*)nullptr);
+    hipError_t e = hipGetLastError();
+    tend(p, slot, s);
+    HIPCHK(e);
+    return NLINV_OK;
+}
+
+int nlinv_irgnm_solve(nlinv_plan p, const nlinv_c32* y, const float* P, const nlinv_irgnm_params* prm,
+                      nlinv_c32* rho_inout, nlinv_c32* chat_inout, const nlinv_c32* rho_ref,
+                      const nlinv_c32* chat_ref, nlinv_c32* image_out, double* stats_out, void* stream) {
+    if (!p) return NLINV_EINVAL;
+    CHK(check_params(prm));
+    if (p->dims.size() != 1) return NLINV_EINVAL;
+    nlinv_frame f{};
+    f.y = y;
+    f.P = P;
+    f.rho = rho_inout;
+    f.chat = chat_inout;
+    f.rho_ref = rho_ref;
+    f.chat_ref = chat_ref;
+    f.image = image_out;
+    f.stats = stats_out;
+    CHK(validate_frames(p, &f, 1));
+    return solve_all(p, &f, *prm, (hipStream_t)stream);
+}
+
+int nlinv_irgnm_solve_batch(nlinv_plan p, const nlinv_frame* frames, const nlinv_irgnm_params* prm,
+                            void* stream) {
+    if (!p) return NLINV_EINVAL;
+    CHK(check_params(prm));
+    CHK(validate_frames(p, frames, (int)p->dims.size()));
+    return solve_all(p, frames, *prm, (hipStream_t)stream);
+}
+
+int nlinv_irgnm_solve_series(nlinv_plan p, int32_t count, const nlinv_frame* frames,
+                             const nlinv_irgnm_params* prm, void* stream) {
+    if (!p || count < 0) return NLINV_EINVAL;
+    CHK(check_params(prm));
+    if (p->dims.size() != 1) return NLINV_EINVAL;
+    CHK(validate_frames(p, frames, count));
+    const hipStream_t s = (hipStream_t)stream;
+    for (int t = 0; t < count; ++t) {
+        nlinv_frame f = frames[t];
+        nlinv_irgnm_params q = *prm;
+        if (t > 0) {
+            // x0 = x_ref = the previous frame's result, in data units
+            q.flags |= NLINV_WARM_START;
+            HIPCHK(hipMemcpyAsync(f.rho, frames[t - 1].rho, class0(p)->rplane() * sizeof(float2),
+                                  hipMemcpyDeviceToDevice, s));
+            HIPCHK(hipMemcpyAsync(f.chat, frames[t - 1].chat,
+                                  (size_t)p->dims[0].ncoils * class0(p)->cplane() * sizeof(float2),
+                                  hipMemcpyDeviceToDevice, s));
+            f.rho_ref = frames[t - 1].rho;
+            f.chat_ref = frames[t - 1].chat;
+        }
+        CHK(solve_all(p, &f, q, s));
+    }
+    return NLINV_OK;
+}
+
+int nlinv_plan_autotune(nlinv_plan p, void* stream) {
+    if (!p) return NLINV_EINVAL;
+    const hipStream_t s = (hipStream_t)stream;
+    const std::string arch = arch_name(p->device);
+    const char* path = std::getenv("NLINV_TUNE_CACHE");
+    std::map<std::string, std::pair<int, int>> cache;
+    if (path) {
+        std::ifstream in(path);
+        std::string a;
+        int n, np, cv, rv;
+        while (in >> a >> n >> np >> cv >> rv) {
+            std::ostringstream k;
+            k << a << ' ' << n << ' ' << np;
+            cache[k.str()] = {cv, rv};
+        }
+    }
+    bool changed = false;
+    for (Class& C : p->classes) {
+        std::ostringstream k;
+        k << arch << ' ' << C.n << ' ' << C.nplanes;
+        auto it = cache.find(k.str());
+        if (it != cache.end() && col_ok(C.n, it->second.first) && row_ok(C.n, it->second.second)) {
+            C.colv = it->second.first;
+            C.rowv = it->second.second;
+            continue;
+        }
+        CHK(tune_class(p, C, s));
+        cache[k.str()] = {C.colv, C.rowv};
+        changed = true;
+    }
+    CHK(drop_graph(p));   // variants are baked into a captured graph
+    if (path && changed) {
+        std::ofstream o(path);
+        for (auto& kv : cache) o << kv.first << ' ' << kv.second.first << ' ' << kv.second.second << '\n';
+    }
+    return NLINV_OK;
+}
+
+int nlinv_plan_variant(nlinv_plan p, int32_t n, int32_t* col_variant, int32_t* row_variant) {
+    if (!p || !col_variant || !row_variant) return NLINV_EINVAL;
+    for (Class& C : p->classes)
+        if (C.n == n) {
+            *col_variant = C.colv;
+            *row_variant = C.rowv;
+            return NLINV_OK;
+        }
+    *col_variant = *row_variant = -1;
+    return NLINV_EINVAL;
+}
+
+int nlinv_plan_set_variant(nlinv_plan p, int32_t n, int32_t col_variant, int32_t row_variant) {
+    if (!p) return NLINV_EINVAL;
+    if (!col_ok(n, col_variant) || !row_ok(n, row_variant)) return NLINV_EINVAL;
+    bool found = false;
+    for (Class& C : p->classes)
+        if (C.n == n) {
+            C.colv = col_variant;
+            C.rowv = row_variant;
+            found = true;
+        }
+    if (!found) return NLINV_EINVAL;
+    CHK(drop_graph(p));
+    return NLINV_OK;
+}
+
+int nlinv_plan_timing_enable(nlinv_plan p, int32_t kclass, int32_t enable) {
+    if (!p || kclass < 0 || kclass >= KC_NUM) return NLINV_EINVAL;
+    if (enable && p->ev.empty()) {
+        p->ev.resize(2 * kTimingSlots);
+        p->ev_used.assign(kTimingSlots, 0);
+        for (auto& e : p->ev) HIPCHK(hipEventCreate(&e));
+    }
+    p->timing[kclass] = enable != 0;
+    CHK(drop_graph(p));   // a captured graph holds the old brackets
+    return NLINV_OK;
+}
+
+int nlinv_plan_timing_read(nlinv_plan p, int32_t* launches, double* total_ms) {
+    if (!p || !launches || !total_ms) return NLINV_EINVAL;
+    int cnt = 0;
+    double tot = 0.0;
+    for (int k = 0; k < (int)p->ev_used.size(); ++k) {
+        if (!p->ev_used[k]) continue;
+        HIPCHK(hipEventSynchronize(p->ev[2 * k + 1]));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, p->ev[2 * k], p->ev[2 * k + 1]));
+        tot += ms;
+        ++cnt;
+        if (p->ev_used[k] == 1) p->ev_used[k] = 0;
+    }
+    *launches = cnt;
+    *total_ms = tot;
+    return NLINV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,64 @@
+"""The C ABI library: it loads, exports every entry point include/nlinv.h
+declares, and rejects bad arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1301_1215_amd import _native as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "nlinv.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nlinv_\w+)\s*\(", src)) - {"NLINV_STATS_LEN"})
+
+
+def test_header_declares_the_five_operators_and_solves():
+    names = declared_functions()
+    for f in ("nlinv_forward", "nlinv_deriv", "nlinv_adjoint", "nlinv_normal", "nlinv_irgnm_solve",
+              "nlinv_irgnm_solve_batch", "nlinv_irgnm_solve_series"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = N.load()
+    missing = [f for f in declared_functions() if not hasattr(lib, f)]
+    assert not missing, missing
+    assert sorted(N.EXPORTED) == declared_functions()
+
+
+def _create(n, n_om, J, a=220.0, l=32.0):
+    lib = N.load()
+    h = ctypes.c_void_p()
+    d = (N.nlinv_dims * 1)(N.nlinv_dims(n, n_om, J, a, l))
+    return lib.nlinv_plan_create(ctypes.byref(h), d, 1)
+
+
+@pytest.mark.parametrize("n,n_om,J,code", [
+    (100, 50, 4, N.NLINV_EUNSUPPORTED),    # 100 = 2^2 5^2
+    (6, 6, 1, N.NLINV_EUNSUPPORTED),       # below the smallest grid
+    (2048, 64, 1, N.NLINV_EUNSUPPORTED),   # above the largest grid
+    (64, 33, 4, N.NLINV_EUNSUPPORTED),     # odd Omega side
+    (64, 128, 4, N.NLINV_EUNSUPPORTED),    # Omega larger than the grid
+    (64, 32, 65, N.NLINV_EUNSUPPORTED),    # too many coils
+    (64, 32, 0, N.NLINV_EINVAL),
+    (0, 0, 1, N.NLINV_EINVAL),
+])
+def test_plan_create_rejects_bad_dims(n, n_om, J, code):
+    assert _create(n, n_om, J) == code
+
+
+def test_null_arguments():
+    lib = N.load()
+    d = (N.nlinv_dims * 1)(N.nlinv_dims(64, 32, 4, 220.0, 32.0))
+    assert lib.nlinv_plan_create(None, d, 1) == N.NLINV_EINVAL
+    assert lib.nlinv_plan_destroy(None) == N.NLINV_OK
+    assert lib.nlinv_forward(None, None, None, None, None, None, None) == N.NLINV_EINVAL
+    assert lib.nlinv_irgnm_solve(None, None, None, None, None, None, None, None, None, None, None) == N.NLINV_EINVAL
+    assert lib.nlinv_status_string(N.NLINV_EUNSUPPORTED) == b"unsupported size"
+    assert lib.nlinv_kernel_class_name(-1) is None
+    assert len(N.nlinv_kernel_class_names()) > 10

@@ -1,0 +1,140 @@
+"""GPU parity of every operator call of the C ABI against the FP64 oracle.
+
+Bar: relative L2 error <= 1e-5 per apply (FP32 on the GPU, FP64 oracle on
+the same complex64 / float32 inputs)."""
+import numpy as np
+import pytest
+
+from oracle import nlinv_oracle as O
+from paper_1301_1215_amd import Plan
+from tests.gpu_util import dev, host, rel, rand_c, soft_mask
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+SIZES = [8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024]
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_fft_engine_is_the_centred_unitary_dft(n):
+    """One coil, chat = n * delta at DC (so c = 1), P = 1, Omega = grid:
+    F(rho) is the centred DFT of rho, on every supported grid size."""
+    rng = np.random.default_rng([10, n])
+    rho = rand_c((n, n), rng)
+    chat = np.zeros((1, n, n), np.complex64)
+    chat[0, n // 2, n // 2] = n
+    with Plan(n, n, 1) as pl:
+        y = host(pl.forward(dev(rho), dev(chat), dev(np.ones((n, n), np.float32))))
+    assert rel(y[0], O.dft2c(rho)) < TOL
+
+
+@pytest.mark.parametrize("n", [8, 12, 48, 384, 1024])
+def test_coil_maps_inverse_weighted_dft(n):
+    rng = np.random.default_rng([11, n])
+    n_om = n // 2
+    d = O.Dims(n, n_om, 3)
+    chat = rand_c((3, n, n), rng)
+    with Plan(n, n_om, 3) as pl:
+        c = host(pl.coil_maps(dev(chat)))
+    assert rel(c, O.coil_maps(chat, d)) < TOL
+
+
+SHAPES = [(64, 64, 8), (384, 192, 12), (96, 48, 3), (48, 24, 2), (128, 64, 5), (512, 256, 4),
+          (32, 32, 1), (24, 12, 3), (1024, 512, 2), (8, 2, 1), (192, 96, 7), (768, 384, 1)]
+
+
+def _point(n, n_om, J, seed):
+    rng = np.random.default_rng([12, n, n_om, J, seed])
+    rho = rand_c((n_om, n_om), rng)
+    chat = rand_c((J, n, n), rng)
+    P = soft_mask(n, rng)
+    return rng, rho, chat, P
+
+
+@pytest.mark.parametrize("n,n_om,J", SHAPES)
+def test_operators_match_oracle(n, n_om, J):
+    rng, rho, chat, P = _point(n, n_om, J, 0)
+    drho, dchat = rand_c((n_om, n_om), rng), rand_c((J, n, n), rng)
+    z = rand_c((J, n, n), rng)
+    alpha = 0.3
+    d = O.Dims(n, n_om, J)
+    with Plan(n, n_om, J) as pl:
+        g_rho, g_chat, gP, g_drho, g_dchat, gz = map(dev, (rho, chat, P, drho, dchat, z))
+        y, c = pl.forward(g_rho, g_chat, gP, return_c=True)
+        dy = pl.deriv(g_rho, g_chat, gP, g_drho, g_dchat, c=c)
+        dy_nc = pl.deriv(g_rho, g_chat, gP, g_drho, g_dchat)
+        ar, ac = pl.adjoint(g_rho, g_chat, gP, gz, c=c)
+        nr, nc = pl.normal(g_rho, g_chat, gP, alpha, g_drho, g_dchat, c=c)
+        img = pl.image(g_rho, c)
+        y, c, dy, dy_nc, ar, ac, nr, nc, img = map(host, (y, c, dy, dy_nc, ar, ac, nr, nc, img))
+    c_ref = O.coil_maps(chat, d)
+    assert rel(c, c_ref) < TOL
+    assert rel(y, O.forward(rho, chat, P, d)) < TOL
+    dy_ref = O.deriv(rho, chat, P, drho, dchat, d)
+    assert rel(dy, dy_ref) < TOL
+    assert rel(dy_nc, dy_ref) < TOL
+    a_ref = O.adjoint(rho, chat, P, z, d)
+    assert rel(ar, a_ref[0]) < TOL
+    assert rel(ac, a_ref[1]) < TOL
+    n_ref = O.normal(rho, chat, P, alpha, drho, dchat, d)
+    assert rel(nr, n_ref[0]) < TOL
+    assert rel(nc, n_ref[1]) < TOL
+    assert rel(img, O.combined_image(rho, chat, d)) < TOL
+
+
+@pytest.mark.parametrize("n,n_om,J", [(64, 32, 4), (384, 192, 12), (48, 48, 2)])
+def test_adjoint_identity_in_fp32(n, n_om, J):
+    """<DF h, z> = <h, DF^H z> evaluated on the GPU outputs."""
+    rng, rho, chat, P = _point(n, n_om, J, 1)
+    h_rho, h_chat, z = rand_c((n_om, n_om), rng), rand_c((J, n, n), rng), rand_c((J, n, n), rng)
+    with Plan(n, n_om, J) as pl:
+        dy = host(pl.deriv(dev(rho), dev(chat), dev(P), dev(h_rho), dev(h_chat)))
+        ar, ac = map(host, pl.adjoint(dev(rho), dev(chat), dev(P), dev(z)))
+    lhs = np.vdot(dy.astype(np.complex128), z.astype(np.complex128))
+    rhs = np.vdot(h_rho.astype(np.complex128), ar) + np.vdot(h_chat.astype(np.complex128), ac)
+    assert abs(lhs - rhs) / abs(lhs) < TOL
+
+
+@pytest.mark.parametrize("n,n_om,J", [(32, 32, 4), (256, 256, 8), (96, 48, 3)])
+def test_mask_gradient_matches_oracle(n, n_om, J):
+    rng, rho, chat, P = _point(n, n_om, J, 2)
+    g = rand_c((J, n, n), rng)
+    d = O.Dims(n, n_om, J)
+    with Plan(n, n_om, J) as pl:
+        gP = host(pl.mask_gradient(dev(rho), dev(chat), dev(g)))
+    assert rel(gP, O.mask_gradient(rho, chat, P, g, d)) < TOL
+
+
+@pytest.mark.parametrize("n,n_om,J", [(384, 192, 12), (64, 64, 8)])
+def test_every_pass_variant_gives_the_same_operator(n, n_om, J):
+    from paper_1301_1215_amd._native import NlinvError
+    rng, rho, chat, P = _point(n, n_om, J, 3)
+    drho, dchat = rand_c((n_om, n_om), rng), rand_c((J, n, n), rng)
+    d = O.Dims(n, n_om, J)
+    n_ref = O.normal(rho, chat, P, 0.5, drho, dchat, d)
+    with Plan(n, n_om, J) as pl:
+        tried = 0
+        for cv in range(3):
+            for rv in range(4):
+                try:
+                    pl.set_variant(n, cv, rv)
+                except NlinvError:
+                    continue
+                tried += 1
+                nr, nc = map(host, pl.normal(dev(rho), dev(chat), dev(P), 0.5, dev(drho), dev(dchat)))
+                assert rel(nr, n_ref[0]) < TOL, (cv, rv)
+                assert rel(nc, n_ref[1]) < TOL, (cv, rv)
+        assert tried >= 4
+
+
+def test_kernel_timing_counts_launches():
+    n, n_om, J = 128, 64, 4
+    rng, rho, chat, P = _point(n, n_om, J, 4)
+    with Plan(n, n_om, J) as pl:
+        pl.timing_enable("col_psf")
+        args = tuple(map(dev, (rho, chat, P)))
+        for _ in range(3):
+            pl.normal(*args, 0.5, dev(rho), dev(chat))
+        cnt, ms = pl.timing_read()
+        assert cnt == 3 and ms > 0
+        assert pl.timing_read()[0] == 0

@@ -1,0 +1,123 @@
+"""GPU parity of the IRGNM solves (single frame, graph, batch, series)
+against the FP64 oracle: image NRMSE <= 1e-3."""
+import numpy as np
+import pytest
+
+from oracle import nlinv_oracle as O
+from paper_1301_1215_amd import Plan, synth
+from tests.gpu_util import dev, host, rel
+
+pytestmark = pytest.mark.gpu
+
+NRMSE = 1e-3
+
+
+def oracle_solve(fr, newton, cg, **kw):
+    O.set_workers(8)
+    return O.irgnm(fr.y, fr.P, O.Dims(fr.n, fr.n_om, fr.ncoils),
+                   O.IRGNMParams(newton_steps=newton, cg_iters=cg, **kw))
+
+
+def gpu_solve(fr, newton, cg, use_graph=False, **kw):
+    with Plan(fr.n, fr.n_om, fr.ncoils) as pl:
+        out = pl.solve(dev(fr.y), dev(fr.P), Plan.params(newton, cg, use_graph=use_graph, **kw))
+        return {k: host(v) for k, v in out.items()}
+
+
+def test_single_frame_64_matches_oracle():
+    fr = synth.single_frame_64()
+    ref = oracle_solve(fr, 6, 10)
+    got = gpu_solve(fr, 6, 10)
+    assert rel(got["image"], ref.image) < NRMSE
+    assert rel(got["rho"], ref.rho) < NRMSE
+    st = got["stats"]
+    assert abs(st[0] - ref.scale) / ref.scale < 1e-6 and st[1] == 0
+    assert np.allclose(st[2:8], ref.r0_norms, rtol=1e-4)
+    rr = st[8:].reshape(6, 10)
+    assert np.allclose(rr, np.array(ref.cg_rr), rtol=2e-3)
+
+
+def test_realtime_384_matches_oracle():
+    fr = synth.realtime_384()
+    ref = oracle_solve(fr, 7, 10)
+    got = gpu_solve(fr, 7, 10, use_graph=True)
+    assert rel(got["image"], ref.image) < NRMSE
+    assert rel(got["rho"], ref.rho) < NRMSE
+    assert np.allclose(got["stats"][2:9], ref.r0_norms, rtol=1e-4)
+
+
+def test_graph_replay_is_bitwise_eager():
+    fr = synth.make_frame(2, 3, 128, 64, 6, "radial", spokes=11)
+    with Plan(fr.n, fr.n_om, fr.ncoils) as pl:
+        y, P = dev(fr.y), dev(fr.P)
+        e = {k: host(v) for k, v in pl.solve(y, P, Plan.params(3, 5)).items()}
+        for _ in range(3):   # replays, with eager work in between
+            g = {k: host(v) for k, v in pl.solve(y, P, Plan.params(3, 5, use_graph=True)).items()}
+            for k in e:
+                assert np.array_equal(e[k], g[k]), k
+            pl.normal(dev(np.ones((64, 64), np.complex64)), dev(np.zeros((6, 128, 128), np.complex64)), P,
+                      1.0, dev(np.ones((64, 64), np.complex64)), dev(np.ones((6, 128, 128), np.complex64)))
+
+
+def test_warm_start_and_reference():
+    fr = synth.make_frame(1, 5, 64, 32, 4, "radial", spokes=9)
+    d = O.Dims(64, 32, 4)
+    rng = np.random.default_rng([3, 3])
+    rho0 = (0.5 + 0.1 * rng.standard_normal((32, 32))).astype(np.complex64)
+    chat0 = (0.01 * rng.standard_normal((4, 64, 64))).astype(np.complex64)
+    rref = (0.3 * np.ones((32, 32))).astype(np.complex64)
+    cref = np.zeros((4, 64, 64), np.complex64)
+    ref = O.irgnm(fr.y, fr.P, d, O.IRGNMParams(4, 6), rho0=rho0, chat0=chat0, rho_ref=rref, chat_ref=cref)
+    with Plan(64, 32, 4) as pl:
+        out = pl.solve(dev(fr.y), dev(fr.P), Plan.params(4, 6, warm_start=True), rho0=dev(rho0),
+                       chat0=dev(chat0), rho_ref=dev(rref), chat_ref=dev(cref))
+        assert rel(host(out["image"]), ref.image) < NRMSE
+        assert rel(host(out["chat"]), ref.chat) < NRMSE
+
+
+def test_ragged_batch_matches_single_frames_and_oracle():
+    shapes = [(64, 32, 3, 7), (48, 24, 2, 9), (64, 32, 4, 11), (96, 48, 2, 7), (48, 24, 5, 5)]
+    frames = [synth.make_frame(4, 100 + i, n, m, J, "radial", spokes=S, mask_frame=i)
+              for i, (n, m, J, S) in enumerate(shapes)]
+    prm = Plan.params(4, 6, use_graph=True)
+    with Plan(frames=[(f.n, f.n_om, f.ncoils) for f in frames]) as pl:
+        outs = pl.solve_batch([(dev(f.y), dev(f.P)) for f in frames], prm)
+        outs = [{k: host(v) for k, v in o.items()} for o in outs]
+    for f, o in zip(frames, outs):
+        single = gpu_solve(f, 4, 6)
+        for k in ("rho", "chat", "image", "stats"):
+            assert np.array_equal(o[k], single[k]), k
+        ref = oracle_solve(f, 4, 6)
+        assert rel(o["image"], ref.image) < NRMSE
+
+
+def test_temporal_series_matches_oracle():
+    ph = synth.temporal_phantom()
+    frames = [synth.temporal_frame(t, ph, n=64, ncoils=4, spokes=9) for t in range(3)]
+    ref = O.irgnm_series([f.y for f in frames], [f.P for f in frames], O.Dims(64, 32, 4), O.IRGNMParams(4, 6))
+    with Plan(64, 32, 4) as pl:
+        outs = pl.solve_series([(dev(f.y), dev(f.P)) for f in frames], Plan.params(4, 6, use_graph=True))
+        for o, r in zip(outs, ref):
+            assert rel(host(o["image"]), r.image) < NRMSE
+            assert rel(host(o["rho"]), r.rho) < NRMSE
+
+
+def test_non_finite_data_sets_the_flag():
+    fr = synth.make_frame(1, 7, 32, 16, 2, "radial", spokes=5)
+    y = fr.y.copy()
+    y[0, 16, 16] = np.nan
+    with Plan(32, 16, 2) as pl:
+        st = host(pl.solve(dev(y), dev(fr.P), Plan.params(2, 3))["stats"])
+    assert int(st[1]) & 2
+
+
+def test_breakdown_on_zero_data():
+    """y = 0 with scaling off: b = 0, so <r,r> = 0 and CG stops at once."""
+    y = np.zeros((2, 32, 32), np.complex64)
+    P = np.ones((32, 32), np.float32)
+    with Plan(32, 16, 2) as pl:
+        out = pl.solve(dev(y), dev(P), Plan.params(2, 3, scale_norm=0.0))
+        st = host(out["stats"])
+        assert int(st[1]) & 1
+        assert np.all(st[2 + 2:] == -1.0)
+        assert np.all(host(out["chat"]) == 0) and np.all(host(out["rho"]) == 1)
