@@ -78,12 +78,74 @@ def cpu_baseline(newton_sample: int):
                       f"FP64 numpy/scipy.fft with {cores} FFT workers; {dt:.1f} s measured, scaled to a frame"}
 
 
+def dominant_class(pl, data, prm, outs, names):
+    """Kernel class with the largest summed duration in one step."""
+    import torch
+    totals = {}
+    for k in names:
+        pl.timing_enable(k, True)
+        pl.solve_batch(data, prm, outs)
+        torch.cuda.synchronize()
+        cnt, ms = pl.timing_read()
+        pl.timing_enable(k, False)
+        if cnt:
+            totals[k] = (ms, cnt)
+    kc = max(totals, key=lambda k: totals[k][0])
+    log("bench: kernel-class totals per step (ms, launches): " +
+        ", ".join(f"{k}={v[0]:.3f}/{v[1]}" for k, v in sorted(totals.items(), key=lambda kv: -kv[1][0])))
+    return kc
+
+
+def compare_paths(a, data, outs, B):
+    """Plain path (one frame per solve call, eager launches) and back-to-back
+    DF^H DF applies on one frame."""
+    import numpy as np
+    import torch
+    from paper_1301_1215_amd import Plan, synth
+    from paper_1301_1215_amd import _native as NAT
+    img0 = outs[0]["image"].clone()
+    plain = Plan(N, N_OM, J)
+    pprm = Plan.params(NEWTON, CG, use_graph=False)
+    pout = plain.solve(*data[0], pprm)
+    torch.cuda.synchronize()
+    spot = float((pout["image"] - img0).abs().pow(2).sum().sqrt() / img0.abs().pow(2).sum().sqrt())
+    t0 = time.perf_counter()
+    for i in range(a.plain_frames):
+        plain.solve(*data[i % B], pprm)
+    torch.cuda.synchronize()
+    plain_fps = a.plain_frames / (time.perf_counter() - t0)
+    rng = np.random.default_rng([2, 0, 3])
+    rho = torch.from_numpy(synth.random_complex((N_OM, N_OM), rng)).cuda()
+    chat = torch.from_numpy(synth.random_complex((J, N, N), rng)).cuda()
+    c = plain.coil_maps(chat)
+    h_r = torch.from_numpy(synth.random_complex((N_OM, N_OM), rng)).cuda()
+    h_c = torch.from_numpy(synth.random_complex((J, N, N), rng)).cuda()
+    o_r, o_c = torch.empty_like(h_r), torch.empty_like(h_c)
+    P0 = data[0][1]
+    for _ in range(10):
+        NAT.nlinv_normal(plain.handle, rho, chat, c, P0, 0.5, h_r, h_c, o_r, o_c)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.applies):
+        NAT.nlinv_normal(plain.handle, rho, chat, c, P0, 0.5, h_r, h_c, o_r, o_c)
+    torch.cuda.synchronize()
+    ap_s = a.applies / (time.perf_counter() - t0)
+    nb = normal_bytes(N, N_OM, J)
+    plain.close()
+    return {"plain_frames_per_s": plain_fps, "normal_applies_per_s": ap_s,
+            "normal_algorithmic_GBps": nb * ap_s / 1e9, "batched_vs_plain_image_rel": spot}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--frames", type=int, default=8, help="frames per batched step")
+    ap.add_argument("--compare", action="store_true",
+                    help="also time the plain path (one frame per solve, eager) and DF^H DF applies; "
+                         "their launches share kernels with the timed path, so keep this off for the "
+                         "rocprofv3 run that backs the roofline")
     ap.add_argument("--plain-frames", type=int, default=4)
     ap.add_argument("--applies", type=int, default=200)
     ap.add_argument("--cpu-newton", type=int, default=2, help="Newton steps of the CPU oracle sample (0: skip)")
@@ -123,24 +185,23 @@ def main():
     torch.cuda.synchronize()
     names = NAT.nlinv_kernel_class_names()
     kc = a.kernel_class
-    if kc is None:
-        # per-class totals of one step, one class bracketed at a time
-        totals = {}
+    timing_path = "graph" if not a.no_graph else "eager"
+    try:
+        if kc is None:
+            kc = dominant_class(pl, data, prm, outs, names)
+        pl.timing_enable(kc, True)
+        pl.solve_batch(data, prm, outs)       # recapture with the brackets of this class
+        torch.cuda.synchronize()
+        pl.timing_read()
+    except NAT.NlinvError as e:
+        # event brackets inside the captured graph unavailable: time this class on eager launches
+        log(f"bench: graph-side kernel timing failed ({e}); timing kernels on eager launches")
+        timing_path = "eager"
         for k in names:
-            pl.timing_enable(k, True)
-            pl.solve_batch(data, prm, outs)
-            torch.cuda.synchronize()
-            cnt, ms = pl.timing_read()
             pl.timing_enable(k, False)
-            if cnt:
-                totals[k] = (ms, cnt)
-        kc = max(totals, key=lambda k: totals[k][0])
-        log("bench: kernel-class totals per step (ms, launches): " +
-            ", ".join(f"{k}={v[0]:.3f}/{v[1]}" for k, v in sorted(totals.items(), key=lambda kv: -kv[1][0])))
-    pl.timing_enable(kc, True)
-    pl.solve_batch(data, prm, outs)       # recapture with the brackets of this class
-    torch.cuda.synchronize()
-    pl.timing_read()
+        eprm = Plan.params(NEWTON, CG, use_graph=False)
+        if kc is None:
+            kc = dominant_class(pl, data, eprm, outs, names)
 
     # timed region
     log(f"bench: timing {a.steps} steps of {B} frames")
@@ -151,46 +212,24 @@ def main():
         pl.solve_batch(data, prm, outs)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    # graph-owned brackets hold the last replay; eager ones every launch
-    launches, kms = pl.timing_read()
+    if timing_path == "graph" or a.no_graph:
+        # graph-owned brackets hold the last replay; eager ones every launch
+        launches, kms = pl.timing_read()
+    else:
+        # the same steps again on eager launches, with this class bracketed
+        pl.timing_enable(kc, True)
+        for _ in range(a.steps):
+            pl.solve_batch(data, eprm, outs)
+        torch.cuda.synchronize()
+        launches, kms = pl.timing_read()
     pl.timing_enable(kc, False)
     ms_step = 1e3 * dt / a.steps
     fps = B * a.steps / dt
     log(f"bench: {ms_step:.2f} ms/step, {fps:.1f} frames/s; {kc}: {launches} launches, {kms:.3f} ms")
 
-    # parity spot check of the timed configuration against a plain single-frame solve
-    img0 = outs[0]["image"].clone()
-
-    # plain path: one frame per solve, eager launches
-    plain = Plan(N, N_OM, J)
-    pprm = Plan.params(NEWTON, CG, use_graph=False)
-    pout = plain.solve(*data[0], pprm)
-    torch.cuda.synchronize()
-    spot = float((pout["image"] - img0).abs().pow(2).sum().sqrt() / img0.abs().pow(2).sum().sqrt())
-    t0 = time.perf_counter()
-    for i in range(a.plain_frames):
-        plain.solve(*data[i % B], pprm)
-    torch.cuda.synchronize()
-    plain_fps = a.plain_frames / (time.perf_counter() - t0)
-
-    # DF^H DF applies, back to back on one frame
-    rng = np.random.default_rng([2, 0, 3])
-    rho = torch.from_numpy(synth.random_complex((N_OM, N_OM), rng)).cuda()
-    chat = torch.from_numpy(synth.random_complex((J, N, N), rng)).cuda()
-    c = plain.coil_maps(chat)
-    h_r = torch.from_numpy(synth.random_complex((N_OM, N_OM), rng)).cuda()
-    h_c = torch.from_numpy(synth.random_complex((J, N, N), rng)).cuda()
-    o_r, o_c = torch.empty_like(h_r), torch.empty_like(h_c)
-    P0 = data[0][1]
-    for _ in range(10):
-        NAT.nlinv_normal(plain.handle, rho, chat, c, P0, 0.5, h_r, h_c, o_r, o_c)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(a.applies):
-        NAT.nlinv_normal(plain.handle, rho, chat, c, P0, 0.5, h_r, h_c, o_r, o_c)
-    torch.cuda.synchronize()
-    ap_s = a.applies / (time.perf_counter() - t0)
-    nb = normal_bytes(N, N_OM, J)
+    extras = {}
+    if a.compare:
+        extras = compare_paths(a, data, outs, B)
 
     # roofline of the dominant kernel class
     per_launch = kernel_bytes(kc, N, N_OM, J * B, B)
@@ -198,7 +237,8 @@ def main():
     achieved = per_launch / (avg_ms * 1e-3) / 1e9 if launches else None
     roof = {"bound": "hbm", "kernel": kc, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBPS) if achieved else None, "traffic": None,
-            "bytes_per_launch": per_launch, "avg_launch_ms": avg_ms, "launches_timed": launches}
+            "bytes_per_launch": per_launch, "avg_launch_ms": avg_ms, "launches_timed": launches,
+            "event_timing_on": timing_path}
 
     cpu = cpu_baseline(a.cpu_newton) if a.cpu_newton > 0 else None
     out = {
@@ -209,10 +249,7 @@ def main():
         "config": {"workload": "realtime_384: 384x384 grid, Omega 192x192, 12 coils, 15 radial spokes, "
                                "7 Newton x 10 CG",
                    "frames_per_step": B, "path": "batched" + ("" if a.no_graph else "+hipGraph")},
-        "plain_frames_per_s": plain_fps,
-        "normal_applies_per_s": ap_s,
-        "normal_algorithmic_GBps": nb * ap_s / 1e9,
-        "batched_vs_plain_image_rel": spot,
+        **extras,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

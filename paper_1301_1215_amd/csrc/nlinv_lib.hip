@@ -164,6 +164,7 @@ struct nlinv_plan_s {
     std::vector<unsigned char> ev_used;
     int ev_next = 0;
     bool capturing = false;
+    bool timing_failed = false;
 };
 
 namespace {
@@ -207,6 +208,32 @@ int nseg(const SegGeom& g) { return g.nplanes * g.cseg + g.nframes * g.rseg; }
 
 // ---- timing brackets --------------------------------------------------------
 
+// Under stream capture an event record is added as an explicit event-record
+// node after the stream's current capture dependencies, and becomes the new
+// dependency set, so that it lands between the kernels it brackets.  A
+// failure is cleared from HIP's last-error state (it must not fail the
+// solve) and reported by nlinv_plan_timing_read.
+hipError_t record_event(nlinv_plan_s* p, hipEvent_t e, hipStream_t s) {
+    if (!p->capturing) return hipEventRecord(e, s);
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    hipGraph_t g = nullptr;
+    const hipGraphNode_t* deps = nullptr;
+    size_t nd = 0;
+    hipError_t r = hipStreamGetCaptureInfo_v2(s, &st, nullptr, &g, &deps, &nd);
+    if (r == hipSuccess && (st != hipStreamCaptureStatusActive || !g)) r = hipErrorIllegalState;
+    if (r == hipSuccess) {
+        std::vector<hipGraphNode_t> d(deps, deps + nd);
+        hipGraphNode_t node = nullptr;
+        r = hipGraphAddEventRecordNode(&node, g, d.empty() ? nullptr : d.data(), d.size(), e);
+        if (r == hipSuccess) r = hipStreamUpdateCaptureDependencies(s, &node, 1, hipStreamSetCaptureDependencies);
+    }
+    if (r != hipSuccess) {
+        (void)hipGetLastError();
+        p->timing_failed = true;
+    }
+    return r;
+}
+
 // Slots: ev_used 0 = free, 1 = recorded by an eager launch (read once),
 // 2 = owned by the captured graph (re-recorded by every replay).
 int tbegin(nlinv_plan_s* p, int kc, hipStream_t s) {
@@ -215,14 +242,14 @@ int tbegin(nlinv_plan_s* p, int kc, hipStream_t s) {
         const int slot = p->ev_next;
         p->ev_next = (p->ev_next + 1) % kTimingSlots;
         if (p->ev_used[slot] == 2) continue;
-        if (hipEventRecord(p->ev[2 * slot], s) != hipSuccess) return -1;
+        if (record_event(p, p->ev[2 * slot], s) != hipSuccess) return -1;
         return slot;
     }
     return -1;
 }
 void tend(nlinv_plan_s* p, int slot, hipStream_t s) {
     if (slot < 0) return;
-    if (hipEventRecord(p->ev[2 * slot + 1], s) == hipSuccess) p->ev_used[slot] = p->capturing ? 2 : 1;
+    if (record_event(p, p->ev[2 * slot + 1], s) == hipSuccess) p->ev_used[slot] = p->capturing ? 2 : 1;
 }
 int drop_graph(nlinv_plan_s* p) {
     if (!p->gexec) return NLINV_OK;
@@ -1183,6 +1210,10 @@ int nlinv_plan_timing_enable(nlinv_plan p, int32_t kclass, int32_t enable) {
 
 int nlinv_plan_timing_read(nlinv_plan p, int32_t* launches, double* total_ms) {
     if (!p || !launches || !total_ms) return NLINV_EINVAL;
+    if (p->timing_failed) {
+        p->timing_failed = false;
+        return NLINV_EHIP;
+    }
     int cnt = 0;
     double tot = 0.0;
     for (int k = 0; k < (int)p->ev_used.size(); ++k) {

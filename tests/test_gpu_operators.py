@@ -138,3 +138,78 @@ def test_kernel_timing_counts_launches():
         cnt, ms = pl.timing_read()
         assert cnt == 3 and ms > 0
         assert pl.timing_read()[0] == 0
+
+
+# 1D transforms done by one launch of each pass class (per plane)
+TRANSFORMS_1D = {"col_winv_ifft": 1, "col_p_ifft": 1, "col_fft_p": 1, "col_fft_p_resid": 1, "col_psf": 2,
+                 "col_fft_winv_add": 1, "col_fft_gprod": 1, "row_cache": 1, "row_fwd": 1, "row_deriv": 2,
+                 "row_adj": 2}
+
+
+def _launch_counts(pl, fn):
+    from paper_1301_1215_amd import _native as NAT
+    import torch
+    counts = {}
+    for k in NAT.nlinv_kernel_class_names():
+        pl.timing_enable(k, True)
+        fn()
+        torch.cuda.synchronize()
+        cnt, _ = pl.timing_read()
+        pl.timing_enable(k, False)
+        if cnt:
+            counts[k] = cnt
+    return counts
+
+
+def test_transform_counts_match_table1():
+    """Table 1: F, DF and DF^H each take two 2D transforms (F including the
+    W^{-1} of the sensitivities; DF and DF^H with them cached), and DF^H one
+    channel summation."""
+    from tests.test_oracle_pins import _table1
+    t1 = _table1()
+    n, n_om, J = 64, 32, 3
+    rng, rho, chat, P = _point(n, n_om, J, 5)
+    with Plan(n, n_om, J) as pl:
+        r, c_, Pd, z = dev(rho), dev(chat), dev(P), dev(rand_c((J, n, n), rng))
+        c = pl.coil_maps(c_)
+        ops = {"F": lambda: pl.forward(r, c_, Pd),
+               "DF": lambda: pl.deriv(r, c_, Pd, r, c_, c=c),
+               "DFH": lambda: pl.adjoint(r, c_, Pd, z, c=c)}
+        for name, fn in ops.items():
+            counts = _launch_counts(pl, fn)
+            n1d = sum(TRANSFORMS_1D.get(k, 0) * v for k, v in counts.items())
+            assert n1d == 2 * t1[name]["fft"], (name, counts)
+            assert counts.get("coil_sum", 0) == t1[name]["sum_c"], (name, counts)
+
+
+def test_autotune_picks_valid_variants_and_keeps_parity(tmp_path, monkeypatch):
+    monkeypatch.setenv("NLINV_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    n, n_om, J = 192, 96, 6
+    rng, rho, chat, P = _point(n, n_om, J, 6)
+    drho, dchat = rand_c((n_om, n_om), rng), rand_c((J, n, n), rng)
+    d = O.Dims(n, n_om, J)
+    ref = O.normal(rho, chat, P, 0.5, drho, dchat, d)
+    with Plan(n, n_om, J) as pl:
+        pl.autotune()
+        cv, rv = pl.variant(n)
+        assert cv >= 0 and rv >= 0
+        nr, nc = map(host, pl.normal(dev(rho), dev(chat), dev(P), 0.5, dev(drho), dev(dchat)))
+        assert rel(nr, ref[0]) < TOL and rel(nc, ref[1]) < TOL
+    assert (tmp_path / "tune.txt").read_text().split()[1:5] == ["192", str(J), str(cv), str(rv)]
+    with Plan(n, n_om, J) as pl2:    # served from the cache file
+        pl2.autotune()
+        assert pl2.variant(n) == (cv, rv)
+
+
+def test_kernel_timing_inside_a_replayed_graph():
+    from paper_1301_1215_amd import synth
+    fr = synth.make_frame(2, 9, 64, 32, 3, "radial", spokes=9)
+    with Plan(64, 32, 3) as pl:
+        pl.timing_enable("col_psf")
+        prm = Plan.params(2, 4, use_graph=True)
+        for _ in range(3):
+            pl.solve(dev(fr.y), dev(fr.P), prm)
+        cnt, ms = pl.timing_read()
+        assert cnt == 2 * 4 and ms > 0     # one replay's launches
+        cnt2, _ = pl.timing_read()         # graph-owned brackets stay readable
+        assert cnt2 == cnt
