@@ -35,13 +35,16 @@ def log(*a):
 # of `frames` frames (n x n grid, m x m Omega); complex64 = 8 B, P float32 = 4 B
 def kernel_bytes(kc: str, n: int, m: int, planes: int, frames: int) -> float:
     c, mn, mm, nn = 8.0, float(m * n), float(m * m), float(n * n)
+    # the 1/w table (4 n^2 B per class) is shared by all planes and L2-resident: not counted
     per = {
-        "col_winv_ifft": planes * c * (nn + mn),
+        "col_winv_ifft": planes * c * (nn + mn),                               # read chat, write T
+        "col_pupd_winv_ifft": planes * c * (3 * nn + mn) + frames * 3 * c * mm,  # read r, p; write p, T
         "col_p_ifft": planes * c * (nn + mn) + frames * 4 * nn,
         "col_fft_p": planes * c * (mn + nn) + frames * 4 * nn,
         "col_fft_p_resid": planes * c * (mn + 2 * nn) + frames * 4 * nn,
         "col_psf": planes * c * (2 * mn) + frames * 4 * nn,
-        "col_fft_winv_add": planes * c * (mn + 2 * nn),
+        "col_fft_winv_add": planes * c * (mn + 3 * nn),                        # read T, x, x_ref; write
+        "col_fft_winv_axpy_dot": planes * c * (mn + 2 * nn),                   # read T, p; write q
         "row_cache": planes * c * (mn + mm),
         "row_fwd": planes * c * (mm + mn) + frames * c * mm,
         "row_deriv": planes * c * (2 * mn + mm) + frames * 2 * c * mm,
@@ -49,7 +52,6 @@ def kernel_bytes(kc: str, n: int, m: int, planes: int, frames: int) -> float:
         "coil_sum": planes * c * mm + frames * 2 * c * mm,
         "vec_dot": (planes * nn + frames * mm) * 2 * c,
         "vec_xr_update": (planes * nn + frames * mm) * 6 * c,
-        "vec_p_update": (planes * nn + frames * mm) * 3 * c,
     }
     return per.get(kc, float("nan"))
 
@@ -76,6 +78,23 @@ def cpu_baseline(newton_sample: int):
     return {"value": 1.0 / per_frame, "unit": "frames/s", "cores": cores, "kind": "oracle",
             "sample": f"{newton_sample} of {NEWTON} Newton steps (x{CG} CG) of one 384x384, 12-coil frame, "
                       f"FP64 numpy/scipy.fft with {cores} FFT workers; {dt:.1f} s measured, scaled to a frame"}
+
+
+def stream_probe(nbytes=1 << 30, reps=20):
+    """Read + write GB/s of a device-to-device copy of `nbytes`."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
 def dominant_class(pl, data, prm, outs, names):
@@ -150,8 +169,10 @@ def main():
     ap.add_argument("--applies", type=int, default=200)
     ap.add_argument("--cpu-newton", type=int, default=2, help="Newton steps of the CPU oracle sample (0: skip)")
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default pass variants")
     ap.add_argument("--kernel-class", default=None, help="kernel class for the roofline (default: dominant)")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="also measure a 1 GiB device-to-device copy (the practical HBM ceiling)")
     a = ap.parse_args()
 
     if a.gpus != 1:
@@ -174,8 +195,10 @@ def main():
     data = [(torch.from_numpy(f.y).cuda(), torch.from_numpy(f.P).cuda()) for f in frames]
     prm = Plan.params(NEWTON, CG, use_graph=not a.no_graph)
     pl = Plan(frames=[(N, N_OM, J)] * B)
-    if a.autotune:
+    if not a.no_autotune:
+        os.environ.setdefault("NLINV_TUNE_VERBOSE", "1")
         pl.autotune()
+        log(f"bench: autotuned pass variants for n={N}: (column, row) = {pl.variant(N)}")
     outs = [pl._frame_out(pl.frames[i], prm) for i in range(B)]
     stream = torch.cuda.current_stream()
 
@@ -240,6 +263,8 @@ def main():
             "bytes_per_launch": per_launch, "avg_launch_ms": avg_ms, "launches_timed": launches,
             "event_timing_on": timing_path}
 
+    if a.stream_probe:
+        extras["stream_copy_GBps"] = stream_probe()
     cpu = cpu_baseline(a.cpu_newton) if a.cpu_newton > 0 else None
     out = {
         "metric": "IRGNM frames/sec and DF^H.DF applies/sec (HBM GB/s) at <=1e-3 NRMSE vs FP64",

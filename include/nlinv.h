@@ -25,8 +25,9 @@
  *     next synchronisation.  Compute calls never allocate device memory.
  *   - Return value: NLINV_OK (0) or a negative status.  NLINV_EINVAL for a
  *     NULL / misaligned pointer or bad argument, NLINV_EUNSUPPORTED for a
- *     grid size that is not 2^p 3^q in [8, 1024] or Omega sides that are odd
- *     or larger than n, NLINV_ENOMEM when plan creation cannot allocate,
+ *     grid size outside {8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384,
+ *     512, 768, 1024} (2^p and 3 * 2^p), Omega sides that are odd or larger
+ *     than n, or more than 64 coils, NLINV_ENOMEM when plan creation cannot allocate,
  *     NLINV_EHIP for a HIP error (its code: nlinv_last_hip_error()).
  *     No C++ exception crosses this interface.
  *   - Outputs must not alias inputs except where a name ends in _inout.
@@ -48,7 +49,7 @@ typedef struct nlinv_plan_s* nlinv_plan;
 /* Geometry of one frame.  sobolev_a = 220 and sobolev_l = 32 give the
  * weight (1 + 220 |k|^2)^16 on the coil sensitivities. */
 typedef struct {
-    int32_t n;          /* grid side (square grid), 2^p 3^q, 8 <= n <= 1024 */
+    int32_t n;          /* grid side (square grid): 2^p or 3 * 2^p, 8 <= n <= 1024 */
     int32_t n_om;       /* side of the centred image region Omega, even, <= n */
     int32_t ncoils;     /* J, 1..64 */
     float sobolev_a;
@@ -175,18 +176,21 @@ int nlinv_irgnm_solve_series(nlinv_plan plan, int32_t count, const nlinv_frame* 
                              const nlinv_irgnm_params* prm, void* stream);
 
 /* ---- autotuning -----------------------------------------------------------
- * Time the FFT pass variants (lines per workgroup, whole-plane-in-LDS
- * kernels where the plane fits) for every grid size of the plan on `stream`
- * (which must not be capturing) and keep the fastest.  Results are cached
- * per (device architecture, n, planes) in the text file named by
- * NLINV_TUNE_CACHE, if set.  Without this call a fixed default is used. */
+ * Time the FFT pass variants (lines per workgroup) of every pass mode for
+ * every shape class of the plan on `stream` (which must not be capturing),
+ * and keep the fastest per mode.  It overwrites the plan's workspace, so call
+ * it between solves.  Results are cached per (device architecture, n, planes)
+ * in the text file named by NLINV_TUNE_CACHE, if set; NLINV_TUNE_VERBOSE
+ * prints the timings to stderr.  Without this call a fixed default is used. */
 int nlinv_plan_autotune(nlinv_plan plan, void* stream);
 
-/* Choice made for grid size n (-1 if n is not in the plan): the variant index
- * used by column passes / row passes. */
+/* Choice made for grid size n (NLINV_EINVAL if n is not in the plan): the
+ * variant index of the PSF column pass and of the derivative row pass of the
+ * CG loop. */
 int nlinv_plan_variant(nlinv_plan plan, int32_t n, int32_t* col_variant, int32_t* row_variant);
 
-/* Force a variant (for tests): returns NLINV_EINVAL for an unknown index. */
+/* Force one variant on every column / row pass of grid size n (for tests):
+ * returns NLINV_EINVAL for an index that is not valid for n. */
 int nlinv_plan_set_variant(nlinv_plan plan, int32_t n, int32_t col_variant, int32_t row_variant);
 
 /* ---- kernel timing --------------------------------------------------------

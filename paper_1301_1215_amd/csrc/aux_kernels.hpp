@@ -13,6 +13,8 @@ namespace nlinv {
 // ---------------------------------------------------------------------------
 
 // out[f][e] = sum_{p in f} aux[p][e] + s1_f add1[f][e] + s2_f add2[f][e]
+// One workgroup per (frame, segment of `seg_len` elements); with `partial`
+// set it also writes Re<add1, out> of its segment to partial[poff + f*segs + k].
 struct CoilSumArgs {
     const float2* aux;       // [planes][E]
     float2* out;             // [frames][E]
@@ -26,22 +28,35 @@ struct CoilSumArgs {
     int nplanes;
     int nframes;
     int E;                   // elements per frame (m*m)
+    int segs, seg_len;
+    double* partial;
+    long long poff;
 };
 
 __global__ __launch_bounds__(kThreads) void k_coil_sum(CoilSumArgs a) {
-    const long long tot = (long long)a.nframes * a.E;
-    for (long long g = (long long)blockIdx.x * kThreads + threadIdx.x; g < tot;
-         g += (long long)gridDim.x * kThreads) {
-        const int f = (int)(g / a.E), e = (int)(g % a.E);
-        const int p0 = a.frame_plane0 ? a.frame_plane0[f] : 0;
-        const int np = a.frame_planes ? a.frame_planes[f] : a.nplanes;
+    __shared__ double red[4];
+    const int f = blockIdx.x / a.segs, k = blockIdx.x % a.segs;
+    const int e0 = k * a.seg_len, e1 = min(a.E, e0 + a.seg_len);
+    const int p0 = a.frame_plane0 ? a.frame_plane0[f] : 0;
+    const int np = a.frame_planes ? a.frame_planes[f] : a.nplanes;
+    const float s1 = a.s1 ? a.s1[f] : a.c1;
+    const float s2 = a.s2 ? a.s2[f] : a.c2;
+    double acc = 0.0;
+    for (int e = e0 + threadIdx.x; e < e1; e += kThreads) {
+        const long long g = (long long)f * a.E + e;
         float2 s = make_float2(0.f, 0.f);
         for (int p = 0; p < np; ++p) s = cadd(s, a.aux[(long long)(p0 + p) * a.E + e]);
-        const float s1 = a.s1 ? a.s1[f] : a.c1;
-        const float s2 = a.s2 ? a.s2[f] : a.c2;
         if (a.add1) { const float2 u = a.add1[g]; s.x += s1 * u.x; s.y += s1 * u.y; }
         if (a.add2) { const float2 u = a.add2[g]; s.x += s2 * u.x; s.y += s2 * u.y; }
         a.out[g] = s;
+        if (a.partial && a.add1) { const float2 u = a.add1[g]; acc += (double)(u.x * s.x + u.y * s.y); }
+    }
+    if (a.partial) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) a.partial[a.poff + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
     }
 }
 
@@ -130,9 +145,7 @@ struct VecPtrs {
 enum VecOp : int {
     VEC_DOT = 0,        // partial = Re<v0, v1>
     VEC_XR_UPDATE = 1,  // v0 += a v1 (x += a p);  v2 -= a v3 (r -= a q);  partial = |v2|^2
-    VEC_P_UPDATE = 2,   // v0 = v1 + beta v0        (p = r + beta p)
-    VEC_COPY = 3,       // v0 = v1
-    VEC_ADD = 4,        // v0 += v1
+    VEC_ADD = 2,        // v0 += v1
 };
 
 template <int OP>
@@ -152,7 +165,7 @@ __global__ __launch_bounds__(kThreads) void k_vec(SegGeom g, VecPtrs v, const fl
     const int n4 = len / 2;
     double acc = 0.0;
     const float av = a_f ? a_f[f] : 0.f;
-    const float bv = b_f ? b_f[f] : 0.f;
+    (void)b_f;
     for (int i = threadIdx.x; i < n4; i += kThreads) {
         if constexpr (OP == VEC_DOT) {
             const float4 p = y0[i], q = y1[i];
@@ -167,13 +180,6 @@ __global__ __launch_bounds__(kThreads) void k_vec(SegGeom g, VecPtrs v, const fl
             y0[i] = x;
             y2[i] = r;
             acc += (double)r.x * r.x + (double)r.y * r.y + (double)r.z * r.z + (double)r.w * r.w;
-        } else if constexpr (OP == VEC_P_UPDATE) {
-            float4 p = y0[i];
-            const float4 r = y1[i];
-            p.x = r.x + bv * p.x; p.y = r.y + bv * p.y; p.z = r.z + bv * p.z; p.w = r.w + bv * p.w;
-            y0[i] = p;
-        } else if constexpr (OP == VEC_COPY) {
-            y0[i] = y1[i];
         } else if constexpr (OP == VEC_ADD) {
             float4 p = y0[i];
             const float4 r = y1[i];
@@ -222,12 +228,13 @@ enum ScalarOp : int {
     SC_R0NORM = 1,     // stats[2 + step] = ||r0||
     SC_RR0 = 2,        // rr = <b, b>; new Newton step: clear breakdown
     SC_GAMMA = 3,      // gamma = Re<p, q>; a = rr / gamma or breakdown
-    SC_RR = 4,         // rr' = <r, r>; beta = rr'/rr; rr = rr'; stats
+    SC_RR = 4,         // rr' = <r, r>; beta = rr'/rr; rr = rr'; stats of CG iteration `it`
 };
 
 __global__ __launch_bounds__(kThreads) void k_scalar(int op, SegGeom g, const double* partial,
                                                      const int* frame_plane0, const int* frame_planes,
-                                                     Scalars sc, float scale_norm, int step) {
+                                                     Scalars sc, float scale_norm, int step, int it,
+                                                     int nsteps, int ncg) {
     __shared__ double red[4];
     const int f = blockIdx.x;
     const double t = frame_total(g, partial, f, frame_plane0, frame_planes, red);
@@ -263,20 +270,14 @@ __global__ __launch_bounds__(kThreads) void k_scalar(int op, SegGeom g, const do
     } else if (op == SC_RR) {
         if (sc.brk[f]) {
             sc.beta[f] = 0.f;
+            st[2 + nsteps + step * ncg + it] = -1.0;
         } else {
             if (!isfinite(t)) st[1] = (double)((int)st[1] | 2);
             sc.beta[f] = (float)(t / sc.rr[f]);
             sc.rr[f] = t;
+            st[2 + nsteps + step * ncg + it] = t;
         }
     }
-}
-
-// stats of CG iteration `it` of Newton step `step`: <r,r> or -1 after a breakdown
-__global__ void k_cg_stat(Scalars sc, int nframes, int nsteps, int ncg, int step, int it) {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nframes) return;
-    double* st = sc.stats + (long long)f * sc.stats_len;
-    st[2 + nsteps + step * ncg + it] = sc.brk[f] ? -1.0 : sc.rr[f];
 }
 
 // per-frame: alpha[f] = value, alpha[F + f] = -value
@@ -296,6 +297,22 @@ __global__ __launch_bounds__(kThreads) void k_scale_rho(float2* x, const float2*
         const float2 v = src ? src[g] : make_float2(1.f, 0.f);
         x[g] = cscale(v, sf);
         (void)use_inv;
+    }
+}
+
+// Convert planes between row-major [planes][n][n] and the column-tiled
+// layout [planes][n/tw][n][tw] used inside a solve (to_tiled = 0: back).
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_tile(const T* src, T* dst, int nplanes, int n, int tw,
+                                                  int to_tiled) {
+    const long long nn = (long long)n * n, tot = nplanes * nn;
+    for (long long g = (long long)blockIdx.x * kThreads + threadIdx.x; g < tot;
+         g += (long long)gridDim.x * kThreads) {
+        const long long pl = g / nn, e = g % nn;
+        const int r = (int)(e / n), c = (int)(e % n);
+        const long long t = pl * nn + ((long long)(c / tw) * n + r) * tw + (c % tw);
+        if (to_tiled) dst[t] = src[g];
+        else dst[g] = src[t];
     }
 }
 

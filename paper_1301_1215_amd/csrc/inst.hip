@@ -9,7 +9,9 @@ namespace nlinv {
 
 template <int N, int L>
 static hipError_t col_L(int mode, const ColArgs& a, int nplanes, hipStream_t s) {
-    const dim3 grid(N / L, nplanes), block(kThreads);
+    // 1D grid, a multiple of 8 blocks: the kernel deals work items to XCDs
+    const int total = (N / L) * nplanes;
+    const dim3 grid(8 * ((total + 7) / 8)), block(kThreads);
     switch (mode) {
         case COL_WINV_IFFT_CROP: hipLaunchKernelGGL((k_col<N, L, COL_WINV_IFFT_CROP>), grid, block, 0, s, a); break;
         case COL_P_IFFT_CROP: hipLaunchKernelGGL((k_col<N, L, COL_P_IFFT_CROP>), grid, block, 0, s, a); break;
@@ -18,6 +20,8 @@ static hipError_t col_L(int mode, const ColArgs& a, int nplanes, hipStream_t s) 
         case COL_PAD_FFT_P2_IFFT: hipLaunchKernelGGL((k_col<N, L, COL_PAD_FFT_P2_IFFT>), grid, block, 0, s, a); break;
         case COL_PAD_FFT_WINV_ADD: hipLaunchKernelGGL((k_col<N, L, COL_PAD_FFT_WINV_ADD>), grid, block, 0, s, a); break;
         case COL_PAD_FFT_GPROD: hipLaunchKernelGGL((k_col<N, L, COL_PAD_FFT_GPROD>), grid, block, 0, s, a); break;
+        case COL_PUPD_WINV_IFFT_CROP: hipLaunchKernelGGL((k_col<N, L, COL_PUPD_WINV_IFFT_CROP>), grid, block, 0, s, a); break;
+        case COL_PAD_FFT_WINV_AXPY_DOT: hipLaunchKernelGGL((k_col<N, L, COL_PAD_FFT_WINV_AXPY_DOT>), grid, block, 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -42,6 +46,7 @@ hipError_t launch_col(int mode, int variant, const ColArgs& a, int nplanes, hipS
     if constexpr (col_variant_ok(N, 0)) { if (variant == 0) return col_L<N, kColL[0]>(mode, a, nplanes, s); }
     if constexpr (col_variant_ok(N, 1)) { if (variant == 1) return col_L<N, kColL[1]>(mode, a, nplanes, s); }
     if constexpr (col_variant_ok(N, 2)) { if (variant == 2) return col_L<N, kColL[2]>(mode, a, nplanes, s); }
+    if constexpr (col_variant_ok(N, 3)) { if (variant == 3) return col_L<N, kColL[3]>(mode, a, nplanes, s); }
     return hipErrorInvalidValue;
 }
 

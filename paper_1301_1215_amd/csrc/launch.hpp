@@ -13,13 +13,13 @@ namespace nlinv {
     X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
 
 // Pass variants = lines (columns or rows) per 256-thread workgroup.
-constexpr int kColL[] = {8, 16, 4};
-constexpr int kRowL[] = {4, 8, 2, 1};
-constexpr int kNumColVariants = 3;
+constexpr int kColL[] = {16, 8, 32, 4};
+constexpr int kRowL[] = {8, 16, 4, 2};
+constexpr int kNumColVariants = 4;
 constexpr int kNumRowVariants = 4;
 
 constexpr bool col_variant_ok(int n, int v) {
-    return v >= 0 && v < kNumColVariants && n % kColL[v] == 0 && n * kColL[v] <= 16384;
+    return v >= 0 && v < kNumColVariants && n % kColL[v] == 0 && n * kColL[v] <= 8192;
 }
 constexpr bool row_variant_ok(int n, int v) {
     return v >= 0 && v < kNumRowVariants && n * kRowL[v] <= 8192;

@@ -45,6 +45,9 @@ constexpr int kMaxNewton = 32;
 constexpr int kMaxCG = 256;
 constexpr int kStatsCap = 2 + kMaxNewton + kMaxNewton * kMaxCG;
 constexpr int kSegLen = 4096;        // complex elements per reduction segment
+constexpr int kCoilSeg = 512;        // Omega pixels per coil-sum workgroup
+constexpr int kColModes = 9;         // ColMode values
+constexpr int kRowModes = 4;         // RowMode values
 constexpr int kTimingSlots = 8192;   // event pairs for kernel timing
 
 bool size_supported(int n) {
@@ -81,13 +84,15 @@ bool row_ok(int n, int v) { return row_variant_ok(n, v); }
 // kernel classes for timing
 enum KClass : int {
     KC_COL_WINV_IFFT = 0, KC_COL_P_IFFT, KC_COL_FFT_P, KC_COL_FFT_P_RESID, KC_COL_PSF,
-    KC_COL_FFT_WINV_ADD, KC_COL_FFT_GPROD, KC_ROW_CACHE, KC_ROW_FWD, KC_ROW_DERIV, KC_ROW_ADJ,
-    KC_COIL_SUM, KC_VEC_DOT, KC_VEC_XR, KC_VEC_P, KC_VEC_OTHER, KC_SCALAR, KC_IMAGE, KC_NUM
+    KC_COL_FFT_WINV_ADD, KC_COL_FFT_GPROD, KC_COL_PUPD_WINV_IFFT, KC_COL_FFT_WINV_AXPY_DOT,
+    KC_ROW_CACHE, KC_ROW_FWD, KC_ROW_DERIV, KC_ROW_ADJ,
+    KC_COIL_SUM, KC_VEC_DOT, KC_VEC_XR, KC_VEC_OTHER, KC_SCALAR, KC_IMAGE, KC_NUM
 };
 const char* kKClassNames[KC_NUM] = {
     "col_winv_ifft", "col_p_ifft", "col_fft_p", "col_fft_p_resid", "col_psf",
-    "col_fft_winv_add", "col_fft_gprod", "row_cache", "row_fwd", "row_deriv", "row_adj",
-    "coil_sum", "vec_dot", "vec_xr_update", "vec_p_update", "vec_other", "scalar", "image"};
+    "col_fft_winv_add", "col_fft_gprod", "col_pupd_winv_ifft", "col_fft_winv_axpy_dot",
+    "row_cache", "row_fwd", "row_deriv", "row_adj",
+    "coil_sum", "vec_dot", "vec_xr_update", "vec_other", "scalar", "image"};
 
 int col_kclass(int mode) {
     switch (mode) {
@@ -97,6 +102,8 @@ int col_kclass(int mode) {
         case COL_PAD_FFT_P_RESID: return KC_COL_FFT_P_RESID;
         case COL_PAD_FFT_P2_IFFT: return KC_COL_PSF;
         case COL_PAD_FFT_WINV_ADD: return KC_COL_FFT_WINV_ADD;
+        case COL_PUPD_WINV_IFFT_CROP: return KC_COL_PUPD_WINV_IFFT;
+        case COL_PAD_FFT_WINV_AXPY_DOT: return KC_COL_FFT_WINV_AXPY_DOT;
         default: return KC_COL_FFT_GPROD;
     }
 }
@@ -117,12 +124,16 @@ struct Class {
     int nframes = 0, nplanes = 0;
     std::vector<int> frames;     // plan frame index of each class frame
     std::vector<int> J, plane0;
-    int colv = 0, rowv = 0;
+    int colv[kColModes] = {};    // pass variant per column mode
+    int rowv[kRowModes] = {};    // and per row mode
 
     int* plane_frame = nullptr;
     int* frame_plane0 = nullptr;
     int* frame_planes = nullptr;
     float2* tw = nullptr;
+    float* winv = nullptr;       // [n][n] 1/w, row-major
+    float* winv_t = nullptr;     // the same, column-tiled (solve layout)
+    int tilew = 16;              // tile width of the solve layout
     float2 *x_c = nullptr, *x_r = nullptr, *dx_c = nullptr, *dx_r = nullptr;
     float2 *r_c = nullptr, *r_r = nullptr, *p_c = nullptr, *p_r = nullptr;
     float2 *q_c = nullptr, *q_r = nullptr, *xr_c = nullptr, *xr_r = nullptr;
@@ -263,14 +274,15 @@ int drop_graph(nlinv_plan_s* p) {
 
 // ---- launch helpers -----------------------------------------------------------
 
-ColArgs col_args(const nlinv_plan_s* p, const Class& C) {
+ColArgs col_args(const nlinv_plan_s* p, const Class& C, int tiled) {
     ColArgs a{};
+    a.tiled = tiled;
     a.m = C.m;
     a.lo = C.lo;
-    a.sob_a = p->sob_a;
-    a.sob_hl = p->sob_hl;
     a.rs = (float)(1.0 / std::sqrt((double)C.n));
-    a.tw = C.tw;
+    a.tw2 = C.tw;
+    a.winv = tiled ? C.winv_t : C.winv;
+    (void)p;
     return a;
 }
 
@@ -279,13 +291,15 @@ RowArgs row_args(const Class& C) {
     a.m = C.m;
     a.lo = C.lo;
     a.rs = (float)(1.0 / std::sqrt((double)C.n));
-    a.tw = C.tw;
+    a.tw2 = C.tw;
     return a;
 }
 
-int run_col(nlinv_plan_s* p, const Class& C, int mode, const ColArgs& a, int nplanes, hipStream_t s) {
+int run_col(nlinv_plan_s* p, const Class& C, int mode, const ColArgs& a0, int nplanes, hipStream_t s) {
+    ColArgs a = a0;
+    a.nplanes = nplanes;
     const int slot = tbegin(p, col_kclass(mode), s);
-    hipError_t e = col_dispatch(C.n, mode, C.colv, a, nplanes, s);
+    hipError_t e = col_dispatch(C.n, mode, C.colv[mode], a, nplanes, s);
     tend(p, slot, s);
     HIPCHK(e);
     return NLINV_OK;
@@ -293,7 +307,7 @@ int run_col(nlinv_plan_s* p, const Class& C, int mode, const ColArgs& a, int npl
 
 int run_row(nlinv_plan_s* p, const Class& C, int mode, const RowArgs& a, hipStream_t s) {
     const int slot = tbegin(p, row_kclass(mode), s);
-    hipError_t e = row_dispatch(C.n, mode, C.rowv, a, s);
+    hipError_t e = row_dispatch(C.n, mode, C.rowv[mode], a, s);
     tend(p, slot, s);
     HIPCHK(e);
     return NLINV_OK;
@@ -308,7 +322,7 @@ int grid_for(long long n, int per = kThreads) {
 
 int run_coil_sum(nlinv_plan_s* p, const CoilSumArgs& a, hipStream_t s) {
     const int slot = tbegin(p, KC_COIL_SUM, s);
-    hipLaunchKernelGGL(k_coil_sum, dim3(grid_for((long long)a.nframes * a.E)), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(k_coil_sum, dim3(a.nframes * a.segs), dim3(kThreads), 0, s, a);
     hipError_t e = hipGetLastError();
     tend(p, slot, s);
     HIPCHK(e);
@@ -318,8 +332,7 @@ int run_coil_sum(nlinv_plan_s* p, const CoilSumArgs& a, hipStream_t s) {
 template <int OP>
 int run_vec(nlinv_plan_s* p, const SegGeom& g, const VecPtrs& v, const float* a_f, const float* b_f,
             double* partial, hipStream_t s) {
-    const int kc = OP == VEC_DOT ? KC_VEC_DOT : OP == VEC_XR_UPDATE ? KC_VEC_XR
-                 : OP == VEC_P_UPDATE ? KC_VEC_P : KC_VEC_OTHER;
+    const int kc = OP == VEC_DOT ? KC_VEC_DOT : OP == VEC_XR_UPDATE ? KC_VEC_XR : KC_VEC_OTHER;
     const int slot = tbegin(p, kc, s);
     hipLaunchKernelGGL((k_vec<OP>), dim3(nseg(g)), dim3(kThreads), 0, s, g, v, a_f, b_f, partial);
     hipError_t e = hipGetLastError();
@@ -329,10 +342,10 @@ int run_vec(nlinv_plan_s* p, const SegGeom& g, const VecPtrs& v, const float* a_
 }
 
 int run_scalar(nlinv_plan_s* p, Class& C, int op, const SegGeom& g, float scale_norm, int step,
-               hipStream_t s) {
+               hipStream_t s, int it = 0, int nsteps = 0, int ncg = 0) {
     const int slot = tbegin(p, KC_SCALAR, s);
     hipLaunchKernelGGL(k_scalar, dim3(C.nframes), dim3(kThreads), 0, s, op, g, C.partial,
-                       C.frame_plane0, C.frame_planes, C.sc, scale_norm, step);
+                       C.frame_plane0, C.frame_planes, C.sc, scale_norm, step, it, nsteps, ncg);
     hipError_t e = hipGetLastError();
     tend(p, slot, s);
     HIPCHK(e);
@@ -348,17 +361,51 @@ VecPtrs vptrs(float2* c0, float2* r0, float2* c1 = nullptr, float2* r1 = nullptr
 
 // ---- operator sequences (shared by the single-frame calls and the solve) --
 
+
+
 struct Frames {               // which planes / frames a sequence acts on
     int nplanes, nframes;
     const int* plane_frame;   // nullable
     const int* frame_plane0;  // nullable
     const int* frame_planes;  // nullable
+    int tiled;                // n x n planes in the column-tiled solve layout
 };
+
+Frames single_frame(int J) { return Frames{J, 1, nullptr, nullptr, nullptr, 0}; }
+Frames class_frames(const Class& C) {
+    return Frames{C.nplanes, C.nframes, C.plane_frame, C.frame_plane0, C.frame_planes, 1};
+}
+
+
+// one workgroup per (frame, segment of up to kCoilSeg Omega pixels)
+CoilSumArgs coil_sum_args(const Class& C, const Frames& fr, float2* out, const float2* add1,
+                          const float2* add2, const float* s1, const float* s2, float c1, float c2,
+                          double* partial, long long poff) {
+    CoilSumArgs cs{};
+    cs.aux = C.aux;
+    cs.out = out;
+    cs.add1 = add1;
+    cs.add2 = add2;
+    cs.s1 = s1;
+    cs.s2 = s2;
+    cs.c1 = c1;
+    cs.c2 = c2;
+    cs.frame_plane0 = fr.frame_plane0;
+    cs.frame_planes = fr.frame_planes;
+    cs.nplanes = fr.nplanes;
+    cs.nframes = fr.nframes;
+    cs.E = C.m * C.m;
+    cs.segs = (cs.E + kCoilSeg - 1) / kCoilSeg;
+    cs.seg_len = (cs.E + cs.segs - 1) / cs.segs;
+    cs.partial = partial;
+    cs.poff = poff;
+    return cs;
+}
 
 // c = E^H W^{-1} chat
 int seq_coil_maps(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2* chat, float2* c_out,
                   hipStream_t s) {
-    ColArgs a = col_args(p, C);
+    ColArgs a = col_args(p, C, fr.tiled);
     a.in = chat;
     a.out = C.T;
     a.plane_frame = fr.plane_frame;
@@ -382,7 +429,7 @@ int seq_forward(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2*
     r.plane_frame = fr.plane_frame;
     r.nlines = fr.nplanes * C.m;
     CHK(run_row(p, C, ROW_FWD, r, s));
-    ColArgs a = col_args(p, C);
+    ColArgs a = col_args(p, C, fr.tiled);
     a.in = C.T;
     a.out = out;
     a.P = P;
@@ -400,7 +447,7 @@ int seq_forward(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2*
 // T = row-DFT(E(drho . c + rho . E^H W^{-1} dchat))   (first half of DF)
 int seq_deriv_head(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2* rho, const float2* c,
                    const float2* drho, const float2* dchat, hipStream_t s) {
-    ColArgs a = col_args(p, C);
+    ColArgs a = col_args(p, C, fr.tiled);
     a.in = dchat;
     a.out = C.T;
     a.plane_frame = fr.plane_frame;
@@ -432,7 +479,7 @@ int seq_adjoint_tail(nlinv_plan_s* p, const Class& C, const Frames& fr, const fl
     r.plane_frame = fr.plane_frame;
     r.nlines = fr.nplanes * C.m;
     CHK(run_row(p, C, ROW_ADJ, r, s));
-    ColArgs a = col_args(p, C);
+    ColArgs a = col_args(p, C, fr.tiled);
     a.in = C.T;
     a.out = dchat_out;
     a.plane_frame = fr.plane_frame;
@@ -443,21 +490,62 @@ int seq_adjoint_tail(nlinv_plan_s* p, const Class& C, const Frames& fr, const fl
     a.c1 = c1;
     a.c2 = c2;
     CHK(run_col(p, C, COL_PAD_FFT_WINV_ADD, a, fr.nplanes, s));
-    CoilSumArgs cs{};
-    cs.aux = C.aux;
-    cs.out = drho_out;
-    cs.add1 = add1r;
-    cs.add2 = add2r;
-    cs.s1 = s1;
-    cs.s2 = s2;
-    cs.c1 = c1;
-    cs.c2 = c2;
-    cs.frame_plane0 = fr.frame_plane0;
-    cs.frame_planes = fr.frame_planes;
-    cs.nplanes = fr.nplanes;
-    cs.nframes = fr.nframes;
-    cs.E = C.m * C.m;
-    return run_coil_sum(p, cs, s);
+    return run_coil_sum(p, coil_sum_args(C, fr, drho_out, add1r, add2r, s1, s2, c1, c2, nullptr, 0), s);
+}
+
+// (DF^H DF + alpha) p inside CG, with the direction update p = r + beta p
+// folded into the first column pass (beta == nullptr: p = r) and the
+// partials of Re<p, q> written by the last column pass and the coil sum;
+// `g` receives the geometry of those partials.
+int seq_normal_cg(nlinv_plan_s* p, Class& C, const float* beta, SegGeom& g, hipStream_t s) {
+    const Frames fr = class_frames(C);
+    ColArgs a = col_args(p, C, fr.tiled);
+    a.in = C.p_c;
+    a.out = C.T;
+    a.plane_frame = fr.plane_frame;
+    a.r_in = C.r_c;
+    a.p_out = C.p_c;
+    a.beta = beta;
+    a.pr = C.p_r;
+    a.rr = C.r_r;
+    CHK(run_col(p, C, COL_PUPD_WINV_IFFT_CROP, a, fr.nplanes, s));
+    RowArgs r = row_args(C);
+    r.in = C.T;
+    r.out = C.T;
+    r.c = C.c;
+    r.rho = C.x_r;
+    r.drho = C.p_r;
+    r.plane_frame = fr.plane_frame;
+    r.nlines = fr.nplanes * C.m;
+    CHK(run_row(p, C, ROW_DERIV, r, s));
+    ColArgs b = col_args(p, C, fr.tiled);
+    b.in = C.T;
+    b.out = C.T;
+    b.P = C.P;
+    b.p_stride = C.cplane();
+    b.plane_frame = fr.plane_frame;
+    CHK(run_col(p, C, COL_PAD_FFT_P2_IFFT, b, fr.nplanes, s));
+    r.aux = C.aux;
+    r.drho = nullptr;
+    CHK(run_row(p, C, ROW_ADJ, r, s));
+    const int ntiles = C.n / kColL[C.colv[COL_PAD_FFT_WINV_AXPY_DOT]];
+    ColArgs e = col_args(p, C, fr.tiled);
+    e.in = C.T;
+    e.out = C.q_c;
+    e.plane_frame = fr.plane_frame;
+    e.add1 = C.p_c;
+    e.s1 = C.alpha;
+    e.partial = C.partial;
+    CHK(run_col(p, C, COL_PAD_FFT_WINV_AXPY_DOT, e, fr.nplanes, s));
+    CoilSumArgs cs = coil_sum_args(C, fr, C.q_r, C.p_r, nullptr, C.alpha, nullptr, 0.f, 0.f, C.partial,
+                                   (long long)C.nplanes * ntiles);
+    CHK(run_coil_sum(p, cs, s));
+    g = C.geom;
+    g.cseg = ntiles;
+    g.clen = 0;
+    g.rseg = cs.segs;
+    g.rlen = 0;
+    return NLINV_OK;
 }
 
 // (drho_out, dchat_out) = (DF^H DF + alpha) (drho, dchat)
@@ -466,7 +554,7 @@ int seq_normal(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2* 
                const float2* drho, const float2* dchat, float2* drho_out, float2* dchat_out,
                hipStream_t s) {
     CHK(seq_deriv_head(p, C, fr, rho, c, drho, dchat, s));
-    ColArgs a = col_args(p, C);
+    ColArgs a = col_args(p, C, fr.tiled);
     a.in = C.T;
     a.out = C.T;
     a.P = P;
@@ -477,10 +565,6 @@ int seq_normal(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2* 
                             alpha_f, nullptr, alpha_c, 0.f, s);
 }
 
-Frames single_frame(int J) { return Frames{J, 1, nullptr, nullptr, nullptr}; }
-Frames class_frames(const Class& C) {
-    return Frames{C.nplanes, C.nframes, C.plane_frame, C.frame_plane0, C.frame_planes};
-}
 
 // ---- the Newton loop of one solve (device-only work: capturable) ------------
 
@@ -507,7 +591,7 @@ int enqueue_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s
             CHK(run_scalar(p, C, SC_R0NORM, C.geomC, 0.f, step, s));
             // b = DF^H r0 - alpha (x_n - x_ref) into r
             {
-                ColArgs a = col_args(p, C);
+                ColArgs a = col_args(p, C, fr.tiled);
                 a.in = C.q_c;
                 a.out = C.T;
                 a.P = C.P;
@@ -517,7 +601,6 @@ int enqueue_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s
                 CHK(seq_adjoint_tail(p, C, fr, C.x_r, C.c, C.r_r, C.r_c, C.x_c, C.x_r, C.xr_c, C.xr_r,
                                      C.alpha + C.nframes, C.alpha, 0.f, 0.f, s));
             }
-            CHK(run_vec<VEC_COPY>(p, C.geom, vptrs(C.p_c, C.p_r, C.r_c, C.r_r), nullptr, nullptr, nullptr, s));
             {
                 const int slot = tbegin(p, KC_VEC_OTHER, s);
                 hipLaunchKernelGGL(k_fill, dim3(grid_for((long long)C.nplanes * ps)), dim3(kThreads), 0, s,
@@ -532,18 +615,12 @@ int enqueue_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s
         }
         for (int it = 0; it < K; ++it) {
             for (Class& C : p->classes) {
-                const Frames fr = class_frames(C);
-                CHK(seq_normal(p, C, fr, C.x_r, C.c, C.P, C.cplane(), C.alpha, 0.f, C.p_r, C.p_c, C.q_r,
-                               C.q_c, s));
-                CHK(run_vec<VEC_DOT>(p, C.geom, vptrs(C.p_c, C.p_r, C.q_c, C.q_r), nullptr, nullptr, C.partial, s));
-                CHK(run_scalar(p, C, SC_GAMMA, C.geom, 0.f, step, s));
+                SegGeom g{};
+                CHK(seq_normal_cg(p, C, it == 0 ? nullptr : C.sc.beta, g, s));
+                CHK(run_scalar(p, C, SC_GAMMA, g, 0.f, step, s));
                 CHK(run_vec<VEC_XR_UPDATE>(p, C.geom, vptrs(C.dx_c, C.dx_r, C.p_c, C.p_r, C.r_c, C.r_r, C.q_c, C.q_r),
                                            C.sc.a, nullptr, C.partial, s));
-                CHK(run_scalar(p, C, SC_RR, C.geom, 0.f, step, s));
-                hipLaunchKernelGGL(k_cg_stat, dim3((C.nframes + 63) / 64), dim3(64), 0, s, C.sc, C.nframes, N, K,
-                                   step, it);
-                HIPCHK(hipGetLastError());
-                CHK(run_vec<VEC_P_UPDATE>(p, C.geom, vptrs(C.p_c, C.p_r, C.r_c, C.r_r), nullptr, C.sc.beta, nullptr, s));
+                CHK(run_scalar(p, C, SC_RR, C.geom, 0.f, step, s, it, N, K));
             }
         }
         for (Class& C : p->classes)
@@ -551,6 +628,18 @@ int enqueue_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s
     }
     // sensitivities of the final x (for the image)
     for (Class& C : p->classes) CHK(seq_coil_maps(p, C, class_frames(C), C.x_c, C.c, s));
+    return NLINV_OK;
+}
+
+// row-major <-> column-tiled copies of `nplanes` planes of class C
+template <class T>
+int tile_copy(nlinv_plan_s* p, const Class& C, const T* src, T* dst, int nplanes, int to_tiled, hipStream_t s) {
+    const int slot = tbegin(p, KC_VEC_OTHER, s);
+    hipLaunchKernelGGL((k_tile<T>), dim3(grid_for((long long)nplanes * C.cplane())), dim3(kThreads), 0, s, src, dst,
+                       nplanes, C.n, C.tilew, to_tiled);
+    hipError_t e = hipGetLastError();
+    tend(p, slot, s);
+    HIPCHK(e);
     return NLINV_OK;
 }
 
@@ -571,9 +660,9 @@ int setup_frames(nlinv_plan_s* p, const nlinv_frame* frames, const nlinv_irgnm_p
         for (int lf = 0; lf < C.nframes; ++lf) {
             const nlinv_frame& F = frames[C.frames[lf]];
             const size_t cb = (size_t)C.J[lf] * C.cplane() * sizeof(float2);
-            HIPCHK(hipMemcpyAsync(C.y + (size_t)C.plane0[lf] * C.cplane(), F.y, cb, hipMemcpyDeviceToDevice, s));
-            HIPCHK(hipMemcpyAsync(C.P + (size_t)lf * C.cplane(), F.P, C.cplane() * sizeof(float),
-                                  hipMemcpyDeviceToDevice, s));
+            (void)cb;
+            CHK(tile_copy(p, C, (const float2*)F.y, C.y + (size_t)C.plane0[lf] * C.cplane(), C.J[lf], 1, s));
+            CHK(tile_copy(p, C, F.P, C.P + (size_t)lf * C.cplane(), 1, 1, s));
         }
         CHK(run_vec<VEC_DOT>(p, C.geomC, vptrs(C.y, nullptr, C.y, nullptr), nullptr, nullptr, C.partial, s));
         CHK(run_scalar(p, C, SC_YNORM, C.geomC, prm.scale_norm, 0, s));
@@ -585,7 +674,7 @@ int setup_frames(nlinv_plan_s* p, const nlinv_frame* frames, const nlinv_irgnm_p
             float2* xc = C.x_c + (size_t)C.plane0[lf] * C.cplane();
             float2* xr = C.x_r + (size_t)lf * C.rplane();
             if (warm) {
-                HIPCHK(hipMemcpyAsync(xc, F.chat, cb, hipMemcpyDeviceToDevice, s));
+                CHK(tile_copy(p, C, (const float2*)F.chat, xc, C.J[lf], 1, s));
                 HIPCHK(hipMemcpyAsync(xr, F.rho, C.rplane() * sizeof(float2), hipMemcpyDeviceToDevice, s));
             } else {
                 HIPCHK(hipMemsetAsync(xc, 0, cb, s));
@@ -606,7 +695,7 @@ int setup_frames(nlinv_plan_s* p, const nlinv_frame* frames, const nlinv_irgnm_p
             float2* rc = C.xr_c + (size_t)C.plane0[lf] * C.cplane();
             float2* rr = C.xr_r + (size_t)lf * C.rplane();
             if (F.rho_ref && F.chat_ref) {
-                HIPCHK(hipMemcpyAsync(rc, F.chat_ref, cb, hipMemcpyDeviceToDevice, s));
+                CHK(tile_copy(p, C, (const float2*)F.chat_ref, rc, C.J[lf], 1, s));
                 HIPCHK(hipMemcpyAsync(rr, F.rho_ref, C.rplane() * sizeof(float2), hipMemcpyDeviceToDevice, s));
             } else {
                 HIPCHK(hipMemcpyAsync(rc, C.x_c + (size_t)C.plane0[lf] * C.cplane(), cb, hipMemcpyDeviceToDevice, s));
@@ -652,7 +741,9 @@ int finish_frames(nlinv_plan_s* p, const nlinv_frame* frames, const nlinv_irgnm_
             const size_t cb = (size_t)C.J[lf] * C.cplane() * sizeof(float2);
             const size_t rb = C.rplane() * sizeof(float2);
             HIPCHK(hipMemcpyAsync(F.rho, C.dx_r + (size_t)lf * C.rplane(), rb, hipMemcpyDeviceToDevice, s));
-            HIPCHK(hipMemcpyAsync(F.chat, C.x_c + (size_t)C.plane0[lf] * C.cplane(), cb, hipMemcpyDeviceToDevice, s));
+            CHK(tile_copy(p, C, (const float2*)(C.x_c + (size_t)C.plane0[lf] * C.cplane()), (float2*)F.chat,
+                          C.J[lf], 0, s));
+            (void)cb;
             if (F.image)
                 HIPCHK(hipMemcpyAsync(F.image, C.aux + (size_t)lf * C.rplane(), rb, hipMemcpyDeviceToDevice, s));
             if (F.stats)
@@ -712,12 +803,15 @@ int solve_all(nlinv_plan_s* p, const nlinv_frame* frames, const nlinv_irgnm_para
 
 // ---- twiddles -------------------------------------------------------------------
 
+// tw2[k1][j2] = exp(-2 pi i k1 j2 / n) for the split n = N1 * N2 of the line FFTs
 int make_twiddles(nlinv_plan_s* p, Class& C) {
+    const int n1 = split_n1(C.n), n2 = C.n / n1;
     std::vector<float2> h(C.n);
-    for (int k = 0; k < C.n; ++k) {
-        const double ang = -2.0 * M_PI * (double)k / (double)C.n;
-        h[k] = make_float2((float)std::cos(ang), (float)std::sin(ang));
-    }
+    for (int k1 = 0; k1 < n1; ++k1)
+        for (int j2 = 0; j2 < n2; ++j2) {
+            const double ang = -2.0 * M_PI * (double)(k1 * j2) / (double)C.n;
+            h[k1 * n2 + j2] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+        }
     CHK(dalloc(p, &C.tw, C.n));
     HIPCHK(hipMemcpy(C.tw, h.data(), C.n * sizeof(float2), hipMemcpyHostToDevice));
     return NLINV_OK;
@@ -734,8 +828,30 @@ int default_row_variant(int n) {
     return -1;
 }
 
+// 1/w[kappa] = (1 + a |k|^2)^(-l/2), k_d = (kappa_d - n/2)/n, in FP64 on the host
+int make_weight_table(nlinv_plan_s* p, Class& C) {
+    std::vector<float> h((size_t)C.n * C.n);
+    for (int r = 0; r < C.n; ++r)
+        for (int c = 0; c < C.n; ++c) {
+            const double k0 = (double)(r - C.n / 2) / C.n, k1 = (double)(c - C.n / 2) / C.n;
+            h[(size_t)r * C.n + c] = (float)std::pow(1.0 + (double)p->sob_a * (k0 * k0 + k1 * k1),
+                                                     -(double)p->sob_hl);
+        }
+    CHK(dalloc(p, &C.winv, h.size()));
+    HIPCHK(hipMemcpy(C.winv, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
+    std::vector<float> t(h.size());
+    for (int r = 0; r < C.n; ++r)
+        for (int c = 0; c < C.n; ++c)
+            t[((size_t)(c / C.tilew) * C.n + r) * C.tilew + (c % C.tilew)] = h[(size_t)r * C.n + c];
+    CHK(dalloc(p, &C.winv_t, t.size()));
+    HIPCHK(hipMemcpy(C.winv_t, t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice));
+    return NLINV_OK;
+}
+
 int build_class(nlinv_plan_s* p, Class& C) {
+    C.tilew = C.n % 16 == 0 ? 16 : C.n % 8 == 0 ? 8 : 4;     // as plane_tile<N>()
     CHK(make_twiddles(p, C));
+    CHK(make_weight_table(p, C));
     const long long cn = C.cplane(), rn = C.rplane();
     const size_t cv = (size_t)C.nplanes * cn, rv = (size_t)C.nframes * rn;
     std::vector<int> pf(C.nplanes), fp0(C.nframes), fpn(C.nframes);
@@ -760,7 +876,10 @@ int build_class(nlinv_plan_s* p, Class& C) {
     CHK(dalloc(p, &C.T, (size_t)C.nplanes * C.m * C.n));
     make_geom(C.geom, C.nplanes, C.nframes, cn, rn, true, C.plane_frame);
     make_geom(C.geomC, C.nplanes, C.nframes, cn, rn, false, C.plane_frame);
-    CHK(dalloc(p, &C.partial, (size_t)std::max(nseg(C.geom), nseg(C.geomC))));
+    // partials: the segment geometries, or (column tiles of the narrowest
+    // variant per plane) + (coil-sum segments per frame)
+    const size_t tiles = (size_t)C.nplanes * (C.n / 4) + (size_t)C.nframes * ((rn + kCoilSeg - 1) / kCoilSeg);
+    CHK(dalloc(p, &C.partial, std::max<size_t>(tiles, (size_t)std::max(nseg(C.geom), nseg(C.geomC)))));
     CHK(dalloc(p, &C.alpha, (size_t)2 * C.nframes));
     CHK(dalloc(p, &C.sc.rr, C.nframes));
     CHK(dalloc(p, &C.sc.a, C.nframes));
@@ -771,8 +890,8 @@ int build_class(nlinv_plan_s* p, Class& C) {
     CHK(dalloc(p, &C.sc.stats, (size_t)C.nframes * kStatsCap));
     C.sc.alpha = C.alpha;
     C.sc.stats_len = kStatsCap;
-    C.colv = default_col_variant(C.n);
-    C.rowv = default_row_variant(C.n);
+    for (int& v : C.colv) v = default_col_variant(C.n);
+    for (int& v : C.rowv) v = default_row_variant(C.n);
     return NLINV_OK;
 }
 
@@ -787,7 +906,8 @@ void free_plan(nlinv_plan_s* p) {
 
 int check_dims(const nlinv_dims& d) {
     if (d.n <= 0 || d.n_om <= 0 || d.ncoils <= 0) return NLINV_EINVAL;
-    if (!size_supported(d.n)) return NLINV_EUNSUPPORTED;
+    if (!size_supported(d.n) || !supported_len(d.n)) return NLINV_EUNSUPPORTED;
+    if (default_col_variant(d.n) < 0 || default_row_variant(d.n) < 0) return NLINV_EUNSUPPORTED;
     if ((d.n_om & 1) || d.n_om > d.n) return NLINV_EUNSUPPORTED;
     if (d.ncoils > 64) return NLINV_EUNSUPPORTED;
     if (!(d.sobolev_a >= 0.f) || !(d.sobolev_l >= 0.f)) return NLINV_EINVAL;
@@ -796,57 +916,105 @@ int check_dims(const nlinv_dims& d) {
 
 Class* class0(nlinv_plan_s* p) { return &p->classes[p->loc[0].first]; }
 
-// time `reps` launches of a representative pass for every variant; keep the fastest
+// Arguments of a representative launch of each pass mode on the class
+// workspace (the contents are scratch at tuning time: a solve recomputes
+// everything from its inputs).
+ColArgs tune_col_args(nlinv_plan_s* p, Class& C, int mode) {
+    const Frames fr = class_frames(C);
+    ColArgs a = col_args(p, C, fr.tiled);
+    a.plane_frame = fr.plane_frame;
+    a.P = C.P;
+    a.p_stride = C.cplane();
+    a.in = C.T;
+    a.out = C.T;
+    switch (mode) {
+        case COL_WINV_IFFT_CROP: a.in = C.x_c; break;
+        case COL_PUPD_WINV_IFFT_CROP:
+            a.in = C.p_c; a.r_in = C.r_c; a.p_out = C.p_c; a.beta = C.sc.beta; a.pr = C.p_r; a.rr = C.r_r;
+            break;
+        case COL_P_IFFT_CROP: a.in = C.q_c; break;
+        case COL_PAD_FFT_P: a.out = C.q_c; break;
+        case COL_PAD_FFT_P_RESID: a.out = C.q_c; a.add1 = C.y; a.s1 = C.sc.s; break;
+        case COL_PAD_FFT_WINV_ADD:
+            a.out = C.r_c; a.add1 = C.x_c; a.add2 = C.xr_c; a.s1 = C.alpha + C.nframes; a.s2 = C.alpha;
+            break;
+        case COL_PAD_FFT_WINV_AXPY_DOT: a.out = C.q_c; a.add1 = C.p_c; a.s1 = C.alpha; a.partial = C.partial; break;
+        default: break;
+    }
+    return a;
+}
+
+RowArgs tune_row_args(Class& C, int mode) {
+    const Frames fr = class_frames(C);
+    RowArgs r = row_args(C);
+    r.in = C.T;
+    r.out = C.T;
+    r.c = C.c;
+    r.rho = C.x_r;
+    r.drho = C.p_r;
+    r.aux = C.aux;
+    r.c_out = C.c;
+    r.plane_frame = fr.plane_frame;
+    r.nlines = fr.nplanes * C.m;
+    (void)mode;
+    return r;
+}
+
+// Time `reps` launches of every valid variant of every pass mode the solve
+// uses and keep the fastest per mode; NLINV_TUNE_VERBOSE prints the table.
 int tune_class(nlinv_plan_s* p, Class& C, hipStream_t s) {
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
+    const bool verbose = std::getenv("NLINV_TUNE_VERBOSE") != nullptr;
     const int reps = 10;
-    const Frames fr = class_frames(C);
-    float best = 1e30f;
-    int bestv = C.colv;
-    for (int v = 0; v < kNumColVariants; ++v) {
-        if (!col_ok(C.n, v)) continue;
-        C.colv = v;
-        ColArgs a = col_args(p, C);
-        a.in = C.T;
-        a.out = C.T;
-        a.P = C.P;
-        a.p_stride = C.cplane();
-        a.plane_frame = fr.plane_frame;
-        CHK(run_col(p, C, COL_PAD_FFT_P2_IFFT, a, fr.nplanes, s));   // warm-up
+    const int nplanes = C.nplanes;
+    auto timeit = [&](auto&& launch, float& ms) -> int {
+        CHK(launch());
         HIPCHK(hipEventRecord(e0, s));
-        for (int r = 0; r < reps; ++r) CHK(run_col(p, C, COL_PAD_FFT_P2_IFFT, a, fr.nplanes, s));
+        for (int r = 0; r < reps; ++r) CHK(launch());
         HIPCHK(hipEventRecord(e1, s));
         HIPCHK(hipEventSynchronize(e1));
-        float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) { best = ms; bestv = v; }
+        ms /= reps;
+        return NLINV_OK;
+    };
+    const int col_modes[] = {COL_WINV_IFFT_CROP, COL_PUPD_WINV_IFFT_CROP, COL_P_IFFT_CROP, COL_PAD_FFT_P,
+                             COL_PAD_FFT_P_RESID, COL_PAD_FFT_P2_IFFT, COL_PAD_FFT_WINV_ADD,
+                             COL_PAD_FFT_WINV_AXPY_DOT};
+    for (int mode : col_modes) {
+        const ColArgs a = tune_col_args(p, C, mode);
+        float best = 1e30f;
+        int bestv = C.colv[mode];
+        for (int v = 0; v < kNumColVariants; ++v) {
+            if (!col_ok(C.n, v)) continue;
+            C.colv[mode] = v;
+            float ms = 0.f;
+            CHK(timeit([&] { return run_col(p, C, mode, a, nplanes, s); }, ms));
+            if (verbose)
+                std::fprintf(stderr, "nlinv tune n=%d planes=%d %s L=%d: %.1f us\n", C.n, nplanes,
+                             kKClassNames[col_kclass(mode)], kColL[v], 1e3 * ms);
+            if (ms < best) { best = ms; bestv = v; }
+        }
+        C.colv[mode] = bestv;
     }
-    C.colv = bestv;
-    best = 1e30f;
-    bestv = C.rowv;
-    for (int v = 0; v < kNumRowVariants; ++v) {
-        if (!row_ok(C.n, v)) continue;
-        C.rowv = v;
-        RowArgs r = row_args(C);
-        r.in = C.T;
-        r.out = C.T;
-        r.c = C.c;
-        r.rho = C.x_r;
-        r.drho = C.p_r;
-        r.plane_frame = fr.plane_frame;
-        r.nlines = fr.nplanes * C.m;
-        CHK(run_row(p, C, ROW_DERIV, r, s));
-        HIPCHK(hipEventRecord(e0, s));
-        for (int k = 0; k < reps; ++k) CHK(run_row(p, C, ROW_DERIV, r, s));
-        HIPCHK(hipEventRecord(e1, s));
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) { best = ms; bestv = v; }
+    const int row_modes[] = {ROW_CACHE, ROW_FWD, ROW_DERIV, ROW_ADJ};
+    for (int mode : row_modes) {
+        const RowArgs r = tune_row_args(C, mode);
+        float best = 1e30f;
+        int bestv = C.rowv[mode];
+        for (int v = 0; v < kNumRowVariants; ++v) {
+            if (!row_ok(C.n, v)) continue;
+            C.rowv[mode] = v;
+            float ms = 0.f;
+            CHK(timeit([&] { return run_row(p, C, mode, r, s); }, ms));
+            if (verbose)
+                std::fprintf(stderr, "nlinv tune n=%d planes=%d %s L=%d: %.1f us\n", C.n, nplanes,
+                             kKClassNames[row_kclass(mode)], kRowL[v], 1e3 * ms);
+            if (ms < best) { best = ms; bestv = v; }
+        }
+        C.rowv[mode] = bestv;
     }
-    C.rowv = bestv;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return NLINV_OK;
@@ -980,7 +1148,7 @@ int nlinv_deriv(nlinv_plan p, const nlinv_c32* rho, const nlinv_c32* chat, const
         cc = C.c;
     }
     CHK(seq_deriv_head(p, C, fr, (const float2*)rho, cc, (const float2*)drho, (const float2*)dchat, s));
-    ColArgs a = col_args(p, C);
+    ColArgs a = col_args(p, C, fr.tiled);
     a.in = C.T;
     a.out = (float2*)dy_out;
     a.P = P;
@@ -1002,7 +1170,7 @@ int nlinv_adjoint(nlinv_plan p, const nlinv_c32* rho, const nlinv_c32* chat, con
         CHK(seq_coil_maps(p, C, fr, (const float2*)chat, C.c, s));
         cc = C.c;
     }
-    ColArgs a = col_args(p, C);
+    ColArgs a = col_args(p, C, fr.tiled);
     a.in = (const float2*)dy;
     a.out = C.T;
     a.P = P;
@@ -1050,7 +1218,7 @@ int nlinv_mask_gradient(nlinv_plan p, const nlinv_c32* rho, const nlinv_c32* cha
     r.out = C.T;
     r.nlines = J * C.m;
     CHK(run_row(p, C, ROW_FWD, r, s));
-    ColArgs a = col_args(p, C);
+    ColArgs a = col_args(p, C, fr.tiled);
     a.in = C.T;
     a.out = C.q_c;                  // real products Re(conj g . S) [J][n][n] as floats
     a.add1 = (const float2*)g;
@@ -1136,15 +1304,23 @@ int nlinv_plan_autotune(nlinv_plan p, void* stream) {
     const hipStream_t s = (hipStream_t)stream;
     const std::string arch = arch_name(p->device);
     const char* path = std::getenv("NLINV_TUNE_CACHE");
-    std::map<std::string, std::pair<int, int>> cache;
+    // cache lines: arch n planes <kColModes column variants> <kRowModes row variants>
+    std::map<std::string, std::vector<int>> cache;
     if (path) {
         std::ifstream in(path);
-        std::string a;
-        int n, np, cv, rv;
-        while (in >> a >> n >> np >> cv >> rv) {
+        std::string line;
+        while (std::getline(in, line)) {
+            std::istringstream ls(line);
+            std::string a;
+            int n, np;
+            if (!(ls >> a >> n >> np)) continue;
+            std::vector<int> v;
+            int x;
+            while (ls >> x) v.push_back(x);
+            if ((int)v.size() != kColModes + kRowModes) continue;
             std::ostringstream k;
             k << a << ' ' << n << ' ' << np;
-            cache[k.str()] = {cv, rv};
+            cache[k.str()] = v;
         }
     }
     bool changed = false;
@@ -1152,19 +1328,29 @@ int nlinv_plan_autotune(nlinv_plan p, void* stream) {
         std::ostringstream k;
         k << arch << ' ' << C.n << ' ' << C.nplanes;
         auto it = cache.find(k.str());
-        if (it != cache.end() && col_ok(C.n, it->second.first) && row_ok(C.n, it->second.second)) {
-            C.colv = it->second.first;
-            C.rowv = it->second.second;
+        bool ok = it != cache.end();
+        if (ok)
+            for (int i = 0; i < kColModes + kRowModes; ++i)
+                ok = ok && (i < kColModes ? col_ok(C.n, it->second[i]) : row_ok(C.n, it->second[i]));
+        if (ok) {
+            for (int i = 0; i < kColModes; ++i) C.colv[i] = it->second[i];
+            for (int i = 0; i < kRowModes; ++i) C.rowv[i] = it->second[kColModes + i];
             continue;
         }
         CHK(tune_class(p, C, s));
-        cache[k.str()] = {C.colv, C.rowv};
+        std::vector<int> v(C.colv, C.colv + kColModes);
+        v.insert(v.end(), C.rowv, C.rowv + kRowModes);
+        cache[k.str()] = v;
         changed = true;
     }
     CHK(drop_graph(p));   // variants are baked into a captured graph
     if (path && changed) {
         std::ofstream o(path);
-        for (auto& kv : cache) o << kv.first << ' ' << kv.second.first << ' ' << kv.second.second << '\n';
+        for (auto& kv : cache) {
+            o << kv.first;
+            for (int x : kv.second) o << ' ' << x;
+            o << '\n';
+        }
     }
     return NLINV_OK;
 }
@@ -1173,8 +1359,8 @@ int nlinv_plan_variant(nlinv_plan p, int32_t n, int32_t* col_variant, int32_t* r
     if (!p || !col_variant || !row_variant) return NLINV_EINVAL;
     for (Class& C : p->classes)
         if (C.n == n) {
-            *col_variant = C.colv;
-            *row_variant = C.rowv;
+            *col_variant = C.colv[COL_PAD_FFT_P2_IFFT];
+            *row_variant = C.rowv[ROW_DERIV];
             return NLINV_OK;
         }
     *col_variant = *row_variant = -1;
@@ -1187,8 +1373,8 @@ int nlinv_plan_set_variant(nlinv_plan p, int32_t n, int32_t col_variant, int32_t
     bool found = false;
     for (Class& C : p->classes)
         if (C.n == n) {
-            C.colv = col_variant;
-            C.rowv = row_variant;
+            for (int& v : C.colv) v = col_variant;
+            for (int& v : C.rowv) v = row_variant;
             found = true;
         }
     if (!found) return NLINV_EINVAL;

@@ -1,5 +1,5 @@
 // Fused pass kernels of the NLINV operators (Schaetz & Uecker, Eqs. 2-3)
-// and the CG vector / FP64 reduction kernels, for gfx950.
+// for gfx950.
 //
 // Data layout in HBM (complex64 interleaved, C-contiguous):
 //   coil planes  [planes][n][n]   chat-like vectors and k-space data
@@ -11,9 +11,8 @@
 // a shape class (all frames of a class share n and m).
 //
 // A 2D centred unitary DFT is a column pass (transform along axis 0) and a
-// row pass (axis 1).  Along one axis, the centred DFT is an ordinary DFT
-// between two checkerboard signs (-1)^index, times 1/sqrt(n); the global sign
-// (-1)^(n/2) of each axis cancels between the two axes of a square grid.
+// row pass (axis 1), each a two-register-stage line FFT (fft_core.hpp) with
+// the centring of Centre<N> and the unitary 1/sqrt(n) folded into its stores.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -24,12 +23,39 @@ namespace nlinv {
 
 __device__ __forceinline__ float sgn(int i) { return (i & 1) ? -1.0f : 1.0f; }
 
-// 1/w = (1 + a |k|^2)^(-l/2), k_d = (kappa_d - n/2)/n, evaluated in the log domain
-// (w reaches 5e32 at the grid corners for a = 220, l = 32).
-__device__ __forceinline__ float winv(int r, int c, int n, float a, float hl) {
-    const int d0 = r - n / 2, d1 = c - n / 2;
-    const float k2 = (float)(d0 * d0 + d1 * d1) / (float)(n * n);
-    return expf(-hl * log1pf(a * k2));
+// Centring.  With x' = x shifted by n/2, the centred DFT is the plain DFT of
+// x' shifted by n/2 again: position p holds slot (p - n/2) mod n on both
+// sides.  When N1 and N2 are even the shift is a compile-time permutation of
+// the register index (k1 -> k1 + N1/2 on input, k2 -> k2 + N2/2 on output);
+// otherwise the slot keeps its position and the checkerboard sign (-1)^p
+// does the shift (the per-axis sign (-1)^(n/2) cancels on a square grid).
+template <int N>
+struct Centre {
+    static constexpr int N1 = split_n1(N), N2 = N / N1;
+    static constexpr bool PERM = (N1 % 2 == 0) && (N2 % 2 == 0);
+    // position of stage-1 input slot j2 + N2 k1
+    static __device__ __forceinline__ int in_pos(int j2, int k1) {
+        return PERM ? j2 + N2 * ((k1 + N1 / 2) % N1) : j2 + N2 * k1;
+    }
+    // position of stage-2 output slot k1 + N1 k2
+    static __device__ __forceinline__ int out_pos(int k1, int k2) {
+        return PERM ? k1 + N1 * ((k2 + N2 / 2) % N2) : k1 + N1 * k2;
+    }
+    static __device__ __forceinline__ float sign(int pos) { return PERM ? 1.0f : sgn(pos); }
+};
+
+// Inside a solve the n x n planes (CG vectors, data, P, 1/w) are stored
+// column-tiled: [n / TW][n][TW], TW = 16 (8 or 4 when n is not a multiple of
+// 16), so that a column pass reads and writes contiguous blocks instead of
+// TW-wide row segments n apart.  The operator entry points take the plain
+// row-major layout of the caller's arrays.
+template <int N>
+constexpr int plane_tile() { return N % 16 == 0 ? 16 : N % 8 == 0 ? 8 : 4; }
+
+template <int N>
+__device__ __forceinline__ long long big_idx(int r, int col, int tiled) {
+    constexpr int TW = plane_tile<N>();
+    return tiled ? ((long long)(col / TW) * N + r) * TW + (col % TW) : (long long)r * N + col;
 }
 
 // ---------------------------------------------------------------------------
@@ -44,6 +70,8 @@ enum ColMode : int {
     COL_PAD_FFT_P2_IFFT = 4,  // T = crop_rows(IDFT_0(P^2 . DFT_0(pad_rows(T))))   (in place)
     COL_PAD_FFT_WINV_ADD = 5, // out = DFT_0(pad_rows(T)) / w + a1_f add1 + a2_f add2
     COL_PAD_FFT_GPROD = 6,    // outR = Re(conj(g) . DFT_0(pad_rows(T)))  (mask gradient)
+    COL_PUPD_WINV_IFFT_CROP = 7,   // CG: p = r + beta p (written back), then as COL_WINV_IFFT_CROP
+    COL_PAD_FFT_WINV_AXPY_DOT = 8, // CG: out = DFT_0(pad_rows(T)) / w + a1_f add1, Re<add1, out> partials
 };
 
 struct ColArgs {
@@ -58,92 +86,228 @@ struct ColArgs {
     const float* s2;
     float c1, c2;
     int m, lo;
-    float sob_a, sob_hl;
+    int nplanes;
     float rs;                 // 1/sqrt(n)
-    const float2* tw;         // exp(-2 pi i k / n), k < n
+    const float2* tw2;        // [N1][N2]: exp(-2 pi i k1 j2 / n)
+    const float* winv;        // [n][n]: 1/w, the inverse Sobolev weight
+    // COL_PUPD_WINV_IFFT_CROP: the direction update p = r + beta_f p is done
+    // at load (in = p is rewritten); beta == nullptr means p = r.
+    const float2* r_in;       // chat part of r (nullable: no update)
+    float2* p_out;            // chat part of p
+    const float* beta;
+    float2* pr;               // rho part of p [frames][m*m], updated by the first plane of each frame
+    const float2* rr;         // rho part of r
+    // COL_PAD_FFT_WINV_AXPY_DOT: Re<add1, out> per workgroup into partial[plane * tiles + tile]
+    double* partial;
+    int tiled;                // n x n planes, P and 1/w column-tiled (inside a solve)
 };
+
+// Work item w = tile * nplanes + plane (planes of a tile adjacent, so the P
+// tile of a frame is reused); blocks are dealt to the 8 XCDs round robin, so
+// block b runs item (b % 8) * per + b / 8: each XCD owns a contiguous range.
+__device__ __forceinline__ bool col_item(int ntiles, int nplanes, int& tile, int& plane) {
+    const int total = ntiles * nplanes;
+    const int per = (total + 7) / 8;
+    const int b = blockIdx.x;
+    const int w = (b & 7) * per + (b >> 3);
+    if (w >= total) return false;
+    tile = w / nplanes;
+    plane = w % nplanes;
+    return true;
+}
 
 template <int N, int L, int MODE>
 __global__ __launch_bounds__(kThreads) void k_col(ColArgs a) {
-    __shared__ float2 tile[N * L];
-    __shared__ float2 tw[N];
-    const int plane = blockIdx.y;
-    const int col0 = blockIdx.x * L;
+    using CT = Centre<N>;
+    constexpr int N1 = CT::N1, N2 = CT::N2;
+    constexpr bool TWO = (MODE == COL_PAD_FFT_P2_IFFT);
+    constexpr bool PUPD = (MODE == COL_PUPD_WINV_IFFT_CROP);
+    constexpr bool WINV_IN = (MODE == COL_WINV_IFFT_CROP) || PUPD;
+    constexpr bool INV1 = WINV_IN || (MODE == COL_P_IFFT_CROP);
+    constexpr bool IN_CROP = !INV1;
+    constexpr bool OUT_CROP = INV1 || TWO;
+    constexpr bool DOT = (MODE == COL_PAD_FFT_WINV_AXPY_DOT);
+    constexpr bool WINV_OUT = (MODE == COL_PAD_FFT_WINV_ADD) || DOT;
+    __shared__ float2 bufA[N * L];                 // stage-1 results, [k1][j2][l]
+    __shared__ float2 bufB[TWO ? N * L : 1];       // slot order [slot][l] between two transforms
+    __shared__ double red[DOT ? kThreads / 64 : 1];
+
+    int tile, plane;
+    if (!col_item(N / L, a.nplanes, tile, plane)) return;
+    const int col0 = tile * L;
     const int f = a.plane_frame ? a.plane_frame[plane] : 0;
     const int m = a.m, lo = a.lo;
-    for (int i = threadIdx.x; i < N; i += kThreads) tw[i] = a.tw[i];
-
-    constexpr bool IN_CROP = (MODE >= COL_PAD_FFT_P);
-    constexpr bool INV1 = (MODE == COL_WINV_IFFT_CROP || MODE == COL_P_IFFT_CROP);
     const float* P = a.P + (long long)f * a.p_stride;
+    const long long pofs = (long long)plane * (IN_CROP ? m : N) * N;
+    const float2* src = a.in + pofs;
 
-    if constexpr (IN_CROP) {
-        const float2* src = a.in + (long long)plane * m * N;
-        for (int idx = threadIdx.x; idx < N * L; idx += kThreads) {
-            const int r = idx / L, c = idx % L;
-            const int ri = r - lo;
-            float2 v = make_float2(0.f, 0.f);
-            if (ri >= 0 && ri < m) v = cscale(src[(long long)ri * N + col0 + c], sgn(r));
-            tile[idx] = v;
-        }
-    } else {
-        const float2* src = a.in + (long long)plane * N * N;
-        for (int idx = threadIdx.x; idx < N * L; idx += kThreads) {
-            const int r = idx / L, c = idx % L;
-            float2 v = src[(long long)r * N + col0 + c];
-            float s = sgn(r);
-            if constexpr (MODE == COL_WINV_IFFT_CROP) s *= winv(r, col0 + c, N, a.sob_a, a.sob_hl);
-            if constexpr (MODE == COL_P_IFFT_CROP) s *= P[(long long)r * N + col0 + c];
-            tile[idx] = cscale(v, s);
-        }
-    }
-    __syncthreads();
-    fft_lines<N, L, L, 1, INV1>(tile, tw);
-
-    if constexpr (MODE == COL_PAD_FFT_P2_IFFT) {
-        // post-sign of the forward and pre-sign of the inverse cancel
-        const float rs2 = a.rs * a.rs;
-        for (int idx = threadIdx.x; idx < N * L; idx += kThreads) {
-            const int r = idx / L, c = idx % L;
-            const float p = P[(long long)r * N + col0 + c];
-            tile[idx] = cscale(tile[idx], p * p * rs2);
-        }
-        __syncthreads();
-        fft_lines<N, L, L, 1, true>(tile, tw);
-    }
-
-    if constexpr (MODE == COL_WINV_IFFT_CROP || MODE == COL_P_IFFT_CROP || MODE == COL_PAD_FFT_P2_IFFT) {
-        float2* dst = a.out + (long long)plane * m * N;
-        for (int idx = threadIdx.x; idx < m * L; idx += kThreads) {
-            const int ri = idx / L, c = idx % L;
-            const int r = ri + lo;
-            const float s = (MODE == COL_PAD_FFT_P2_IFFT) ? sgn(r) : sgn(r) * a.rs;
-            dst[(long long)ri * N + col0 + c] = cscale(tile[r * L + c], s);
-        }
-    } else {
-        const long long pbase = (long long)plane * N * N;
-        const float s1 = a.s1 ? a.s1[f] : a.c1;
-        const float s2 = a.s2 ? a.s2[f] : a.c2;
-        for (int idx = threadIdx.x; idx < N * L; idx += kThreads) {
-            const int r = idx / L, c = idx % L;
-            const long long o = (long long)r * N + col0 + c;
-            float2 v = cscale(tile[idx], sgn(r) * a.rs);
-            if constexpr (MODE == COL_PAD_FFT_P) {
-                a.out[pbase + o] = cscale(v, P[o]);
-            } else if constexpr (MODE == COL_PAD_FFT_P_RESID) {
-                const float2 y = a.add1[pbase + o];
-                const float p = P[o];
-                a.out[pbase + o] = make_float2(s1 * y.x - p * v.x, s1 * y.y - p * v.y);
-            } else if constexpr (MODE == COL_PAD_FFT_WINV_ADD) {
-                v = cscale(v, winv(r, col0 + c, N, a.sob_a, a.sob_hl));
-                if (a.add1) { const float2 u = a.add1[pbase + o]; v.x += s1 * u.x; v.y += s1 * u.y; }
-                if (a.add2) { const float2 u = a.add2[pbase + o]; v.x += s2 * u.x; v.y += s2 * u.y; }
-                a.out[pbase + o] = v;
-            } else if constexpr (MODE == COL_PAD_FFT_GPROD) {
-                const float2 g = a.add1[pbase + o];
-                reinterpret_cast<float*>(a.out)[pbase + o] = g.x * v.x + g.y * v.y;
+    if constexpr (PUPD) {
+        // rho part of the direction update, done by the first plane of each frame
+        if (plane == 0 || (a.plane_frame && a.plane_frame[plane - 1] != f)) {
+            const int E = m * m, ntiles = N / L;
+            const int chunk = (E + ntiles - 1) / ntiles;
+            const int e0 = tile * chunk, e1 = min(E, e0 + chunk);
+            const float bf = a.beta ? a.beta[f] : 0.f;
+            float2* pr = a.pr + (long long)f * E;
+            const float2* rr = a.rr + (long long)f * E;
+            for (int e = e0 + threadIdx.x; e < e1; e += kThreads) {
+                const float2 r = rr[e];
+                pr[e] = a.beta ? make_float2(r.x + bf * pr[e].x, r.y + bf * pr[e].y) : r;
             }
         }
+    }
+
+    // ---- stage 1 of the first transform: positions in_pos(j2, k1) straight from HBM
+    for (int t = threadIdx.x; t < L * N2; t += kThreads) {
+        const int l = t % L, j2 = t / L, col = col0 + l;
+        float2 v[N1];
+        static_for<0, N1>([&](auto K) {
+            constexpr int k1 = K;
+            const int r = CT::in_pos(j2, k1);
+            float2 x = make_float2(0.f, 0.f);
+            if constexpr (IN_CROP) {
+                const int ri = r - lo;
+                if (ri >= 0 && ri < m) x = cscale(src[(long long)ri * N + col], CT::sign(r));
+            } else {
+                const long long o = big_idx<N>(r, col, a.tiled);
+                if constexpr (WINV_IN) {
+                    if constexpr (PUPD) {    // p = r + beta p, written back
+                        const float2 rv = a.r_in[pofs + o];
+                        if (a.beta) {
+                            const float b = a.beta[f];
+                            const float2 pv = src[o];
+                            x = make_float2(rv.x + b * pv.x, rv.y + b * pv.y);
+                        } else {
+                            x = rv;
+                        }
+                        a.p_out[pofs + o] = x;
+                    } else {
+                        x = src[o];
+                    }
+                    x = cscale(x, CT::sign(r) * a.winv[o]);
+                } else {   // COL_P_IFFT_CROP
+                    x = cscale(src[o], CT::sign(r) * P[o]);
+                }
+            }
+            v[k1] = x;
+        });
+        RegDFT<N1, INV1>::run(v);
+        static_for<0, N1>([&](auto K) {
+            constexpr int k1 = K;
+            float2 x = v[k1];
+            if constexpr (k1 > 0) {
+                const float2 w = a.tw2[k1 * N2 + j2];
+                x = INV1 ? cmulc(x, w) : cmul(x, w);
+            }
+            bufA[(k1 * N2 + j2) * L + l] = x;
+        });
+    }
+    __syncthreads();
+
+    if constexpr (TWO) {
+        // stage 2 of the forward transform, times P^2 and 1/n at each output
+        // position, kept in slot order (the inverse reads the same slots)
+        const float rs2 = a.rs * a.rs;
+        for (int t = threadIdx.x; t < L * N1; t += kThreads) {
+            const int l = t % L, k1 = t / L, col = col0 + l;
+            float2 v[N2];
+            static_for<0, N2>([&](auto J) {
+                constexpr int j2 = J;
+                v[j2] = bufA[(k1 * N2 + j2) * L + l];
+            });
+            RegDFT<N2, false>::run(v);
+            static_for<0, N2>([&](auto K) {
+                constexpr int k2 = K;
+                const int r = CT::out_pos(k1, k2);
+                const float p = P[big_idx<N>(r, col, a.tiled)];
+                bufB[(k1 + N1 * k2) * L + l] = cscale(v[k2], p * p * rs2);
+            });
+        }
+        __syncthreads();
+        // stage 1 of the inverse transform, slots j2 + N2 k1 of bufB
+        for (int t = threadIdx.x; t < L * N2; t += kThreads) {
+            const int l = t % L, j2 = t / L;
+            float2 v[N1];
+            static_for<0, N1>([&](auto K) {
+                constexpr int k1 = K;
+                v[k1] = bufB[(j2 + N2 * k1) * L + l];
+            });
+            RegDFT<N1, true>::run(v);
+            static_for<0, N1>([&](auto K) {
+                constexpr int k1 = K;
+                float2 x = v[k1];
+                if constexpr (k1 > 0) x = cmulc(x, a.tw2[k1 * N2 + j2]);
+                bufA[(k1 * N2 + j2) * L + l] = x;
+            });
+        }
+        __syncthreads();
+    }
+
+    // ---- stage 2 of the last transform, straight to HBM
+    constexpr bool INV2 = INV1 || TWO;
+    const long long pbase = (long long)plane * N * N;
+    const float s1 = a.s1 ? a.s1[f] : a.c1;
+    const float s2 = a.s2 ? a.s2[f] : a.c2;
+    double acc = 0.0;
+    for (int t = threadIdx.x; t < L * N1; t += kThreads) {
+        const int l = t % L, k1 = t / L, col = col0 + l;
+        float2 v[N2];
+        static_for<0, N2>([&](auto J) {
+            constexpr int j2 = J;
+            v[j2] = bufA[(k1 * N2 + j2) * L + l];
+        });
+        RegDFT<N2, INV2>::run(v);
+        float facc = 0.f;
+        static_for<0, N2>([&](auto K) {
+            constexpr int k2 = K;
+            const int r = TWO ? (k1 + N1 * k2) : CT::out_pos(k1, k2);
+            // TWO: the forward pass left slots in place, so the inverse's
+            // output slot s sits at position s; its pre-shift is in the input
+            // slots (P^2 was applied at the shifted positions)
+            const int rp = TWO ? CT::out_pos(k1, k2) : r;
+            if constexpr (OUT_CROP) {
+                const int ri = rp - lo;
+                if (ri >= 0 && ri < m) {
+                    const float s = TWO ? CT::sign(rp) : CT::sign(rp) * a.rs;
+                    a.out[((long long)plane * m + ri) * N + col] = cscale(v[k2], s);
+                }
+            } else {
+                const long long o = big_idx<N>(rp, col, a.tiled);
+                float2 x = v[k2];
+                if constexpr (MODE == COL_PAD_FFT_P) {
+                    a.out[pbase + o] = cscale(x, CT::sign(rp) * a.rs * P[o]);
+                } else if constexpr (MODE == COL_PAD_FFT_P_RESID) {
+                    const float2 y = a.add1[pbase + o];
+                    const float p = CT::sign(rp) * a.rs * P[o];
+                    a.out[pbase + o] = make_float2(s1 * y.x - p * x.x, s1 * y.y - p * x.y);
+                } else if constexpr (WINV_OUT) {
+                    x = cscale(x, CT::sign(rp) * a.rs * a.winv[o]);
+                    if (DOT || a.add1) {
+                        const float2 u = a.add1[pbase + o];
+                        x.x += s1 * u.x;
+                        x.y += s1 * u.y;
+                        if constexpr (DOT) facc += u.x * x.x + u.y * x.y;
+                    }
+                    if constexpr (!DOT) {
+                        if (a.add2) { const float2 u = a.add2[pbase + o]; x.x += s2 * u.x; x.y += s2 * u.y; }
+                    }
+                    a.out[pbase + o] = x;
+                } else if constexpr (MODE == COL_PAD_FFT_GPROD) {
+                    const float2 g = a.add1[pbase + o];
+                    x = cscale(x, CT::sign(rp) * a.rs);
+                    reinterpret_cast<float*>(a.out)[pbase + o] = g.x * x.x + g.y * x.y;
+                }
+            }
+        });
+        acc += (double)facc;
+    }
+    if constexpr (DOT) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            a.partial[(long long)plane * (N / L) + tile] = (red[0] + red[1]) + (red[2] + red[3]);
     }
 }
 
@@ -170,80 +334,129 @@ struct RowArgs {
     int nlines;              // planes * m
     int m, lo;
     float rs;
-    const float2* tw;
+    const float2* tw2;       // [N1][N2]
 };
 
 template <int N, int L, int MODE>
 __global__ __launch_bounds__(kThreads) void k_row(RowArgs a) {
-    __shared__ float2 tile[L * N];
-    __shared__ float2 tw[N];
+    using CT = Centre<N>;
+    constexpr int N1 = CT::N1, N2 = CT::N2;
+    constexpr int S2 = N2 + 1;                      // padded stride of [line][k1][j2]
+    __shared__ float2 bufA[L * N1 * S2];
+    __shared__ float2 bufB[L * N];                  // position order [line][pos]
     const int line0 = blockIdx.x * L;
     const int m = a.m, lo = a.lo;
-    for (int i = threadIdx.x; i < N; i += kThreads) tw[i] = a.tw[i];
 
     if constexpr (MODE == ROW_FWD) {
         for (int idx = threadIdx.x; idx < L * N; idx += kThreads) {
-            const int l = idx / N, pos = idx % N;
-            const int line = line0 + l;
-            float2 v = make_float2(0.f, 0.f);
-            const int q = pos - lo;
-            if (line < a.nlines && q >= 0 && q < m) {
-                const int plane = line / m, i = line % m;
-                const int f = a.plane_frame ? a.plane_frame[plane] : 0;
-                const float2 cv = a.c[((long long)plane * m + i) * m + q];
-                const float2 rv = a.rho[((long long)f * m + i) * m + q];
-                v = cscale(cmul(rv, cv), sgn(pos));
-            }
-            tile[idx] = v;
-        }
-        __syncthreads();
-    } else {
-        for (int idx = threadIdx.x; idx < L * N; idx += kThreads) {
-            const int l = idx / N, pos = idx % N;
-            const int line = line0 + l;
-            float2 v = make_float2(0.f, 0.f);
-            if (line < a.nlines) v = cscale(a.in[(long long)line * N + pos], sgn(pos));
-            tile[idx] = v;
-        }
-        __syncthreads();
-        fft_lines<N, L, 1, N, true>(tile, tw);
-        // crop to Omega columns, pointwise products, zero-pad
-        for (int idx = threadIdx.x; idx < L * N; idx += kThreads) {
-            const int l = idx / N, pos = idx % N;
-            const int line = line0 + l;
+            const int ll = idx / N, pos = idx % N;
+            const int line = line0 + ll;
             const int q = pos - lo;
             float2 z = make_float2(0.f, 0.f);
             if (line < a.nlines && q >= 0 && q < m) {
                 const int plane = line / m, i = line % m;
-                const float2 u = cscale(tile[idx], sgn(pos) * a.rs);
-                const long long oc = ((long long)plane * m + i) * m + q;
-                if constexpr (MODE == ROW_CACHE) {
-                    a.c_out[oc] = u;
-                } else {
-                    const int f = a.plane_frame ? a.plane_frame[plane] : 0;
-                    const long long orh = ((long long)f * m + i) * m + q;
-                    const float2 cv = a.c[oc];
-                    const float2 rv = a.rho[orh];
-                    if constexpr (MODE == ROW_DERIV) {
-                        const float2 dr = a.drho[orh];
-                        z = cadd(cmul(dr, cv), cmul(rv, u));
-                    } else {  // ROW_ADJ
-                        a.aux[oc] = cconjmul(cv, u);
-                        z = cconjmul(rv, u);
-                    }
-                    z = cscale(z, sgn(pos));
-                }
+                const int f = a.plane_frame ? a.plane_frame[plane] : 0;
+                z = cscale(cmul(a.rho[((long long)f * m + i) * m + q], a.c[((long long)plane * m + i) * m + q]),
+                           CT::sign(pos));
             }
-            if constexpr (MODE != ROW_CACHE) tile[idx] = z;
+            bufB[idx] = z;
+        }
+        __syncthreads();
+    } else {
+        // inverse transform of the T rows: stage 1 from HBM
+        for (int t = threadIdx.x; t < L * N2; t += kThreads) {
+            const int ll = t / N2, j2 = t % N2;
+            const int line = line0 + ll;
+            float2 v[N1];
+            static_for<0, N1>([&](auto K) {
+                constexpr int k1 = K;
+                const int p = CT::in_pos(j2, k1);
+                v[k1] = line < a.nlines ? cscale(a.in[(long long)line * N + p], CT::sign(p)) : make_float2(0.f, 0.f);
+            });
+            RegDFT<N1, true>::run(v);
+            static_for<0, N1>([&](auto K) {
+                constexpr int k1 = K;
+                float2 x = v[k1];
+                if constexpr (k1 > 0) x = cmulc(x, a.tw2[k1 * N2 + j2]);
+                bufA[(ll * N1 + k1) * S2 + j2] = x;
+            });
+        }
+        __syncthreads();
+        // stage 2, crop to Omega columns, pointwise products, zero-pad into bufB
+        for (int t = threadIdx.x; t < L * N1; t += kThreads) {
+            const int ll = t / N1, k1 = t % N1;
+            const int line = line0 + ll;
+            float2 v[N2];
+            static_for<0, N2>([&](auto J) {
+                constexpr int j2 = J;
+                v[j2] = bufA[(ll * N1 + k1) * S2 + j2];
+            });
+            RegDFT<N2, true>::run(v);
+            const int plane = line / m, i = line % m;
+            const bool live = line < a.nlines;
+            const int f = (live && a.plane_frame) ? a.plane_frame[plane] : 0;
+            static_for<0, N2>([&](auto K) {
+                constexpr int k2 = K;
+                const int pos = CT::out_pos(k1, k2);
+                const int q = pos - lo;
+                float2 z = make_float2(0.f, 0.f);
+                if (live && q >= 0 && q < m) {
+                    const float2 u = cscale(v[k2], CT::sign(pos) * a.rs);
+                    const long long oc = ((long long)plane * m + i) * m + q;
+                    if constexpr (MODE == ROW_CACHE) {
+                        a.c_out[oc] = u;
+                    } else {
+                        const long long orh = ((long long)f * m + i) * m + q;
+                        const float2 cv = a.c[oc];
+                        const float2 rv = a.rho[orh];
+                        if constexpr (MODE == ROW_DERIV) {
+                            z = cadd(cmul(a.drho[orh], cv), cmul(rv, u));
+                        } else {  // ROW_ADJ
+                            a.aux[oc] = cconjmul(cv, u);
+                            z = cconjmul(rv, u);
+                        }
+                        z = cscale(z, CT::sign(pos));
+                    }
+                }
+                if constexpr (MODE != ROW_CACHE) bufB[ll * N + pos] = z;
+            });
         }
         if constexpr (MODE == ROW_CACHE) return;
         __syncthreads();
     }
-    fft_lines<N, L, 1, N, false>(tile, tw);
-    for (int idx = threadIdx.x; idx < L * N; idx += kThreads) {
-        const int l = idx / N, pos = idx % N;
-        const int line = line0 + l;
-        if (line < a.nlines) a.out[(long long)line * N + pos] = cscale(tile[idx], sgn(pos) * a.rs);
+    // forward transform of bufB: stage 1
+    for (int t = threadIdx.x; t < L * N2; t += kThreads) {
+        const int ll = t / N2, j2 = t % N2;
+        float2 v[N1];
+        static_for<0, N1>([&](auto K) {
+            constexpr int k1 = K;
+            v[k1] = bufB[ll * N + CT::in_pos(j2, k1)];
+        });
+        RegDFT<N1, false>::run(v);
+        static_for<0, N1>([&](auto K) {
+            constexpr int k1 = K;
+            float2 x = v[k1];
+            if constexpr (k1 > 0) x = cmul(x, a.tw2[k1 * N2 + j2]);
+            bufA[(ll * N1 + k1) * S2 + j2] = x;
+        });
+    }
+    __syncthreads();
+    // stage 2 to HBM
+    for (int t = threadIdx.x; t < L * N1; t += kThreads) {
+        const int ll = t / N1, k1 = t % N1;
+        const int line = line0 + ll;
+        if (line >= a.nlines) continue;
+        float2 v[N2];
+        static_for<0, N2>([&](auto J) {
+            constexpr int j2 = J;
+            v[j2] = bufA[(ll * N1 + k1) * S2 + j2];
+        });
+        RegDFT<N2, false>::run(v);
+        static_for<0, N2>([&](auto K) {
+            constexpr int k2 = K;
+            const int pos = CT::out_pos(k1, k2);
+            a.out[(long long)line * N + pos] = cscale(v[k2], CT::sign(pos) * a.rs);
+        });
     }
 }
 

@@ -35,7 +35,10 @@ def _create(n, n_om, J, a=220.0, l=32.0):
     lib = N.load()
     h = ctypes.c_void_p()
     d = (N.nlinv_dims * 1)(N.nlinv_dims(n, n_om, J, a, l))
-    return lib.nlinv_plan_create(ctypes.byref(h), d, 1)
+    st = lib.nlinv_plan_create(ctypes.byref(h), d, 1)
+    if st == N.NLINV_OK:
+        lib.nlinv_plan_destroy(h)
+    return st
 
 
 @pytest.mark.parametrize("n,n_om,J,code", [
@@ -62,3 +65,11 @@ def test_null_arguments():
     assert lib.nlinv_status_string(N.NLINV_EUNSUPPORTED) == b"unsupported size"
     assert lib.nlinv_kernel_class_name(-1) is None
     assert len(N.nlinv_kernel_class_names()) > 10
+
+
+@pytest.mark.parametrize("n", [8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024])
+def test_every_supported_size_passes_the_host_checks(n):
+    """Plan creation checks sizes and pass variants on the host before any
+    HIP call; a supported size gets past them (to NLINV_OK on a GPU, or to a
+    HIP error where there is none)."""
+    assert _create(n, n // 2, 4) in (N.NLINV_OK, N.NLINV_EHIP)
