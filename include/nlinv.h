@@ -202,6 +202,13 @@ int nlinv_plan_timing_enable(nlinv_plan plan, int32_t kclass, int32_t enable);
 int nlinv_plan_timing_read(nlinv_plan plan, int32_t* launches, double* total_ms);
 const char* nlinv_kernel_class_name(int32_t kclass);   /* NULL past the last */
 
+/* ---- measurement ----------------------------------------------------------
+ * Bandwidth probe: copy `bytes` (a multiple of 16) from src to dst (device,
+ * 16-byte aligned, not overlapping) with a plain streaming kernel.  It gives
+ * the practical HBM ceiling next to the 8 TB/s specification, and is the
+ * copy of known size that calibrates hardware traffic counters. */
+int nlinv_bandwidth_probe(const void* src, void* dst, size_t bytes, void* stream);
+
 const char* nlinv_status_string(int status);
 int nlinv_last_hip_error(void);
 

@@ -21,7 +21,7 @@ EXPORTED = (
     "nlinv_adjoint", "nlinv_normal", "nlinv_mask_gradient", "nlinv_image", "nlinv_irgnm_solve",
     "nlinv_irgnm_solve_batch", "nlinv_irgnm_solve_series", "nlinv_plan_autotune", "nlinv_plan_variant",
     "nlinv_plan_set_variant", "nlinv_plan_timing_enable", "nlinv_plan_timing_read",
-    "nlinv_kernel_class_name", "nlinv_status_string", "nlinv_last_hip_error",
+    "nlinv_kernel_class_name", "nlinv_status_string", "nlinv_last_hip_error", "nlinv_bandwidth_probe",
 )
 
 
@@ -84,6 +84,7 @@ def load(path: str | None = None):
         "nlinv_plan_timing_read": ([vp, C.POINTER(i32), C.POINTER(C.c_double)], C.c_int),
         "nlinv_kernel_class_name": ([i32], C.c_char_p),
         "nlinv_status_string": ([C.c_int], C.c_char_p),
+        "nlinv_bandwidth_probe": ([vp, vp, C.c_size_t, vp], C.c_int),
         "nlinv_last_hip_error": ([], C.c_int),
     }
     for name, (args, res) in sig.items():
@@ -278,3 +279,9 @@ def nlinv_plan_timing_read(plan):
     n, ms = C.c_int32(), C.c_double()
     check(load().nlinv_plan_timing_read(plan, C.byref(n), C.byref(ms)), "nlinv_plan_timing_read")
     return n.value, ms.value
+
+
+def nlinv_bandwidth_probe(src, dst, nbytes=None, stream=None):
+    nbytes = src.numel() * src.element_size() if nbytes is None else int(nbytes)
+    check(load().nlinv_bandwidth_probe(_ptr(src, None, "src"), _ptr(dst, None, "dst"), nbytes, _stream(stream)),
+          "nlinv_bandwidth_probe")

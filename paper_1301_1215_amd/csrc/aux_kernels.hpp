@@ -9,91 +9,10 @@
 namespace nlinv {
 
 // ---------------------------------------------------------------------------
-// coil sums over the planes of each frame (fixed order: deterministic)
-// ---------------------------------------------------------------------------
-
-// out[f][e] = sum_{p in f} aux[p][e] + s1_f add1[f][e] + s2_f add2[f][e]
-// One workgroup per (frame, segment of `seg_len` elements); with `partial`
-// set it also writes Re<add1, out> of its segment to partial[poff + f*segs + k].
-struct CoilSumArgs {
-    const float2* aux;       // [planes][E]
-    float2* out;             // [frames][E]
-    const float2* add1;
-    const float2* add2;
-    const float* s1;
-    const float* s2;
-    float c1, c2;
-    const int* frame_plane0; // nullable: single frame with `nplanes` planes
-    const int* frame_planes;
-    int nplanes;
-    int nframes;
-    int E;                   // elements per frame (m*m)
-    int segs, seg_len;
-    double* partial;
-    long long poff;
-};
-
-__global__ __launch_bounds__(kThreads) void k_coil_sum(CoilSumArgs a) {
-    __shared__ double red[4];
-    const int f = blockIdx.x / a.segs, k = blockIdx.x % a.segs;
-    const int e0 = k * a.seg_len, e1 = min(a.E, e0 + a.seg_len);
-    const int p0 = a.frame_plane0 ? a.frame_plane0[f] : 0;
-    const int np = a.frame_planes ? a.frame_planes[f] : a.nplanes;
-    const float s1 = a.s1 ? a.s1[f] : a.c1;
-    const float s2 = a.s2 ? a.s2[f] : a.c2;
-    double acc = 0.0;
-    for (int e = e0 + threadIdx.x; e < e1; e += kThreads) {
-        const long long g = (long long)f * a.E + e;
-        float2 s = make_float2(0.f, 0.f);
-        for (int p = 0; p < np; ++p) s = cadd(s, a.aux[(long long)(p0 + p) * a.E + e]);
-        if (a.add1) { const float2 u = a.add1[g]; s.x += s1 * u.x; s.y += s1 * u.y; }
-        if (a.add2) { const float2 u = a.add2[g]; s.x += s2 * u.x; s.y += s2 * u.y; }
-        a.out[g] = s;
-        if (a.partial && a.add1) { const float2 u = a.add1[g]; acc += (double)(u.x * s.x + u.y * s.y); }
-    }
-    if (a.partial) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-        __syncthreads();
-        if (threadIdx.x == 0) a.partial[a.poff + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
-    }
-}
-
-// gP[f][e] = sum_{p in f} gprod[p][e]   (real)
-__global__ __launch_bounds__(kThreads) void k_coil_sum_real(const float* gprod, float* out, int nplanes, int E) {
-    for (int e = blockIdx.x * kThreads + threadIdx.x; e < E; e += gridDim.x * kThreads) {
-        float s = 0.f;
-        for (int p = 0; p < nplanes; ++p) s += gprod[(long long)p * E + e];
-        out[e] = s;
-    }
-}
-
-// image[f][e] = rho[f][e] . sqrt(sum_{p in f} |c[p][e]|^2) * inv_s[f]
-__global__ __launch_bounds__(kThreads) void k_image(const float2* rho, const float2* c, float2* img,
-                                                    const int* frame_plane0, const int* frame_planes,
-                                                    int nplanes, int nframes, int E, const float* inv_s) {
-    const long long tot = (long long)nframes * E;
-    for (long long g = (long long)blockIdx.x * kThreads + threadIdx.x; g < tot;
-         g += (long long)gridDim.x * kThreads) {
-        const int f = (int)(g / E), e = (int)(g % E);
-        const int p0 = frame_plane0 ? frame_plane0[f] : 0;
-        const int np = frame_planes ? frame_planes[f] : nplanes;
-        float s = 0.f;
-        for (int p = 0; p < np; ++p) {
-            const float2 v = c[(long long)(p0 + p) * E + e];
-            s += v.x * v.x + v.y * v.y;
-        }
-        const float sc = sqrtf(s) * (inv_s ? inv_s[f] : 1.0f);
-        img[g] = cscale(rho[g], sc);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// segmented vector kernels over the two parts of a class-wide CG vector:
+// segment geometry of a class-wide CG vector:
 //   chat part [planes][n*n] in `cseg` segments per plane,
-//   rho part  [frames][m*m] in `rseg` segments per frame.
-// One workgroup per segment; reductions give one FP64 partial per segment.
+//   rho part  [frames][m*m] in `rseg` segments per frame;
+// one FP64 partial per segment, summed per frame in a fixed order.
 // ---------------------------------------------------------------------------
 
 struct SegGeom {
@@ -125,8 +44,9 @@ __device__ __forceinline__ void seg_locate(const SegGeom& g, int s, bool& is_c, 
     }
 }
 
+// Sum over a 256-thread workgroup in a fixed order (wavefront shuffle, then
+// the 4 waves); the result is valid in thread 0.
 __device__ __forceinline__ double block_sum(double v, double* red) {
-    // wavefront reduce then across the 4 waves, fixed order
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -134,8 +54,200 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     __syncthreads();
     double t = 0.0;
     if (threadIdx.x == 0) t = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
     return t;
 }
+
+// Partials are read with device-coherent loads: the last workgroup of a
+// kernel reads what the others wrote in the same launch.
+__device__ __forceinline__ double load_partial(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Fixed-order total of frame f: the chat segments of its planes (plane
+// order), then its rho segments.  All threads call it; valid in thread 0.
+__device__ __forceinline__ double frame_total(const SegGeom& g, const double* partial, int f,
+                                              const int* frame_plane0, const int* frame_planes,
+                                              double* red) {
+    const int p0 = frame_plane0 ? frame_plane0[f] : 0;
+    const int np = frame_planes ? frame_planes[f] : g.nplanes;
+    const int nc = np * g.cseg;
+    const int tot = nc + g.rseg;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < tot; i += kThreads) {
+        acc += (i < nc) ? load_partial(partial + (long long)p0 * g.cseg + i)
+                        : load_partial(partial + (long long)g.nplanes * g.cseg + (long long)f * g.rseg + (i - nc));
+    }
+    return block_sum(acc, red);
+}
+
+// CG and Newton scalars of every frame of a class, all on the device.
+struct Scalars {
+    double* rr;        // [F] <r, r>
+    float* a;          // [F] CG step a = rr / gamma
+    float* beta;       // [F]
+    int* brk;          // [F] breakdown in the current Newton step
+    float* alpha;      // [F] current alpha (and -alpha at alpha + F)
+    float* s;          // [F] data scale
+    float* inv_s;      // [F]
+    double* stats;     // [F][stats_len]
+    int stats_len;
+};
+
+enum ScalarOp : int {
+    SC_NONE = -1,
+    SC_YNORM = 0,      // s = scale_norm / ||y|| (scale_norm > 0 and ||y|| > 0), else 1
+    SC_R0NORM = 1,     // stats[2 + step] = ||r0||
+    SC_RR0 = 2,        // rr = <b, b>; new Newton step: clear breakdown
+    SC_GAMMA = 3,      // gamma = Re<p, q>; a = rr / gamma or breakdown
+    SC_RR = 4,         // rr' = <r, r>; beta = rr'/rr; rr = rr'; stats of CG iteration `it`
+};
+
+// Where a scalar op is applied: which op, geometry of its partials, indices
+// for the stats.
+struct ScalarStep {
+    int op;
+    SegGeom g;
+    const double* partial;
+    const int* frame_plane0;
+    const int* frame_planes;
+    float scale_norm;
+    int step, it, nsteps, ncg;
+};
+
+// The scalar logic for frame f given the total t (thread 0 only).
+__device__ __forceinline__ void scalar_apply(const ScalarStep& ss, const Scalars& sc, int f, double t) {
+    double* st = sc.stats + (long long)f * sc.stats_len;
+    const int op = ss.op;
+    if (op == SC_YNORM) {
+        const double nrm = sqrt(t);
+        const float s = (ss.scale_norm > 0.f && nrm > 0.0) ? (float)(ss.scale_norm / nrm) : 1.0f;
+        sc.s[f] = s;
+        sc.inv_s[f] = 1.0f / s;
+        st[0] = (double)s;
+        st[1] = 0.0;
+        if (!isfinite(nrm)) st[1] = 2.0;
+    } else if (op == SC_R0NORM) {
+        st[2 + ss.step] = sqrt(t);
+        if (!isfinite(t)) st[1] = (double)((int)st[1] | 2);
+    } else if (op == SC_RR0) {
+        sc.rr[f] = t;
+        sc.brk[f] = 0;
+    } else if (op == SC_GAMMA) {
+        const double rr = sc.rr[f];
+        if (sc.brk[f] || rr == 0.0 || !(t > 0.0) || !isfinite(rr)) {
+            if (!sc.brk[f]) {
+                int fl = (int)st[1] | 1;
+                if (!isfinite(t) || !isfinite(rr)) fl |= 2;
+                st[1] = (double)fl;
+            }
+            sc.brk[f] = 1;
+            sc.a[f] = 0.f;
+        } else {
+            sc.a[f] = (float)(rr / t);
+        }
+    } else if (op == SC_RR) {
+        double* slot = st + 2 + ss.nsteps + ss.step * ss.ncg + ss.it;
+        if (sc.brk[f]) {
+            sc.beta[f] = 0.f;
+            *slot = -1.0;
+        } else {
+            if (!isfinite(t)) st[1] = (double)((int)st[1] | 2);
+            sc.beta[f] = (float)(t / sc.rr[f]);
+            sc.rr[f] = t;
+            *slot = t;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// coil sums over the planes of each frame (fixed order: deterministic)
+// ---------------------------------------------------------------------------
+
+// out[f][e] = sum_{p in f} aux[p][e] + s1_f add1[f][e] + s2_f add2[f][e]
+// One thread per Omega pixel, one workgroup per (frame, segment of
+// `seg_len` pixels); with `partial` set it also writes Re<add1, out> of its
+// segment to partial[poff + f*segs + k].
+struct CoilSumArgs {
+    const float2* aux;       // [planes][E]
+    float2* out;             // [frames][E]
+    const float2* add1;
+    const float2* add2;
+    const float* s1;
+    const float* s2;
+    float c1, c2;
+    const int* frame_plane0; // nullable: single frame with `nplanes` planes
+    const int* frame_planes;
+    int nplanes;
+    int nframes;
+    int E;                   // elements per frame (m*m)
+    int segs, seg_len;       // seg_len <= kThreads
+    double* partial;
+    long long poff;
+};
+
+__global__ __launch_bounds__(kThreads) void k_coil_sum(CoilSumArgs a) {
+    __shared__ double red[4];
+    const int f = blockIdx.x / a.segs, k = blockIdx.x % a.segs;
+    const int e = k * a.seg_len + threadIdx.x;
+    const int p0 = a.frame_plane0 ? a.frame_plane0[f] : 0;
+    const int np = a.frame_planes ? a.frame_planes[f] : a.nplanes;
+    double acc = 0.0;
+    if (threadIdx.x < a.seg_len && e < a.E) {
+        const long long g = (long long)f * a.E + e;
+        const float2* src = a.aux + (long long)p0 * a.E + e;
+        float2 s0 = make_float2(0.f, 0.f), s1 = s0;
+        int p = 0;
+        for (; p + 1 < np; p += 2) {     // two independent chains, combined in a fixed order
+            s0 = cadd(s0, src[(long long)p * a.E]);
+            s1 = cadd(s1, src[(long long)(p + 1) * a.E]);
+        }
+        if (p < np) s0 = cadd(s0, src[(long long)p * a.E]);
+        float2 s = cadd(s0, s1);
+        const float c1 = a.s1 ? a.s1[f] : a.c1;
+        const float c2 = a.s2 ? a.s2[f] : a.c2;
+        if (a.add1) { const float2 u = a.add1[g]; s.x += c1 * u.x; s.y += c1 * u.y; }
+        if (a.add2) { const float2 u = a.add2[g]; s.x += c2 * u.x; s.y += c2 * u.y; }
+        a.out[g] = s;
+        if (a.partial && a.add1) { const float2 u = a.add1[g]; acc = (double)(u.x * s.x + u.y * s.y); }
+    }
+    if (a.partial) {
+        const double t = block_sum(acc, red);
+        if (threadIdx.x == 0) a.partial[a.poff + blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_coil_sum_real(const float* gprod, float* out, int nplanes, int E) {
+    for (int e = blockIdx.x * kThreads + threadIdx.x; e < E; e += gridDim.x * kThreads) {
+        float s = 0.f;
+        for (int p = 0; p < nplanes; ++p) s += gprod[(long long)p * E + e];
+        out[e] = s;
+    }
+}
+
+// image[f][e] = rho[f][e] . sqrt(sum_{p in f} |c[p][e]|^2) * inv_s[f]
+__global__ __launch_bounds__(kThreads) void k_image(const float2* rho, const float2* c, float2* img,
+                                                    const int* frame_plane0, const int* frame_planes,
+                                                    int nplanes, int nframes, int E, const float* inv_s) {
+    const long long tot = (long long)nframes * E;
+    for (long long g = (long long)blockIdx.x * kThreads + threadIdx.x; g < tot;
+         g += (long long)gridDim.x * kThreads) {
+        const int f = (int)(g / E), e = (int)(g % E);
+        const int p0 = frame_plane0 ? frame_plane0[f] : 0;
+        const int np = frame_planes ? frame_planes[f] : nplanes;
+        float s = 0.f;
+        for (int p = 0; p < np; ++p) {
+            const float2 v = c[(long long)(p0 + p) * E + e];
+            s += v.x * v.x + v.y * v.y;
+        }
+        const float sc = sqrtf(s) * (inv_s ? inv_s[f] : 1.0f);
+        img[g] = cscale(rho[g], sc);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// CG vector kernels: one workgroup per segment of the class-wide vector
+// ---------------------------------------------------------------------------
 
 struct VecPtrs {
     float2* c0; float2* c1; float2* c2; float2* c3;   // chat parts
@@ -148,9 +260,15 @@ enum VecOp : int {
     VEC_ADD = 2,        // v0 += v1
 };
 
+// VEC_XR_UPDATE with gamma.op == SC_GAMMA: every workgroup first sums the
+// Re<p, q> partials of its frame (written by the previous kernels) in the
+// fixed order and applies the CG step logic itself, so no separate scalar
+// launch is needed; the first workgroup of each frame records a, the
+// breakdown flag and the stats.  All workgroups of a frame compute the same a.
 template <int OP>
 __global__ __launch_bounds__(kThreads) void k_vec(SegGeom g, VecPtrs v, const float* a_f,
-                                                  const float* b_f, double* partial) {
+                                                  const float* b_f, double* partial, ScalarStep gamma,
+                                                  Scalars sc) {
     __shared__ double red[4];
     bool is_c; int owner, f, len; long long base;
     seg_locate(g, blockIdx.x, is_c, owner, f, base, len);
@@ -164,8 +282,23 @@ __global__ __launch_bounds__(kThreads) void k_vec(SegGeom g, VecPtrs v, const fl
     float4* y3 = reinterpret_cast<float4*>(x3 + base);
     const int n4 = len / 2;
     double acc = 0.0;
-    const float av = a_f ? a_f[f] : 0.f;
+    float av = a_f ? a_f[f] : 0.f;
     (void)b_f;
+    if constexpr (OP == VEC_XR_UPDATE) {
+        if (gamma.op == SC_GAMMA) {
+            __shared__ float a_sh;
+            const double t = frame_total(gamma.g, gamma.partial, f, gamma.frame_plane0, gamma.frame_planes, red);
+            if (threadIdx.x == 0) {
+                const double rr = sc.rr[f];
+                const bool brk = sc.brk[f] || rr == 0.0 || !(t > 0.0) || !isfinite(rr);
+                a_sh = brk ? 0.f : (float)(rr / t);
+                const int p0 = gamma.frame_plane0 ? gamma.frame_plane0[f] : 0;
+                if (is_c && owner == p0 && blockIdx.x % g.cseg == 0) scalar_apply(gamma, sc, f, t);
+            }
+            __syncthreads();
+            av = a_sh;
+        }
+    }
     for (int i = threadIdx.x; i < n4; i += kThreads) {
         if constexpr (OP == VEC_DOT) {
             const float4 p = y0[i], q = y1[i];
@@ -193,91 +326,12 @@ __global__ __launch_bounds__(kThreads) void k_vec(SegGeom g, VecPtrs v, const fl
     }
 }
 
-// Sum the partials of each frame in a fixed order: the chat segments of its
-// planes (plane order), then its rho segments.  One workgroup per frame.
-__device__ __forceinline__ double frame_total(const SegGeom& g, const double* partial, int f,
-                                              const int* frame_plane0, const int* frame_planes,
-                                              double* red) {
-    const int p0 = frame_plane0 ? frame_plane0[f] : 0;
-    const int np = frame_planes ? frame_planes[f] : g.nplanes;
-    const int nc = np * g.cseg;
-    const int tot = nc + g.rseg;
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < tot; i += kThreads) {
-        acc += (i < nc) ? partial[p0 * g.cseg + i]
-                        : partial[g.nplanes * g.cseg + f * g.rseg + (i - nc)];
-    }
-    return block_sum(acc, red);
-}
-
-// CG and Newton scalars of every frame of a class, all on the device.
-struct Scalars {
-    double* rr;        // [F] <r, r>
-    float* a;          // [F] CG step a = rr / gamma
-    float* beta;       // [F]
-    int* brk;          // [F] breakdown in the current Newton step
-    float* alpha;      // [F] current alpha (and -alpha at alpha + F)
-    float* s;          // [F] data scale
-    float* inv_s;      // [F]
-    double* stats;     // [F][stats_len]
-    int stats_len;
-};
-
-enum ScalarOp : int {
-    SC_YNORM = 0,      // s = scale_norm / ||y|| (scale_norm > 0 and ||y|| > 0), else 1
-    SC_R0NORM = 1,     // stats[2 + step] = ||r0||
-    SC_RR0 = 2,        // rr = <b, b>; new Newton step: clear breakdown
-    SC_GAMMA = 3,      // gamma = Re<p, q>; a = rr / gamma or breakdown
-    SC_RR = 4,         // rr' = <r, r>; beta = rr'/rr; rr = rr'; stats of CG iteration `it`
-};
-
-__global__ __launch_bounds__(kThreads) void k_scalar(int op, SegGeom g, const double* partial,
-                                                     const int* frame_plane0, const int* frame_planes,
-                                                     Scalars sc, float scale_norm, int step, int it,
-                                                     int nsteps, int ncg) {
+// One workgroup per frame: total of its partials, then the scalar step.
+__global__ __launch_bounds__(kThreads) void k_scalar(ScalarStep ss, Scalars sc) {
     __shared__ double red[4];
     const int f = blockIdx.x;
-    const double t = frame_total(g, partial, f, frame_plane0, frame_planes, red);
-    if (threadIdx.x != 0) return;
-    double* st = sc.stats + (long long)f * sc.stats_len;
-    if (op == SC_YNORM) {
-        const double nrm = sqrt(t);
-        const float s = (scale_norm > 0.f && nrm > 0.0) ? (float)(scale_norm / nrm) : 1.0f;
-        sc.s[f] = s;
-        sc.inv_s[f] = 1.0f / s;
-        st[0] = (double)s;
-        st[1] = 0.0;
-        if (!isfinite(nrm)) st[1] = 2.0;
-    } else if (op == SC_R0NORM) {
-        st[2 + step] = sqrt(t);
-        if (!isfinite(t)) st[1] = (double)((int)st[1] | 2);
-    } else if (op == SC_RR0) {
-        sc.rr[f] = t;
-        sc.brk[f] = 0;
-    } else if (op == SC_GAMMA) {
-        const double rr = sc.rr[f];
-        if (sc.brk[f] || rr == 0.0 || !(t > 0.0) || !isfinite(rr)) {
-            if (!sc.brk[f]) {
-                int fl = (int)st[1] | 1;
-                if (!isfinite(t) || !isfinite(rr)) fl |= 2;
-                st[1] = (double)fl;
-            }
-            sc.brk[f] = 1;
-            sc.a[f] = 0.f;
-        } else {
-            sc.a[f] = (float)(rr / t);
-        }
-    } else if (op == SC_RR) {
-        if (sc.brk[f]) {
-            sc.beta[f] = 0.f;
-            st[2 + nsteps + step * ncg + it] = -1.0;
-        } else {
-            if (!isfinite(t)) st[1] = (double)((int)st[1] | 2);
-            sc.beta[f] = (float)(t / sc.rr[f]);
-            sc.rr[f] = t;
-            st[2 + nsteps + step * ncg + it] = t;
-        }
-    }
+    const double t = frame_total(ss.g, ss.partial, f, ss.frame_plane0, ss.frame_planes, red);
+    if (threadIdx.x == 0) scalar_apply(ss, sc, f, t);
 }
 
 // per-frame: alpha[f] = value, alpha[F + f] = -value
@@ -314,6 +368,14 @@ __global__ __launch_bounds__(kThreads) void k_tile(const T* src, T* dst, int npl
         if (to_tiled) dst[t] = src[g];
         else dst[g] = src[t];
     }
+}
+
+// Bandwidth probe: a plain 16-byte-per-thread streaming copy (the practical
+// HBM ceiling, and the known-size copy that calibrates traffic counters).
+__global__ __launch_bounds__(kThreads) void k_stream_copy(const float4* __restrict__ src,
+                                                          float4* __restrict__ dst, long long n16) {
+    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n16; i += (long long)gridDim.x * kThreads)
+        dst[i] = src[i];
 }
 
 __global__ __launch_bounds__(kThreads) void k_fill(float2* x, long long n, float2 v) {

@@ -11,7 +11,7 @@ template <int N, int L>
 static hipError_t col_L(int mode, const ColArgs& a, int nplanes, hipStream_t s) {
     // 1D grid, a multiple of 8 blocks: the kernel deals work items to XCDs
     const int total = (N / L) * nplanes;
-    const dim3 grid(8 * ((total + 7) / 8)), block(kThreads);
+    const dim3 grid(8 * ((total + 7) / 8)), block(pass_threads(N, L));
     switch (mode) {
         case COL_WINV_IFFT_CROP: hipLaunchKernelGGL((k_col<N, L, COL_WINV_IFFT_CROP>), grid, block, 0, s, a); break;
         case COL_P_IFFT_CROP: hipLaunchKernelGGL((k_col<N, L, COL_P_IFFT_CROP>), grid, block, 0, s, a); break;
@@ -29,7 +29,7 @@ static hipError_t col_L(int mode, const ColArgs& a, int nplanes, hipStream_t s) 
 
 template <int N, int L>
 static hipError_t row_L(int mode, const RowArgs& a, hipStream_t s) {
-    const dim3 grid((a.nlines + L - 1) / L), block(kThreads);
+    const dim3 grid((a.nlines + L - 1) / L), block(pass_threads(N, L));
     switch (mode) {
         case ROW_CACHE: hipLaunchKernelGGL((k_row<N, L, ROW_CACHE>), grid, block, 0, s, a); break;
         case ROW_FWD: hipLaunchKernelGGL((k_row<N, L, ROW_FWD>), grid, block, 0, s, a); break;

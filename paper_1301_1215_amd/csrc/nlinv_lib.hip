@@ -45,7 +45,7 @@ constexpr int kMaxNewton = 32;
 constexpr int kMaxCG = 256;
 constexpr int kStatsCap = 2 + kMaxNewton + kMaxNewton * kMaxCG;
 constexpr int kSegLen = 4096;        // complex elements per reduction segment
-constexpr int kCoilSeg = 512;        // Omega pixels per coil-sum workgroup
+constexpr int kCoilSeg = kThreads;   // Omega pixels per coil-sum workgroup (one per thread)
 constexpr int kColModes = 9;         // ColMode values
 constexpr int kRowModes = 4;         // RowMode values
 constexpr int kTimingSlots = 8192;   // event pairs for kernel timing
@@ -141,6 +141,7 @@ struct Class {
     float* P = nullptr;
     float2 *c = nullptr, *T = nullptr, *aux = nullptr;
     double* partial = nullptr;
+    double* partial2 = nullptr;  // <r,r> partials of the x/r update (it reads Re<p,q> from `partial`)
     float* alpha = nullptr;      // [2F]: alpha, -alpha
     SegGeom geom{}, geomC{};
     Scalars sc{};
@@ -329,23 +330,45 @@ int run_coil_sum(nlinv_plan_s* p, const CoilSumArgs& a, hipStream_t s) {
     return NLINV_OK;
 }
 
+ScalarStep no_fold() {
+    ScalarStep f{};
+    f.op = SC_NONE;
+    return f;
+}
+
 template <int OP>
 int run_vec(nlinv_plan_s* p, const SegGeom& g, const VecPtrs& v, const float* a_f, const float* b_f,
-            double* partial, hipStream_t s) {
+            double* partial, hipStream_t s, const ScalarStep& gamma = no_fold(), const Scalars& sc = Scalars{}) {
     const int kc = OP == VEC_DOT ? KC_VEC_DOT : OP == VEC_XR_UPDATE ? KC_VEC_XR : KC_VEC_OTHER;
     const int slot = tbegin(p, kc, s);
-    hipLaunchKernelGGL((k_vec<OP>), dim3(nseg(g)), dim3(kThreads), 0, s, g, v, a_f, b_f, partial);
+    hipLaunchKernelGGL((k_vec<OP>), dim3(nseg(g)), dim3(kThreads), 0, s, g, v, a_f, b_f, partial, gamma, sc);
     hipError_t e = hipGetLastError();
     tend(p, slot, s);
     HIPCHK(e);
     return NLINV_OK;
 }
 
+ScalarStep scalar_step(const Class& C, int op, const SegGeom& g, float scale_norm, int step, int it = 0,
+                       int nsteps = 0, int ncg = 0, const double* partial = nullptr) {
+    ScalarStep ss{};
+    ss.op = op;
+    ss.g = g;
+    ss.partial = partial ? partial : C.partial;
+    ss.frame_plane0 = C.frame_plane0;
+    ss.frame_planes = C.frame_planes;
+    ss.scale_norm = scale_norm;
+    ss.step = step;
+    ss.it = it;
+    ss.nsteps = nsteps;
+    ss.ncg = ncg;
+    return ss;
+}
+
 int run_scalar(nlinv_plan_s* p, Class& C, int op, const SegGeom& g, float scale_norm, int step,
-               hipStream_t s, int it = 0, int nsteps = 0, int ncg = 0) {
+               hipStream_t s, int it = 0, int nsteps = 0, int ncg = 0, const double* partial = nullptr) {
     const int slot = tbegin(p, KC_SCALAR, s);
-    hipLaunchKernelGGL(k_scalar, dim3(C.nframes), dim3(kThreads), 0, s, op, g, C.partial,
-                       C.frame_plane0, C.frame_planes, C.sc, scale_norm, step, it, nsteps, ncg);
+    hipLaunchKernelGGL(k_scalar, dim3(C.nframes), dim3(kThreads), 0, s,
+                       scalar_step(C, op, g, scale_norm, step, it, nsteps, ncg, partial), C.sc);
     hipError_t e = hipGetLastError();
     tend(p, slot, s);
     HIPCHK(e);
@@ -540,6 +563,7 @@ int seq_normal_cg(nlinv_plan_s* p, Class& C, const float* beta, SegGeom& g, hipS
     CoilSumArgs cs = coil_sum_args(C, fr, C.q_r, C.p_r, nullptr, C.alpha, nullptr, 0.f, 0.f, C.partial,
                                    (long long)C.nplanes * ntiles);
     CHK(run_coil_sum(p, cs, s));
+    // geometry of the Re<p, q> partials: column tiles per plane, coil-sum segments per frame
     g = C.geom;
     g.cseg = ntiles;
     g.clen = 0;
@@ -617,10 +641,11 @@ int enqueue_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s
             for (Class& C : p->classes) {
                 SegGeom g{};
                 CHK(seq_normal_cg(p, C, it == 0 ? nullptr : C.sc.beta, g, s));
-                CHK(run_scalar(p, C, SC_GAMMA, g, 0.f, step, s));
+                // a = <r,r> / Re<p,q> in every workgroup, then dx += a p, r -= a q, <r,r> partials
                 CHK(run_vec<VEC_XR_UPDATE>(p, C.geom, vptrs(C.dx_c, C.dx_r, C.p_c, C.p_r, C.r_c, C.r_r, C.q_c, C.q_r),
-                                           C.sc.a, nullptr, C.partial, s));
-                CHK(run_scalar(p, C, SC_RR, C.geom, 0.f, step, s, it, N, K));
+                                           nullptr, nullptr, C.partial2, s, scalar_step(C, SC_GAMMA, g, 0.f, step),
+                                           C.sc));
+                CHK(run_scalar(p, C, SC_RR, C.geom, 0.f, step, s, it, N, K, C.partial2));
             }
         }
         for (Class& C : p->classes)
@@ -881,6 +906,7 @@ int build_class(nlinv_plan_s* p, Class& C) {
     const size_t tiles = (size_t)C.nplanes * (C.n / 4) + (size_t)C.nframes * ((rn + kCoilSeg - 1) / kCoilSeg);
     CHK(dalloc(p, &C.partial, std::max<size_t>(tiles, (size_t)std::max(nseg(C.geom), nseg(C.geomC)))));
     CHK(dalloc(p, &C.alpha, (size_t)2 * C.nframes));
+    CHK(dalloc(p, &C.partial2, (size_t)nseg(C.geom)));
     CHK(dalloc(p, &C.sc.rr, C.nframes));
     CHK(dalloc(p, &C.sc.a, C.nframes));
     CHK(dalloc(p, &C.sc.beta, C.nframes));
@@ -1048,6 +1074,17 @@ const char* nlinv_status_string(int status) {
 }
 
 int nlinv_last_hip_error(void) { return g_last_hip; }
+
+int nlinv_bandwidth_probe(const void* src, void* dst, size_t bytes, void* stream) {
+    if (!src || !dst || !aligned(src) || !aligned(dst) || (bytes & 15)) return NLINV_EINVAL;
+    const long long n16 = (long long)(bytes / 16);
+    const int blocks = (int)std::min<long long>((n16 + kThreads - 1) / kThreads, 8 * 256 * 8);
+    if (n16 == 0) return NLINV_OK;
+    hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(kThreads), 0, (hipStream_t)stream,
+                       (const float4*)src, (float4*)dst, n16);
+    HIPCHK(hipGetLastError());
+    return NLINV_OK;
+}
 
 const char* nlinv_kernel_class_name(int32_t kclass) {
     if (kclass < 0 || kclass >= KC_NUM) return nullptr;

@@ -58,6 +58,14 @@ __device__ __forceinline__ long long big_idx(int r, int col, int tiled) {
     return tiled ? ((long long)(col / TW) * N + r) * TW + (col % TW) : (long long)r * N + col;
 }
 
+// Threads of a pass workgroup over L lines: enough for one task per thread in
+// the larger of the two FFT stages (L*N1 or L*N2 tasks), in whole wavefronts.
+constexpr int pass_threads(int n, int L) {
+    const int n1 = split_n1(n), n2 = n / n1;
+    const int t = L * (n1 > n2 ? n1 : n2);
+    return ((t + 63) / 64) * 64;
+}
+
 // ---------------------------------------------------------------------------
 // column passes: a workgroup transforms L adjacent columns of one plane
 // ---------------------------------------------------------------------------
@@ -117,7 +125,8 @@ __device__ __forceinline__ bool col_item(int ntiles, int nplanes, int& tile, int
 }
 
 template <int N, int L, int MODE>
-__global__ __launch_bounds__(kThreads) void k_col(ColArgs a) {
+__global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
+    constexpr int NT = pass_threads(N, L);
     using CT = Centre<N>;
     constexpr int N1 = CT::N1, N2 = CT::N2;
     constexpr bool TWO = (MODE == COL_PAD_FFT_P2_IFFT);
@@ -128,9 +137,9 @@ __global__ __launch_bounds__(kThreads) void k_col(ColArgs a) {
     constexpr bool OUT_CROP = INV1 || TWO;
     constexpr bool DOT = (MODE == COL_PAD_FFT_WINV_AXPY_DOT);
     constexpr bool WINV_OUT = (MODE == COL_PAD_FFT_WINV_ADD) || DOT;
-    __shared__ float2 bufA[N * L];                 // stage-1 results, [k1][j2][l]
-    __shared__ float2 bufB[TWO ? N * L : 1];       // slot order [slot][l] between two transforms
-    __shared__ double red[DOT ? kThreads / 64 : 1];
+    __shared__ float2 bufA[N * L];                 // stage-1 results [k1][j2][l]; slot order [slot][l]
+    __shared__ double red[DOT ? NT / 64 : 1];
+    static_assert(NT % 64 == 0 && NT <= 1024, "pass workgroup size");
 
     int tile, plane;
     if (!col_item(N / L, a.nplanes, tile, plane)) return;
@@ -150,7 +159,7 @@ __global__ __launch_bounds__(kThreads) void k_col(ColArgs a) {
             const float bf = a.beta ? a.beta[f] : 0.f;
             float2* pr = a.pr + (long long)f * E;
             const float2* rr = a.rr + (long long)f * E;
-            for (int e = e0 + threadIdx.x; e < e1; e += kThreads) {
+            for (int e = e0 + threadIdx.x; e < e1; e += NT) {
                 const float2 r = rr[e];
                 pr[e] = a.beta ? make_float2(r.x + bf * pr[e].x, r.y + bf * pr[e].y) : r;
             }
@@ -158,7 +167,7 @@ __global__ __launch_bounds__(kThreads) void k_col(ColArgs a) {
     }
 
     // ---- stage 1 of the first transform: positions in_pos(j2, k1) straight from HBM
-    for (int t = threadIdx.x; t < L * N2; t += kThreads) {
+    for (int t = threadIdx.x; t < L * N2; t += NT) {
         const int l = t % L, j2 = t / L, col = col0 + l;
         float2 v[N1];
         static_for<0, N1>([&](auto K) {
@@ -205,40 +214,63 @@ __global__ __launch_bounds__(kThreads) void k_col(ColArgs a) {
     __syncthreads();
 
     if constexpr (TWO) {
+        // Every stage has at most one task per thread, so the intermediate
+        // stays in bufA: read into registers, barrier, write back.
+        static_assert(L * N1 <= NT && L * N2 <= NT, "one task per thread");
         // stage 2 of the forward transform, times P^2 and 1/n at each output
         // position, kept in slot order (the inverse reads the same slots)
         const float rs2 = a.rs * a.rs;
-        for (int t = threadIdx.x; t < L * N1; t += kThreads) {
+        {
+            const int t = threadIdx.x;
+            const bool act = t < L * N1;
             const int l = t % L, k1 = t / L, col = col0 + l;
             float2 v[N2];
-            static_for<0, N2>([&](auto J) {
-                constexpr int j2 = J;
-                v[j2] = bufA[(k1 * N2 + j2) * L + l];
-            });
-            RegDFT<N2, false>::run(v);
-            static_for<0, N2>([&](auto K) {
-                constexpr int k2 = K;
-                const int r = CT::out_pos(k1, k2);
-                const float p = P[big_idx<N>(r, col, a.tiled)];
-                bufB[(k1 + N1 * k2) * L + l] = cscale(v[k2], p * p * rs2);
-            });
+            if (act) {
+                static_for<0, N2>([&](auto J) {
+                    constexpr int j2 = J;
+                    v[j2] = bufA[(k1 * N2 + j2) * L + l];
+                });
+                RegDFT<N2, false>::run(v);
+                static_for<0, N2>([&](auto K) {
+                    constexpr int k2 = K;
+                    const int r = CT::out_pos(k1, k2);
+                    const float p = P[big_idx<N>(r, col, a.tiled)];
+                    v[k2] = cscale(v[k2], p * p * rs2);
+                });
+            }
+            __syncthreads();
+            if (act) {
+                static_for<0, N2>([&](auto K) {
+                    constexpr int k2 = K;
+                    bufA[(k1 + N1 * k2) * L + l] = v[k2];
+                });
+            }
         }
         __syncthreads();
-        // stage 1 of the inverse transform, slots j2 + N2 k1 of bufB
-        for (int t = threadIdx.x; t < L * N2; t += kThreads) {
+        // stage 1 of the inverse transform, slots j2 + N2 k1
+        {
+            const int t = threadIdx.x;
+            const bool act = t < L * N2;
             const int l = t % L, j2 = t / L;
             float2 v[N1];
-            static_for<0, N1>([&](auto K) {
-                constexpr int k1 = K;
-                v[k1] = bufB[(j2 + N2 * k1) * L + l];
-            });
-            RegDFT<N1, true>::run(v);
-            static_for<0, N1>([&](auto K) {
-                constexpr int k1 = K;
-                float2 x = v[k1];
-                if constexpr (k1 > 0) x = cmulc(x, a.tw2[k1 * N2 + j2]);
-                bufA[(k1 * N2 + j2) * L + l] = x;
-            });
+            if (act) {
+                static_for<0, N1>([&](auto K) {
+                    constexpr int k1 = K;
+                    v[k1] = bufA[(j2 + N2 * k1) * L + l];
+                });
+                RegDFT<N1, true>::run(v);
+                static_for<0, N1>([&](auto K) {
+                    constexpr int k1 = K;
+                    if constexpr (k1 > 0) v[k1] = cmulc(v[k1], a.tw2[k1 * N2 + j2]);
+                });
+            }
+            __syncthreads();
+            if (act) {
+                static_for<0, N1>([&](auto K) {
+                    constexpr int k1 = K;
+                    bufA[(k1 * N2 + j2) * L + l] = v[k1];
+                });
+            }
         }
         __syncthreads();
     }
@@ -249,7 +281,7 @@ __global__ __launch_bounds__(kThreads) void k_col(ColArgs a) {
     const float s1 = a.s1 ? a.s1[f] : a.c1;
     const float s2 = a.s2 ? a.s2[f] : a.c2;
     double acc = 0.0;
-    for (int t = threadIdx.x; t < L * N1; t += kThreads) {
+    for (int t = threadIdx.x; t < L * N1; t += NT) {
         const int l = t % L, k1 = t / L, col = col0 + l;
         float2 v[N2];
         static_for<0, N2>([&](auto J) {
@@ -306,8 +338,11 @@ __global__ __launch_bounds__(kThreads) void k_col(ColArgs a) {
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
         __syncthreads();
-        if (threadIdx.x == 0)
-            a.partial[(long long)plane * (N / L) + tile] = (red[0] + red[1]) + (red[2] + red[3]);
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < NT / 64; ++w) t += red[w];
+            a.partial[(long long)plane * (N / L) + tile] = t;
+        }
     }
 }
 
@@ -338,17 +373,21 @@ struct RowArgs {
 };
 
 template <int N, int L, int MODE>
-__global__ __launch_bounds__(kThreads) void k_row(RowArgs a) {
+__global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
     using CT = Centre<N>;
     constexpr int N1 = CT::N1, N2 = CT::N2;
+    constexpr int NT = pass_threads(N, L);
     constexpr int S2 = N2 + 1;                      // padded stride of [line][k1][j2]
-    __shared__ float2 bufA[L * N1 * S2];
-    __shared__ float2 bufB[L * N];                  // position order [line][pos]
+    static_assert(L * N1 <= NT && L * N2 <= NT, "one task per thread");
+    // [line][k1][j2] (padded) for the stage exchange, or [line][pos] between
+    // the two transforms: every stage reads into registers, waits, then writes
+    __shared__ float2 buf[L * N1 * S2];
     const int line0 = blockIdx.x * L;
     const int m = a.m, lo = a.lo;
+    const int t = threadIdx.x;
 
     if constexpr (MODE == ROW_FWD) {
-        for (int idx = threadIdx.x; idx < L * N; idx += kThreads) {
+        for (int idx = t; idx < L * N; idx += NT) {
             const int ll = idx / N, pos = idx % N;
             const int line = line0 + ll;
             const int q = pos - lo;
@@ -359,12 +398,12 @@ __global__ __launch_bounds__(kThreads) void k_row(RowArgs a) {
                 z = cscale(cmul(a.rho[((long long)f * m + i) * m + q], a.c[((long long)plane * m + i) * m + q]),
                            CT::sign(pos));
             }
-            bufB[idx] = z;
+            buf[ll * N + pos] = z;
         }
         __syncthreads();
     } else {
         // inverse transform of the T rows: stage 1 from HBM
-        for (int t = threadIdx.x; t < L * N2; t += kThreads) {
+        if (t < L * N2) {
             const int ll = t / N2, j2 = t % N2;
             const int line = line0 + ll;
             float2 v[N1];
@@ -378,85 +417,104 @@ __global__ __launch_bounds__(kThreads) void k_row(RowArgs a) {
                 constexpr int k1 = K;
                 float2 x = v[k1];
                 if constexpr (k1 > 0) x = cmulc(x, a.tw2[k1 * N2 + j2]);
-                bufA[(ll * N1 + k1) * S2 + j2] = x;
+                buf[(ll * N1 + k1) * S2 + j2] = x;
             });
         }
         __syncthreads();
-        // stage 2, crop to Omega columns, pointwise products, zero-pad into bufB
-        for (int t = threadIdx.x; t < L * N1; t += kThreads) {
+        // stage 2, crop to Omega columns, pointwise products, zero-pad
+        {
+            const bool act = t < L * N1;
             const int ll = t / N1, k1 = t % N1;
             const int line = line0 + ll;
             float2 v[N2];
-            static_for<0, N2>([&](auto J) {
-                constexpr int j2 = J;
-                v[j2] = bufA[(ll * N1 + k1) * S2 + j2];
-            });
-            RegDFT<N2, true>::run(v);
-            const int plane = line / m, i = line % m;
-            const bool live = line < a.nlines;
-            const int f = (live && a.plane_frame) ? a.plane_frame[plane] : 0;
-            static_for<0, N2>([&](auto K) {
-                constexpr int k2 = K;
-                const int pos = CT::out_pos(k1, k2);
-                const int q = pos - lo;
-                float2 z = make_float2(0.f, 0.f);
-                if (live && q >= 0 && q < m) {
-                    const float2 u = cscale(v[k2], CT::sign(pos) * a.rs);
-                    const long long oc = ((long long)plane * m + i) * m + q;
-                    if constexpr (MODE == ROW_CACHE) {
-                        a.c_out[oc] = u;
-                    } else {
-                        const long long orh = ((long long)f * m + i) * m + q;
-                        const float2 cv = a.c[oc];
-                        const float2 rv = a.rho[orh];
-                        if constexpr (MODE == ROW_DERIV) {
-                            z = cadd(cmul(a.drho[orh], cv), cmul(rv, u));
-                        } else {  // ROW_ADJ
-                            a.aux[oc] = cconjmul(cv, u);
-                            z = cconjmul(rv, u);
+            if (act) {
+                static_for<0, N2>([&](auto J) {
+                    constexpr int j2 = J;
+                    v[j2] = buf[(ll * N1 + k1) * S2 + j2];
+                });
+                RegDFT<N2, true>::run(v);
+                const int plane = line / m, i = line % m;
+                const bool live = line < a.nlines;
+                const int f = (live && a.plane_frame) ? a.plane_frame[plane] : 0;
+                static_for<0, N2>([&](auto K) {
+                    constexpr int k2 = K;
+                    const int pos = CT::out_pos(k1, k2);
+                    const int q = pos - lo;
+                    float2 z = make_float2(0.f, 0.f);
+                    if (live && q >= 0 && q < m) {
+                        const float2 u = cscale(v[k2], CT::sign(pos) * a.rs);
+                        const long long oc = ((long long)plane * m + i) * m + q;
+                        if constexpr (MODE == ROW_CACHE) {
+                            a.c_out[oc] = u;
+                        } else {
+                            const long long orh = ((long long)f * m + i) * m + q;
+                            const float2 cv = a.c[oc];
+                            const float2 rv = a.rho[orh];
+                            if constexpr (MODE == ROW_DERIV) {
+                                z = cadd(cmul(a.drho[orh], cv), cmul(rv, u));
+                            } else {  // ROW_ADJ
+                                a.aux[oc] = cconjmul(cv, u);
+                                z = cconjmul(rv, u);
+                            }
+                            z = cscale(z, CT::sign(pos));
                         }
-                        z = cscale(z, CT::sign(pos));
                     }
-                }
-                if constexpr (MODE != ROW_CACHE) bufB[ll * N + pos] = z;
-            });
+                    v[k2] = z;
+                });
+            }
+            if constexpr (MODE == ROW_CACHE) return;
+            __syncthreads();
+            if (act) {
+                static_for<0, N2>([&](auto K) {
+                    constexpr int k2 = K;
+                    buf[ll * N + CT::out_pos(k1, k2)] = v[k2];
+                });
+            }
         }
-        if constexpr (MODE == ROW_CACHE) return;
         __syncthreads();
     }
-    // forward transform of bufB: stage 1
-    for (int t = threadIdx.x; t < L * N2; t += kThreads) {
+    // forward transform: stage 1 from the position-ordered lines
+    {
+        const bool act = t < L * N2;
         const int ll = t / N2, j2 = t % N2;
         float2 v[N1];
-        static_for<0, N1>([&](auto K) {
-            constexpr int k1 = K;
-            v[k1] = bufB[ll * N + CT::in_pos(j2, k1)];
-        });
-        RegDFT<N1, false>::run(v);
-        static_for<0, N1>([&](auto K) {
-            constexpr int k1 = K;
-            float2 x = v[k1];
-            if constexpr (k1 > 0) x = cmul(x, a.tw2[k1 * N2 + j2]);
-            bufA[(ll * N1 + k1) * S2 + j2] = x;
-        });
+        if (act) {
+            static_for<0, N1>([&](auto K) {
+                constexpr int k1 = K;
+                v[k1] = buf[ll * N + CT::in_pos(j2, k1)];
+            });
+            RegDFT<N1, false>::run(v);
+            static_for<0, N1>([&](auto K) {
+                constexpr int k1 = K;
+                if constexpr (k1 > 0) v[k1] = cmul(v[k1], a.tw2[k1 * N2 + j2]);
+            });
+        }
+        __syncthreads();
+        if (act) {
+            static_for<0, N1>([&](auto K) {
+                constexpr int k1 = K;
+                buf[(ll * N1 + k1) * S2 + j2] = v[k1];
+            });
+        }
     }
     __syncthreads();
     // stage 2 to HBM
-    for (int t = threadIdx.x; t < L * N1; t += kThreads) {
+    if (t < L * N1) {
         const int ll = t / N1, k1 = t % N1;
         const int line = line0 + ll;
-        if (line >= a.nlines) continue;
-        float2 v[N2];
-        static_for<0, N2>([&](auto J) {
-            constexpr int j2 = J;
-            v[j2] = bufA[(ll * N1 + k1) * S2 + j2];
-        });
-        RegDFT<N2, false>::run(v);
-        static_for<0, N2>([&](auto K) {
-            constexpr int k2 = K;
-            const int pos = CT::out_pos(k1, k2);
-            a.out[(long long)line * N + pos] = cscale(v[k2], CT::sign(pos) * a.rs);
-        });
+        if (line < a.nlines) {
+            float2 v[N2];
+            static_for<0, N2>([&](auto J) {
+                constexpr int j2 = J;
+                v[j2] = buf[(ll * N1 + k1) * S2 + j2];
+            });
+            RegDFT<N2, false>::run(v);
+            static_for<0, N2>([&](auto K) {
+                constexpr int k2 = K;
+                const int pos = CT::out_pos(k1, k2);
+                a.out[(long long)line * N + pos] = cscale(v[k2], CT::sign(pos) * a.rs);
+            });
+        }
     }
 }
 
