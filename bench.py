@@ -56,6 +56,37 @@ def kernel_bytes(kc: str, n: int, m: int, planes: int, frames: int) -> float:
     return per.get(kc, float("nan"))
 
 
+def kernel_source_hash():
+    import glob
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1301_1215_amd", "csrc")
+    h = hashlib.sha256()
+    for pth in sorted(glob.glob(os.path.join(csrc, "*.hpp")) + glob.glob(os.path.join(csrc, "*.hip"))):
+        h.update(open(pth, "rb").read())
+    return h.hexdigest()
+
+
+def pmc_traffic(kc: str, frames: int):
+    """HBM bytes per launch of kernel class `kc` from the committed
+    FETCH_SIZE / WRITE_SIZE summary, or None when the kernels changed since
+    the counters were taken or the batch differs."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic__realtime_384_b4.txt")
+    if not os.path.exists(path):
+        return None
+    meta, traffic = {}, {}
+    for line in open(path):
+        f = line.split()
+        if not f or f[0].startswith("#"):
+            continue
+        if f[0] == "traffic" and len(f) == 7:
+            traffic[f[1]] = int(f[6])
+        elif len(f) == 2:
+            meta[f[0]] = f[1]
+    if meta.get("source_sha256") != kernel_source_hash() or int(meta.get("frames_per_step", -1)) != frames:
+        return None
+    return traffic.get(kc)
+
+
 def normal_bytes(n, m, J, frames=1):
     """Compulsory bytes of one (DF^H DF + alpha) apply: read h, c|Omega, rho, P; write N h."""
     N_, NO = n * n, m * m
@@ -113,7 +144,33 @@ def dominant_class(pl, data, prm, outs, names):
     kc = max(totals, key=lambda k: totals[k][0])
     log("bench: kernel-class totals per step (ms, launches): " +
         ", ".join(f"{k}={v[0]:.3f}/{v[1]}" for k, v in sorted(totals.items(), key=lambda kv: -kv[1][0])))
+    dominant_class.totals = totals
     return kc
+
+
+# kernel classes of one (DF^H DF + alpha) apply inside CG (the first one also does p = r + beta p)
+APPLY_CLASSES = ("col_pupd_winv_ifft", "row_deriv", "col_psf", "row_adj", "col_fft_winv_axpy_dot", "coil_sum")
+
+
+def apply_rates(totals, B):
+    """N_alpha applies/s and GB/s from the per-class totals of one step:
+    algorithmic = compulsory bytes B_normal per frame-apply; schedule = the
+    bytes the pass schedule moves (the byte model, which the traffic
+    counters reproduce)."""
+    K = NEWTON * CG
+    ms = 0.0
+    sched = 0.0
+    for k in APPLY_CLASSES:
+        if k not in totals:
+            return {}
+        t, cnt = totals[k]
+        ms += t * (K / cnt)                     # the coil sum and row_adj also run for the right-hand sides
+        sched += kernel_bytes(k, N, N_OM, J * B, B) * K
+    per_s = B * K / (ms * 1e-3)
+    return {"normal_applies_per_s": per_s,
+            "normal_apply_us": 1e3 * ms / K,
+            "normal_algorithmic_GBps": normal_bytes(N, N_OM, J, B) * K / (ms * 1e-3) / 1e9,
+            "normal_schedule_GBps": sched / (ms * 1e-3) / 1e9}
 
 
 def compare_paths(a, data, outs, B):
@@ -152,8 +209,57 @@ def compare_paths(a, data, outs, B):
     ap_s = a.applies / (time.perf_counter() - t0)
     nb = normal_bytes(N, N_OM, J)
     plain.close()
-    return {"plain_frames_per_s": plain_fps, "normal_applies_per_s": ap_s,
-            "normal_algorithmic_GBps": nb * ap_s / 1e9, "batched_vs_plain_image_rel": spot}
+    return {"plain_frames_per_s": plain_fps, "plain_normal_applies_per_s": ap_s,
+            "plain_normal_algorithmic_GBps": nb * ap_s / 1e9, "batched_vs_plain_image_rel": spot}
+
+
+def other_workload(a):
+    """Frames/s of the other workloads (no roofline line): 64x64 8-coil
+    Cartesian frames batched (6 x 10), the 64-frame ragged batch (7 x 10),
+    or the 512x512 32-coil series, 8 sequential warm-started frames per step."""
+    import torch
+    from paper_1301_1215_amd import Plan, synth
+    if a.workload == "single_64":
+        B = a.frames
+        frames = [synth.make_frame(1, t, 64, 64, 8, "cartesian", newton=6) for t in range(B)]
+        newton, desc = 6, f"single_64: {B} frames of 64x64, 8 coils, Cartesian 28/64 rows, 6 Newton x 10 CG"
+    elif a.workload == "ragged_64":
+        frames = synth.ragged_batch(64)
+        B, newton = 64, 7
+        desc = "ragged_64: 64 frames, n in {128,192,256,384}, J in {8,12,16,32}, spokes in {11,15,21}, 7x10"
+    else:
+        ph = synth.temporal_phantom()
+        frames = [synth.temporal_frame(t, ph) for t in range(8)]
+        B, newton = 8, 7
+        desc = "series_512: 8 sequential frames of 512x512, 32 coils, 13 spokes, warm-started, 7x10"
+    data = [(torch.from_numpy(f.y).cuda(), torch.from_numpy(f.P).cuda()) for f in frames]
+    prm = Plan.params(newton, CG, use_graph=not a.no_graph)
+    if a.workload == "series_512":
+        pl = Plan(512, 256, 32)
+        run = lambda outs: pl.solve_series(data, prm, outs)
+        outs = [pl._frame_out(pl.dims, prm) for _ in range(B)]
+    else:
+        pl = Plan(frames=[(f.n, f.n_om, f.ncoils) for f in frames])
+        run = lambda outs: pl.solve_batch(data, prm, outs)
+        outs = [pl._frame_out(fd, prm) for fd in pl.frames]
+    if not a.no_autotune:
+        pl.autotune()
+    for _ in range(max(1, a.warmup)):
+        run(outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        run(outs)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = {"metric": "IRGNM frames/sec", "value": B * a.steps / dt, "unit": "frames/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 * dt / a.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "c64 (fp32), fp64 CG dots/scalars",
+           "data": "synthetic", "config": {"workload": desc, "frames_per_step": B,
+                                           "path": ("series" if a.workload == "series_512" else "batched")
+                                           + ("" if a.no_graph else "+hipGraph")},
+           "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -174,6 +280,9 @@ def main():
     ap.add_argument("--kernel-class", default=None, help="kernel class for the roofline (default: dominant)")
     ap.add_argument("--stream-probe", action="store_true",
                     help="also measure a 1 GiB device-to-device copy (the practical HBM ceiling)")
+    ap.add_argument("--workload", default="realtime_384",
+                    choices=["realtime_384", "single_64", "ragged_64", "series_512"],
+                    help="realtime_384 (the benchmark line); the others report frames/s only")
     a = ap.parse_args()
 
     if a.gpus != 1:
@@ -189,6 +298,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     NAT.load()
+    if a.workload != "realtime_384":
+        return other_workload(a)
     B = a.frames
     log(f"bench: generating {B} frames of {N}x{N}, {J} coils, {SPOKES} spokes")
     frames = [synth.make_frame(2, t, N, N_OM, J, "radial", spokes=SPOKES, newton=NEWTON, cg=CG,
@@ -252,15 +363,17 @@ def main():
     log(f"bench: {ms_step:.2f} ms/step, {fps:.1f} frames/s; {kc}: {launches} launches, {kms:.3f} ms")
 
     extras = {}
+    if getattr(dominant_class, "totals", None):
+        extras.update(apply_rates(dominant_class.totals, B))
     if a.compare:
-        extras = compare_paths(a, data, outs, B)
+        extras.update(compare_paths(a, data, outs, B))
 
     # roofline of the dominant kernel class
     per_launch = kernel_bytes(kc, N, N_OM, J * B, B)
     avg_ms = kms / max(launches, 1)
     achieved = per_launch / (avg_ms * 1e-3) / 1e9 if launches else None
     roof = {"bound": "hbm", "kernel": kc, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBPS) if achieved else None, "traffic": None,
+            "frac": (achieved / HBM_PEAK_GBPS) if achieved else None, "traffic": pmc_traffic(kc, B),
             "bytes_per_launch": per_launch, "avg_launch_ms": avg_ms, "launches_timed": launches,
             "event_timing_on": timing_path}
 
