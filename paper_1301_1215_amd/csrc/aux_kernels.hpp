@@ -99,16 +99,19 @@ enum ScalarOp : int {
     SC_YNORM = 0,      // s = scale_norm / ||y|| (scale_norm > 0 and ||y|| > 0), else 1
     SC_R0NORM = 1,     // stats[2 + step] = ||r0||
     SC_RR0 = 2,        // rr = <b, b>; new Newton step: clear breakdown
-    SC_GAMMA = 3,      // gamma = Re<p, q>; a = rr / gamma or breakdown
+    SC_GAMMA = 3,      // gamma = Re<p, q> (or |DF p|^2 + alpha |p|^2); a = rr / gamma or breakdown
     SC_RR = 4,         // rr' = <r, r>; beta = rr'/rr; rr = rr'; stats of CG iteration `it`
 };
 
 // Where a scalar op is applied: which op, geometry of its partials, indices
-// for the stats.
+// for the stats.  With `partial2` set the total is
+// sum(partial) + alpha_f * sum(partial2) (geometry g2).
 struct ScalarStep {
     int op;
     SegGeom g;
     const double* partial;
+    SegGeom g2;
+    const double* partial2;
     const int* frame_plane0;
     const int* frame_planes;
     float scale_norm;
@@ -168,6 +171,8 @@ __device__ __forceinline__ void scalar_apply(const ScalarStep& ss, const Scalars
 // One thread per Omega pixel, one workgroup per (frame, segment of
 // `seg_len` pixels); with `partial` set it also writes Re<add1, out> of its
 // segment to partial[poff + f*segs + k].
+// CG form (r_upd set): the sum q (with add1 = p, s1 = alpha) is not stored;
+// instead r -= a_f q and dx += a_f p, and the partial is |r|^2.
 struct CoilSumArgs {
     const float2* aux;       // [planes][E]
     float2* out;             // [frames][E]
@@ -184,6 +189,9 @@ struct CoilSumArgs {
     int segs, seg_len;       // seg_len <= kThreads
     double* partial;
     long long poff;
+    float2* r_upd;           // CG form: rho part of r (in place), nullable
+    float2* dx_upd;          // rho part of dx (in place)
+    const float* cg_a;       // [frames] CG step a
 };
 
 __global__ __launch_bounds__(kThreads) void k_coil_sum(CoilSumArgs a) {
@@ -208,8 +216,22 @@ __global__ __launch_bounds__(kThreads) void k_coil_sum(CoilSumArgs a) {
         const float c2 = a.s2 ? a.s2[f] : a.c2;
         if (a.add1) { const float2 u = a.add1[g]; s.x += c1 * u.x; s.y += c1 * u.y; }
         if (a.add2) { const float2 u = a.add2[g]; s.x += c2 * u.x; s.y += c2 * u.y; }
-        a.out[g] = s;
-        if (a.partial && a.add1) { const float2 u = a.add1[g]; acc = (double)(u.x * s.x + u.y * s.y); }
+        if (a.r_upd) {
+            const float av = a.cg_a[f];
+            const float2 u = a.add1[g];
+            float2 r = a.r_upd[g];
+            r.x -= av * s.x;
+            r.y -= av * s.y;
+            a.r_upd[g] = r;
+            float2 d = a.dx_upd[g];
+            d.x += av * u.x;
+            d.y += av * u.y;
+            a.dx_upd[g] = d;
+            acc = (double)(r.x * r.x + r.y * r.y);
+        } else {
+            a.out[g] = s;
+            if (a.partial && a.add1) { const float2 u = a.add1[g]; acc = (double)(u.x * s.x + u.y * s.y); }
+        }
     }
     if (a.partial) {
         const double t = block_sum(acc, red);
@@ -250,69 +272,31 @@ __global__ __launch_bounds__(kThreads) void k_image(const float2* rho, const flo
 // ---------------------------------------------------------------------------
 
 struct VecPtrs {
-    float2* c0; float2* c1; float2* c2; float2* c3;   // chat parts
-    float2* r0; float2* r1; float2* r2; float2* r3;   // rho parts
+    float2* c0; float2* c1;   // chat parts
+    float2* r0; float2* r1;   // rho parts
 };
 
 enum VecOp : int {
     VEC_DOT = 0,        // partial = Re<v0, v1>
-    VEC_XR_UPDATE = 1,  // v0 += a v1 (x += a p);  v2 -= a v3 (r -= a q);  partial = |v2|^2
-    VEC_ADD = 2,        // v0 += v1
+    VEC_ADD = 1,        // v0 += v1
 };
 
-// VEC_XR_UPDATE with gamma.op == SC_GAMMA: every workgroup first sums the
-// Re<p, q> partials of its frame (written by the previous kernels) in the
-// fixed order and applies the CG step logic itself, so no separate scalar
-// launch is needed; the first workgroup of each frame records a, the
-// breakdown flag and the stats.  All workgroups of a frame compute the same a.
 template <int OP>
-__global__ __launch_bounds__(kThreads) void k_vec(SegGeom g, VecPtrs v, const float* a_f,
-                                                  const float* b_f, double* partial, ScalarStep gamma,
-                                                  Scalars sc) {
+__global__ __launch_bounds__(kThreads) void k_vec(SegGeom g, VecPtrs v, double* partial) {
     __shared__ double red[4];
     bool is_c; int owner, f, len; long long base;
     seg_locate(g, blockIdx.x, is_c, owner, f, base, len);
     float2* x0 = is_c ? v.c0 : v.r0;
     float2* x1 = is_c ? v.c1 : v.r1;
-    float2* x2 = is_c ? v.c2 : v.r2;
-    float2* x3 = is_c ? v.c3 : v.r3;
     float4* y0 = reinterpret_cast<float4*>(x0 + base);
     float4* y1 = reinterpret_cast<float4*>(x1 + base);
-    float4* y2 = reinterpret_cast<float4*>(x2 + base);
-    float4* y3 = reinterpret_cast<float4*>(x3 + base);
     const int n4 = len / 2;
     double acc = 0.0;
-    float av = a_f ? a_f[f] : 0.f;
-    (void)b_f;
-    if constexpr (OP == VEC_XR_UPDATE) {
-        if (gamma.op == SC_GAMMA) {
-            __shared__ float a_sh;
-            const double t = frame_total(gamma.g, gamma.partial, f, gamma.frame_plane0, gamma.frame_planes, red);
-            if (threadIdx.x == 0) {
-                const double rr = sc.rr[f];
-                const bool brk = sc.brk[f] || rr == 0.0 || !(t > 0.0) || !isfinite(rr);
-                a_sh = brk ? 0.f : (float)(rr / t);
-                const int p0 = gamma.frame_plane0 ? gamma.frame_plane0[f] : 0;
-                if (is_c && owner == p0 && blockIdx.x % g.cseg == 0) scalar_apply(gamma, sc, f, t);
-            }
-            __syncthreads();
-            av = a_sh;
-        }
-    }
+    (void)f; (void)owner;
     for (int i = threadIdx.x; i < n4; i += kThreads) {
         if constexpr (OP == VEC_DOT) {
             const float4 p = y0[i], q = y1[i];
             acc += (double)p.x * q.x + (double)p.y * q.y + (double)p.z * q.z + (double)p.w * q.w;
-        } else if constexpr (OP == VEC_XR_UPDATE) {
-            float4 x = y0[i];
-            const float4 p = y1[i];
-            float4 r = y2[i];
-            const float4 q = y3[i];
-            x.x += av * p.x; x.y += av * p.y; x.z += av * p.z; x.w += av * p.w;
-            r.x -= av * q.x; r.y -= av * q.y; r.z -= av * q.z; r.w -= av * q.w;
-            y0[i] = x;
-            y2[i] = r;
-            acc += (double)r.x * r.x + (double)r.y * r.y + (double)r.z * r.z + (double)r.w * r.w;
         } else if constexpr (OP == VEC_ADD) {
             float4 p = y0[i];
             const float4 r = y1[i];
@@ -320,7 +304,7 @@ __global__ __launch_bounds__(kThreads) void k_vec(SegGeom g, VecPtrs v, const fl
             y0[i] = p;
         }
     }
-    if constexpr (OP == VEC_DOT || OP == VEC_XR_UPDATE) {
+    if constexpr (OP == VEC_DOT) {
         const double t = block_sum(acc, red);
         if (threadIdx.x == 0) partial[blockIdx.x] = t;
     }
@@ -330,7 +314,11 @@ __global__ __launch_bounds__(kThreads) void k_vec(SegGeom g, VecPtrs v, const fl
 __global__ __launch_bounds__(kThreads) void k_scalar(ScalarStep ss, Scalars sc) {
     __shared__ double red[4];
     const int f = blockIdx.x;
-    const double t = frame_total(ss.g, ss.partial, f, ss.frame_plane0, ss.frame_planes, red);
+    double t = frame_total(ss.g, ss.partial, f, ss.frame_plane0, ss.frame_planes, red);
+    if (ss.partial2) {
+        const double t2 = frame_total(ss.g2, ss.partial2, f, ss.frame_plane0, ss.frame_planes, red);
+        if (threadIdx.x == 0) t += (double)sc.alpha[f] * t2;
+    }
     if (threadIdx.x == 0) scalar_apply(ss, sc, f, t);
 }
 

@@ -21,7 +21,7 @@ static hipError_t col_L(int mode, const ColArgs& a, int nplanes, hipStream_t s) 
         case COL_PAD_FFT_WINV_ADD: hipLaunchKernelGGL((k_col<N, L, COL_PAD_FFT_WINV_ADD>), grid, block, 0, s, a); break;
         case COL_PAD_FFT_GPROD: hipLaunchKernelGGL((k_col<N, L, COL_PAD_FFT_GPROD>), grid, block, 0, s, a); break;
         case COL_PUPD_WINV_IFFT_CROP: hipLaunchKernelGGL((k_col<N, L, COL_PUPD_WINV_IFFT_CROP>), grid, block, 0, s, a); break;
-        case COL_PAD_FFT_WINV_AXPY_DOT: hipLaunchKernelGGL((k_col<N, L, COL_PAD_FFT_WINV_AXPY_DOT>), grid, block, 0, s, a); break;
+        case COL_PAD_FFT_WINV_CG_UPD: hipLaunchKernelGGL((k_col<N, L, COL_PAD_FFT_WINV_CG_UPD>), grid, block, 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -84,15 +84,15 @@ bool row_ok(int n, int v) { return row_variant_ok(n, v); }
 // kernel classes for timing
 enum KClass : int {
     KC_COL_WINV_IFFT = 0, KC_COL_P_IFFT, KC_COL_FFT_P, KC_COL_FFT_P_RESID, KC_COL_PSF,
-    KC_COL_FFT_WINV_ADD, KC_COL_FFT_GPROD, KC_COL_PUPD_WINV_IFFT, KC_COL_FFT_WINV_AXPY_DOT,
+    KC_COL_FFT_WINV_ADD, KC_COL_FFT_GPROD, KC_COL_PUPD_WINV_IFFT, KC_COL_FFT_WINV_CG_UPD,
     KC_ROW_CACHE, KC_ROW_FWD, KC_ROW_DERIV, KC_ROW_ADJ,
-    KC_COIL_SUM, KC_VEC_DOT, KC_VEC_XR, KC_VEC_OTHER, KC_SCALAR, KC_IMAGE, KC_NUM
+    KC_COIL_SUM, KC_VEC_DOT, KC_VEC_OTHER, KC_SCALAR, KC_IMAGE, KC_NUM
 };
 const char* kKClassNames[KC_NUM] = {
     "col_winv_ifft", "col_p_ifft", "col_fft_p", "col_fft_p_resid", "col_psf",
-    "col_fft_winv_add", "col_fft_gprod", "col_pupd_winv_ifft", "col_fft_winv_axpy_dot",
+    "col_fft_winv_add", "col_fft_gprod", "col_pupd_winv_ifft", "col_fft_winv_cg_update",
     "row_cache", "row_fwd", "row_deriv", "row_adj",
-    "coil_sum", "vec_dot", "vec_xr_update", "vec_other", "scalar", "image"};
+    "coil_sum", "vec_dot", "vec_other", "scalar", "image"};
 
 int col_kclass(int mode) {
     switch (mode) {
@@ -103,7 +103,7 @@ int col_kclass(int mode) {
         case COL_PAD_FFT_P2_IFFT: return KC_COL_PSF;
         case COL_PAD_FFT_WINV_ADD: return KC_COL_FFT_WINV_ADD;
         case COL_PUPD_WINV_IFFT_CROP: return KC_COL_PUPD_WINV_IFFT;
-        case COL_PAD_FFT_WINV_AXPY_DOT: return KC_COL_FFT_WINV_AXPY_DOT;
+        case COL_PAD_FFT_WINV_CG_UPD: return KC_COL_FFT_WINV_CG_UPD;
         default: return KC_COL_FFT_GPROD;
     }
 }
@@ -140,8 +140,9 @@ struct Class {
     float2* y = nullptr;
     float* P = nullptr;
     float2 *c = nullptr, *T = nullptr, *aux = nullptr;
-    double* partial = nullptr;
-    double* partial2 = nullptr;  // <r,r> partials of the x/r update (it reads Re<p,q> from `partial`)
+    double* partial = nullptr;   // general partials; in CG: |DF p|^2 of the PSF pass
+    double* partial2 = nullptr;  // CG: |r|^2 after the update
+    double* part_p = nullptr;    // CG: |p|^2 of the direction update
     float* alpha = nullptr;      // [2F]: alpha, -alpha
     SegGeom geom{}, geomC{};
     Scalars sc{};
@@ -330,18 +331,11 @@ int run_coil_sum(nlinv_plan_s* p, const CoilSumArgs& a, hipStream_t s) {
     return NLINV_OK;
 }
 
-ScalarStep no_fold() {
-    ScalarStep f{};
-    f.op = SC_NONE;
-    return f;
-}
-
 template <int OP>
-int run_vec(nlinv_plan_s* p, const SegGeom& g, const VecPtrs& v, const float* a_f, const float* b_f,
-            double* partial, hipStream_t s, const ScalarStep& gamma = no_fold(), const Scalars& sc = Scalars{}) {
-    const int kc = OP == VEC_DOT ? KC_VEC_DOT : OP == VEC_XR_UPDATE ? KC_VEC_XR : KC_VEC_OTHER;
+int run_vec(nlinv_plan_s* p, const SegGeom& g, const VecPtrs& v, double* partial, hipStream_t s) {
+    const int kc = OP == VEC_DOT ? KC_VEC_DOT : KC_VEC_OTHER;
     const int slot = tbegin(p, kc, s);
-    hipLaunchKernelGGL((k_vec<OP>), dim3(nseg(g)), dim3(kThreads), 0, s, g, v, a_f, b_f, partial, gamma, sc);
+    hipLaunchKernelGGL((k_vec<OP>), dim3(nseg(g)), dim3(kThreads), 0, s, g, v, partial);
     hipError_t e = hipGetLastError();
     tend(p, slot, s);
     HIPCHK(e);
@@ -364,21 +358,23 @@ ScalarStep scalar_step(const Class& C, int op, const SegGeom& g, float scale_nor
     return ss;
 }
 
-int run_scalar(nlinv_plan_s* p, Class& C, int op, const SegGeom& g, float scale_norm, int step,
-               hipStream_t s, int it = 0, int nsteps = 0, int ncg = 0, const double* partial = nullptr) {
+int launch_scalar(nlinv_plan_s* p, Class& C, const ScalarStep& ss, hipStream_t s) {
     const int slot = tbegin(p, KC_SCALAR, s);
-    hipLaunchKernelGGL(k_scalar, dim3(C.nframes), dim3(kThreads), 0, s,
-                       scalar_step(C, op, g, scale_norm, step, it, nsteps, ncg, partial), C.sc);
+    hipLaunchKernelGGL(k_scalar, dim3(C.nframes), dim3(kThreads), 0, s, ss, C.sc);
     hipError_t e = hipGetLastError();
     tend(p, slot, s);
     HIPCHK(e);
     return NLINV_OK;
 }
 
-VecPtrs vptrs(float2* c0, float2* r0, float2* c1 = nullptr, float2* r1 = nullptr,
-              float2* c2 = nullptr, float2* r2 = nullptr, float2* c3 = nullptr, float2* r3 = nullptr) {
+int run_scalar(nlinv_plan_s* p, Class& C, int op, const SegGeom& g, float scale_norm, int step,
+               hipStream_t s, int it = 0, int nsteps = 0, int ncg = 0, const double* partial = nullptr) {
+    return launch_scalar(p, C, scalar_step(C, op, g, scale_norm, step, it, nsteps, ncg, partial), s);
+}
+
+VecPtrs vptrs(float2* c0, float2* r0, float2* c1 = nullptr, float2* r1 = nullptr) {
     VecPtrs v{};
-    v.c0 = c0; v.r0 = r0; v.c1 = c1; v.r1 = r1; v.c2 = c2; v.r2 = r2; v.c3 = c3; v.r3 = r3;
+    v.c0 = c0; v.r0 = r0; v.c1 = c1; v.r1 = r1;
     return v;
 }
 
@@ -516,11 +512,17 @@ int seq_adjoint_tail(nlinv_plan_s* p, const Class& C, const Frames& fr, const fl
     return run_coil_sum(p, coil_sum_args(C, fr, drho_out, add1r, add2r, s1, s2, c1, c2, nullptr, 0), s);
 }
 
-// (DF^H DF + alpha) p inside CG, with the direction update p = r + beta p
-// folded into the first column pass (beta == nullptr: p = r) and the
-// partials of Re<p, q> written by the last column pass and the coil sum;
-// `g` receives the geometry of those partials.
-int seq_normal_cg(nlinv_plan_s* p, Class& C, const float* beta, SegGeom& g, hipStream_t s) {
+// One CG iteration on every frame of class C (Newton step `step`, CG
+// iteration `it` of K).  The step length needs gamma = Re<p, N_alpha p>,
+// which equals |DF p|^2 + alpha |p|^2: the direction update p = r + beta p,
+// folded into the first column pass (beta == nullptr: p = r), writes the
+// |p|^2 partials and the PSF pass the |DF p|^2 partials, so a = <r,r>/gamma
+// is known before the adjoint half of N_alpha p is computed.  The last column
+// pass and the coil sum then form q = N_alpha p in registers and apply
+// r -= a q, dx += a p directly (q is never stored), writing the |r|^2
+// partials from which beta follows.
+int seq_cg_iteration(nlinv_plan_s* p, Class& C, const float* beta, int step, int it, int nsteps, int ncg,
+                     hipStream_t s) {
     const Frames fr = class_frames(C);
     ColArgs a = col_args(p, C, fr.tiled);
     a.in = C.p_c;
@@ -531,6 +533,7 @@ int seq_normal_cg(nlinv_plan_s* p, Class& C, const float* beta, SegGeom& g, hipS
     a.beta = beta;
     a.pr = C.p_r;
     a.rr = C.r_r;
+    a.partial = C.part_p;
     CHK(run_col(p, C, COL_PUPD_WINV_IFFT_CROP, a, fr.nplanes, s));
     RowArgs r = row_args(C);
     r.in = C.T;
@@ -547,29 +550,46 @@ int seq_normal_cg(nlinv_plan_s* p, Class& C, const float* beta, SegGeom& g, hipS
     b.P = C.P;
     b.p_stride = C.cplane();
     b.plane_frame = fr.plane_frame;
+    b.partial = C.partial;
     CHK(run_col(p, C, COL_PAD_FFT_P2_IFFT, b, fr.nplanes, s));
+    // a = <r,r> / (|DF p|^2 + alpha |p|^2) per frame
+    {
+        const int tp = C.n / kColL[C.colv[COL_PUPD_WINV_IFFT_CROP]];
+        const int tg = C.n / kColL[C.colv[COL_PAD_FFT_P2_IFFT]];
+        ScalarStep ss = scalar_step(C, SC_GAMMA, C.geom, 0.f, step, it, nsteps, ncg, C.partial);
+        ss.g.cseg = tg;
+        ss.g.rseg = 0;
+        ss.g2 = C.geom;
+        ss.g2.cseg = tp;
+        ss.g2.rseg = tp;
+        ss.partial2 = C.part_p;
+        CHK(launch_scalar(p, C, ss, s));
+    }
     r.aux = C.aux;
     r.drho = nullptr;
     CHK(run_row(p, C, ROW_ADJ, r, s));
-    const int ntiles = C.n / kColL[C.colv[COL_PAD_FFT_WINV_AXPY_DOT]];
+    const int tu = C.n / kColL[C.colv[COL_PAD_FFT_WINV_CG_UPD]];
     ColArgs e = col_args(p, C, fr.tiled);
     e.in = C.T;
-    e.out = C.q_c;
+    e.out = C.r_c;
+    e.dx = C.dx_c;
     e.plane_frame = fr.plane_frame;
     e.add1 = C.p_c;
     e.s1 = C.alpha;
-    e.partial = C.partial;
-    CHK(run_col(p, C, COL_PAD_FFT_WINV_AXPY_DOT, e, fr.nplanes, s));
-    CoilSumArgs cs = coil_sum_args(C, fr, C.q_r, C.p_r, nullptr, C.alpha, nullptr, 0.f, 0.f, C.partial,
-                                   (long long)C.nplanes * ntiles);
+    e.cg_a = C.sc.a;
+    e.partial = C.partial2;
+    CHK(run_col(p, C, COL_PAD_FFT_WINV_CG_UPD, e, fr.nplanes, s));
+    CoilSumArgs cs = coil_sum_args(C, fr, nullptr, C.p_r, nullptr, C.alpha, nullptr, 0.f, 0.f, C.partial2,
+                                   (long long)C.nplanes * tu);
+    cs.r_upd = C.r_r;
+    cs.dx_upd = C.dx_r;
+    cs.cg_a = C.sc.a;
     CHK(run_coil_sum(p, cs, s));
-    // geometry of the Re<p, q> partials: column tiles per plane, coil-sum segments per frame
-    g = C.geom;
-    g.cseg = ntiles;
-    g.clen = 0;
+    // beta = <r,r>' / <r,r> from the |r|^2 partials: column tiles per plane, coil-sum segments per frame
+    SegGeom g = C.geom;
+    g.cseg = tu;
     g.rseg = cs.segs;
-    g.rlen = 0;
-    return NLINV_OK;
+    return run_scalar(p, C, SC_RR, g, 0.f, step, s, it, nsteps, ncg, C.partial2);
 }
 
 // (drho_out, dchat_out) = (DF^H DF + alpha) (drho, dchat)
@@ -611,7 +631,7 @@ int enqueue_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s
             CHK(seq_coil_maps(p, C, fr, C.x_c, C.c, s));
             // r0 = s y - F(x_n) into q, its norm
             CHK(seq_forward(p, C, fr, C.x_r, C.c, C.P, ps, C.q_c, C.y, C.sc.s, s));
-            CHK(run_vec<VEC_DOT>(p, C.geomC, vptrs(C.q_c, nullptr, C.q_c, nullptr), nullptr, nullptr, C.partial, s));
+            CHK(run_vec<VEC_DOT>(p, C.geomC, vptrs(C.q_c, nullptr, C.q_c, nullptr), C.partial, s));
             CHK(run_scalar(p, C, SC_R0NORM, C.geomC, 0.f, step, s));
             // b = DF^H r0 - alpha (x_n - x_ref) into r
             {
@@ -634,22 +654,15 @@ int enqueue_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s
                 tend(p, slot, s);
                 HIPCHK(hipGetLastError());
             }
-            CHK(run_vec<VEC_DOT>(p, C.geom, vptrs(C.r_c, C.r_r, C.r_c, C.r_r), nullptr, nullptr, C.partial, s));
+            CHK(run_vec<VEC_DOT>(p, C.geom, vptrs(C.r_c, C.r_r, C.r_c, C.r_r), C.partial, s));
             CHK(run_scalar(p, C, SC_RR0, C.geom, 0.f, step, s));
         }
         for (int it = 0; it < K; ++it) {
-            for (Class& C : p->classes) {
-                SegGeom g{};
-                CHK(seq_normal_cg(p, C, it == 0 ? nullptr : C.sc.beta, g, s));
-                // a = <r,r> / Re<p,q> in every workgroup, then dx += a p, r -= a q, <r,r> partials
-                CHK(run_vec<VEC_XR_UPDATE>(p, C.geom, vptrs(C.dx_c, C.dx_r, C.p_c, C.p_r, C.r_c, C.r_r, C.q_c, C.q_r),
-                                           nullptr, nullptr, C.partial2, s, scalar_step(C, SC_GAMMA, g, 0.f, step),
-                                           C.sc));
-                CHK(run_scalar(p, C, SC_RR, C.geom, 0.f, step, s, it, N, K, C.partial2));
-            }
+            for (Class& C : p->classes)
+                CHK(seq_cg_iteration(p, C, it == 0 ? nullptr : C.sc.beta, step, it, N, K, s));
         }
         for (Class& C : p->classes)
-            CHK(run_vec<VEC_ADD>(p, C.geom, vptrs(C.x_c, C.x_r, C.dx_c, C.dx_r), nullptr, nullptr, nullptr, s));
+            CHK(run_vec<VEC_ADD>(p, C.geom, vptrs(C.x_c, C.x_r, C.dx_c, C.dx_r), nullptr, s));
     }
     // sensitivities of the final x (for the image)
     for (Class& C : p->classes) CHK(seq_coil_maps(p, C, class_frames(C), C.x_c, C.c, s));
@@ -689,7 +702,7 @@ int setup_frames(nlinv_plan_s* p, const nlinv_frame* frames, const nlinv_irgnm_p
             CHK(tile_copy(p, C, (const float2*)F.y, C.y + (size_t)C.plane0[lf] * C.cplane(), C.J[lf], 1, s));
             CHK(tile_copy(p, C, F.P, C.P + (size_t)lf * C.cplane(), 1, 1, s));
         }
-        CHK(run_vec<VEC_DOT>(p, C.geomC, vptrs(C.y, nullptr, C.y, nullptr), nullptr, nullptr, C.partial, s));
+        CHK(run_vec<VEC_DOT>(p, C.geomC, vptrs(C.y, nullptr, C.y, nullptr), C.partial, s));
         CHK(run_scalar(p, C, SC_YNORM, C.geomC, prm.scale_norm, 0, s));
         // x0: warm start copies the caller's x (rho scaled below); else rho = 1 (scaled units), chat = 0
         const bool warm = (prm.flags & NLINV_WARM_START) != 0;
@@ -906,7 +919,8 @@ int build_class(nlinv_plan_s* p, Class& C) {
     const size_t tiles = (size_t)C.nplanes * (C.n / 4) + (size_t)C.nframes * ((rn + kCoilSeg - 1) / kCoilSeg);
     CHK(dalloc(p, &C.partial, std::max<size_t>(tiles, (size_t)std::max(nseg(C.geom), nseg(C.geomC)))));
     CHK(dalloc(p, &C.alpha, (size_t)2 * C.nframes));
-    CHK(dalloc(p, &C.partial2, (size_t)nseg(C.geom)));
+    CHK(dalloc(p, &C.partial2, std::max<size_t>(tiles, (size_t)nseg(C.geom))));
+    CHK(dalloc(p, &C.part_p, (size_t)(C.nplanes + C.nframes) * (C.n / 4)));
     CHK(dalloc(p, &C.sc.rr, C.nframes));
     CHK(dalloc(p, &C.sc.a, C.nframes));
     CHK(dalloc(p, &C.sc.beta, C.nframes));
@@ -957,14 +971,18 @@ ColArgs tune_col_args(nlinv_plan_s* p, Class& C, int mode) {
         case COL_WINV_IFFT_CROP: a.in = C.x_c; break;
         case COL_PUPD_WINV_IFFT_CROP:
             a.in = C.p_c; a.r_in = C.r_c; a.p_out = C.p_c; a.beta = C.sc.beta; a.pr = C.p_r; a.rr = C.r_r;
+            a.partial = C.part_p;
             break;
+        case COL_PAD_FFT_P2_IFFT: a.partial = C.partial; break;
         case COL_P_IFFT_CROP: a.in = C.q_c; break;
         case COL_PAD_FFT_P: a.out = C.q_c; break;
         case COL_PAD_FFT_P_RESID: a.out = C.q_c; a.add1 = C.y; a.s1 = C.sc.s; break;
         case COL_PAD_FFT_WINV_ADD:
             a.out = C.r_c; a.add1 = C.x_c; a.add2 = C.xr_c; a.s1 = C.alpha + C.nframes; a.s2 = C.alpha;
             break;
-        case COL_PAD_FFT_WINV_AXPY_DOT: a.out = C.q_c; a.add1 = C.p_c; a.s1 = C.alpha; a.partial = C.partial; break;
+        case COL_PAD_FFT_WINV_CG_UPD:
+            a.out = C.r_c; a.dx = C.dx_c; a.add1 = C.p_c; a.s1 = C.alpha; a.cg_a = C.sc.a; a.partial = C.partial2;
+            break;
         default: break;
     }
     return a;
@@ -1007,7 +1025,7 @@ int tune_class(nlinv_plan_s* p, Class& C, hipStream_t s) {
     };
     const int col_modes[] = {COL_WINV_IFFT_CROP, COL_PUPD_WINV_IFFT_CROP, COL_P_IFFT_CROP, COL_PAD_FFT_P,
                              COL_PAD_FFT_P_RESID, COL_PAD_FFT_P2_IFFT, COL_PAD_FFT_WINV_ADD,
-                             COL_PAD_FFT_WINV_AXPY_DOT};
+                             COL_PAD_FFT_WINV_CG_UPD};
     for (int mode : col_modes) {
         const ColArgs a = tune_col_args(p, C, mode);
         float best = 1e30f;

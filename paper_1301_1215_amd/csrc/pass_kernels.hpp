@@ -78,8 +78,9 @@ enum ColMode : int {
     COL_PAD_FFT_P2_IFFT = 4,  // T = crop_rows(IDFT_0(P^2 . DFT_0(pad_rows(T))))   (in place)
     COL_PAD_FFT_WINV_ADD = 5, // out = DFT_0(pad_rows(T)) / w + a1_f add1 + a2_f add2
     COL_PAD_FFT_GPROD = 6,    // outR = Re(conj(g) . DFT_0(pad_rows(T)))  (mask gradient)
-    COL_PUPD_WINV_IFFT_CROP = 7,   // CG: p = r + beta p (written back), then as COL_WINV_IFFT_CROP
-    COL_PAD_FFT_WINV_AXPY_DOT = 8, // CG: out = DFT_0(pad_rows(T)) / w + a1_f add1, Re<add1, out> partials
+    COL_PUPD_WINV_IFFT_CROP = 7,   // CG: p = r + beta p (written back), then as COL_WINV_IFFT_CROP; |p|^2 partials
+    COL_PAD_FFT_WINV_CG_UPD = 8,   // CG: q = DFT_0(pad_rows(T)) / w + alpha_f p (not stored);
+                                   //     r -= a_f q, dx += a_f p; |r|^2 partials
 };
 
 struct ColArgs {
@@ -105,10 +106,35 @@ struct ColArgs {
     const float* beta;
     float2* pr;               // rho part of p [frames][m*m], updated by the first plane of each frame
     const float2* rr;         // rho part of r
-    // COL_PAD_FFT_WINV_AXPY_DOT: Re<add1, out> per workgroup into partial[plane * tiles + tile]
+    // COL_PAD_FFT_WINV_CG_UPD: out = r (updated in place), add1 = p, s1 = alpha
+    float2* dx;               // chat part of the CG solution (updated in place)
+    const float* cg_a;        // [frames] CG step a
+    // FP64 partial sums, one per workgroup at partial[plane * tiles + tile]
+    // (tiles = n / L), when non-null:
+    //   COL_PUPD_WINV_IFFT_CROP   |p|^2 of the chat part; the first plane of
+    //                             each frame adds the rho part's |p|^2 at
+    //                             partial[nplanes * tiles + frame * tiles + tile]
+    //   COL_PAD_FFT_P2_IFFT       |P . DFT(...)|^2 = |DF h|^2 of the plane's coil
+    //   COL_PAD_FFT_WINV_CG_UPD   |r|^2 after the update
     double* partial;
     int tiled;                // n x n planes, P and 1/w column-tiled (inside a solve)
 };
+
+// Sum over an NT-thread workgroup in a fixed order (wavefront shuffle, then
+// the waves in order); the result is valid in thread 0 and `red` (NT/64
+// doubles) is free again on return.
+template <int NT>
+__device__ __forceinline__ double wg_sum(double v, double* red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < NT / 64; ++w) t += red[w];
+    __syncthreads();
+    return t;
+}
 
 // Work item w = tile * nplanes + plane (planes of a tile adjacent, so the P
 // tile of a frame is reused); blocks are dealt to the 8 XCDs round robin, so
@@ -135,10 +161,11 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
     constexpr bool INV1 = WINV_IN || (MODE == COL_P_IFFT_CROP);
     constexpr bool IN_CROP = !INV1;
     constexpr bool OUT_CROP = INV1 || TWO;
-    constexpr bool DOT = (MODE == COL_PAD_FFT_WINV_AXPY_DOT);
-    constexpr bool WINV_OUT = (MODE == COL_PAD_FFT_WINV_ADD) || DOT;
+    constexpr bool CGU = (MODE == COL_PAD_FFT_WINV_CG_UPD);
+    constexpr bool WINV_OUT = (MODE == COL_PAD_FFT_WINV_ADD) || CGU;
+    constexpr bool RED = CGU || PUPD || TWO;       // modes that can write partial sums
     __shared__ float2 bufA[N * L];                 // stage-1 results [k1][j2][l]; slot order [slot][l]
-    __shared__ double red[DOT ? NT / 64 : 1];
+    __shared__ double red[RED ? NT / 64 : 1];
     static_assert(NT % 64 == 0 && NT <= 1024, "pass workgroup size");
 
     int tile, plane;
@@ -149,10 +176,14 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
     const float* P = a.P + (long long)f * a.p_stride;
     const long long pofs = (long long)plane * (IN_CROP ? m : N) * N;
     const float2* src = a.in + pofs;
+    double acc = 0.0;     // this thread's share of the workgroup's partial sum
+    double acc_rho = 0.0;
+    bool first_plane = false;
 
     if constexpr (PUPD) {
         // rho part of the direction update, done by the first plane of each frame
-        if (plane == 0 || (a.plane_frame && a.plane_frame[plane - 1] != f)) {
+        first_plane = plane == 0 || (a.plane_frame && a.plane_frame[plane - 1] != f);
+        if (first_plane) {
             const int E = m * m, ntiles = N / L;
             const int chunk = (E + ntiles - 1) / ntiles;
             const int e0 = tile * chunk, e1 = min(E, e0 + chunk);
@@ -161,7 +192,9 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
             const float2* rr = a.rr + (long long)f * E;
             for (int e = e0 + threadIdx.x; e < e1; e += NT) {
                 const float2 r = rr[e];
-                pr[e] = a.beta ? make_float2(r.x + bf * pr[e].x, r.y + bf * pr[e].y) : r;
+                const float2 pv = a.beta ? make_float2(r.x + bf * pr[e].x, r.y + bf * pr[e].y) : r;
+                pr[e] = pv;
+                acc_rho += (double)(pv.x * pv.x + pv.y * pv.y);
             }
         }
     }
@@ -170,6 +203,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
     for (int t = threadIdx.x; t < L * N2; t += NT) {
         const int l = t % L, j2 = t / L, col = col0 + l;
         float2 v[N1];
+        float pacc = 0.f;
         static_for<0, N1>([&](auto K) {
             constexpr int k1 = K;
             const int r = CT::in_pos(j2, k1);
@@ -190,6 +224,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                             x = rv;
                         }
                         a.p_out[pofs + o] = x;
+                        pacc += x.x * x.x + x.y * x.y;
                     } else {
                         x = src[o];
                     }
@@ -200,6 +235,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
             }
             v[k1] = x;
         });
+        if constexpr (PUPD) acc += (double)pacc;
         RegDFT<N1, INV1>::run(v);
         static_for<0, N1>([&](auto K) {
             constexpr int k1 = K;
@@ -231,12 +267,15 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                     v[j2] = bufA[(k1 * N2 + j2) * L + l];
                 });
                 RegDFT<N2, false>::run(v);
+                float kacc = 0.f;
                 static_for<0, N2>([&](auto K) {
                     constexpr int k2 = K;
                     const int r = CT::out_pos(k1, k2);
                     const float p = P[big_idx<N>(r, col, a.tiled)];
+                    kacc += p * p * (v[k2].x * v[k2].x + v[k2].y * v[k2].y);
                     v[k2] = cscale(v[k2], p * p * rs2);
                 });
+                acc += (double)kacc * (double)rs2;   // |P K|^2 with K = rs . v (unitary DFT)
             }
             __syncthreads();
             if (act) {
@@ -280,7 +319,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
     const long long pbase = (long long)plane * N * N;
     const float s1 = a.s1 ? a.s1[f] : a.c1;
     const float s2 = a.s2 ? a.s2[f] : a.c2;
-    double acc = 0.0;
+    const float av = CGU ? a.cg_a[f] : 0.f;
     for (int t = threadIdx.x; t < L * N1; t += NT) {
         const int l = t % L, k1 = t / L, col = col0 + l;
         float2 v[N2];
@@ -312,17 +351,24 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                     const float2 y = a.add1[pbase + o];
                     const float p = CT::sign(rp) * a.rs * P[o];
                     a.out[pbase + o] = make_float2(s1 * y.x - p * x.x, s1 * y.y - p * x.y);
+                } else if constexpr (CGU) {
+                    x = cscale(x, CT::sign(rp) * a.rs * a.winv[o]);
+                    const float2 u = a.add1[pbase + o];            // p
+                    x.x += s1 * u.x;                                 // q = N_alpha p
+                    x.y += s1 * u.y;
+                    float2 r = a.out[pbase + o];
+                    r.x -= av * x.x;
+                    r.y -= av * x.y;
+                    a.out[pbase + o] = r;
+                    float2 d = a.dx[pbase + o];
+                    d.x += av * u.x;
+                    d.y += av * u.y;
+                    a.dx[pbase + o] = d;
+                    facc += r.x * r.x + r.y * r.y;
                 } else if constexpr (WINV_OUT) {
                     x = cscale(x, CT::sign(rp) * a.rs * a.winv[o]);
-                    if (DOT || a.add1) {
-                        const float2 u = a.add1[pbase + o];
-                        x.x += s1 * u.x;
-                        x.y += s1 * u.y;
-                        if constexpr (DOT) facc += u.x * x.x + u.y * x.y;
-                    }
-                    if constexpr (!DOT) {
-                        if (a.add2) { const float2 u = a.add2[pbase + o]; x.x += s2 * u.x; x.y += s2 * u.y; }
-                    }
+                    if (a.add1) { const float2 u = a.add1[pbase + o]; x.x += s1 * u.x; x.y += s1 * u.y; }
+                    if (a.add2) { const float2 u = a.add2[pbase + o]; x.x += s2 * u.x; x.y += s2 * u.y; }
                     a.out[pbase + o] = x;
                 } else if constexpr (MODE == COL_PAD_FFT_GPROD) {
                     const float2 g = a.add1[pbase + o];
@@ -333,15 +379,17 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
         });
         acc += (double)facc;
     }
-    if constexpr (DOT) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = 0.0;
-            for (int w = 0; w < NT / 64; ++w) t += red[w];
-            a.partial[(long long)plane * (N / L) + tile] = t;
+    if constexpr (RED) {
+        if (a.partial) {   // uniform over the workgroup
+            constexpr long long ntiles = N / L;
+            const double t = wg_sum<NT>(acc, red);
+            if (threadIdx.x == 0) a.partial[(long long)plane * ntiles + tile] = t;
+            if constexpr (PUPD) {
+                if (first_plane) {
+                    const double tr = wg_sum<NT>(acc_rho, red);
+                    if (threadIdx.x == 0) a.partial[((long long)a.nplanes + f) * ntiles + tile] = tr;
+                }
+            }
         }
     }
 }

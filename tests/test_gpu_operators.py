@@ -114,7 +114,7 @@ def test_every_pass_variant_gives_the_same_operator(n, n_om, J):
     n_ref = O.normal(rho, chat, P, 0.5, drho, dchat, d)
     with Plan(n, n_om, J) as pl:
         tried = 0
-        for cv in range(3):
+        for cv in range(4):
             for rv in range(4):
                 try:
                     pl.set_variant(n, cv, rv)
