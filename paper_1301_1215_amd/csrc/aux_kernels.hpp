@@ -58,14 +58,9 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return t;
 }
 
-// Partials are read with device-coherent loads: the last workgroup of a
-// kernel reads what the others wrote in the same launch.
-__device__ __forceinline__ double load_partial(const double* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Fixed-order total of frame f: the chat segments of its planes (plane
-// order), then its rho segments.  All threads call it; valid in thread 0.
+// order), then its rho segments; the partials come from earlier kernels.
+// All threads call it; valid in thread 0.
 __device__ __forceinline__ double frame_total(const SegGeom& g, const double* partial, int f,
                                               const int* frame_plane0, const int* frame_planes,
                                               double* red) {
@@ -75,8 +70,8 @@ __device__ __forceinline__ double frame_total(const SegGeom& g, const double* pa
     const int tot = nc + g.rseg;
     double acc = 0.0;
     for (int i = threadIdx.x; i < tot; i += kThreads) {
-        acc += (i < nc) ? load_partial(partial + (long long)p0 * g.cseg + i)
-                        : load_partial(partial + (long long)g.nplanes * g.cseg + (long long)f * g.rseg + (i - nc));
+        acc += (i < nc) ? partial[(long long)p0 * g.cseg + i]
+                        : partial[(long long)g.nplanes * g.cseg + (long long)f * g.rseg + (i - nc)];
     }
     return block_sum(acc, red);
 }

@@ -12,7 +12,8 @@ namespace nlinv {
 #define NLINV_FOR_EACH_SIZE(X) \
     X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
 
-// Pass variants = lines (columns or rows) per 256-thread workgroup.
+// Pass variants: lines (columns or rows) per workgroup (its size follows
+// from the lines and the line FFT split, pass_threads()).
 constexpr int kColL[] = {16, 8, 32, 4};
 constexpr int kRowL[] = {8, 16, 4, 2};
 constexpr int kNumColVariants = 4;

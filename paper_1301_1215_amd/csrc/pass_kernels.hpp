@@ -164,7 +164,11 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
     constexpr bool CGU = (MODE == COL_PAD_FFT_WINV_CG_UPD);
     constexpr bool WINV_OUT = (MODE == COL_PAD_FFT_WINV_ADD) || CGU;
     constexpr bool RED = CGU || PUPD || TWO;       // modes that can write partial sums
-    __shared__ float2 bufA[N * L];                 // stage-1 results [k1][j2][l]; slot order [slot][l]
+    // Exchange buffer [k1][j2][l] (slot j2 + N2 k1 of line l), each k1 row
+    // padded by L entries: the L-line groups of one wavefront then fall on
+    // different LDS banks in every access pattern below.
+    constexpr int RS = (N2 + 1) * L;               // k1 row stride
+    __shared__ float2 bufA[N1 * RS];
     __shared__ double red[RED ? NT / 64 : 1];
     static_assert(NT % 64 == 0 && NT <= 1024, "pass workgroup size");
 
@@ -244,7 +248,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                 const float2 w = a.tw2[k1 * N2 + j2];
                 x = INV1 ? cmulc(x, w) : cmul(x, w);
             }
-            bufA[(k1 * N2 + j2) * L + l] = x;
+            bufA[k1 * RS + j2 * L + l] = x;
         });
     }
     __syncthreads();
@@ -264,7 +268,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
             if (act) {
                 static_for<0, N2>([&](auto J) {
                     constexpr int j2 = J;
-                    v[j2] = bufA[(k1 * N2 + j2) * L + l];
+                    v[j2] = bufA[k1 * RS + j2 * L + l];
                 });
                 RegDFT<N2, false>::run(v);
                 float kacc = 0.f;
@@ -281,7 +285,8 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
             if (act) {
                 static_for<0, N2>([&](auto K) {
                     constexpr int k2 = K;
-                    bufA[(k1 + N1 * k2) * L + l] = v[k2];
+                    const int sl = k1 + N1 * k2;           // slot sl = j2' + N2 k1'
+                    bufA[(sl / N2) * RS + (sl % N2) * L + l] = v[k2];
                 });
             }
         }
@@ -295,7 +300,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
             if (act) {
                 static_for<0, N1>([&](auto K) {
                     constexpr int k1 = K;
-                    v[k1] = bufA[(j2 + N2 * k1) * L + l];
+                    v[k1] = bufA[k1 * RS + j2 * L + l];
                 });
                 RegDFT<N1, true>::run(v);
                 static_for<0, N1>([&](auto K) {
@@ -307,7 +312,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
             if (act) {
                 static_for<0, N1>([&](auto K) {
                     constexpr int k1 = K;
-                    bufA[(k1 * N2 + j2) * L + l] = v[k1];
+                    bufA[k1 * RS + j2 * L + l] = v[k1];
                 });
             }
         }
@@ -325,7 +330,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
         float2 v[N2];
         static_for<0, N2>([&](auto J) {
             constexpr int j2 = J;
-            v[j2] = bufA[(k1 * N2 + j2) * L + l];
+            v[j2] = bufA[k1 * RS + j2 * L + l];
         });
         RegDFT<N2, INV2>::run(v);
         float facc = 0.f;
