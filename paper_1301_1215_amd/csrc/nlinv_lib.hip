@@ -133,7 +133,7 @@ struct Class {
     float2* tw = nullptr;
     float* winv = nullptr;       // [n][n] 1/w, row-major
     float* winv_t = nullptr;     // the same, column-tiled (solve layout)
-    int tilew = 16;              // tile width of the solve layout
+    int tilew = 8;               // tile width of the solve layout
     float2 *x_c = nullptr, *x_r = nullptr, *dx_c = nullptr, *dx_r = nullptr;
     float2 *r_c = nullptr, *r_r = nullptr, *p_c = nullptr, *p_r = nullptr;
     float2 *q_c = nullptr, *q_r = nullptr, *xr_c = nullptr, *xr_r = nullptr;
@@ -887,7 +887,7 @@ int make_weight_table(nlinv_plan_s* p, Class& C) {
 }
 
 int build_class(nlinv_plan_s* p, Class& C) {
-    C.tilew = C.n % 16 == 0 ? 16 : C.n % 8 == 0 ? 8 : 4;     // as plane_tile<N>()
+    C.tilew = plane_tile_width(C.n);
     CHK(make_twiddles(p, C));
     CHK(make_weight_table(p, C));
     const long long cn = C.cplane(), rn = C.rplane();

@@ -45,12 +45,16 @@ struct Centre {
 };
 
 // Inside a solve the n x n planes (CG vectors, data, P, 1/w) are stored
-// column-tiled: [n / TW][n][TW], TW = 16 (8 or 4 when n is not a multiple of
-// 16), so that a column pass reads and writes contiguous blocks instead of
-// TW-wide row segments n apart.  The operator entry points take the plain
-// row-major layout of the caller's arrays.
+// column-tiled: [n / TW][n][TW], TW = 8 (4 when n is not a multiple of 8),
+// so that a column pass reads and writes contiguous blocks instead of
+// TW-wide row segments n apart.  A pass over L >= TW columns then covers
+// whole tiles, hence whole cache lines: a tile wider than L would leave
+// each line split between two workgroups, which fetch it twice.  The
+// operator entry points take the plain row-major layout of the caller's
+// arrays.
+constexpr int plane_tile_width(int n) { return n % 8 == 0 ? 8 : 4; }
 template <int N>
-constexpr int plane_tile() { return N % 16 == 0 ? 16 : N % 8 == 0 ? 8 : 4; }
+constexpr int plane_tile() { return plane_tile_width(N); }
 
 template <int N>
 __device__ __forceinline__ long long big_idx(int r, int col, int tiled) {
