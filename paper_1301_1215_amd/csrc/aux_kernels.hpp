@@ -4,159 +4,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "cg_scalars.hpp"
 #include "fft_core.hpp"
 
 namespace nlinv {
-
-// ---------------------------------------------------------------------------
-// segment geometry of a class-wide CG vector:
-//   chat part [planes][n*n] in `cseg` segments per plane,
-//   rho part  [frames][m*m] in `rseg` segments per frame;
-// one FP64 partial per segment, summed per frame in a fixed order.
-// ---------------------------------------------------------------------------
-
-struct SegGeom {
-    int nplanes, nframes;
-    int cn, rn;          // elements per plane / per frame (complex)
-    int cseg, rseg;      // segments per plane / per frame
-    int clen, rlen;      // elements per segment (even), last one ragged
-    const int* plane_frame;
-};
-
-__device__ __forceinline__ void seg_locate(const SegGeom& g, int s, bool& is_c, int& owner, int& f,
-                                           long long& base, int& len) {
-    const int ncs = g.nplanes * g.cseg;
-    if (s < ncs) {
-        is_c = true;
-        owner = s / g.cseg;
-        const int k = s % g.cseg;
-        f = g.plane_frame ? g.plane_frame[owner] : 0;
-        base = (long long)owner * g.cn + (long long)k * g.clen;
-        len = min(g.clen, g.cn - k * g.clen);
-    } else {
-        is_c = false;
-        const int t = s - ncs;
-        owner = t / g.rseg;
-        const int k = t % g.rseg;
-        f = owner;
-        base = (long long)owner * g.rn + (long long)k * g.rlen;
-        len = min(g.rlen, g.rn - k * g.rlen);
-    }
-}
-
-// Sum over a 256-thread workgroup in a fixed order (wavefront shuffle, then
-// the 4 waves); the result is valid in thread 0.
-__device__ __forceinline__ double block_sum(double v, double* red) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) red[wv] = v;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x == 0) t = (red[0] + red[1]) + (red[2] + red[3]);
-    __syncthreads();
-    return t;
-}
-
-// Fixed-order total of frame f: the chat segments of its planes (plane
-// order), then its rho segments; the partials come from earlier kernels.
-// All threads call it; valid in thread 0.
-__device__ __forceinline__ double frame_total(const SegGeom& g, const double* partial, int f,
-                                              const int* frame_plane0, const int* frame_planes,
-                                              double* red) {
-    const int p0 = frame_plane0 ? frame_plane0[f] : 0;
-    const int np = frame_planes ? frame_planes[f] : g.nplanes;
-    const int nc = np * g.cseg;
-    const int tot = nc + g.rseg;
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < tot; i += kThreads) {
-        acc += (i < nc) ? partial[(long long)p0 * g.cseg + i]
-                        : partial[(long long)g.nplanes * g.cseg + (long long)f * g.rseg + (i - nc)];
-    }
-    return block_sum(acc, red);
-}
-
-// CG and Newton scalars of every frame of a class, all on the device.
-struct Scalars {
-    double* rr;        // [F] <r, r>
-    float* a;          // [F] CG step a = rr / gamma
-    float* beta;       // [F]
-    int* brk;          // [F] breakdown in the current Newton step
-    float* alpha;      // [F] current alpha (and -alpha at alpha + F)
-    float* s;          // [F] data scale
-    float* inv_s;      // [F]
-    double* stats;     // [F][stats_len]
-    int stats_len;
-};
-
-enum ScalarOp : int {
-    SC_NONE = -1,
-    SC_YNORM = 0,      // s = scale_norm / ||y|| (scale_norm > 0 and ||y|| > 0), else 1
-    SC_R0NORM = 1,     // stats[2 + step] = ||r0||
-    SC_RR0 = 2,        // rr = <b, b>; new Newton step: clear breakdown
-    SC_GAMMA = 3,      // gamma = Re<p, q> (or |DF p|^2 + alpha |p|^2); a = rr / gamma or breakdown
-    SC_RR = 4,         // rr' = <r, r>; beta = rr'/rr; rr = rr'; stats of CG iteration `it`
-};
-
-// Where a scalar op is applied: which op, geometry of its partials, indices
-// for the stats.  With `partial2` set the total is
-// sum(partial) + alpha_f * sum(partial2) (geometry g2).
-struct ScalarStep {
-    int op;
-    SegGeom g;
-    const double* partial;
-    SegGeom g2;
-    const double* partial2;
-    const int* frame_plane0;
-    const int* frame_planes;
-    float scale_norm;
-    int step, it, nsteps, ncg;
-};
-
-// The scalar logic for frame f given the total t (thread 0 only).
-__device__ __forceinline__ void scalar_apply(const ScalarStep& ss, const Scalars& sc, int f, double t) {
-    double* st = sc.stats + (long long)f * sc.stats_len;
-    const int op = ss.op;
-    if (op == SC_YNORM) {
-        const double nrm = sqrt(t);
-        const float s = (ss.scale_norm > 0.f && nrm > 0.0) ? (float)(ss.scale_norm / nrm) : 1.0f;
-        sc.s[f] = s;
-        sc.inv_s[f] = 1.0f / s;
-        st[0] = (double)s;
-        st[1] = 0.0;
-        if (!isfinite(nrm)) st[1] = 2.0;
-    } else if (op == SC_R0NORM) {
-        st[2 + ss.step] = sqrt(t);
-        if (!isfinite(t)) st[1] = (double)((int)st[1] | 2);
-    } else if (op == SC_RR0) {
-        sc.rr[f] = t;
-        sc.brk[f] = 0;
-    } else if (op == SC_GAMMA) {
-        const double rr = sc.rr[f];
-        if (sc.brk[f] || rr == 0.0 || !(t > 0.0) || !isfinite(rr)) {
-            if (!sc.brk[f]) {
-                int fl = (int)st[1] | 1;
-                if (!isfinite(t) || !isfinite(rr)) fl |= 2;
-                st[1] = (double)fl;
-            }
-            sc.brk[f] = 1;
-            sc.a[f] = 0.f;
-        } else {
-            sc.a[f] = (float)(rr / t);
-        }
-    } else if (op == SC_RR) {
-        double* slot = st + 2 + ss.nsteps + ss.step * ss.ncg + ss.it;
-        if (sc.brk[f]) {
-            sc.beta[f] = 0.f;
-            *slot = -1.0;
-        } else {
-            if (!isfinite(t)) st[1] = (double)((int)st[1] | 2);
-            sc.beta[f] = (float)(t / sc.rr[f]);
-            sc.rr[f] = t;
-            *slot = t;
-        }
-    }
-}
 
 // ---------------------------------------------------------------------------
 // coil sums over the planes of each frame (fixed order: deterministic)
@@ -166,6 +17,7 @@ __device__ __forceinline__ void scalar_apply(const ScalarStep& ss, const Scalars
 // One thread per Omega pixel, one workgroup per (frame, segment of
 // `seg_len` pixels); with `partial` set it also writes Re<add1, out> of its
 // segment to partial[poff + f*segs + k].
+// With self_dot the partial is |out|^2 instead.
 // CG form (r_upd set): the sum q (with add1 = p, s1 = alpha) is not stored;
 // instead r -= a_f q and dx += a_f p, and the partial is |r|^2.
 struct CoilSumArgs {
@@ -184,6 +36,7 @@ struct CoilSumArgs {
     int segs, seg_len;       // seg_len <= kThreads
     double* partial;
     long long poff;
+    int self_dot;
     float2* r_upd;           // CG form: rho part of r (in place), nullable
     float2* dx_upd;          // rho part of dx (in place)
     const float* cg_a;       // [frames] CG step a
@@ -225,7 +78,8 @@ __global__ __launch_bounds__(kThreads) void k_coil_sum(CoilSumArgs a) {
             acc = (double)(r.x * r.x + r.y * r.y);
         } else {
             a.out[g] = s;
-            if (a.partial && a.add1) { const float2 u = a.add1[g]; acc = (double)(u.x * s.x + u.y * s.y); }
+            if (a.self_dot) acc = (double)(s.x * s.x + s.y * s.y);
+            else if (a.partial && a.add1) { const float2 u = a.add1[g]; acc = (double)(u.x * s.x + u.y * s.y); }
         }
     }
     if (a.partial) {

@@ -294,6 +294,7 @@ RowArgs row_args(const Class& C) {
     a.lo = C.lo;
     a.rs = (float)(1.0 / std::sqrt((double)C.n));
     a.tw2 = C.tw;
+    a.fold.op = SC_NONE;
     return a;
 }
 
@@ -438,9 +439,10 @@ int seq_coil_maps(nlinv_plan_s* p, const Class& C, const Frames& fr, const float
 }
 
 // out = P . DFT(E(rho . c))  or, with y != NULL, out = s y - P . DFT(E(rho . c))
+// (then with `partial` set: |out|^2 per column tile into it, `g` its geometry)
 int seq_forward(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2* rho, const float2* c,
                 const float* P, long long p_stride, float2* out, const float2* y, const float* s_y,
-                hipStream_t s) {
+                hipStream_t s, double* partial = nullptr, SegGeom* g = nullptr) {
     RowArgs r = row_args(C);
     r.c = c;
     r.rho = rho;
@@ -458,6 +460,12 @@ int seq_forward(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2*
         a.add1 = y;
         a.s1 = s_y;
         a.c1 = 1.f;
+        a.partial = partial;
+        if (g) {
+            *g = C.geom;
+            g->cseg = C.n / kColL[C.colv[COL_PAD_FFT_P_RESID]];
+            g->rseg = 0;
+        }
         return run_col(p, C, COL_PAD_FFT_P_RESID, a, fr.nplanes, s);
     }
     return run_col(p, C, COL_PAD_FFT_P, a, fr.nplanes, s);
@@ -485,10 +493,11 @@ int seq_deriv_head(nlinv_plan_s* p, const Class& C, const Frames& fr, const floa
 // from T = crop_rows(IDFT_0(...)): u = crop(IDFT_1(T)); aux = conj(c) u;
 // dchat_out = W^{-H} E(conj(rho) u) + s1 add1 + s2 add2;
 // drho_out = sum_j aux + s1 add1r + s2 add2r
+// (with `partial` set: |(drho_out, dchat_out)|^2 partials into it, `g` their geometry)
 int seq_adjoint_tail(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2* rho, const float2* c,
                      float2* drho_out, float2* dchat_out, const float2* add1c, const float2* add1r,
                      const float2* add2c, const float2* add2r, const float* s1, const float* s2,
-                     float c1, float c2, hipStream_t s) {
+                     float c1, float c2, hipStream_t s, double* partial = nullptr, SegGeom* g = nullptr) {
     RowArgs r = row_args(C);
     r.in = C.T;
     r.out = C.T;
@@ -508,8 +517,18 @@ int seq_adjoint_tail(nlinv_plan_s* p, const Class& C, const Frames& fr, const fl
     a.s2 = s2;
     a.c1 = c1;
     a.c2 = c2;
+    a.partial = partial;
     CHK(run_col(p, C, COL_PAD_FFT_WINV_ADD, a, fr.nplanes, s));
-    return run_coil_sum(p, coil_sum_args(C, fr, drho_out, add1r, add2r, s1, s2, c1, c2, nullptr, 0), s);
+    const int nt = C.n / kColL[C.colv[COL_PAD_FFT_WINV_ADD]];
+    CoilSumArgs cs = coil_sum_args(C, fr, drho_out, add1r, add2r, s1, s2, c1, c2, partial,
+                                   (long long)fr.nplanes * nt);
+    cs.self_dot = partial != nullptr;
+    if (g) {
+        *g = C.geom;
+        g->cseg = nt;
+        g->rseg = cs.segs;
+    }
+    return run_coil_sum(p, cs, s);
 }
 
 // One CG iteration on every frame of class C (Newton step `step`, CG
@@ -552,7 +571,7 @@ int seq_cg_iteration(nlinv_plan_s* p, Class& C, const float* beta, int step, int
     b.plane_frame = fr.plane_frame;
     b.partial = C.partial;
     CHK(run_col(p, C, COL_PAD_FFT_P2_IFFT, b, fr.nplanes, s));
-    // a = <r,r> / (|DF p|^2 + alpha |p|^2) per frame
+    // a = <r,r> / (|DF p|^2 + alpha |p|^2) per frame, folded into the adjoint row pass
     {
         const int tp = C.n / kColL[C.colv[COL_PUPD_WINV_IFFT_CROP]];
         const int tg = C.n / kColL[C.colv[COL_PAD_FFT_P2_IFFT]];
@@ -563,7 +582,8 @@ int seq_cg_iteration(nlinv_plan_s* p, Class& C, const float* beta, int step, int
         ss.g2.cseg = tp;
         ss.g2.rseg = tp;
         ss.partial2 = C.part_p;
-        CHK(launch_scalar(p, C, ss, s));
+        r.fold = ss;
+        r.sc = C.sc;
     }
     r.aux = C.aux;
     r.drho = nullptr;
@@ -630,9 +650,9 @@ int enqueue_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s
             // linearisation cache c at x_n
             CHK(seq_coil_maps(p, C, fr, C.x_c, C.c, s));
             // r0 = s y - F(x_n) into q, its norm
-            CHK(seq_forward(p, C, fr, C.x_r, C.c, C.P, ps, C.q_c, C.y, C.sc.s, s));
-            CHK(run_vec<VEC_DOT>(p, C.geomC, vptrs(C.q_c, nullptr, C.q_c, nullptr), C.partial, s));
-            CHK(run_scalar(p, C, SC_R0NORM, C.geomC, 0.f, step, s));
+            SegGeom g0{};
+            CHK(seq_forward(p, C, fr, C.x_r, C.c, C.P, ps, C.q_c, C.y, C.sc.s, s, C.partial, &g0));
+            CHK(run_scalar(p, C, SC_R0NORM, g0, 0.f, step, s));
             // b = DF^H r0 - alpha (x_n - x_ref) into r
             {
                 ColArgs a = col_args(p, C, fr.tiled);
@@ -642,8 +662,10 @@ int enqueue_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s
                 a.p_stride = ps;
                 a.plane_frame = fr.plane_frame;
                 CHK(run_col(p, C, COL_P_IFFT_CROP, a, fr.nplanes, s));
+                SegGeom gb{};
                 CHK(seq_adjoint_tail(p, C, fr, C.x_r, C.c, C.r_r, C.r_c, C.x_c, C.x_r, C.xr_c, C.xr_r,
-                                     C.alpha + C.nframes, C.alpha, 0.f, 0.f, s));
+                                     C.alpha + C.nframes, C.alpha, 0.f, 0.f, s, C.partial, &gb));
+                CHK(run_scalar(p, C, SC_RR0, gb, 0.f, step, s));
             }
             {
                 const int slot = tbegin(p, KC_VEC_OTHER, s);
@@ -654,8 +676,6 @@ int enqueue_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s
                 tend(p, slot, s);
                 HIPCHK(hipGetLastError());
             }
-            CHK(run_vec<VEC_DOT>(p, C.geom, vptrs(C.r_c, C.r_r, C.r_c, C.r_r), C.partial, s));
-            CHK(run_scalar(p, C, SC_RR0, C.geom, 0.f, step, s));
         }
         for (int it = 0; it < K; ++it) {
             for (Class& C : p->classes)
@@ -1031,7 +1051,9 @@ int tune_class(nlinv_plan_s* p, Class& C, hipStream_t s) {
         float best = 1e30f;
         int bestv = C.colv[mode];
         for (int v = 0; v < kNumColVariants; ++v) {
-            if (!col_ok(C.n, v)) continue;
+            // fewer lines than the tile width would split cache lines between
+            // workgroups: cheap when timed warm here, not in a solve
+            if (!col_ok(C.n, v) || kColL[v] < C.tilew) continue;
             C.colv[mode] = v;
             float ms = 0.f;
             CHK(timeit([&] { return run_col(p, C, mode, a, nplanes, s); }, ms));
@@ -1442,7 +1464,10 @@ int nlinv_plan_timing_enable(nlinv_plan p, int32_t kclass, int32_t enable) {
     if (enable && p->ev.empty()) {
         p->ev.resize(2 * kTimingSlots);
         p->ev_used.assign(kTimingSlots, 0);
-        for (auto& e : p->ev) HIPCHK(hipEventCreate(&e));
+        // timing-only events: no system-scope fence (cache writeback) at
+        // each record, which would stall the kernels around the bracket;
+        // their times are read after the stream has been synchronised
+        for (auto& e : p->ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     }
     p->timing[kclass] = enable != 0;
     CHK(drop_graph(p));   // a captured graph holds the old brackets

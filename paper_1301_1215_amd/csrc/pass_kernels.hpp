@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "cg_scalars.hpp"
 #include "fft_core.hpp"
 
 namespace nlinv {
@@ -118,7 +119,9 @@ struct ColArgs {
     //   COL_PUPD_WINV_IFFT_CROP   |p|^2 of the chat part; the first plane of
     //                             each frame adds the rho part's |p|^2 at
     //                             partial[nplanes * tiles + frame * tiles + tile]
+    //   COL_PAD_FFT_P_RESID       |out|^2 (the residual's norm)
     //   COL_PAD_FFT_P2_IFFT       |P . DFT(...)|^2 = |DF h|^2 of the plane's coil
+    //   COL_PAD_FFT_WINV_ADD      |out|^2
     //   COL_PAD_FFT_WINV_CG_UPD   |r|^2 after the update
     double* partial;
     int tiled;                // n x n planes, P and 1/w column-tiled (inside a solve)
@@ -167,7 +170,8 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
     constexpr bool OUT_CROP = INV1 || TWO;
     constexpr bool CGU = (MODE == COL_PAD_FFT_WINV_CG_UPD);
     constexpr bool WINV_OUT = (MODE == COL_PAD_FFT_WINV_ADD) || CGU;
-    constexpr bool RED = CGU || PUPD || TWO;       // modes that can write partial sums
+    constexpr bool RESID = (MODE == COL_PAD_FFT_P_RESID);
+    constexpr bool RED = CGU || PUPD || TWO || RESID || (MODE == COL_PAD_FFT_WINV_ADD);  // can write partial sums
     // Exchange buffer [k1][j2][l] (slot j2 + N2 k1 of line l), each k1 row
     // padded by L entries: the L-line groups of one wavefront then fall on
     // different LDS banks in every access pattern below.
@@ -359,7 +363,9 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                 } else if constexpr (MODE == COL_PAD_FFT_P_RESID) {
                     const float2 y = a.add1[pbase + o];
                     const float p = CT::sign(rp) * a.rs * P[o];
-                    a.out[pbase + o] = make_float2(s1 * y.x - p * x.x, s1 * y.y - p * x.y);
+                    const float2 z = make_float2(s1 * y.x - p * x.x, s1 * y.y - p * x.y);
+                    a.out[pbase + o] = z;
+                    facc += z.x * z.x + z.y * z.y;
                 } else if constexpr (CGU) {
                     x = cscale(x, CT::sign(rp) * a.rs * a.winv[o]);
                     const float2 u = a.add1[pbase + o];            // p
@@ -379,6 +385,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                     if (a.add1) { const float2 u = a.add1[pbase + o]; x.x += s1 * u.x; x.y += s1 * u.y; }
                     if (a.add2) { const float2 u = a.add2[pbase + o]; x.x += s2 * u.x; x.y += s2 * u.y; }
                     a.out[pbase + o] = x;
+                    facc += x.x * x.x + x.y * x.y;
                 } else if constexpr (MODE == COL_PAD_FFT_GPROD) {
                     const float2 g = a.add1[pbase + o];
                     x = cscale(x, CT::sign(rp) * a.rs);
@@ -427,6 +434,11 @@ struct RowArgs {
     int m, lo;
     float rs;
     const float2* tw2;       // [N1][N2]
+    // ROW_ADJ: a per-frame scalar step folded into the launch (op SC_NONE or
+    // partial == nullptr: none), done by the first wavefront of the first
+    // workgroups before their lines
+    ScalarStep fold;
+    Scalars sc;
 };
 
 template <int N, int L, int MODE>
@@ -442,6 +454,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
     const int line0 = blockIdx.x * L;
     const int m = a.m, lo = a.lo;
     const int t = threadIdx.x;
+    if constexpr (MODE == ROW_ADJ) fold_scalar_step(a.fold, a.sc);
 
     if constexpr (MODE == ROW_FWD) {
         for (int idx = t; idx < L * N; idx += NT) {
