@@ -134,7 +134,7 @@ struct Class {
     float* winv = nullptr;       // [n][n] 1/w, row-major
     float* winv_t = nullptr;     // the same, column-tiled (solve layout)
     int tilew = 8;               // tile width of the solve layout
-    float2 *x_c = nullptr, *x_r = nullptr, *dx_c = nullptr, *dx_r = nullptr;
+    float2 *x_c = nullptr, *x_r = nullptr, *dx_r = nullptr;   // the chat part of dx goes into x_c
     float2 *r_c = nullptr, *r_r = nullptr, *p_c = nullptr, *p_r = nullptr;
     float2 *q_c = nullptr, *q_r = nullptr, *xr_c = nullptr, *xr_r = nullptr;
     float2* y = nullptr;
@@ -592,7 +592,11 @@ int seq_cg_iteration(nlinv_plan_s* p, Class& C, const float* beta, int step, int
     ColArgs e = col_args(p, C, fr.tiled);
     e.in = C.T;
     e.out = C.r_c;
-    e.dx = C.dx_c;
+    // the step's chat part goes straight into x: x's chat part is not read
+    // during CG (the linearisation uses the cached sensitivities c, and the
+    // right-hand side is formed before it); its rho part is (rho in DF), so
+    // that part collects in dx_r until CG ends
+    e.dx = C.x_c;
     e.plane_frame = fr.plane_frame;
     e.add1 = C.p_c;
     e.s1 = C.alpha;
@@ -669,8 +673,6 @@ int enqueue_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s
             }
             {
                 const int slot = tbegin(p, KC_VEC_OTHER, s);
-                hipLaunchKernelGGL(k_fill, dim3(grid_for((long long)C.nplanes * ps)), dim3(kThreads), 0, s,
-                                   C.dx_c, (long long)C.nplanes * ps, make_float2(0.f, 0.f));
                 hipLaunchKernelGGL(k_fill, dim3(grid_for((long long)C.nframes * C.rplane())), dim3(kThreads), 0, s,
                                    C.dx_r, (long long)C.nframes * C.rplane(), make_float2(0.f, 0.f));
                 tend(p, slot, s);
@@ -681,8 +683,11 @@ int enqueue_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s
             for (Class& C : p->classes)
                 CHK(seq_cg_iteration(p, C, it == 0 ? nullptr : C.sc.beta, step, it, N, K, s));
         }
-        for (Class& C : p->classes)
-            CHK(run_vec<VEC_ADD>(p, C.geom, vptrs(C.x_c, C.x_r, C.dx_c, C.dx_r), nullptr, s));
+        for (Class& C : p->classes) {   // rho += drho (the chat part is already in x)
+            SegGeom g = C.geom;
+            g.nplanes = 0;
+            CHK(run_vec<VEC_ADD>(p, g, vptrs(nullptr, C.x_r, nullptr, C.dx_r), nullptr, s));
+        }
     }
     // sensitivities of the final x (for the image)
     for (Class& C : p->classes) CHK(seq_coil_maps(p, C, class_frames(C), C.x_c, C.c, s));
@@ -924,7 +929,7 @@ int build_class(nlinv_plan_s* p, Class& C) {
     HIPCHK(hipMemcpy(C.plane_frame, pf.data(), pf.size() * sizeof(int), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(C.frame_plane0, fp0.data(), fp0.size() * sizeof(int), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(C.frame_planes, fpn.data(), fpn.size() * sizeof(int), hipMemcpyHostToDevice));
-    float2** cvecs[] = {&C.x_c, &C.dx_c, &C.r_c, &C.p_c, &C.q_c, &C.xr_c, &C.y};
+    float2** cvecs[] = {&C.x_c, &C.r_c, &C.p_c, &C.q_c, &C.xr_c, &C.y};
     for (float2** v : cvecs) CHK(dalloc(p, v, cv));
     float2** rvecs[] = {&C.x_r, &C.dx_r, &C.r_r, &C.p_r, &C.q_r, &C.xr_r};
     for (float2** v : rvecs) CHK(dalloc(p, v, rv));
@@ -1001,7 +1006,7 @@ ColArgs tune_col_args(nlinv_plan_s* p, Class& C, int mode) {
             a.out = C.r_c; a.add1 = C.x_c; a.add2 = C.xr_c; a.s1 = C.alpha + C.nframes; a.s2 = C.alpha;
             break;
         case COL_PAD_FFT_WINV_CG_UPD:
-            a.out = C.r_c; a.dx = C.dx_c; a.add1 = C.p_c; a.s1 = C.alpha; a.cg_a = C.sc.a; a.partial = C.partial2;
+            a.out = C.r_c; a.dx = C.q_c; a.add1 = C.p_c;   // q_c: scratch here a.s1 = C.alpha; a.cg_a = C.sc.a; a.partial = C.partial2;
             break;
         default: break;
     }

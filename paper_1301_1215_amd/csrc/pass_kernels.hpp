@@ -112,7 +112,7 @@ struct ColArgs {
     float2* pr;               // rho part of p [frames][m*m], updated by the first plane of each frame
     const float2* rr;         // rho part of r
     // COL_PAD_FFT_WINV_CG_UPD: out = r (updated in place), add1 = p, s1 = alpha
-    float2* dx;               // chat part of the CG solution (updated in place)
+    float2* dx;               // chat part of the accumulated step (x itself inside a solve)
     const float* cg_a;        // [frames] CG step a
     // FP64 partial sums, one per workgroup at partial[plane * tiles + tile]
     // (tiles = n / L), when non-null:
