@@ -12,18 +12,32 @@ static hipError_t col_L(int mode, const ColArgs& a, int nplanes, hipStream_t s) 
     // 1D grid, a multiple of 8 blocks: the kernel deals work items to XCDs
     const int total = (N / L) * nplanes;
     const dim3 grid(8 * ((total + 7) / 8)), block(pass_threads(N, L));
-    switch (mode) {
-        case COL_WINV_IFFT_CROP: hipLaunchKernelGGL((k_col<N, L, COL_WINV_IFFT_CROP>), grid, block, 0, s, a); break;
-        case COL_P_IFFT_CROP: hipLaunchKernelGGL((k_col<N, L, COL_P_IFFT_CROP>), grid, block, 0, s, a); break;
-        case COL_PAD_FFT_P: hipLaunchKernelGGL((k_col<N, L, COL_PAD_FFT_P>), grid, block, 0, s, a); break;
-        case COL_PAD_FFT_P_RESID: hipLaunchKernelGGL((k_col<N, L, COL_PAD_FFT_P_RESID>), grid, block, 0, s, a); break;
-        case COL_PAD_FFT_P2_IFFT: hipLaunchKernelGGL((k_col<N, L, COL_PAD_FFT_P2_IFFT>), grid, block, 0, s, a); break;
-        case COL_PAD_FFT_WINV_ADD: hipLaunchKernelGGL((k_col<N, L, COL_PAD_FFT_WINV_ADD>), grid, block, 0, s, a); break;
-        case COL_PAD_FFT_GPROD: hipLaunchKernelGGL((k_col<N, L, COL_PAD_FFT_GPROD>), grid, block, 0, s, a); break;
-        case COL_PUPD_WINV_IFFT_CROP: hipLaunchKernelGGL((k_col<N, L, COL_PUPD_WINV_IFFT_CROP>), grid, block, 0, s, a); break;
-        case COL_PAD_FFT_WINV_CG_UPD: hipLaunchKernelGGL((k_col<N, L, COL_PAD_FFT_WINV_CG_UPD>), grid, block, 0, s, a); break;
-        default: return hipErrorInvalidValue;
+#define NLINV_COL(MODE, T) hipLaunchKernelGGL((k_col<N, L, MODE, T>), grid, block, 0, s, a)
+    if (a.tiled) {   // inside a solve: every mode
+        switch (mode) {
+            case COL_WINV_IFFT_CROP: NLINV_COL(COL_WINV_IFFT_CROP, true); break;
+            case COL_P_IFFT_CROP: NLINV_COL(COL_P_IFFT_CROP, true); break;
+            case COL_PAD_FFT_P: NLINV_COL(COL_PAD_FFT_P, true); break;
+            case COL_PAD_FFT_P_RESID: NLINV_COL(COL_PAD_FFT_P_RESID, true); break;
+            case COL_PAD_FFT_P2_IFFT: NLINV_COL(COL_PAD_FFT_P2_IFFT, true); break;
+            case COL_PAD_FFT_WINV_ADD: NLINV_COL(COL_PAD_FFT_WINV_ADD, true); break;
+            case COL_PAD_FFT_GPROD: NLINV_COL(COL_PAD_FFT_GPROD, true); break;
+            case COL_PUPD_WINV_IFFT_CROP: NLINV_COL(COL_PUPD_WINV_IFFT_CROP, true); break;
+            case COL_PAD_FFT_WINV_CG_UPD: NLINV_COL(COL_PAD_FFT_WINV_CG_UPD, true); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else {         // the operator entry points on row-major arrays
+        switch (mode) {
+            case COL_WINV_IFFT_CROP: NLINV_COL(COL_WINV_IFFT_CROP, false); break;
+            case COL_P_IFFT_CROP: NLINV_COL(COL_P_IFFT_CROP, false); break;
+            case COL_PAD_FFT_P: NLINV_COL(COL_PAD_FFT_P, false); break;
+            case COL_PAD_FFT_P2_IFFT: NLINV_COL(COL_PAD_FFT_P2_IFFT, false); break;
+            case COL_PAD_FFT_WINV_ADD: NLINV_COL(COL_PAD_FFT_WINV_ADD, false); break;
+            case COL_PAD_FFT_GPROD: NLINV_COL(COL_PAD_FFT_GPROD, false); break;
+            default: return hipErrorInvalidValue;
+        }
     }
+#undef NLINV_COL
     return hipGetLastError();
 }
 

@@ -298,7 +298,35 @@ RowArgs row_args(const Class& C) {
     return a;
 }
 
+// Every operand a pass mode reads or writes unconditionally must be set: a
+// launch with one missing is refused here instead of faulting on the GPU.
+bool col_operands_ok(int mode, const ColArgs& a) {
+    if (!a.in || !a.out || !a.tw2) return false;
+    switch (mode) {
+        case COL_WINV_IFFT_CROP: return a.winv;
+        case COL_P_IFFT_CROP: case COL_PAD_FFT_P: case COL_PAD_FFT_P2_IFFT: return a.P;
+        case COL_PAD_FFT_P_RESID: return a.P && a.add1;
+        case COL_PAD_FFT_WINV_ADD: return a.winv;
+        case COL_PAD_FFT_GPROD: return a.add1;
+        case COL_PUPD_WINV_IFFT_CROP: return a.winv && a.r_in && a.p_out && a.pr && a.rr;
+        case COL_PAD_FFT_WINV_CG_UPD: return a.winv && a.add1 && a.dx && a.cg_a;
+        default: return false;
+    }
+}
+
+bool row_operands_ok(int mode, const RowArgs& a) {
+    if (!a.tw2 || (mode != ROW_FWD && !a.in) || (mode != ROW_CACHE && !a.out)) return false;
+    switch (mode) {
+        case ROW_CACHE: return a.c_out;
+        case ROW_FWD: return a.rho && a.c;
+        case ROW_DERIV: return a.rho && a.c && a.drho;
+        case ROW_ADJ: return a.rho && a.c && a.aux;
+        default: return false;
+    }
+}
+
 int run_col(nlinv_plan_s* p, const Class& C, int mode, const ColArgs& a0, int nplanes, hipStream_t s) {
+    if (!col_operands_ok(mode, a0)) return NLINV_EINVAL;
     ColArgs a = a0;
     a.nplanes = nplanes;
     const int slot = tbegin(p, col_kclass(mode), s);
@@ -309,6 +337,7 @@ int run_col(nlinv_plan_s* p, const Class& C, int mode, const ColArgs& a0, int np
 }
 
 int run_row(nlinv_plan_s* p, const Class& C, int mode, const RowArgs& a, hipStream_t s) {
+    if (!row_operands_ok(mode, a)) return NLINV_EINVAL;
     const int slot = tbegin(p, row_kclass(mode), s);
     hipError_t e = row_dispatch(C.n, mode, C.rowv[mode], a, s);
     tend(p, slot, s);
@@ -324,6 +353,7 @@ int grid_for(long long n, int per = kThreads) {
 }
 
 int run_coil_sum(nlinv_plan_s* p, const CoilSumArgs& a, hipStream_t s) {
+    if (!a.aux || (a.r_upd ? !(a.add1 && a.dx_upd && a.cg_a) : !a.out)) return NLINV_EINVAL;
     const int slot = tbegin(p, KC_COIL_SUM, s);
     hipLaunchKernelGGL(k_coil_sum, dim3(a.nframes * a.segs), dim3(kThreads), 0, s, a);
     hipError_t e = hipGetLastError();
@@ -1006,7 +1036,9 @@ ColArgs tune_col_args(nlinv_plan_s* p, Class& C, int mode) {
             a.out = C.r_c; a.add1 = C.x_c; a.add2 = C.xr_c; a.s1 = C.alpha + C.nframes; a.s2 = C.alpha;
             break;
         case COL_PAD_FFT_WINV_CG_UPD:
-            a.out = C.r_c; a.dx = C.q_c; a.add1 = C.p_c;   // q_c: scratch here a.s1 = C.alpha; a.cg_a = C.sc.a; a.partial = C.partial2;
+            // q_c stands in for x (scratch: tuning must not touch the solution)
+            a.out = C.r_c; a.dx = C.q_c; a.add1 = C.p_c;
+            a.s1 = C.alpha; a.cg_a = C.sc.a; a.partial = C.partial2;
             break;
         default: break;
     }

@@ -58,7 +58,7 @@ template <int N>
 constexpr int plane_tile() { return plane_tile_width(N); }
 
 template <int N>
-__device__ __forceinline__ long long big_idx(int r, int col, int tiled) {
+__device__ __forceinline__ long long big_idx(int r, int col, bool tiled) {
     constexpr int TW = plane_tile<N>();
     return tiled ? ((long long)(col / TW) * N + r) * TW + (col % TW) : (long long)r * N + col;
 }
@@ -157,7 +157,9 @@ __device__ __forceinline__ bool col_item(int ntiles, int nplanes, int& tile, int
     return true;
 }
 
-template <int N, int L, int MODE>
+// TILED: the n x n operands are in the column-tiled solve layout (as
+// ColArgs::tiled, fixed at compile time so no access computes both forms).
+template <int N, int L, int MODE, bool TILED>
 __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
     constexpr int NT = pass_threads(N, L);
     using CT = Centre<N>;
@@ -224,7 +226,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                 const int ri = r - lo;
                 if (ri >= 0 && ri < m) x = cscale(src[(long long)ri * N + col], CT::sign(r));
             } else {
-                const long long o = big_idx<N>(r, col, a.tiled);
+                const long long o = big_idx<N>(r, col, TILED);
                 if constexpr (WINV_IN) {
                     if constexpr (PUPD) {    // p = r + beta p, written back
                         const float2 rv = a.r_in[pofs + o];
@@ -283,7 +285,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                 static_for<0, N2>([&](auto K) {
                     constexpr int k2 = K;
                     const int r = CT::out_pos(k1, k2);
-                    const float p = P[big_idx<N>(r, col, a.tiled)];
+                    const float p = P[big_idx<N>(r, col, TILED)];
                     kacc += p * p * (v[k2].x * v[k2].x + v[k2].y * v[k2].y);
                     v[k2] = cscale(v[k2], p * p * rs2);
                 });
@@ -356,7 +358,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                     a.out[((long long)plane * m + ri) * N + col] = cscale(v[k2], s);
                 }
             } else {
-                const long long o = big_idx<N>(rp, col, a.tiled);
+                const long long o = big_idx<N>(rp, col, TILED);
                 float2 x = v[k2];
                 if constexpr (MODE == COL_PAD_FFT_P) {
                     a.out[pbase + o] = cscale(x, CT::sign(rp) * a.rs * P[o]);
