@@ -63,6 +63,19 @@ __device__ __forceinline__ long long big_idx(int r, int col, bool tiled) {
     return tiled ? ((long long)(col / TW) * N + r) * TW + (col % TW) : (long long)r * N + col;
 }
 
+// Outputs per chunk of a pointwise stage (a divisor of the stage length,
+// at most cmax): the operands of a chunk are loaded together.
+constexpr int pointwise_chunk(int n2, int cmax = 8) {
+    for (int c = cmax; c > 1; --c)
+        if (n2 % c == 0) return c;
+    return 1;
+}
+// The row passes' products and the CG-update pass hold more operands per
+// output; these chunk caps keep them at or under 128 VGPRs (4 waves per
+// SIMD on gfx950), which measured faster than larger chunks at 3 waves.
+constexpr int kRowChunk = 3;
+constexpr int kCgChunk = 6;
+
 // Threads of a pass workgroup over L lines: enough for one task per thread in
 // the larger of the two FFT stages (L*N1 or L*N2 tasks), in whole wavefronts.
 constexpr int pass_threads(int n, int L) {
@@ -218,37 +231,60 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
         const int l = t % L, j2 = t / L, col = col0 + l;
         float2 v[N1];
         float pacc = 0.f;
-        static_for<0, N1>([&](auto K) {
-            constexpr int k1 = K;
-            const int r = CT::in_pos(j2, k1);
-            float2 x = make_float2(0.f, 0.f);
-            if constexpr (IN_CROP) {
-                const int ri = r - lo;
-                if (ri >= 0 && ri < m) x = cscale(src[(long long)ri * N + col], CT::sign(r));
-            } else {
-                const long long o = big_idx<N>(r, col, TILED);
-                if constexpr (WINV_IN) {
-                    if constexpr (PUPD) {    // p = r + beta p, written back
-                        const float2 rv = a.r_in[pofs + o];
-                        if (a.beta) {
-                            const float b = a.beta[f];
-                            const float2 pv = src[o];
-                            x = make_float2(rv.x + b * pv.x, rv.y + b * pv.y);
-                        } else {
-                            x = rv;
+        if constexpr (PUPD) {
+            // p = r + beta p, written back; the operands of a chunk of
+            // elements are loaded before its p values are stored (see the
+            // last stage)
+            constexpr int CH = pointwise_chunk(N1);
+            auto chunks = [&](auto HASB) {
+                constexpr bool HB = decltype(HASB)::value;
+                const float b = HB ? a.beta[f] : 0.f;
+                static_for<0, N1 / CH>([&](auto C) {
+                    float w[CH];
+                    float2 rv[CH], pv[CH];
+                    static_for<0, CH>([&](auto I) {
+                        constexpr int k1 = C * CH + I;
+                        const long long o = big_idx<N>(CT::in_pos(j2, k1), col, TILED);
+                        rv[I] = a.r_in[pofs + o];
+                        if constexpr (HB) pv[I] = src[o];
+                        w[I] = a.winv[o];
+                    });
+                    static_for<0, CH>([&](auto I) {
+                        constexpr int k1 = C * CH + I;
+                        const int r = CT::in_pos(j2, k1);
+                        const long long o = big_idx<N>(r, col, TILED);
+                        float2 x = rv[I];
+                        if constexpr (HB) {
+                            x.x += b * pv[I].x;
+                            x.y += b * pv[I].y;
                         }
                         a.p_out[pofs + o] = x;
                         pacc += x.x * x.x + x.y * x.y;
-                    } else {
-                        x = src[o];
+                        v[k1] = cscale(x, CT::sign(r) * w[I]);
+                    });
+                });
+            };
+            if (a.beta) chunks(std::true_type{});
+            else chunks(std::false_type{});
+        } else {
+            static_for<0, N1>([&](auto K) {
+                constexpr int k1 = K;
+                const int r = CT::in_pos(j2, k1);
+                float2 x = make_float2(0.f, 0.f);
+                if constexpr (IN_CROP) {
+                    const int ri = r - lo;
+                    if (ri >= 0 && ri < m) x = cscale(src[(long long)ri * N + col], CT::sign(r));
+                } else {
+                    const long long o = big_idx<N>(r, col, TILED);
+                    if constexpr (WINV_IN) {
+                        x = cscale(src[o], CT::sign(r) * a.winv[o]);
+                    } else {   // COL_P_IFFT_CROP
+                        x = cscale(src[o], CT::sign(r) * P[o]);
                     }
-                    x = cscale(x, CT::sign(r) * a.winv[o]);
-                } else {   // COL_P_IFFT_CROP
-                    x = cscale(src[o], CT::sign(r) * P[o]);
                 }
-            }
-            v[k1] = x;
-        });
+                v[k1] = x;
+            });
+        }
         if constexpr (PUPD) acc += (double)pacc;
         RegDFT<N1, INV1>::run(v);
         static_for<0, N1>([&](auto K) {
@@ -344,57 +380,95 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
         });
         RegDFT<N2, INV2>::run(v);
         float facc = 0.f;
-        static_for<0, N2>([&](auto K) {
-            constexpr int k2 = K;
-            const int r = TWO ? (k1 + N1 * k2) : CT::out_pos(k1, k2);
-            // TWO: the forward pass left slots in place, so the inverse's
-            // output slot s sits at position s; its pre-shift is in the input
-            // slots (P^2 was applied at the shifted positions)
-            const int rp = TWO ? CT::out_pos(k1, k2) : r;
-            if constexpr (OUT_CROP) {
+        if constexpr (OUT_CROP) {
+            static_for<0, N2>([&](auto K) {
+                constexpr int k2 = K;
+                // TWO: the forward pass left slots in place, so the inverse's
+                // output slot s sits at position s; its pre-shift is in the
+                // input slots (P^2 was applied at the shifted positions)
+                const int rp = CT::out_pos(k1, k2);
                 const int ri = rp - lo;
                 if (ri >= 0 && ri < m) {
                     const float s = TWO ? CT::sign(rp) : CT::sign(rp) * a.rs;
                     a.out[((long long)plane * m + ri) * N + col] = cscale(v[k2], s);
                 }
+            });
+        } else {
+            // The pointwise step over this thread's N2 outputs, CH at a time:
+            // all operands of a chunk are loaded before any of its results is
+            // stored.  (A store may alias a later operand as far as the
+            // compiler can tell, so output-by-output code waits for each
+            // output's loads in turn.)
+            constexpr int CH = pointwise_chunk(N2, CGU ? kCgChunk : 8);
+            auto chunks = [&](auto HAS1, auto HAS2) {
+                constexpr bool H1 = decltype(HAS1)::value, H2 = decltype(HAS2)::value;
+                static_for<0, N2 / CH>([&](auto C) {
+                    float w[CH];
+                    float2 u1[CH], u2[CH], u3[CH];
+                    static_for<0, CH>([&](auto I) {
+                        constexpr int k2 = C * CH + I;
+                        const long long o = big_idx<N>(CT::out_pos(k1, k2), col, TILED);
+                        if constexpr (MODE == COL_PAD_FFT_P || MODE == COL_PAD_FFT_P_RESID) w[I] = P[o];
+                        if constexpr (WINV_OUT || CGU) w[I] = a.winv[o];
+                        if constexpr (MODE == COL_PAD_FFT_P_RESID || MODE == COL_PAD_FFT_GPROD || CGU ||
+                                      (WINV_OUT && H1))
+                            u1[I] = a.add1[pbase + o];
+                        if constexpr (WINV_OUT && H2) u2[I] = a.add2[pbase + o];
+                        if constexpr (CGU) {
+                            u2[I] = a.out[pbase + o];    // r
+                            u3[I] = a.dx[pbase + o];
+                        }
+                    });
+                    static_for<0, CH>([&](auto I) {
+                        constexpr int k2 = C * CH + I;
+                        const int rp = CT::out_pos(k1, k2);
+                        const long long o = big_idx<N>(rp, col, TILED);
+                        float2 x = v[k2];
+                        if constexpr (MODE == COL_PAD_FFT_P) {
+                            a.out[pbase + o] = cscale(x, CT::sign(rp) * a.rs * w[I]);
+                        } else if constexpr (MODE == COL_PAD_FFT_P_RESID) {
+                            const float2 y = u1[I];
+                            const float p = CT::sign(rp) * a.rs * w[I];
+                            const float2 z = make_float2(s1 * y.x - p * x.x, s1 * y.y - p * x.y);
+                            a.out[pbase + o] = z;
+                            facc += z.x * z.x + z.y * z.y;
+                        } else if constexpr (CGU) {
+                            x = cscale(x, CT::sign(rp) * a.rs * w[I]);
+                            const float2 u = u1[I];                          // p
+                            x.x += s1 * u.x;                                 // q = N_alpha p
+                            x.y += s1 * u.y;
+                            float2 r = u2[I];
+                            r.x -= av * x.x;
+                            r.y -= av * x.y;
+                            a.out[pbase + o] = r;
+                            float2 d = u3[I];
+                            d.x += av * u.x;
+                            d.y += av * u.y;
+                            a.dx[pbase + o] = d;
+                            facc += r.x * r.x + r.y * r.y;
+                        } else if constexpr (WINV_OUT) {
+                            x = cscale(x, CT::sign(rp) * a.rs * w[I]);
+                            if constexpr (H1) { x.x += s1 * u1[I].x; x.y += s1 * u1[I].y; }
+                            if constexpr (H2) { x.x += s2 * u2[I].x; x.y += s2 * u2[I].y; }
+                            a.out[pbase + o] = x;
+                            facc += x.x * x.x + x.y * x.y;
+                        } else if constexpr (MODE == COL_PAD_FFT_GPROD) {
+                            const float2 g = u1[I];
+                            x = cscale(x, CT::sign(rp) * a.rs);
+                            reinterpret_cast<float*>(a.out)[pbase + o] = g.x * x.x + g.y * x.y;
+                        }
+                    });
+                });
+            };
+            if constexpr (WINV_OUT) {
+                if (a.add1 && a.add2) chunks(std::true_type{}, std::true_type{});
+                else if (a.add1) chunks(std::true_type{}, std::false_type{});
+                else if (a.add2) chunks(std::false_type{}, std::true_type{});
+                else chunks(std::false_type{}, std::false_type{});
             } else {
-                const long long o = big_idx<N>(rp, col, TILED);
-                float2 x = v[k2];
-                if constexpr (MODE == COL_PAD_FFT_P) {
-                    a.out[pbase + o] = cscale(x, CT::sign(rp) * a.rs * P[o]);
-                } else if constexpr (MODE == COL_PAD_FFT_P_RESID) {
-                    const float2 y = a.add1[pbase + o];
-                    const float p = CT::sign(rp) * a.rs * P[o];
-                    const float2 z = make_float2(s1 * y.x - p * x.x, s1 * y.y - p * x.y);
-                    a.out[pbase + o] = z;
-                    facc += z.x * z.x + z.y * z.y;
-                } else if constexpr (CGU) {
-                    x = cscale(x, CT::sign(rp) * a.rs * a.winv[o]);
-                    const float2 u = a.add1[pbase + o];            // p
-                    x.x += s1 * u.x;                                 // q = N_alpha p
-                    x.y += s1 * u.y;
-                    float2 r = a.out[pbase + o];
-                    r.x -= av * x.x;
-                    r.y -= av * x.y;
-                    a.out[pbase + o] = r;
-                    float2 d = a.dx[pbase + o];
-                    d.x += av * u.x;
-                    d.y += av * u.y;
-                    a.dx[pbase + o] = d;
-                    facc += r.x * r.x + r.y * r.y;
-                } else if constexpr (WINV_OUT) {
-                    x = cscale(x, CT::sign(rp) * a.rs * a.winv[o]);
-                    if (a.add1) { const float2 u = a.add1[pbase + o]; x.x += s1 * u.x; x.y += s1 * u.y; }
-                    if (a.add2) { const float2 u = a.add2[pbase + o]; x.x += s2 * u.x; x.y += s2 * u.y; }
-                    a.out[pbase + o] = x;
-                    facc += x.x * x.x + x.y * x.y;
-                } else if constexpr (MODE == COL_PAD_FFT_GPROD) {
-                    const float2 g = a.add1[pbase + o];
-                    x = cscale(x, CT::sign(rp) * a.rs);
-                    reinterpret_cast<float*>(a.out)[pbase + o] = g.x * x.x + g.y * x.y;
-                }
+                chunks(std::true_type{}, std::true_type{});
             }
-        });
+        }
         acc += (double)facc;
     }
     if constexpr (RED) {
@@ -505,34 +579,55 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
                     v[j2] = buf[(ll * N1 + k1) * S2 + j2];
                 });
                 RegDFT<N2, true>::run(v);
-                const int plane = line / m, i = line % m;
                 const bool live = line < a.nlines;
-                const int f = (live && a.plane_frame) ? a.plane_frame[plane] : 0;
-                static_for<0, N2>([&](auto K) {
-                    constexpr int k2 = K;
-                    const int pos = CT::out_pos(k1, k2);
-                    const int q = pos - lo;
-                    float2 z = make_float2(0.f, 0.f);
-                    if (live && q >= 0 && q < m) {
-                        const float2 u = cscale(v[k2], CT::sign(pos) * a.rs);
-                        const long long oc = ((long long)plane * m + i) * m + q;
-                        if constexpr (MODE == ROW_CACHE) {
-                            a.c_out[oc] = u;
-                        } else {
-                            const long long orh = ((long long)f * m + i) * m + q;
-                            const float2 cv = a.c[oc];
-                            const float2 rv = a.rho[orh];
-                            if constexpr (MODE == ROW_DERIV) {
-                                z = cadd(cmul(a.drho[orh], cv), cmul(rv, u));
-                            } else {  // ROW_ADJ
-                                a.aux[oc] = cconjmul(cv, u);
-                                z = cconjmul(rv, u);
+                // lines past the end read a valid line's operands (discarded)
+                const int line_c = live ? line : a.nlines - 1;
+                const int plane = line_c / m, i = line_c % m;
+                const int f = a.plane_frame ? a.plane_frame[plane] : 0;
+                if constexpr (MODE == ROW_CACHE) {
+                    static_for<0, N2>([&](auto K) {
+                        constexpr int k2 = K;
+                        const int pos = CT::out_pos(k1, k2);
+                        const int q = pos - lo;
+                        if (live && q >= 0 && q < m)
+                            a.c_out[((long long)plane * m + i) * m + q] = cscale(v[k2], CT::sign(pos) * a.rs);
+                    });
+                } else {
+                    // the pointwise products, CH outputs at a time: the operands
+                    // of a chunk are loaded (from a valid column for outputs
+                    // outside Omega) before any of its results is formed
+                    constexpr int CH = pointwise_chunk(N2, kRowChunk);
+                    const long long cbase = ((long long)plane * m + i) * m;
+                    const long long rbase = ((long long)f * m + i) * m;
+                    static_for<0, N2 / CH>([&](auto C) {
+                        float2 cv[CH], rv[CH], dv[CH];
+                        static_for<0, CH>([&](auto I) {
+                            constexpr int k2 = C * CH + I;
+                            const int q = CT::out_pos(k1, k2) - lo;
+                            const int qc = (q >= 0 && q < m) ? q : 0;
+                            cv[I] = a.c[cbase + qc];
+                            rv[I] = a.rho[rbase + qc];
+                            if constexpr (MODE == ROW_DERIV) dv[I] = a.drho[rbase + qc];
+                        });
+                        static_for<0, CH>([&](auto I) {
+                            constexpr int k2 = C * CH + I;
+                            const int pos = CT::out_pos(k1, k2);
+                            const int q = pos - lo;
+                            float2 z = make_float2(0.f, 0.f);
+                            if (live && q >= 0 && q < m) {
+                                const float2 u = cscale(v[k2], CT::sign(pos) * a.rs);
+                                if constexpr (MODE == ROW_DERIV) {
+                                    z = cadd(cmul(dv[I], cv[I]), cmul(rv[I], u));
+                                } else {  // ROW_ADJ
+                                    a.aux[cbase + q] = cconjmul(cv[I], u);
+                                    z = cconjmul(rv[I], u);
+                                }
+                                z = cscale(z, CT::sign(pos));
                             }
-                            z = cscale(z, CT::sign(pos));
-                        }
-                    }
-                    v[k2] = z;
-                });
+                            v[k2] = z;
+                        });
+                    });
+                }
             }
             if constexpr (MODE == ROW_CACHE) return;
             __syncthreads();
