@@ -52,34 +52,45 @@ __global__ __launch_bounds__(kThreads) void k_coil_sum(CoilSumArgs a) {
     if (threadIdx.x < a.seg_len && e < a.E) {
         const long long g = (long long)f * a.E + e;
         const float2* src = a.aux + (long long)p0 * a.E + e;
-        float2 s0 = make_float2(0.f, 0.f), s1 = s0;
-        int p = 0;
-        for (; p + 1 < np; p += 2) {     // two independent chains, combined in a fixed order
-            s0 = cadd(s0, src[(long long)p * a.E]);
-            s1 = cadd(s1, src[(long long)(p + 1) * a.E]);
-        }
-        if (p < np) s0 = cadd(s0, src[(long long)p * a.E]);
-        float2 s = cadd(s0, s1);
+        // the pointwise operands first, so their loads overlap the plane loads
         const float c1 = a.s1 ? a.s1[f] : a.c1;
         const float c2 = a.s2 ? a.s2[f] : a.c2;
-        if (a.add1) { const float2 u = a.add1[g]; s.x += c1 * u.x; s.y += c1 * u.y; }
-        if (a.add2) { const float2 u = a.add2[g]; s.x += c2 * u.x; s.y += c2 * u.y; }
+        const float2 zero = make_float2(0.f, 0.f);
+        const float2 u1 = a.add1 ? a.add1[g] : zero;
+        const float2 u2 = a.add2 ? a.add2[g] : zero;
+        float2 r = a.r_upd ? a.r_upd[g] : zero;
+        float2 d = a.r_upd ? a.dx_upd[g] : zero;
+        // four independent chains over the planes (four loads in flight),
+        // combined in a fixed order
+        float2 s0 = zero, s1 = zero, s2 = zero, s3 = zero;
+        int p = 0;
+        for (; p + 3 < np; p += 4) {
+            const float2 v0 = src[(long long)p * a.E], v1 = src[(long long)(p + 1) * a.E];
+            const float2 v2 = src[(long long)(p + 2) * a.E], v3 = src[(long long)(p + 3) * a.E];
+            s0 = cadd(s0, v0);
+            s1 = cadd(s1, v1);
+            s2 = cadd(s2, v2);
+            s3 = cadd(s3, v3);
+        }
+        if (p < np) s0 = cadd(s0, src[(long long)p * a.E]);
+        if (p + 1 < np) s1 = cadd(s1, src[(long long)(p + 1) * a.E]);
+        if (p + 2 < np) s2 = cadd(s2, src[(long long)(p + 2) * a.E]);
+        float2 s = cadd(cadd(s0, s1), cadd(s2, s3));
+        s.x += c1 * u1.x + c2 * u2.x;
+        s.y += c1 * u1.y + c2 * u2.y;
         if (a.r_upd) {
             const float av = a.cg_a[f];
-            const float2 u = a.add1[g];
-            float2 r = a.r_upd[g];
             r.x -= av * s.x;
             r.y -= av * s.y;
             a.r_upd[g] = r;
-            float2 d = a.dx_upd[g];
-            d.x += av * u.x;
-            d.y += av * u.y;
+            d.x += av * u1.x;
+            d.y += av * u1.y;
             a.dx_upd[g] = d;
             acc = (double)(r.x * r.x + r.y * r.y);
         } else {
             a.out[g] = s;
             if (a.self_dot) acc = (double)(s.x * s.x + s.y * s.y);
-            else if (a.partial && a.add1) { const float2 u = a.add1[g]; acc = (double)(u.x * s.x + u.y * s.y); }
+            else if (a.partial && a.add1) acc = (double)(u1.x * s.x + u1.y * s.y);
         }
     }
     if (a.partial) {
@@ -160,15 +171,10 @@ __global__ __launch_bounds__(kThreads) void k_vec(SegGeom g, VecPtrs v, double* 
 }
 
 // One workgroup per frame: total of its partials, then the scalar step.
-__global__ __launch_bounds__(kThreads) void k_scalar(ScalarStep ss, Scalars sc) {
-    __shared__ double red[4];
-    const int f = blockIdx.x;
-    double t = frame_total(ss.g, ss.partial, f, ss.frame_plane0, ss.frame_planes, red);
-    if (ss.partial2) {
-        const double t2 = frame_total(ss.g2, ss.partial2, f, ss.frame_plane0, ss.frame_planes, red);
-        if (threadIdx.x == 0) t += (double)sc.alpha[f] * t2;
-    }
-    if (threadIdx.x == 0) scalar_apply(ss, sc, f, t);
+// One wavefront per frame: the frame's scalars and its partials are loaded
+// together, summed in a fixed order, then the scalar step.
+__global__ __launch_bounds__(64) void k_scalar(ScalarStep ss, Scalars sc) {
+    fold_scalar_step(ss, sc);
 }
 
 // per-frame: alpha[f] = value, alpha[F + f] = -value

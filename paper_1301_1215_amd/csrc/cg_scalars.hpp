@@ -59,24 +59,6 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return t;
 }
 
-// Fixed-order total of frame f: the chat segments of its planes (plane
-// order), then its rho segments; the partials come from earlier kernels.
-// All threads call it; valid in thread 0.
-__device__ __forceinline__ double frame_total(const SegGeom& g, const double* partial, int f,
-                                              const int* frame_plane0, const int* frame_planes,
-                                              double* red) {
-    const int p0 = frame_plane0 ? frame_plane0[f] : 0;
-    const int np = frame_planes ? frame_planes[f] : g.nplanes;
-    const int nc = np * g.cseg;
-    const int tot = nc + g.rseg;
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < tot; i += kThreads) {
-        acc += (i < nc) ? partial[(long long)p0 * g.cseg + i]
-                        : partial[(long long)g.nplanes * g.cseg + (long long)f * g.rseg + (i - nc)];
-    }
-    return block_sum(acc, red);
-}
-
 // CG and Newton scalars of every frame of a class, all on the device.
 struct Scalars {
     double* rr;        // [F] <r, r>
@@ -114,8 +96,20 @@ struct ScalarStep {
     int step, it, nsteps, ncg;
 };
 
-// The scalar logic for frame f given the total t (thread 0 only).
-__device__ __forceinline__ void scalar_apply(const ScalarStep& ss, const Scalars& sc, int f, double t) {
+// The frame's scalars the step logic reads, loaded before the partials are
+// summed so that the two memory round trips overlap.
+struct FrameScalars {
+    double rr, flags;
+    int brk;
+};
+__device__ __forceinline__ FrameScalars load_frame_scalars(const Scalars& sc, int f) {
+    return FrameScalars{sc.rr[f], sc.stats[(long long)f * sc.stats_len + 1], sc.brk[f]};
+}
+
+// The scalar logic for frame f given the total t and the frame's scalars
+// as loaded before (thread 0 only).
+__device__ __forceinline__ void scalar_apply(const ScalarStep& ss, const Scalars& sc, int f, double t,
+                                             const FrameScalars& fs) {
     double* st = sc.stats + (long long)f * sc.stats_len;
     const int op = ss.op;
     if (op == SC_YNORM) {
@@ -128,15 +122,15 @@ __device__ __forceinline__ void scalar_apply(const ScalarStep& ss, const Scalars
         if (!isfinite(nrm)) st[1] = 2.0;
     } else if (op == SC_R0NORM) {
         st[2 + ss.step] = sqrt(t);
-        if (!isfinite(t)) st[1] = (double)((int)st[1] | 2);
+        if (!isfinite(t)) st[1] = (double)((int)fs.flags | 2);
     } else if (op == SC_RR0) {
         sc.rr[f] = t;
         sc.brk[f] = 0;
     } else if (op == SC_GAMMA) {
-        const double rr = sc.rr[f];
-        if (sc.brk[f] || rr == 0.0 || !(t > 0.0) || !isfinite(rr)) {
-            if (!sc.brk[f]) {
-                int fl = (int)st[1] | 1;
+        const double rr = fs.rr;
+        if (fs.brk || rr == 0.0 || !(t > 0.0) || !isfinite(rr)) {
+            if (!fs.brk) {
+                int fl = (int)fs.flags | 1;
                 if (!isfinite(t) || !isfinite(rr)) fl |= 2;
                 st[1] = (double)fl;
             }
@@ -147,12 +141,12 @@ __device__ __forceinline__ void scalar_apply(const ScalarStep& ss, const Scalars
         }
     } else if (op == SC_RR) {
         double* slot = st + 2 + ss.nsteps + ss.step * ss.ncg + ss.it;
-        if (sc.brk[f]) {
+        if (fs.brk) {
             sc.beta[f] = 0.f;
             *slot = -1.0;
         } else {
-            if (!isfinite(t)) st[1] = (double)((int)st[1] | 2);
-            sc.beta[f] = (float)(t / sc.rr[f]);
+            if (!isfinite(t)) st[1] = (double)((int)fs.flags | 2);
+            sc.beta[f] = (float)(t / fs.rr);
             sc.rr[f] = t;
             *slot = t;
         }
@@ -195,12 +189,13 @@ __device__ __forceinline__ double frame_total_wave(const SegGeom& g, const doubl
 __device__ __forceinline__ void fold_scalar_step(const ScalarStep& ss, const Scalars& sc) {
     if (ss.op == SC_NONE || ss.partial == nullptr || threadIdx.x >= 64) return;
     for (int f = blockIdx.x; f < ss.g.nframes; f += gridDim.x) {
+        const FrameScalars fs = load_frame_scalars(sc, f);
         double t = frame_total_wave(ss.g, ss.partial, f, ss.frame_plane0, ss.frame_planes);
         if (ss.partial2) {
             const double t2 = frame_total_wave(ss.g2, ss.partial2, f, ss.frame_plane0, ss.frame_planes);
             if (threadIdx.x == 0) t += (double)sc.alpha[f] * t2;
         }
-        if (threadIdx.x == 0) scalar_apply(ss, sc, f, t);
+        if (threadIdx.x == 0) scalar_apply(ss, sc, f, t, fs);
     }
 }
 

@@ -391,7 +391,7 @@ ScalarStep scalar_step(const Class& C, int op, const SegGeom& g, float scale_nor
 
 int launch_scalar(nlinv_plan_s* p, Class& C, const ScalarStep& ss, hipStream_t s) {
     const int slot = tbegin(p, KC_SCALAR, s);
-    hipLaunchKernelGGL(k_scalar, dim3(C.nframes), dim3(kThreads), 0, s, ss, C.sc);
+    hipLaunchKernelGGL(k_scalar, dim3(C.nframes), dim3(64), 0, s, ss, C.sc);
     hipError_t e = hipGetLastError();
     tend(p, slot, s);
     HIPCHK(e);
