@@ -78,12 +78,15 @@ def pmc_traffic(kc: str, frames: int):
         if not f or f[0].startswith("#"):
             continue
         if f[0] == "traffic" and len(f) == 7:
-            traffic[f[1]] = int(f[6])
+            # one line per kernel variant; the solve's is the one with the
+            # most dispatches (the others are the autotuner's trial launches)
+            if f[1] not in traffic or int(f[3]) > traffic[f[1]][0]:
+                traffic[f[1]] = (int(f[3]), int(f[6]))
         elif len(f) == 2:
             meta[f[0]] = f[1]
     if meta.get("source_sha256") != kernel_source_hash() or int(meta.get("frames_per_step", -1)) != frames:
         return None
-    return traffic.get(kc)
+    return traffic[kc][1] if kc in traffic else None
 
 
 def normal_bytes(n, m, J, frames=1):
