@@ -44,12 +44,13 @@ def kernel_bytes(kc: str, n: int, m: int, planes: int, frames: int) -> float:
         "col_fft_p_resid": planes * c * (mn + 2 * nn) + frames * 4 * nn,
         "col_psf": planes * c * (2 * mn) + frames * 4 * nn,
         "col_fft_winv_add": planes * c * (mn + 3 * nn),                        # read T, x, x_ref; write
-        "col_fft_winv_cg_update": planes * c * (mn + 5 * nn),                  # read T, p, r, dx; write r, dx
+        # read T, p, r, x (chat) and the coil products; write r, x; rho parts: read p, r, dx; write r, dx
+        "col_fft_winv_cg_update": planes * c * (mn + 5 * nn + mm) + frames * 5 * c * mm,
         "row_cache": planes * c * (mn + mm),
         "row_fwd": planes * c * (mm + mn) + frames * c * mm,
         "row_deriv": planes * c * (2 * mn + mm) + frames * 2 * c * mm,
         "row_adj": planes * c * (2 * mn + 2 * mm) + frames * c * mm,
-        "coil_sum": planes * c * mm + frames * 5 * c * mm,                     # CG form: read p, r, dx; write r, dx
+        "coil_sum": planes * c * mm + frames * 3 * c * mm,                     # right-hand side: read x, x_ref; write
         "vec_dot": (planes * nn + frames * mm) * 2 * c,
     }
     return per.get(kc, float("nan"))
@@ -151,8 +152,8 @@ def dominant_class(pl, data, prm, outs, names):
 
 
 # kernel classes of one (DF^H DF + alpha) apply inside CG; the first also does
-# p = r + beta p, the last two r -= a q and dx += a p (one CG iteration but its scalars)
-APPLY_CLASSES = ("col_pupd_winv_ifft", "row_deriv", "col_psf", "row_adj", "col_fft_winv_cg_update", "coil_sum")
+# p = r + beta p, the last r -= a q and x += a p with the rho parts fused in (one CG iteration but its scalars)
+APPLY_CLASSES = ("col_pupd_winv_ifft", "row_deriv", "col_psf", "row_adj", "col_fft_winv_cg_update")
 
 
 def apply_rates(totals, B):

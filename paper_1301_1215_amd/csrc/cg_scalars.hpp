@@ -59,6 +59,22 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return t;
 }
 
+// Sum over an NT-thread workgroup in a fixed order (wavefront shuffle, then
+// the waves in order); the result is valid in thread 0 and `red` (NT/64
+// doubles) is free again on return.
+template <int NT>
+__device__ __forceinline__ double wg_sum(double v, double* red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < NT / 64; ++w) t += red[w];
+    __syncthreads();
+    return t;
+}
+
 // CG and Newton scalars of every frame of a class, all on the device.
 struct Scalars {
     double* rr;        // [F] <r, r>

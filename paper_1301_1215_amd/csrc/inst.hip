@@ -11,7 +11,8 @@ template <int N, int L>
 static hipError_t col_L(int mode, const ColArgs& a, int nplanes, hipStream_t s) {
     // 1D grid, a multiple of 8 blocks: the kernel deals work items to XCDs
     const int total = (N / L) * nplanes;
-    const dim3 grid(8 * ((total + 7) / 8)), block(pass_threads(N, L));
+    const int extra = mode == COL_PAD_FFT_WINV_CG_UPD ? a.cs_blocks : 0;   // fused coil-sum workgroups
+    const dim3 grid(8 * ((total + 7) / 8) + extra), block(pass_threads(N, L));
 #define NLINV_COL(MODE, T) hipLaunchKernelGGL((k_col<N, L, MODE, T>), grid, block, 0, s, a)
     if (a.tiled) {   // inside a solve: every mode
         switch (mode) {

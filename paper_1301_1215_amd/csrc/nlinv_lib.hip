@@ -309,7 +309,9 @@ bool col_operands_ok(int mode, const ColArgs& a) {
         case COL_PAD_FFT_WINV_ADD: return a.winv;
         case COL_PAD_FFT_GPROD: return a.add1;
         case COL_PUPD_WINV_IFFT_CROP: return a.winv && a.r_in && a.p_out && a.pr && a.rr;
-        case COL_PAD_FFT_WINV_CG_UPD: return a.winv && a.add1 && a.dx && a.cg_a;
+        case COL_PAD_FFT_WINV_CG_UPD:
+            return a.winv && a.add1 && a.dx && a.cg_a &&
+                   (a.cs_blocks == 0 || (a.cs.aux && a.cs.add1 && a.cs.r_upd && a.cs.dx_upd && a.cs.cg_a));
         default: return false;
     }
 }
@@ -632,13 +634,19 @@ int seq_cg_iteration(nlinv_plan_s* p, Class& C, const float* beta, int step, int
     e.s1 = C.alpha;
     e.cg_a = C.sc.a;
     e.partial = C.partial2;
-    CHK(run_col(p, C, COL_PAD_FFT_WINV_CG_UPD, e, fr.nplanes, s));
+    // the rho parts: the coil sum in its CG form, as extra workgroups of the
+    // same launch (segments of one workgroup's size)
     CoilSumArgs cs = coil_sum_args(C, fr, nullptr, C.p_r, nullptr, C.alpha, nullptr, 0.f, 0.f, C.partial2,
                                    (long long)C.nplanes * tu);
     cs.r_upd = C.r_r;
     cs.dx_upd = C.dx_r;
     cs.cg_a = C.sc.a;
-    CHK(run_coil_sum(p, cs, s));
+    const int wg = pass_threads(C.n, kColL[C.colv[COL_PAD_FFT_WINV_CG_UPD]]);
+    cs.segs = (cs.E + wg - 1) / wg;
+    cs.seg_len = (cs.E + cs.segs - 1) / cs.segs;
+    e.cs = cs;
+    e.cs_blocks = C.nframes * cs.segs;
+    CHK(run_col(p, C, COL_PAD_FFT_WINV_CG_UPD, e, fr.nplanes, s));
     // beta = <r,r>' / <r,r> from the |r|^2 partials: column tiles per plane, coil-sum segments per frame
     SegGeom g = C.geom;
     g.cseg = tu;
@@ -971,7 +979,9 @@ int build_class(nlinv_plan_s* p, Class& C) {
     make_geom(C.geomC, C.nplanes, C.nframes, cn, rn, false, C.plane_frame);
     // partials: the segment geometries, or (column tiles of the narrowest
     // variant per plane) + (coil-sum segments per frame)
-    const size_t tiles = (size_t)C.nplanes * (C.n / 4) + (size_t)C.nframes * ((rn + kCoilSeg - 1) / kCoilSeg);
+    // (coil-sum segments are as small as one 64-thread workgroup when fused
+    // into a column pass)
+    const size_t tiles = (size_t)C.nplanes * (C.n / 4) + (size_t)C.nframes * ((rn + 63) / 64);
     CHK(dalloc(p, &C.partial, std::max<size_t>(tiles, (size_t)std::max(nseg(C.geom), nseg(C.geomC)))));
     CHK(dalloc(p, &C.alpha, (size_t)2 * C.nframes));
     CHK(dalloc(p, &C.partial2, std::max<size_t>(tiles, (size_t)nseg(C.geom))));

@@ -18,6 +18,7 @@
 #include <stdint.h>
 
 #include "cg_scalars.hpp"
+#include "coil_sum.hpp"
 #include "fft_core.hpp"
 
 namespace nlinv {
@@ -138,23 +139,14 @@ struct ColArgs {
     //   COL_PAD_FFT_WINV_CG_UPD   |r|^2 after the update
     double* partial;
     int tiled;                // n x n planes, P and 1/w column-tiled (inside a solve)
+    // COL_PAD_FFT_WINV_CG_UPD: the rho parts' CG update (a coil sum in its CG
+    // form) runs as cs_blocks extra workgroups of the same launch, after the
+    // column workgroups; it only needs the coil products and a, so it
+    // overlaps the column work instead of taking a launch of its own
+    CoilSumArgs cs;
+    int cs_blocks;
 };
 
-// Sum over an NT-thread workgroup in a fixed order (wavefront shuffle, then
-// the waves in order); the result is valid in thread 0 and `red` (NT/64
-// doubles) is free again on return.
-template <int NT>
-__device__ __forceinline__ double wg_sum(double v, double* red) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < NT / 64; ++w) t += red[w];
-    __syncthreads();
-    return t;
-}
 
 // Work item w = tile * nplanes + plane (planes of a tile adjacent, so the P
 // tile of a frame is reused); blocks are dealt to the 8 XCDs round robin, so
@@ -195,6 +187,13 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
     __shared__ double red[RED ? NT / 64 : 1];
     static_assert(NT % 64 == 0 && NT <= 1024, "pass workgroup size");
 
+    if constexpr (CGU) {
+        const int ncol = 8 * ((N / L * a.nplanes + 7) / 8);
+        if ((int)blockIdx.x >= ncol) {
+            coil_sum_block<NT>(a.cs, (int)blockIdx.x - ncol, red);
+            return;
+        }
+    }
     int tile, plane;
     if (!col_item(N / L, a.nplanes, tile, plane)) return;
     const int col0 = tile * L;
