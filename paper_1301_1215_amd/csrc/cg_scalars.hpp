@@ -77,7 +77,8 @@ __device__ __forceinline__ double wg_sum(double v, double* red) {
 
 // CG and Newton scalars of every frame of a class, all on the device.
 struct Scalars {
-    double* rr;        // [F] <r, r>
+    double* rr;        // [2][F] <r, r>, by the parity of the CG iteration it belongs to
+                       // (a step folded into a pass reads one while it writes the other)
     float* a;          // [F] CG step a = rr / gamma
     float* beta;       // [F]
     int* brk;          // [F] breakdown in the current Newton step
@@ -86,15 +87,17 @@ struct Scalars {
     float* inv_s;      // [F]
     double* stats;     // [F][stats_len]
     int stats_len;
+    int nframes;       // F
 };
 
 enum ScalarOp : int {
     SC_NONE = -1,
     SC_YNORM = 0,      // s = scale_norm / ||y|| (scale_norm > 0 and ||y|| > 0), else 1
     SC_R0NORM = 1,     // stats[2 + step] = ||r0||
-    SC_RR0 = 2,        // rr = <b, b>; new Newton step: clear breakdown
+    SC_RR0 = 2,        // rr (of CG iteration 0) = <b, b>; new Newton step: clear breakdown
     SC_GAMMA = 3,      // gamma = Re<p, q> (or |DF p|^2 + alpha |p|^2); a = rr / gamma or breakdown
-    SC_RR = 4,         // rr' = <r, r>; beta = rr'/rr; rr = rr'; stats of CG iteration `it`
+    SC_RR = 4,         // after CG iteration `it`: rr' = <r, r>; beta = rr'/rr; rr of
+                       // iteration it+1 = rr'; stats of iteration `it`
 };
 
 // Where a scalar op is applied: which op, geometry of its partials, indices
@@ -118,8 +121,19 @@ struct FrameScalars {
     double rr, flags;
     int brk;
 };
-__device__ __forceinline__ FrameScalars load_frame_scalars(const Scalars& sc, int f) {
-    return FrameScalars{sc.rr[f], sc.stats[(long long)f * sc.stats_len + 1], sc.brk[f]};
+// <r, r> of CG iteration `it` of frame f
+__device__ __forceinline__ double* rr_of(const Scalars& sc, int it, int f) {
+    return sc.rr + (long long)(it & 1) * sc.nframes + f;
+}
+__device__ __forceinline__ FrameScalars load_frame_scalars(const ScalarStep& ss, const Scalars& sc, int f) {
+    return FrameScalars{*rr_of(sc, ss.op == SC_RR0 ? 0 : ss.it, f), sc.stats[(long long)f * sc.stats_len + 1],
+                        sc.brk[f]};
+}
+
+// beta of the direction after CG iteration ss.it, from the total t of
+// <r, r> (what SC_RR records)
+__device__ __forceinline__ float cg_beta(const FrameScalars& fs, double t) {
+    return fs.brk ? 0.f : (float)(t / fs.rr);
 }
 
 // The scalar logic for frame f given the total t and the frame's scalars
@@ -140,7 +154,7 @@ __device__ __forceinline__ void scalar_apply(const ScalarStep& ss, const Scalars
         st[2 + ss.step] = sqrt(t);
         if (!isfinite(t)) st[1] = (double)((int)fs.flags | 2);
     } else if (op == SC_RR0) {
-        sc.rr[f] = t;
+        *rr_of(sc, 0, f) = t;
         sc.brk[f] = 0;
     } else if (op == SC_GAMMA) {
         const double rr = fs.rr;
@@ -162,8 +176,8 @@ __device__ __forceinline__ void scalar_apply(const ScalarStep& ss, const Scalars
             *slot = -1.0;
         } else {
             if (!isfinite(t)) st[1] = (double)((int)fs.flags | 2);
-            sc.beta[f] = (float)(t / fs.rr);
-            sc.rr[f] = t;
+            sc.beta[f] = cg_beta(fs, t);
+            *rr_of(sc, ss.it + 1, f) = t;
             *slot = t;
         }
     }
@@ -205,7 +219,7 @@ __device__ __forceinline__ double frame_total_wave(const SegGeom& g, const doubl
 __device__ __forceinline__ void fold_scalar_step(const ScalarStep& ss, const Scalars& sc) {
     if (ss.op == SC_NONE || ss.partial == nullptr || threadIdx.x >= 64) return;
     for (int f = blockIdx.x; f < ss.g.nframes; f += gridDim.x) {
-        const FrameScalars fs = load_frame_scalars(sc, f);
+        const FrameScalars fs = load_frame_scalars(ss, sc, f);
         double t = frame_total_wave(ss.g, ss.partial, f, ss.frame_plane0, ss.frame_planes);
         if (ss.partial2) {
             const double t2 = frame_total_wave(ss.g2, ss.partial2, f, ss.frame_plane0, ss.frame_planes);

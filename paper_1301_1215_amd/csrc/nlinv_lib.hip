@@ -284,6 +284,7 @@ ColArgs col_args(const nlinv_plan_s* p, const Class& C, int tiled) {
     a.rs = (float)(1.0 / std::sqrt((double)C.n));
     a.tw2 = C.tw;
     a.winv = tiled ? C.winv_t : C.winv;
+    a.fold.op = SC_NONE;
     (void)p;
     return a;
 }
@@ -572,8 +573,18 @@ int seq_adjoint_tail(nlinv_plan_s* p, const Class& C, const Frames& fr, const fl
 // pass and the coil sum then form q = N_alpha p in registers and apply
 // r -= a q, dx += a p directly (q is never stored), writing the |r|^2
 // partials from which beta follows.
-int seq_cg_iteration(nlinv_plan_s* p, Class& C, const float* beta, int step, int it, int nsteps, int ncg,
-                     hipStream_t s) {
+// Geometry of the <r, r> partials a CG iteration leaves: column tiles of the
+// CG-update pass per plane, then the segments of its fused coil sum per frame.
+SegGeom cg_rr_geom(const Class& C) {
+    SegGeom g = C.geom;
+    const int L = kColL[C.colv[COL_PAD_FFT_WINV_CG_UPD]];
+    const int wg = pass_threads(C.n, L);
+    g.cseg = C.n / L;
+    g.rseg = (int)((C.rplane() + wg - 1) / wg);
+    return g;
+}
+
+int seq_cg_iteration(nlinv_plan_s* p, Class& C, int step, int it, int nsteps, int ncg, hipStream_t s) {
     const Frames fr = class_frames(C);
     ColArgs a = col_args(p, C, fr.tiled);
     a.in = C.p_c;
@@ -581,10 +592,14 @@ int seq_cg_iteration(nlinv_plan_s* p, Class& C, const float* beta, int step, int
     a.plane_frame = fr.plane_frame;
     a.r_in = C.r_c;
     a.p_out = C.p_c;
-    a.beta = beta;
+    a.beta = nullptr;                 // it == 0: p = r
     a.pr = C.p_r;
     a.rr = C.r_r;
     a.partial = C.part_p;
+    if (it > 0) {   // beta of the previous iteration, computed inside the pass
+        a.fold = scalar_step(C, SC_RR, cg_rr_geom(C), 0.f, step, it - 1, nsteps, ncg, C.partial2);
+        a.sc = C.sc;
+    }
     CHK(run_col(p, C, COL_PUPD_WINV_IFFT_CROP, a, fr.nplanes, s));
     RowArgs r = row_args(C);
     r.in = C.T;
@@ -641,17 +656,16 @@ int seq_cg_iteration(nlinv_plan_s* p, Class& C, const float* beta, int step, int
     cs.r_upd = C.r_r;
     cs.dx_upd = C.dx_r;
     cs.cg_a = C.sc.a;
-    const int wg = pass_threads(C.n, kColL[C.colv[COL_PAD_FFT_WINV_CG_UPD]]);
-    cs.segs = (cs.E + wg - 1) / wg;
+    const SegGeom grr = cg_rr_geom(C);
+    cs.segs = grr.rseg;
     cs.seg_len = (cs.E + cs.segs - 1) / cs.segs;
     e.cs = cs;
     e.cs_blocks = C.nframes * cs.segs;
     CHK(run_col(p, C, COL_PAD_FFT_WINV_CG_UPD, e, fr.nplanes, s));
-    // beta = <r,r>' / <r,r> from the |r|^2 partials: column tiles per plane, coil-sum segments per frame
-    SegGeom g = C.geom;
-    g.cseg = tu;
-    g.rseg = cs.segs;
-    return run_scalar(p, C, SC_RR, g, 0.f, step, s, it, nsteps, ncg, C.partial2);
+    // beta = <r,r>' / <r,r> from the |r|^2 partials: inside the next
+    // iteration's first pass, or here after the last iteration (its stats)
+    if (it + 1 < ncg) return NLINV_OK;
+    return run_scalar(p, C, SC_RR, grr, 0.f, step, s, it, nsteps, ncg, C.partial2);
 }
 
 // (drho_out, dchat_out) = (DF^H DF + alpha) (drho, dchat)
@@ -718,8 +732,7 @@ int enqueue_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s
             }
         }
         for (int it = 0; it < K; ++it) {
-            for (Class& C : p->classes)
-                CHK(seq_cg_iteration(p, C, it == 0 ? nullptr : C.sc.beta, step, it, N, K, s));
+            for (Class& C : p->classes) CHK(seq_cg_iteration(p, C, step, it, N, K, s));
         }
         for (Class& C : p->classes) {   // rho += drho (the chat part is already in x)
             SegGeom g = C.geom;
@@ -986,7 +999,7 @@ int build_class(nlinv_plan_s* p, Class& C) {
     CHK(dalloc(p, &C.alpha, (size_t)2 * C.nframes));
     CHK(dalloc(p, &C.partial2, std::max<size_t>(tiles, (size_t)nseg(C.geom))));
     CHK(dalloc(p, &C.part_p, (size_t)(C.nplanes + C.nframes) * (C.n / 4)));
-    CHK(dalloc(p, &C.sc.rr, C.nframes));
+    CHK(dalloc(p, &C.sc.rr, (size_t)2 * C.nframes));
     CHK(dalloc(p, &C.sc.a, C.nframes));
     CHK(dalloc(p, &C.sc.beta, C.nframes));
     CHK(dalloc(p, &C.sc.brk, C.nframes));
@@ -994,6 +1007,7 @@ int build_class(nlinv_plan_s* p, Class& C) {
     CHK(dalloc(p, &C.sc.inv_s, C.nframes));
     CHK(dalloc(p, &C.sc.stats, (size_t)C.nframes * kStatsCap));
     C.sc.alpha = C.alpha;
+    C.sc.nframes = C.nframes;
     C.sc.stats_len = kStatsCap;
     for (int& v : C.colv) v = default_col_variant(C.n);
     for (int& v : C.rowv) v = default_row_variant(C.n);

@@ -145,6 +145,12 @@ struct ColArgs {
     // overlaps the column work instead of taking a launch of its own
     CoilSumArgs cs;
     int cs_blocks;
+    // COL_PUPD_WINV_IFFT_CROP: the previous iteration's SC_RR step folded in
+    // (op SC_RR and partial set): every workgroup computes its frame's beta
+    // from the <r, r> partials itself, and the frame's first workgroup
+    // records it (beta is then not read from `beta`)
+    ScalarStep fold;
+    Scalars sc;
 };
 
 
@@ -206,19 +212,39 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
     double acc_rho = 0.0;
     bool first_plane = false;
 
+    bool has_beta = false;
+    float beta = 0.f;
     if constexpr (PUPD) {
-        // rho part of the direction update, done by the first plane of each frame
         first_plane = plane == 0 || (a.plane_frame && a.plane_frame[plane - 1] != f);
+        if (a.fold.op == SC_RR && a.fold.partial) {   // uniform over the workgroup
+            __shared__ float beta_sh;
+            if (threadIdx.x < 64) {
+                const FrameScalars fs = load_frame_scalars(a.fold, a.sc, f);
+                const double t = frame_total_wave(a.fold.g, a.fold.partial, f, a.fold.frame_plane0,
+                                                  a.fold.frame_planes);
+                if (threadIdx.x == 0) {
+                    beta_sh = cg_beta(fs, t);
+                    if (first_plane && tile == 0) scalar_apply(a.fold, a.sc, f, t, fs);
+                }
+            }
+            __syncthreads();
+            has_beta = true;
+            beta = beta_sh;
+        } else if (a.beta) {
+            has_beta = true;
+            beta = a.beta[f];
+        }
+        // rho part of the direction update, done by the first plane of each frame
         if (first_plane) {
             const int E = m * m, ntiles = N / L;
             const int chunk = (E + ntiles - 1) / ntiles;
             const int e0 = tile * chunk, e1 = min(E, e0 + chunk);
-            const float bf = a.beta ? a.beta[f] : 0.f;
+            const float bf = beta;
             float2* pr = a.pr + (long long)f * E;
             const float2* rr = a.rr + (long long)f * E;
             for (int e = e0 + threadIdx.x; e < e1; e += NT) {
                 const float2 r = rr[e];
-                const float2 pv = a.beta ? make_float2(r.x + bf * pr[e].x, r.y + bf * pr[e].y) : r;
+                const float2 pv = has_beta ? make_float2(r.x + bf * pr[e].x, r.y + bf * pr[e].y) : r;
                 pr[e] = pv;
                 acc_rho += (double)(pv.x * pv.x + pv.y * pv.y);
             }
@@ -237,7 +263,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
             constexpr int CH = pointwise_chunk(N1);
             auto chunks = [&](auto HASB) {
                 constexpr bool HB = decltype(HASB)::value;
-                const float b = HB ? a.beta[f] : 0.f;
+                const float b = HB ? beta : 0.f;
                 static_for<0, N1 / CH>([&](auto C) {
                     float w[CH];
                     float2 rv[CH], pv[CH];
@@ -263,7 +289,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                     });
                 });
             };
-            if (a.beta) chunks(std::true_type{});
+            if (has_beta) chunks(std::true_type{});
             else chunks(std::false_type{});
         } else {
             static_for<0, N1>([&](auto K) {
