@@ -41,7 +41,7 @@ def kernel_bytes(kc: str, n: int, m: int, planes: int, frames: int) -> float:
         "col_pupd_winv_ifft": planes * c * (3 * nn + mn) + frames * 3 * c * mm,  # read r, p; write p, T
         "col_p_ifft": planes * c * (nn + mn) + frames * 4 * nn,
         "col_fft_p": planes * c * (mn + nn) + frames * 4 * nn,
-        "col_fft_p_resid": planes * c * (mn + 2 * nn) + frames * 4 * nn,
+        "col_resid_p_ifft": planes * c * (2 * mn + nn) + frames * 4 * nn,       # read T, y, P; write T
         "col_psf": planes * c * (2 * mn) + frames * 4 * nn,
         "col_fft_winv_add": planes * c * (mn + 3 * nn),                        # read T, x, x_ref; write
         # read T, p, r, x (chat) and the coil products; write r, x; rho parts: read p, r, dx; write r, dx

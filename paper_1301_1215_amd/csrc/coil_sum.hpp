@@ -36,6 +36,7 @@ struct CoilSumArgs {
     int self_dot;
     float2* r_upd;           // CG form: rho part of r (in place), nullable
     float2* dx_upd;          // rho part of dx (in place)
+    int dx_zero;             // dx starts from 0 (first CG iteration): not read
     const float* cg_a;       // [frames] CG step a
 };
 
@@ -58,7 +59,7 @@ __device__ __forceinline__ void coil_sum_block(const CoilSumArgs& a, int b, doub
         const float2 u1 = a.add1 ? a.add1[g] : zero;
         const float2 u2 = a.add2 ? a.add2[g] : zero;
         float2 r = a.r_upd ? a.r_upd[g] : zero;
-        float2 d = a.r_upd ? a.dx_upd[g] : zero;
+        float2 d = (a.r_upd && !a.dx_zero) ? a.dx_upd[g] : zero;
         // four independent chains over the planes (four loads in flight),
         // combined in a fixed order
         float2 s0 = zero, s1 = zero, s2 = zero, s3 = zero;

@@ -19,7 +19,7 @@ static hipError_t col_L(int mode, const ColArgs& a, int nplanes, hipStream_t s) 
             case COL_WINV_IFFT_CROP: NLINV_COL(COL_WINV_IFFT_CROP, true); break;
             case COL_P_IFFT_CROP: NLINV_COL(COL_P_IFFT_CROP, true); break;
             case COL_PAD_FFT_P: NLINV_COL(COL_PAD_FFT_P, true); break;
-            case COL_PAD_FFT_P_RESID: NLINV_COL(COL_PAD_FFT_P_RESID, true); break;
+            case COL_RESID_P_IFFT: NLINV_COL(COL_RESID_P_IFFT, true); break;
             case COL_PAD_FFT_P2_IFFT: NLINV_COL(COL_PAD_FFT_P2_IFFT, true); break;
             case COL_PAD_FFT_WINV_ADD: NLINV_COL(COL_PAD_FFT_WINV_ADD, true); break;
             case COL_PAD_FFT_GPROD: NLINV_COL(COL_PAD_FFT_GPROD, true); break;

@@ -83,13 +83,13 @@ bool row_ok(int n, int v) { return row_variant_ok(n, v); }
 
 // kernel classes for timing
 enum KClass : int {
-    KC_COL_WINV_IFFT = 0, KC_COL_P_IFFT, KC_COL_FFT_P, KC_COL_FFT_P_RESID, KC_COL_PSF,
+    KC_COL_WINV_IFFT = 0, KC_COL_P_IFFT, KC_COL_FFT_P, KC_COL_RESID_P_IFFT, KC_COL_PSF,
     KC_COL_FFT_WINV_ADD, KC_COL_FFT_GPROD, KC_COL_PUPD_WINV_IFFT, KC_COL_FFT_WINV_CG_UPD,
     KC_ROW_CACHE, KC_ROW_FWD, KC_ROW_DERIV, KC_ROW_ADJ,
     KC_COIL_SUM, KC_VEC_DOT, KC_VEC_OTHER, KC_SCALAR, KC_IMAGE, KC_NUM
 };
 const char* kKClassNames[KC_NUM] = {
-    "col_winv_ifft", "col_p_ifft", "col_fft_p", "col_fft_p_resid", "col_psf",
+    "col_winv_ifft", "col_p_ifft", "col_fft_p", "col_resid_p_ifft", "col_psf",
     "col_fft_winv_add", "col_fft_gprod", "col_pupd_winv_ifft", "col_fft_winv_cg_update",
     "row_cache", "row_fwd", "row_deriv", "row_adj",
     "coil_sum", "vec_dot", "vec_other", "scalar", "image"};
@@ -99,7 +99,7 @@ int col_kclass(int mode) {
         case COL_WINV_IFFT_CROP: return KC_COL_WINV_IFFT;
         case COL_P_IFFT_CROP: return KC_COL_P_IFFT;
         case COL_PAD_FFT_P: return KC_COL_FFT_P;
-        case COL_PAD_FFT_P_RESID: return KC_COL_FFT_P_RESID;
+        case COL_RESID_P_IFFT: return KC_COL_RESID_P_IFFT;
         case COL_PAD_FFT_P2_IFFT: return KC_COL_PSF;
         case COL_PAD_FFT_WINV_ADD: return KC_COL_FFT_WINV_ADD;
         case COL_PUPD_WINV_IFFT_CROP: return KC_COL_PUPD_WINV_IFFT;
@@ -306,7 +306,7 @@ bool col_operands_ok(int mode, const ColArgs& a) {
     switch (mode) {
         case COL_WINV_IFFT_CROP: return a.winv;
         case COL_P_IFFT_CROP: case COL_PAD_FFT_P: case COL_PAD_FFT_P2_IFFT: return a.P;
-        case COL_PAD_FFT_P_RESID: return a.P && a.add1;
+        case COL_RESID_P_IFFT: return a.P && a.add1;
         case COL_PAD_FFT_WINV_ADD: return a.winv;
         case COL_PAD_FFT_GPROD: return a.add1;
         case COL_PUPD_WINV_IFFT_CROP: return a.winv && a.r_in && a.p_out && a.pr && a.rr;
@@ -471,11 +471,9 @@ int seq_coil_maps(nlinv_plan_s* p, const Class& C, const Frames& fr, const float
     return run_row(p, C, ROW_CACHE, r, s);
 }
 
-// out = P . DFT(E(rho . c))  or, with y != NULL, out = s y - P . DFT(E(rho . c))
-// (then with `partial` set: |out|^2 per column tile into it, `g` its geometry)
+// out = P . DFT(E(rho . c))
 int seq_forward(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2* rho, const float2* c,
-                const float* P, long long p_stride, float2* out, const float2* y, const float* s_y,
-                hipStream_t s, double* partial = nullptr, SegGeom* g = nullptr) {
+                const float* P, long long p_stride, float2* out, hipStream_t s) {
     RowArgs r = row_args(C);
     r.c = c;
     r.rho = rho;
@@ -489,19 +487,35 @@ int seq_forward(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2*
     a.P = P;
     a.p_stride = p_stride;
     a.plane_frame = fr.plane_frame;
-    if (y) {
-        a.add1 = y;
-        a.s1 = s_y;
-        a.c1 = 1.f;
-        a.partial = partial;
-        if (g) {
-            *g = C.geom;
-            g->cseg = C.n / kColL[C.colv[COL_PAD_FFT_P_RESID]];
-            g->rseg = 0;
-        }
-        return run_col(p, C, COL_PAD_FFT_P_RESID, a, fr.nplanes, s);
-    }
     return run_col(p, C, COL_PAD_FFT_P, a, fr.nplanes, s);
+}
+
+// Newton step: T = crop_rows(IDFT_0(P . r0)) with the residual
+// r0 = s y - P . DFT(E(rho . c)) never stored (the first step of DF^H r0);
+// |r0|^2 partials into `partial`, `g` receives their geometry.
+int seq_residual_head(nlinv_plan_s* p, const Class& C, const Frames& fr, double* partial, SegGeom* g,
+                      hipStream_t s) {
+    RowArgs r = row_args(C);
+    r.c = C.c;
+    r.rho = C.x_r;
+    r.out = C.T;
+    r.plane_frame = fr.plane_frame;
+    r.nlines = fr.nplanes * C.m;
+    CHK(run_row(p, C, ROW_FWD, r, s));
+    ColArgs a = col_args(p, C, fr.tiled);
+    a.in = C.T;
+    a.out = C.T;
+    a.P = C.P;
+    a.p_stride = C.cplane();
+    a.plane_frame = fr.plane_frame;
+    a.add1 = C.y;
+    a.s1 = C.sc.s;
+    a.c1 = 1.f;
+    a.partial = partial;
+    *g = C.geom;
+    g->cseg = C.n / kColL[C.colv[COL_RESID_P_IFFT]];
+    g->rseg = 0;
+    return run_col(p, C, COL_RESID_P_IFFT, a, fr.nplanes, s);
 }
 
 // T = row-DFT(E(drho . c + rho . E^H W^{-1} dchat))   (first half of DF)
@@ -530,13 +544,18 @@ int seq_deriv_head(nlinv_plan_s* p, const Class& C, const Frames& fr, const floa
 int seq_adjoint_tail(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2* rho, const float2* c,
                      float2* drho_out, float2* dchat_out, const float2* add1c, const float2* add1r,
                      const float2* add2c, const float2* add2r, const float* s1, const float* s2,
-                     float c1, float c2, hipStream_t s, double* partial = nullptr, SegGeom* g = nullptr) {
+                     float c1, float c2, hipStream_t s, double* partial = nullptr, SegGeom* g = nullptr,
+                     const ScalarStep* fold = nullptr) {
     RowArgs r = row_args(C);
     r.in = C.T;
     r.out = C.T;
     r.c = c;
     r.rho = rho;
     r.aux = C.aux;
+    if (fold) {   // a scalar step on partials of earlier kernels, folded into the row pass
+        r.fold = *fold;
+        r.sc = C.sc;
+    }
     r.plane_frame = fr.plane_frame;
     r.nlines = fr.nplanes * C.m;
     CHK(run_row(p, C, ROW_ADJ, r, s));
@@ -573,6 +592,16 @@ int seq_adjoint_tail(nlinv_plan_s* p, const Class& C, const Frames& fr, const fl
 // pass and the coil sum then form q = N_alpha p in registers and apply
 // r -= a q, dx += a p directly (q is never stored), writing the |r|^2
 // partials from which beta follows.
+// Geometry of the <b, b> partials of the Newton right-hand side: column tiles
+// of the W^{-H} pass per plane, then the coil-sum segments per frame (as
+// seq_adjoint_tail reports them).
+SegGeom rhs_geom(const Class& C) {
+    SegGeom g = C.geom;
+    g.cseg = C.n / kColL[C.colv[COL_PAD_FFT_WINV_ADD]];
+    g.rseg = (int)((C.rplane() + kCoilSeg - 1) / kCoilSeg);
+    return g;
+}
+
 // Geometry of the <r, r> partials a CG iteration leaves: column tiles of the
 // CG-update pass per plane, then the segments of its fused coil sum per frame.
 SegGeom cg_rr_geom(const Class& C) {
@@ -596,10 +625,11 @@ int seq_cg_iteration(nlinv_plan_s* p, Class& C, int step, int it, int nsteps, in
     a.pr = C.p_r;
     a.rr = C.r_r;
     a.partial = C.part_p;
-    if (it > 0) {   // beta of the previous iteration, computed inside the pass
-        a.fold = scalar_step(C, SC_RR, cg_rr_geom(C), 0.f, step, it - 1, nsteps, ncg, C.partial2);
-        a.sc = C.sc;
-    }
+    // it > 0: beta of the previous iteration, computed inside the pass;
+    // it == 0: <b, b> of the right-hand side recorded by it
+    a.fold = it > 0 ? scalar_step(C, SC_RR, cg_rr_geom(C), 0.f, step, it - 1, nsteps, ncg, C.partial2)
+                    : scalar_step(C, SC_RR0, rhs_geom(C), 0.f, step, 0, nsteps, ncg, C.partial);
+    a.sc = C.sc;
     CHK(run_col(p, C, COL_PUPD_WINV_IFFT_CROP, a, fr.nplanes, s));
     RowArgs r = row_args(C);
     r.in = C.T;
@@ -655,6 +685,7 @@ int seq_cg_iteration(nlinv_plan_s* p, Class& C, int step, int it, int nsteps, in
                                    (long long)C.nplanes * tu);
     cs.r_upd = C.r_r;
     cs.dx_upd = C.dx_r;
+    cs.dx_zero = it == 0;            // dx = a p: no zero fill of dx beforehand
     cs.cg_a = C.sc.a;
     const SegGeom grr = cg_rr_geom(C);
     cs.segs = grr.rseg;
@@ -705,36 +736,24 @@ int enqueue_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s
             HIPCHK(hipGetLastError());
             // linearisation cache c at x_n
             CHK(seq_coil_maps(p, C, fr, C.x_c, C.c, s));
-            // r0 = s y - F(x_n) into q, its norm
+            // r0 = s y - F(x_n) (its norm) and the first step of DF^H r0
             SegGeom g0{};
-            CHK(seq_forward(p, C, fr, C.x_r, C.c, C.P, ps, C.q_c, C.y, C.sc.s, s, C.partial, &g0));
-            CHK(run_scalar(p, C, SC_R0NORM, g0, 0.f, step, s));
-            // b = DF^H r0 - alpha (x_n - x_ref) into r
+            CHK(seq_residual_head(p, C, fr, C.partial, &g0, s));
+            // b = DF^H r0 - alpha (x_n - x_ref) into r; ||r0|| recorded inside
+            // its adjoint row pass, <b, b> inside the first CG pass
             {
-                ColArgs a = col_args(p, C, fr.tiled);
-                a.in = C.q_c;
-                a.out = C.T;
-                a.P = C.P;
-                a.p_stride = ps;
-                a.plane_frame = fr.plane_frame;
-                CHK(run_col(p, C, COL_P_IFFT_CROP, a, fr.nplanes, s));
+                const ScalarStep r0 = scalar_step(C, SC_R0NORM, g0, 0.f, step);
                 SegGeom gb{};
                 CHK(seq_adjoint_tail(p, C, fr, C.x_r, C.c, C.r_r, C.r_c, C.x_c, C.x_r, C.xr_c, C.xr_r,
-                                     C.alpha + C.nframes, C.alpha, 0.f, 0.f, s, C.partial, &gb));
-                CHK(run_scalar(p, C, SC_RR0, gb, 0.f, step, s));
-            }
-            {
-                const int slot = tbegin(p, KC_VEC_OTHER, s);
-                hipLaunchKernelGGL(k_fill, dim3(grid_for((long long)C.nframes * C.rplane())), dim3(kThreads), 0, s,
-                                   C.dx_r, (long long)C.nframes * C.rplane(), make_float2(0.f, 0.f));
-                tend(p, slot, s);
-                HIPCHK(hipGetLastError());
+                                     C.alpha + C.nframes, C.alpha, 0.f, 0.f, s, C.partial, &gb, &r0));
+                (void)gb;   // the geometry rhs_geom() gives the first CG pass
             }
         }
         for (int it = 0; it < K; ++it) {
             for (Class& C : p->classes) CHK(seq_cg_iteration(p, C, step, it, N, K, s));
         }
         for (Class& C : p->classes) {   // rho += drho (the chat part is already in x)
+            if (K == 0) break;          // no step (dx_r is first written by CG iteration 0)
             SegGeom g = C.geom;
             g.nplanes = 0;
             CHK(run_vec<VEC_ADD>(p, g, vptrs(nullptr, C.x_r, nullptr, C.dx_r), nullptr, s));
@@ -1055,7 +1074,7 @@ ColArgs tune_col_args(nlinv_plan_s* p, Class& C, int mode) {
         case COL_PAD_FFT_P2_IFFT: a.partial = C.partial; break;
         case COL_P_IFFT_CROP: a.in = C.q_c; break;
         case COL_PAD_FFT_P: a.out = C.q_c; break;
-        case COL_PAD_FFT_P_RESID: a.out = C.q_c; a.add1 = C.y; a.s1 = C.sc.s; break;
+        case COL_RESID_P_IFFT: a.add1 = C.y; a.s1 = C.sc.s; break;   // in place on T
         case COL_PAD_FFT_WINV_ADD:
             a.out = C.r_c; a.add1 = C.x_c; a.add2 = C.xr_c; a.s1 = C.alpha + C.nframes; a.s2 = C.alpha;
             break;
@@ -1105,7 +1124,7 @@ int tune_class(nlinv_plan_s* p, Class& C, hipStream_t s) {
         return NLINV_OK;
     };
     const int col_modes[] = {COL_WINV_IFFT_CROP, COL_PUPD_WINV_IFFT_CROP, COL_P_IFFT_CROP, COL_PAD_FFT_P,
-                             COL_PAD_FFT_P_RESID, COL_PAD_FFT_P2_IFFT, COL_PAD_FFT_WINV_ADD,
+                             COL_RESID_P_IFFT, COL_PAD_FFT_P2_IFFT, COL_PAD_FFT_WINV_ADD,
                              COL_PAD_FFT_WINV_CG_UPD};
     for (int mode : col_modes) {
         const ColArgs a = tune_col_args(p, C, mode);
@@ -1267,7 +1286,7 @@ int nlinv_forward(nlinv_plan p, const nlinv_c32* rho, const nlinv_c32* chat, con
     const Frames fr = single_frame(p->dims[0].ncoils);
     float2* c = c_out ? (float2*)c_out : C.c;
     CHK(seq_coil_maps(p, C, fr, (const float2*)chat, c, s));
-    return seq_forward(p, C, fr, (const float2*)rho, c, P, 0, (float2*)y_out, nullptr, nullptr, s);
+    return seq_forward(p, C, fr, (const float2*)rho, c, P, 0, (float2*)y_out, s);
 }
 
 int nlinv_deriv(nlinv_plan p, const nlinv_c32* rho, const nlinv_c32* chat, const nlinv_c32* c,

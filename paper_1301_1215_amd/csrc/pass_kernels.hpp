@@ -93,7 +93,8 @@ enum ColMode : int {
     COL_WINV_IFFT_CROP = 0,   // T = crop_rows(IDFT_0(chat / w))
     COL_P_IFFT_CROP = 1,      // T = crop_rows(IDFT_0(P . z))
     COL_PAD_FFT_P = 2,        // out = P . DFT_0(pad_rows(T))
-    COL_PAD_FFT_P_RESID = 3,  // out = s_f y - P . DFT_0(pad_rows(T))
+    COL_RESID_P_IFFT = 3,     // T = crop_rows(IDFT_0(P . (s_f y - P . DFT_0(pad_rows(T)))))  (in place):
+                              //     the residual of F and the first step of its adjoint
     COL_PAD_FFT_P2_IFFT = 4,  // T = crop_rows(IDFT_0(P^2 . DFT_0(pad_rows(T))))   (in place)
     COL_PAD_FFT_WINV_ADD = 5, // out = DFT_0(pad_rows(T)) / w + a1_f add1 + a2_f add2
     COL_PAD_FFT_GPROD = 6,    // outR = Re(conj(g) . DFT_0(pad_rows(T)))  (mask gradient)
@@ -105,7 +106,7 @@ enum ColMode : int {
 struct ColArgs {
     const float2* in;
     float2* out;
-    const float2* add1;       // RESID: y; WINV_ADD: first added vector; GPROD: g
+    const float2* add1;       // RESID_P_IFFT: y; WINV_ADD: first added vector; GPROD: g
     const float2* add2;
     const float* P;           // [frames][n][n] with stride p_stride (0 = shared)
     long long p_stride;
@@ -133,7 +134,7 @@ struct ColArgs {
     //   COL_PUPD_WINV_IFFT_CROP   |p|^2 of the chat part; the first plane of
     //                             each frame adds the rho part's |p|^2 at
     //                             partial[nplanes * tiles + frame * tiles + tile]
-    //   COL_PAD_FFT_P_RESID       |out|^2 (the residual's norm)
+    //   COL_RESID_P_IFFT          |s y - P . DFT(...)|^2 (the residual's norm)
     //   COL_PAD_FFT_P2_IFFT       |P . DFT(...)|^2 = |DF h|^2 of the plane's coil
     //   COL_PAD_FFT_WINV_ADD      |out|^2
     //   COL_PAD_FFT_WINV_CG_UPD   |r|^2 after the update
@@ -148,7 +149,8 @@ struct ColArgs {
     // COL_PUPD_WINV_IFFT_CROP: the previous iteration's SC_RR step folded in
     // (op SC_RR and partial set): every workgroup computes its frame's beta
     // from the <r, r> partials itself, and the frame's first workgroup
-    // records it (beta is then not read from `beta`)
+    // records it (beta is then not read from `beta`); or, before the first
+    // iteration, the SC_RR0 step, recorded by the frame's first workgroup
     ScalarStep fold;
     Scalars sc;
 };
@@ -175,7 +177,9 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
     constexpr int NT = pass_threads(N, L);
     using CT = Centre<N>;
     constexpr int N1 = CT::N1, N2 = CT::N2;
-    constexpr bool TWO = (MODE == COL_PAD_FFT_P2_IFFT);
+    constexpr bool PSF = (MODE == COL_PAD_FFT_P2_IFFT);
+    constexpr bool RESID = (MODE == COL_RESID_P_IFFT);
+    constexpr bool TWO = PSF || RESID;             // forward, pointwise, inverse in one pass
     constexpr bool PUPD = (MODE == COL_PUPD_WINV_IFFT_CROP);
     constexpr bool WINV_IN = (MODE == COL_WINV_IFFT_CROP) || PUPD;
     constexpr bool INV1 = WINV_IN || (MODE == COL_P_IFFT_CROP);
@@ -183,8 +187,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
     constexpr bool OUT_CROP = INV1 || TWO;
     constexpr bool CGU = (MODE == COL_PAD_FFT_WINV_CG_UPD);
     constexpr bool WINV_OUT = (MODE == COL_PAD_FFT_WINV_ADD) || CGU;
-    constexpr bool RESID = (MODE == COL_PAD_FFT_P_RESID);
-    constexpr bool RED = CGU || PUPD || TWO || RESID || (MODE == COL_PAD_FFT_WINV_ADD);  // can write partial sums
+    constexpr bool RED = CGU || PUPD || TWO || (MODE == COL_PAD_FFT_WINV_ADD);  // can write partial sums
     // Exchange buffer [k1][j2][l] (slot j2 + N2 k1 of line l), each k1 row
     // padded by L entries: the L-line groups of one wavefront then fall on
     // different LDS banks in every access pattern below.
@@ -216,20 +219,29 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
     float beta = 0.f;
     if constexpr (PUPD) {
         first_plane = plane == 0 || (a.plane_frame && a.plane_frame[plane - 1] != f);
-        if (a.fold.op == SC_RR && a.fold.partial) {   // uniform over the workgroup
-            __shared__ float beta_sh;
-            if (threadIdx.x < 64) {
-                const FrameScalars fs = load_frame_scalars(a.fold, a.sc, f);
-                const double t = frame_total_wave(a.fold.g, a.fold.partial, f, a.fold.frame_plane0,
-                                                  a.fold.frame_planes);
-                if (threadIdx.x == 0) {
-                    beta_sh = cg_beta(fs, t);
-                    if (first_plane && tile == 0) scalar_apply(a.fold, a.sc, f, t, fs);
+        // uniform over the workgroup: SC_RR (iteration > 0) gives beta to
+        // every workgroup; SC_RR0 (iteration 0, p = r) is only recorded, by
+        // the frame's first workgroup
+        const bool rr0 = a.fold.op == SC_RR0;
+        const bool designated = first_plane && tile == 0;
+        if (a.fold.partial && (a.fold.op == SC_RR || rr0)) {
+            if (!rr0 || designated) {
+                __shared__ float beta_sh;
+                if (threadIdx.x < 64) {
+                    const FrameScalars fs = load_frame_scalars(a.fold, a.sc, f);
+                    const double t = frame_total_wave(a.fold.g, a.fold.partial, f, a.fold.frame_plane0,
+                                                      a.fold.frame_planes);
+                    if (threadIdx.x == 0) {
+                        beta_sh = rr0 ? 0.f : cg_beta(fs, t);
+                        if (designated) scalar_apply(a.fold, a.sc, f, t, fs);
+                    }
+                }
+                __syncthreads();
+                if (!rr0) {
+                    has_beta = true;
+                    beta = beta_sh;
                 }
             }
-            __syncthreads();
-            has_beta = true;
-            beta = beta_sh;
         } else if (a.beta) {
             has_beta = true;
             beta = a.beta[f];
@@ -328,8 +340,11 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
         // Every stage has at most one task per thread, so the intermediate
         // stays in bufA: read into registers, barrier, write back.
         static_assert(L * N1 <= NT && L * N2 <= NT, "one task per thread");
-        // stage 2 of the forward transform, times P^2 and 1/n at each output
-        // position, kept in slot order (the inverse reads the same slots)
+        // stage 2 of the forward transform, then the pointwise step at each
+        // output position, kept in slot order (the inverse reads the same
+        // slots).  What is handed to the inverse carries the centring sign of
+        // its position, as the forward's raw outputs do, and the inverse's
+        // 1/sqrt(n).
         const float rs2 = a.rs * a.rs;
         {
             const int t = threadIdx.x;
@@ -342,15 +357,41 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                     v[j2] = bufA[k1 * RS + j2 * L + l];
                 });
                 RegDFT<N2, false>::run(v);
-                float kacc = 0.f;
-                static_for<0, N2>([&](auto K) {
-                    constexpr int k2 = K;
-                    const int r = CT::out_pos(k1, k2);
-                    const float p = P[big_idx<N>(r, col, TILED)];
-                    kacc += p * p * (v[k2].x * v[k2].x + v[k2].y * v[k2].y);
-                    v[k2] = cscale(v[k2], p * p * rs2);
-                });
-                acc += (double)kacc * (double)rs2;   // |P K|^2 with K = rs . v (unitary DFT)
+                if constexpr (PSF) {   // times P^2 and 1/n
+                    float kacc = 0.f;
+                    static_for<0, N2>([&](auto K) {
+                        constexpr int k2 = K;
+                        const int r = CT::out_pos(k1, k2);
+                        const float p = P[big_idx<N>(r, col, TILED)];
+                        kacc += p * p * (v[k2].x * v[k2].x + v[k2].y * v[k2].y);
+                        v[k2] = cscale(v[k2], p * p * rs2);
+                    });
+                    acc += (double)kacc * (double)rs2;   // |P K|^2 with K = rs . v (unitary DFT)
+                } else {               // residual q = s y - P K, then P q
+                    const long long pb = (long long)plane * N * N;
+                    const float sy = a.s1 ? a.s1[f] : a.c1;
+                    constexpr int CH = pointwise_chunk(N2);
+                    float racc = 0.f;
+                    static_for<0, N2 / CH>([&](auto C) {
+                        float w[CH];
+                        float2 y[CH];
+                        static_for<0, CH>([&](auto I) {
+                            constexpr int k2 = C * CH + I;
+                            const long long o = big_idx<N>(CT::out_pos(k1, k2), col, TILED);
+                            w[I] = P[o];
+                            y[I] = a.add1[pb + o];
+                        });
+                        static_for<0, CH>([&](auto I) {
+                            constexpr int k2 = C * CH + I;
+                            const float sg = CT::sign(CT::out_pos(k1, k2));
+                            const float pk = w[I] * sg * a.rs;           // P times the forward's factors
+                            const float2 q = make_float2(sy * y[I].x - pk * v[k2].x, sy * y[I].y - pk * v[k2].y);
+                            racc += q.x * q.x + q.y * q.y;
+                            v[k2] = cscale(q, w[I] * sg * a.rs);
+                        });
+                    });
+                    acc += (double)racc;
+                }
             }
             __syncthreads();
             if (act) {
@@ -433,10 +474,9 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                     static_for<0, CH>([&](auto I) {
                         constexpr int k2 = C * CH + I;
                         const long long o = big_idx<N>(CT::out_pos(k1, k2), col, TILED);
-                        if constexpr (MODE == COL_PAD_FFT_P || MODE == COL_PAD_FFT_P_RESID) w[I] = P[o];
+                        if constexpr (MODE == COL_PAD_FFT_P) w[I] = P[o];
                         if constexpr (WINV_OUT || CGU) w[I] = a.winv[o];
-                        if constexpr (MODE == COL_PAD_FFT_P_RESID || MODE == COL_PAD_FFT_GPROD || CGU ||
-                                      (WINV_OUT && H1))
+                        if constexpr (MODE == COL_PAD_FFT_GPROD || CGU || (WINV_OUT && H1))
                             u1[I] = a.add1[pbase + o];
                         if constexpr (WINV_OUT && H2) u2[I] = a.add2[pbase + o];
                         if constexpr (CGU) {
@@ -451,12 +491,6 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                         float2 x = v[k2];
                         if constexpr (MODE == COL_PAD_FFT_P) {
                             a.out[pbase + o] = cscale(x, CT::sign(rp) * a.rs * w[I]);
-                        } else if constexpr (MODE == COL_PAD_FFT_P_RESID) {
-                            const float2 y = u1[I];
-                            const float p = CT::sign(rp) * a.rs * w[I];
-                            const float2 z = make_float2(s1 * y.x - p * x.x, s1 * y.y - p * x.y);
-                            a.out[pbase + o] = z;
-                            facc += z.x * z.x + z.y * z.y;
                         } else if constexpr (CGU) {
                             x = cscale(x, CT::sign(rp) * a.rs * w[I]);
                             const float2 u = u1[I];                          // p

@@ -141,7 +141,7 @@ def test_kernel_timing_counts_launches():
 
 
 # 1D transforms done by one launch of each pass class (per plane)
-TRANSFORMS_1D = {"col_winv_ifft": 1, "col_p_ifft": 1, "col_fft_p": 1, "col_fft_p_resid": 1, "col_psf": 2,
+TRANSFORMS_1D = {"col_winv_ifft": 1, "col_p_ifft": 1, "col_fft_p": 1, "col_resid_p_ifft": 2, "col_psf": 2,
                  "col_fft_winv_add": 1, "col_fft_gprod": 1, "row_cache": 1, "row_fwd": 1, "row_deriv": 2,
                  "row_adj": 2}
 
