@@ -75,6 +75,33 @@ def test_warm_start_and_reference():
         assert rel(host(out["chat"]), ref.chat) < NRMSE
 
 
+def test_zero_cg_iterations_keep_the_start():
+    """No CG iterations: every Newton step leaves x where it is (the oracle's
+    loop does the same); ||r0|| per step still matches."""
+    fr = synth.make_frame(1, 6, 64, 32, 4, "radial", spokes=9)
+    d = O.Dims(64, 32, 4)
+    rng = np.random.default_rng([3, 4])
+    rho0 = (0.5 + 0.1 * rng.standard_normal((32, 32))).astype(np.complex64)
+    chat0 = (0.01 * rng.standard_normal((4, 64, 64))).astype(np.complex64)
+    ref = O.irgnm(fr.y, fr.P, d, O.IRGNMParams(3, 0), rho0=rho0, chat0=chat0)
+    with Plan(64, 32, 4) as pl:
+        out = pl.solve(dev(fr.y), dev(fr.P), Plan.params(3, 0, use_graph=True, warm_start=True), rho0=dev(rho0),
+                       chat0=dev(chat0))
+        got = {k: host(v) for k, v in out.items()}
+    assert rel(got["rho"], ref.rho) < NRMSE and rel(got["chat"], ref.chat) < NRMSE
+    assert rel(got["image"], ref.image) < NRMSE
+    np.testing.assert_allclose(got["stats"][2:5], ref.r0_norms, rtol=1e-4)
+
+
+def test_single_cg_iteration_matches_oracle():
+    """One CG iteration per Newton step: the first iteration is also the last."""
+    fr = synth.single_frame_64()
+    ref = oracle_solve(fr, 3, 1)
+    got = gpu_solve(fr, 3, 1, use_graph=True)
+    assert rel(got["image"], ref.image) < NRMSE
+    np.testing.assert_allclose(got["stats"][2:5], ref.r0_norms, rtol=1e-4)
+
+
 def test_ragged_batch_matches_single_frames_and_oracle():
     shapes = [(64, 32, 3, 7), (48, 24, 2, 9), (64, 32, 4, 11), (96, 48, 2, 7), (48, 24, 5, 5)]
     frames = [synth.make_frame(4, 100 + i, n, m, J, "radial", spokes=S, mask_frame=i)
