@@ -146,6 +146,7 @@ struct Class {
     float* alpha = nullptr;      // [2F]: alpha, -alpha
     SegGeom geom{}, geomC{};
     Scalars sc{};
+    bool chat_ref_zero = false;  // this solve's x_ref has chat = 0 in every frame (not read then)
 
     long long cplane() const { return (long long)n * n; }
     long long rplane() const { return (long long)m * m; }
@@ -154,8 +155,10 @@ struct Class {
 struct GraphKey {
     int newton = -1, cg = -1;
     float a0 = 0, q = 0, amin = 0;
+    std::vector<bool> zero_ref;  // per class: its chat reference is all zero (not read)
     bool operator==(const GraphKey& o) const {
-        return newton == o.newton && cg == o.cg && a0 == o.a0 && q == o.q && amin == o.amin;
+        return newton == o.newton && cg == o.cg && a0 == o.a0 && q == o.q && amin == o.amin &&
+               zero_ref == o.zero_ref;
     }
 };
 
@@ -744,8 +747,9 @@ int enqueue_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s
             {
                 const ScalarStep r0 = scalar_step(C, SC_R0NORM, g0, 0.f, step);
                 SegGeom gb{};
-                CHK(seq_adjoint_tail(p, C, fr, C.x_r, C.c, C.r_r, C.r_c, C.x_c, C.x_r, C.xr_c, C.xr_r,
-                                     C.alpha + C.nframes, C.alpha, 0.f, 0.f, s, C.partial, &gb, &r0));
+                CHK(seq_adjoint_tail(p, C, fr, C.x_r, C.c, C.r_r, C.r_c, C.x_c, C.x_r,
+                                     C.chat_ref_zero ? nullptr : C.xr_c, C.xr_r, C.alpha + C.nframes, C.alpha,
+                                     0.f, 0.f, s, C.partial, &gb, &r0));
                 (void)gb;   // the geometry rhs_geom() gives the first CG pass
             }
         }
@@ -836,6 +840,9 @@ int setup_frames(nlinv_plan_s* p, const nlinv_frame* frames, const nlinv_irgnm_p
                                       hipMemcpyDeviceToDevice, s));
             }
         }
+        bool any_chat_ref = false;
+        for (int lf = 0; lf < C.nframes; ++lf) any_chat_ref = any_chat_ref || frames[C.frames[lf]].chat_ref;
+        C.chat_ref_zero = !warm && !any_chat_ref;   // x_ref = x0, whose chat part is 0
         // a caller's x_ref is in data units: scale its rho part (x0-derived refs already are scaled)
         bool any_ref = false;
         for (int lf = 0; lf < C.nframes; ++lf) {
@@ -905,7 +912,8 @@ int run_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s) {
     // stats_len must be known to the kernels that write stats
     for (Class& C : p->classes) C.sc.stats_len = kStatsCap;
     if (!(prm.flags & NLINV_USE_GRAPH)) return enqueue_newton(p, prm, s);
-    GraphKey key{prm.newton_steps, prm.cg_iters, prm.alpha0, prm.alpha_q, prm.alpha_min};
+    GraphKey key{prm.newton_steps, prm.cg_iters, prm.alpha0, prm.alpha_q, prm.alpha_min, {}};
+    for (const Class& C : p->classes) key.zero_ref.push_back(C.chat_ref_zero);
     if (!p->gexec || !(p->gkey == key)) {
         CHK(drop_graph(p));
         HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));

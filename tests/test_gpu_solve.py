@@ -102,6 +102,27 @@ def test_single_cg_iteration_matches_oracle():
     np.testing.assert_allclose(got["stats"][2:5], ref.r0_norms, rtol=1e-4)
 
 
+def test_graph_follows_the_reference_from_solve_to_solve():
+    """One plan, graph replay: a cold solve (its chat reference is zero and is
+    not read), then a warm start whose reference is not zero; both match the
+    oracle (the captured graph is not reused across the two)."""
+    fr = synth.make_frame(1, 7, 64, 32, 4, "radial", spokes=9)
+    d = O.Dims(64, 32, 4)
+    rng = np.random.default_rng([3, 5])
+    rho0 = (0.5 + 0.1 * rng.standard_normal((32, 32))).astype(np.complex64)
+    chat0 = (0.01 * rng.standard_normal((4, 64, 64))).astype(np.complex64)
+    cold = O.irgnm(fr.y, fr.P, d, O.IRGNMParams(3, 6))
+    warm = O.irgnm(fr.y, fr.P, d, O.IRGNMParams(3, 6), rho0=rho0, chat0=chat0)
+    with Plan(64, 32, 4) as pl:
+        a = pl.solve(dev(fr.y), dev(fr.P), Plan.params(3, 6, use_graph=True))
+        assert rel(host(a["image"]), cold.image) < NRMSE
+        b = pl.solve(dev(fr.y), dev(fr.P), Plan.params(3, 6, use_graph=True, warm_start=True), rho0=dev(rho0),
+                     chat0=dev(chat0))
+        assert rel(host(b["image"]), warm.image) < NRMSE
+        c = pl.solve(dev(fr.y), dev(fr.P), Plan.params(3, 6, use_graph=True))
+        assert rel(host(c["image"]), cold.image) < NRMSE
+
+
 def test_ragged_batch_matches_single_frames_and_oracle():
     shapes = [(64, 32, 3, 7), (48, 24, 2, 9), (64, 32, 4, 11), (96, 48, 2, 7), (48, 24, 5, 5)]
     frames = [synth.make_frame(4, 100 + i, n, m, J, "radial", spokes=S, mask_frame=i)
