@@ -459,18 +459,28 @@ CoilSumArgs coil_sum_args(const Class& C, const Frames& fr, float2* out, const f
 }
 
 // c = E^H W^{-1} chat
+// (inside a solve, optionally with the previous Newton step's rho update
+// and its last CG scalar step folded into the two passes)
 int seq_coil_maps(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2* chat, float2* c_out,
-                  hipStream_t s) {
+                  hipStream_t s, bool rho_update = false, const ScalarStep* fold = nullptr) {
     ColArgs a = col_args(p, C, fr.tiled);
     a.in = chat;
     a.out = C.T;
     a.plane_frame = fr.plane_frame;
+    if (rho_update) {
+        a.rho_acc = C.x_r;
+        a.rho_step = C.dx_r;
+    }
     CHK(run_col(p, C, COL_WINV_IFFT_CROP, a, fr.nplanes, s));
     RowArgs r = row_args(C);
     r.in = C.T;
     r.c_out = c_out;
     r.plane_frame = fr.plane_frame;
     r.nlines = fr.nplanes * C.m;
+    if (fold) {
+        r.fold = *fold;
+        r.sc = C.sc;
+    }
     return run_row(p, C, ROW_CACHE, r, s);
 }
 
@@ -697,9 +707,9 @@ int seq_cg_iteration(nlinv_plan_s* p, Class& C, int step, int it, int nsteps, in
     e.cs_blocks = C.nframes * cs.segs;
     CHK(run_col(p, C, COL_PAD_FFT_WINV_CG_UPD, e, fr.nplanes, s));
     // beta = <r,r>' / <r,r> from the |r|^2 partials: inside the next
-    // iteration's first pass, or here after the last iteration (its stats)
-    if (it + 1 < ncg) return NLINV_OK;
-    return run_scalar(p, C, SC_RR, grr, 0.f, step, s, it, nsteps, ncg, C.partial2);
+    // iteration's first pass; after the last iteration (only its stats are
+    // left) inside the next coil-map pass (the caller does that)
+    return NLINV_OK;
 }
 
 // (drho_out, dchat_out) = (DF^H DF + alpha) (drho, dchat)
@@ -737,8 +747,14 @@ int enqueue_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s
             const long long ps = C.cplane();
             hipLaunchKernelGGL(k_set_alpha, dim3((C.nframes + 63) / 64), dim3(64), 0, s, C.alpha, C.nframes, al);
             HIPCHK(hipGetLastError());
-            // linearisation cache c at x_n
-            CHK(seq_coil_maps(p, C, fr, C.x_c, C.c, s));
+            // linearisation cache c at x_n (with the previous step's rho
+            // update and its last CG step's stats folded in)
+            if (step > 0 && K > 0) {
+                const ScalarStep last = scalar_step(C, SC_RR, cg_rr_geom(C), 0.f, step - 1, K - 1, N, K, C.partial2);
+                CHK(seq_coil_maps(p, C, fr, C.x_c, C.c, s, true, &last));
+            } else {
+                CHK(seq_coil_maps(p, C, fr, C.x_c, C.c, s));
+            }
             // r0 = s y - F(x_n) (its norm) and the first step of DF^H r0
             SegGeom g0{};
             CHK(seq_residual_head(p, C, fr, C.partial, &g0, s));
@@ -756,15 +772,19 @@ int enqueue_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s
         for (int it = 0; it < K; ++it) {
             for (Class& C : p->classes) CHK(seq_cg_iteration(p, C, step, it, N, K, s));
         }
-        for (Class& C : p->classes) {   // rho += drho (the chat part is already in x)
-            if (K == 0) break;          // no step (dx_r is first written by CG iteration 0)
-            SegGeom g = C.geom;
-            g.nplanes = 0;
-            CHK(run_vec<VEC_ADD>(p, g, vptrs(nullptr, C.x_r, nullptr, C.dx_r), nullptr, s));
+        // the chat part of the step is already in x; rho += drho happens in
+        // the next coil-map pass (dx_r is first written by CG iteration 0)
+    }
+    // sensitivities of the final x (for the image), with the last step's
+    // rho update and last CG stats
+    for (Class& C : p->classes) {
+        if (N > 0 && K > 0) {
+            const ScalarStep last = scalar_step(C, SC_RR, cg_rr_geom(C), 0.f, N - 1, K - 1, N, K, C.partial2);
+            CHK(seq_coil_maps(p, C, class_frames(C), C.x_c, C.c, s, true, &last));
+        } else {
+            CHK(seq_coil_maps(p, C, class_frames(C), C.x_c, C.c, s));
         }
     }
-    // sensitivities of the final x (for the image)
-    for (Class& C : p->classes) CHK(seq_coil_maps(p, C, class_frames(C), C.x_c, C.c, s));
     return NLINV_OK;
 }
 

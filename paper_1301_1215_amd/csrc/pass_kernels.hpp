@@ -153,8 +153,12 @@ struct ColArgs {
     // iteration, the SC_RR0 step, recorded by the frame's first workgroup
     ScalarStep fold;
     Scalars sc;
+    // COL_WINV_IFFT_CROP: rho_acc += rho_step on the rho parts [frames][m*m]
+    // (the previous Newton step's rho update), done by the first plane's
+    // workgroups of each frame, a chunk per column tile; nullable
+    float2* rho_acc;
+    const float2* rho_step;
 };
-
 
 // Work item w = tile * nplanes + plane (planes of a tile adjacent, so the P
 // tile of a frame is reused); blocks are dealt to the 8 XCDs round robin, so
@@ -217,6 +221,16 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
 
     bool has_beta = false;
     float beta = 0.f;
+    if constexpr (MODE == COL_WINV_IFFT_CROP) {
+        if (a.rho_acc && (plane == 0 || (a.plane_frame && a.plane_frame[plane - 1] != f))) {
+            const int E = m * m, ntiles = N / L;
+            const int chunk = (E + ntiles - 1) / ntiles;
+            const int e0 = tile * chunk, e1 = min(E, e0 + chunk);
+            float2* x = a.rho_acc + (long long)f * E;
+            const float2* d = a.rho_step + (long long)f * E;
+            for (int e = e0 + threadIdx.x; e < e1; e += NT) x[e] = cadd(x[e], d[e]);
+        }
+    }
     if constexpr (PUPD) {
         first_plane = plane == 0 || (a.plane_frame && a.plane_frame[plane - 1] != f);
         // uniform over the workgroup: SC_RR (iteration > 0) gives beta to
@@ -550,7 +564,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
 // ---------------------------------------------------------------------------
 
 enum RowMode : int {
-    ROW_CACHE = 0,   // c = crop_cols(IDFT_1(T))
+    ROW_CACHE = 0,   // c = crop_cols(IDFT_1(T))  (may fold a scalar step, see RowArgs)
     ROW_FWD = 1,     // T = DFT_1(pad_cols(rho . c))
     ROW_DERIV = 2,   // dc = crop_cols(IDFT_1(T)); T = DFT_1(pad_cols(drho . c + rho . dc))
     ROW_ADJ = 3,     // u = crop_cols(IDFT_1(T)); aux = conj(c) . u; T = DFT_1(pad_cols(conj(rho) . u))
@@ -569,9 +583,9 @@ struct RowArgs {
     int m, lo;
     float rs;
     const float2* tw2;       // [N1][N2]
-    // ROW_ADJ: a per-frame scalar step folded into the launch (op SC_NONE or
-    // partial == nullptr: none), done by the first wavefront of the first
-    // workgroups before their lines
+    // ROW_ADJ, ROW_CACHE: a per-frame scalar step folded into the launch (op
+    // SC_NONE or partial == nullptr: none), done by the first wavefront of
+    // the first workgroups before their lines
     ScalarStep fold;
     Scalars sc;
 };
@@ -589,7 +603,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
     const int line0 = blockIdx.x * L;
     const int m = a.m, lo = a.lo;
     const int t = threadIdx.x;
-    if constexpr (MODE == ROW_ADJ) fold_scalar_step(a.fold, a.sc);
+    if constexpr (MODE == ROW_ADJ || MODE == ROW_CACHE) fold_scalar_step(a.fold, a.sc);
 
     if constexpr (MODE == ROW_FWD) {
         for (int idx = t; idx < L * N; idx += NT) {
