@@ -172,6 +172,12 @@ struct nlinv_plan_s {
     float sob_a = 220.f, sob_hl = 16.f;
     std::vector<void*> allocs;
     hipStream_t cap_stream = nullptr;
+    // shape classes are independent: with more than one, each runs its Newton
+    // loop on a stream of its own (default priority), forked from and joined
+    // back into the caller's stream (as concurrent branches in a graph)
+    std::vector<hipStream_t> lanes;
+    hipEvent_t fork_ev = nullptr;
+    std::vector<hipEvent_t> join_ev;
     hipGraphExec_t gexec = nullptr;
     GraphKey gkey;
     // kernel timing
@@ -738,11 +744,12 @@ float alpha_of(const nlinv_irgnm_params& prm, int step) {
     return (float)a;
 }
 
-int enqueue_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s) {
+// The Newton loop of one shape class on stream s.
+int enqueue_class_newton(nlinv_plan_s* p, Class& C, const nlinv_irgnm_params& prm, hipStream_t s) {
     const int N = prm.newton_steps, K = prm.cg_iters;
     for (int step = 0; step < N; ++step) {
         const float al = alpha_of(prm, step);
-        for (Class& C : p->classes) {
+        {
             const Frames fr = class_frames(C);
             const long long ps = C.cplane();
             hipLaunchKernelGGL(k_set_alpha, dim3((C.nframes + 63) / 64), dim3(64), 0, s, C.alpha, C.nframes, al);
@@ -769,21 +776,30 @@ int enqueue_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s
                 (void)gb;   // the geometry rhs_geom() gives the first CG pass
             }
         }
-        for (int it = 0; it < K; ++it) {
-            for (Class& C : p->classes) CHK(seq_cg_iteration(p, C, step, it, N, K, s));
-        }
+        for (int it = 0; it < K; ++it) CHK(seq_cg_iteration(p, C, step, it, N, K, s));
         // the chat part of the step is already in x; rho += drho happens in
         // the next coil-map pass (dx_r is first written by CG iteration 0)
     }
     // sensitivities of the final x (for the image), with the last step's
     // rho update and last CG stats
-    for (Class& C : p->classes) {
-        if (N > 0 && K > 0) {
-            const ScalarStep last = scalar_step(C, SC_RR, cg_rr_geom(C), 0.f, N - 1, K - 1, N, K, C.partial2);
-            CHK(seq_coil_maps(p, C, class_frames(C), C.x_c, C.c, s, true, &last));
-        } else {
-            CHK(seq_coil_maps(p, C, class_frames(C), C.x_c, C.c, s));
-        }
+    if (N > 0 && K > 0) {
+        const ScalarStep last = scalar_step(C, SC_RR, cg_rr_geom(C), 0.f, N - 1, K - 1, N, K, C.partial2);
+        return seq_coil_maps(p, C, class_frames(C), C.x_c, C.c, s, true, &last);
+    }
+    return seq_coil_maps(p, C, class_frames(C), C.x_c, C.c, s);
+}
+
+int enqueue_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s) {
+    if (p->classes.size() == 1 || p->lanes.size() != p->classes.size()) {
+        for (Class& C : p->classes) CHK(enqueue_class_newton(p, C, prm, s));
+        return NLINV_OK;
+    }
+    HIPCHK(hipEventRecord(p->fork_ev, s));
+    for (size_t i = 0; i < p->classes.size(); ++i) {
+        HIPCHK(hipStreamWaitEvent(p->lanes[i], p->fork_ev, 0));
+        CHK(enqueue_class_newton(p, p->classes[i], prm, p->lanes[i]));
+        HIPCHK(hipEventRecord(p->join_ev[i], p->lanes[i]));
+        HIPCHK(hipStreamWaitEvent(s, p->join_ev[i], 0));
     }
     return NLINV_OK;
 }
@@ -1066,6 +1082,9 @@ void free_plan(nlinv_plan_s* p) {
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    for (hipStream_t q : p->lanes) (void)hipStreamDestroy(q);
+    for (hipEvent_t e : p->join_ev) (void)hipEventDestroy(e);
+    if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
     for (void* q : p->allocs) (void)hipFree(q);
     delete p;
 }
@@ -1284,6 +1303,18 @@ int nlinv_plan_create(nlinv_plan* out, const nlinv_dims* dims, int32_t nframes) 
     }
     e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) { g_last_hip = (int)e; free_plan(p); return NLINV_EHIP; }
+    if (p->classes.size() > 1) {   // one stream per shape class (default priority)
+        e = hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
+        for (size_t i = 0; e == hipSuccess && i < p->classes.size(); ++i) {
+            hipStream_t q = nullptr;
+            hipEvent_t j = nullptr;
+            e = hipStreamCreateWithFlags(&q, hipStreamNonBlocking);
+            if (e == hipSuccess) p->lanes.push_back(q);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&j, hipEventDisableTiming);
+            if (e == hipSuccess) p->join_ev.push_back(j);
+        }
+        if (e != hipSuccess) { g_last_hip = (int)e; free_plan(p); return NLINV_EHIP; }
+    }
     e = hipDeviceSynchronize();
     if (e != hipSuccess) { g_last_hip = (int)e; free_plan(p); return NLINV_EHIP; }
     *out = p;
