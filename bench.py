@@ -25,6 +25,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 N, N_OM, J, SPOKES, NEWTON, CG = 384, 192, 12, 15, 7, 10
+# The timed steps bracket every 7th launch of the roofline's kernel class
+# with HIP events (each event record holds the stream a few microseconds);
+# 7 is coprime with the 10 CG iterations per Newton step, so the bracketed
+# launches cycle through every iteration index.
+TIMING_STRIDE = 7
 
 
 def log(*a):
@@ -328,7 +333,7 @@ def main():
     try:
         if kc is None:
             kc = dominant_class(pl, data, prm, outs, names)
-        pl.timing_enable(kc, True)
+        pl.timing_enable(kc, TIMING_STRIDE)
         pl.solve_batch(data, prm, outs)       # recapture with the brackets of this class
         torch.cuda.synchronize()
         pl.timing_read()
@@ -356,7 +361,7 @@ def main():
         launches, kms = pl.timing_read()
     else:
         # the same steps again on eager launches, with this class bracketed
-        pl.timing_enable(kc, True)
+        pl.timing_enable(kc, TIMING_STRIDE)
         for _ in range(a.steps):
             pl.solve_batch(data, eprm, outs)
         torch.cuda.synchronize()
@@ -379,7 +384,7 @@ def main():
     roof = {"bound": "hbm", "kernel": kc, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBPS) if achieved else None, "traffic": pmc_traffic(kc, B),
             "bytes_per_launch": per_launch, "avg_launch_ms": avg_ms, "launches_timed": launches,
-            "event_timing_on": timing_path}
+            "timing_stride": TIMING_STRIDE, "event_timing_on": timing_path}
 
     if a.stream_probe:
         extras["stream_copy_GBps"] = stream_probe()

@@ -194,10 +194,14 @@ int nlinv_plan_variant(nlinv_plan plan, int32_t n, int32_t* col_variant, int32_t
 int nlinv_plan_set_variant(nlinv_plan plan, int32_t n, int32_t col_variant, int32_t row_variant);
 
 /* ---- kernel timing --------------------------------------------------------
- * When enabled, every launch of the kernel class `kclass` (see
+ * enable = k >= 1: every k-th launch of the kernel class `kclass` (see
  * nlinv_kernel_class_name) made by this plan is bracketed by HIP events on
- * its stream; nlinv_plan_timing_read synchronises those events and returns
- * the launch count and the summed duration in milliseconds, then resets. */
+ * its stream, counting launches from this call and from the start of each
+ * graph capture (k = 1: every launch; each bracket costs the stream a few
+ * microseconds between kernels).  enable = 0: off; negative: NLINV_EINVAL.
+ * nlinv_plan_timing_read synchronises those events and returns the
+ * bracketed launch count and the summed duration in milliseconds, then
+ * resets. */
 int nlinv_plan_timing_enable(nlinv_plan plan, int32_t kclass, int32_t enable);
 int nlinv_plan_timing_read(nlinv_plan plan, int32_t* launches, double* total_ms);
 const char* nlinv_kernel_class_name(int32_t kclass);   /* NULL past the last */

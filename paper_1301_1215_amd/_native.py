@@ -270,9 +270,12 @@ def nlinv_kernel_class_names():
 
 
 def nlinv_plan_timing_enable(plan, kclass, enable=True):
+    """enable: True / 1 brackets every launch of the class, an int k >= 1
+    every k-th, False / 0 turns the brackets off."""
     if isinstance(kclass, str):
         kclass = nlinv_kernel_class_names().index(kclass)
-    check(load().nlinv_plan_timing_enable(plan, int(kclass), 1 if enable else 0), "nlinv_plan_timing_enable")
+    k = (1 if enable else 0) if isinstance(enable, bool) else int(enable)
+    check(load().nlinv_plan_timing_enable(plan, int(kclass), k), "nlinv_plan_timing_enable")
 
 
 def nlinv_plan_timing_read(plan):

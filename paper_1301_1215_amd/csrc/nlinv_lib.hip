@@ -182,6 +182,8 @@ struct nlinv_plan_s {
     GraphKey gkey;
     // kernel timing
     bool timing[KC_NUM] = {};
+    int timing_stride[KC_NUM] = {};   // bracket every stride-th launch of the class
+    long long timing_count[KC_NUM] = {};
     std::vector<hipEvent_t> ev;
     std::vector<unsigned char> ev_used;
     int ev_next = 0;
@@ -260,6 +262,7 @@ hipError_t record_event(nlinv_plan_s* p, hipEvent_t e, hipStream_t s) {
 // 2 = owned by the captured graph (re-recorded by every replay).
 int tbegin(nlinv_plan_s* p, int kc, hipStream_t s) {
     if (!p->timing[kc] || p->ev.empty()) return -1;
+    if (p->timing_count[kc]++ % p->timing_stride[kc] != 0) return -1;
     for (int tries = 0; tries < kTimingSlots; ++tries) {
         const int slot = p->ev_next;
         p->ev_next = (p->ev_next + 1) % kTimingSlots;
@@ -954,6 +957,7 @@ int run_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s) {
         CHK(drop_graph(p));
         HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
         p->capturing = true;
+        for (long long& c : p->timing_count) c = 0;   // the graph's brackets start at launch 0
         const int st = enqueue_newton(p, prm, p->cap_stream);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
@@ -1599,7 +1603,7 @@ int nlinv_plan_set_variant(nlinv_plan p, int32_t n, int32_t col_variant, int32_t
 }
 
 int nlinv_plan_timing_enable(nlinv_plan p, int32_t kclass, int32_t enable) {
-    if (!p || kclass < 0 || kclass >= KC_NUM) return NLINV_EINVAL;
+    if (!p || kclass < 0 || kclass >= KC_NUM || enable < 0) return NLINV_EINVAL;
     if (enable && p->ev.empty()) {
         p->ev.resize(2 * kTimingSlots);
         p->ev_used.assign(kTimingSlots, 0);
@@ -1609,6 +1613,8 @@ int nlinv_plan_timing_enable(nlinv_plan p, int32_t kclass, int32_t enable) {
         for (auto& e : p->ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     }
     p->timing[kclass] = enable != 0;
+    p->timing_stride[kclass] = enable > 0 ? enable : 1;
+    p->timing_count[kclass] = 0;
     CHK(drop_graph(p));   // a captured graph holds the old brackets
     return NLINV_OK;
 }

@@ -138,6 +138,14 @@ def test_kernel_timing_counts_launches():
         cnt, ms = pl.timing_read()
         assert cnt == 3 and ms > 0
         assert pl.timing_read()[0] == 0
+        # every 2nd launch from the enable call: launches 0, 2, 4 of 5
+        pl.timing_enable("col_psf", 2)
+        for _ in range(5):
+            pl.normal(*args, 0.5, dev(rho), dev(chat))
+        assert pl.timing_read()[0] == 3
+        from paper_1301_1215_amd._native import NlinvError
+        with pytest.raises(NlinvError):
+            pl.timing_enable("col_psf", -1)
 
 
 # 1D transforms done by one launch of each pass class (per plane)
