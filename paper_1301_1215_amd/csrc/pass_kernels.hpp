@@ -221,6 +221,11 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
 
     bool has_beta = false;
     float beta = 0.f;
+    // PUPD: the first chunk of this thread's stage-1 operands, loaded before
+    // beta is formed so that their latency overlaps the scalar fold
+    constexpr int CHP = PUPD ? pointwise_chunk(N1) : 1;
+    float2 rv0[CHP], pv0[CHP];
+    float w0[CHP];
     if constexpr (MODE == COL_WINV_IFFT_CROP) {
         if (a.rho_acc && (plane == 0 || (a.plane_frame && a.plane_frame[plane - 1] != f))) {
             const int E = m * m, ntiles = N / L;
@@ -232,6 +237,21 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
         }
     }
     if constexpr (PUPD) {
+        // whether p = r + beta p or p = r is uniform and known from the
+        // arguments; only beta's value waits for the fold
+        const bool fold_rr = a.fold.partial && (a.fold.op == SC_RR || a.fold.op == SC_RR0);
+        has_beta = fold_rr ? a.fold.op == SC_RR : a.beta != nullptr;
+        static_assert(L * N2 <= NT, "one stage-1 task per thread");
+        if ((int)threadIdx.x < L * N2) {
+            const int l = threadIdx.x % L, j2 = threadIdx.x / L, col = col0 + l;
+            static_for<0, CHP>([&](auto I) {
+                constexpr int k1 = I;
+                const long long o = big_idx<N>(CT::in_pos(j2, k1), col, TILED);
+                rv0[I] = a.r_in[pofs + o];
+                pv0[I] = has_beta ? src[o] : make_float2(0.f, 0.f);
+                w0[I] = a.winv[o];
+            });
+        }
         first_plane = plane == 0 || (a.plane_frame && a.plane_frame[plane - 1] != f);
         // uniform over the workgroup: SC_RR (iteration > 0) gives beta to
         // every workgroup; SC_RR0 (iteration 0, p = r) is only recorded, by
@@ -251,13 +271,9 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                     }
                 }
                 __syncthreads();
-                if (!rr0) {
-                    has_beta = true;
-                    beta = beta_sh;
-                }
+                if (!rr0) beta = beta_sh;
             }
         } else if (a.beta) {
-            has_beta = true;
             beta = a.beta[f];
         }
         // rho part of the direction update, done by the first plane of each frame
@@ -286,7 +302,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
             // p = r + beta p, written back; the operands of a chunk of
             // elements are loaded before its p values are stored (see the
             // last stage)
-            constexpr int CH = pointwise_chunk(N1);
+            constexpr int CH = CHP;
             auto chunks = [&](auto HASB) {
                 constexpr bool HB = decltype(HASB)::value;
                 const float b = HB ? beta : 0.f;
@@ -295,10 +311,16 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                     float2 rv[CH], pv[CH];
                     static_for<0, CH>([&](auto I) {
                         constexpr int k1 = C * CH + I;
-                        const long long o = big_idx<N>(CT::in_pos(j2, k1), col, TILED);
-                        rv[I] = a.r_in[pofs + o];
-                        if constexpr (HB) pv[I] = src[o];
-                        w[I] = a.winv[o];
+                        if constexpr (decltype(C)::value == 0) {   // loaded before the fold
+                            rv[I] = rv0[I];
+                            pv[I] = pv0[I];
+                            w[I] = w0[I];
+                        } else {
+                            const long long o = big_idx<N>(CT::in_pos(j2, k1), col, TILED);
+                            rv[I] = a.r_in[pofs + o];
+                            if constexpr (HB) pv[I] = src[o];
+                            w[I] = a.winv[o];
+                        }
                     });
                     static_for<0, CH>([&](auto I) {
                         constexpr int k1 = C * CH + I;
