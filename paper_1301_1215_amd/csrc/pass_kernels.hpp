@@ -59,9 +59,19 @@ template <int N>
 constexpr int plane_tile() { return plane_tile_width(N); }
 
 template <int N>
-__device__ __forceinline__ long long big_idx(int r, int col, bool tiled) {
+__device__ __forceinline__ int big_idx(int r, int col, bool tiled) {
     constexpr int TW = plane_tile<N>();
-    return tiled ? ((long long)(col / TW) * N + r) * TW + (col % TW) : (long long)r * N + col;
+    return tiled ? ((col / TW) * N + r) * TW + (col % TW) : r * N + col;
+}
+
+// Element i of an array that starts at a workgroup-uniform base and spans
+// less than 4 GiB (one plane, one frame's rows): a 32-bit byte offset, which
+// the compiler can address as scalar base + vector offset instead of
+// forming a 64-bit address per access.
+template <class T>
+__device__ __forceinline__ T& elt(T* base, int i) {
+    using B = std::conditional_t<std::is_const<T>::value, const char, char>;
+    return *reinterpret_cast<T*>(reinterpret_cast<B*>(base) + (unsigned)i * (unsigned)sizeof(T));
 }
 
 // Outputs per chunk of a pointwise stage (a divisor of the stage length,
@@ -75,7 +85,7 @@ constexpr int pointwise_chunk(int n2, int cmax = 8) {
 // output; these chunk caps keep them at or under 128 VGPRs (4 waves per
 // SIMD on gfx950), which measured faster than larger chunks at 3 waves.
 constexpr int kRowChunk = 3;
-constexpr int kCgChunk = 6;
+constexpr int kCgChunk = 4;
 
 // Threads of a pass workgroup over L lines: enough for one task per thread in
 // the larger of the two FFT stages (L*N1 or L*N2 tasks), in whole wavefronts.
@@ -246,10 +256,10 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
             const int l = threadIdx.x % L, j2 = threadIdx.x / L, col = col0 + l;
             static_for<0, CHP>([&](auto I) {
                 constexpr int k1 = I;
-                const long long o = big_idx<N>(CT::in_pos(j2, k1), col, TILED);
-                rv0[I] = a.r_in[pofs + o];
-                pv0[I] = has_beta ? src[o] : make_float2(0.f, 0.f);
-                w0[I] = a.winv[o];
+                const int o = big_idx<N>(CT::in_pos(j2, k1), col, TILED);
+                rv0[I] = elt(a.r_in + pofs, o);
+                pv0[I] = has_beta ? elt(src, o) : make_float2(0.f, 0.f);
+                w0[I] = elt(a.winv, o);
             });
         }
         first_plane = plane == 0 || (a.plane_frame && a.plane_frame[plane - 1] != f);
@@ -316,22 +326,22 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                             pv[I] = pv0[I];
                             w[I] = w0[I];
                         } else {
-                            const long long o = big_idx<N>(CT::in_pos(j2, k1), col, TILED);
-                            rv[I] = a.r_in[pofs + o];
-                            if constexpr (HB) pv[I] = src[o];
-                            w[I] = a.winv[o];
+                            const int o = big_idx<N>(CT::in_pos(j2, k1), col, TILED);
+                            rv[I] = elt(a.r_in + pofs, o);
+                            if constexpr (HB) pv[I] = elt(src, o);
+                            w[I] = elt(a.winv, o);
                         }
                     });
                     static_for<0, CH>([&](auto I) {
                         constexpr int k1 = C * CH + I;
                         const int r = CT::in_pos(j2, k1);
-                        const long long o = big_idx<N>(r, col, TILED);
+                        const int o = big_idx<N>(r, col, TILED);
                         float2 x = rv[I];
                         if constexpr (HB) {
                             x.x += b * pv[I].x;
                             x.y += b * pv[I].y;
                         }
-                        a.p_out[pofs + o] = x;
+                        elt(a.p_out + pofs, o) = x;
                         pacc += x.x * x.x + x.y * x.y;
                         v[k1] = cscale(x, CT::sign(r) * w[I]);
                     });
@@ -346,13 +356,13 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                 float2 x = make_float2(0.f, 0.f);
                 if constexpr (IN_CROP) {
                     const int ri = r - lo;
-                    if (ri >= 0 && ri < m) x = cscale(src[(long long)ri * N + col], CT::sign(r));
+                    if (ri >= 0 && ri < m) x = cscale(elt(src, ri * N + col), CT::sign(r));
                 } else {
-                    const long long o = big_idx<N>(r, col, TILED);
+                    const int o = big_idx<N>(r, col, TILED);
                     if constexpr (WINV_IN) {
-                        x = cscale(src[o], CT::sign(r) * a.winv[o]);
+                        x = cscale(elt(src, o), CT::sign(r) * elt(a.winv, o));
                     } else {   // COL_P_IFFT_CROP
-                        x = cscale(src[o], CT::sign(r) * P[o]);
+                        x = cscale(elt(src, o), CT::sign(r) * elt(P, o));
                     }
                 }
                 v[k1] = x;
@@ -364,7 +374,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
             constexpr int k1 = K;
             float2 x = v[k1];
             if constexpr (k1 > 0) {
-                const float2 w = a.tw2[k1 * N2 + j2];
+                const float2 w = elt(a.tw2, k1 * N2 + j2);
                 x = INV1 ? cmulc(x, w) : cmul(x, w);
             }
             bufA[k1 * RS + j2 * L + l] = x;
@@ -398,7 +408,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                     static_for<0, N2>([&](auto K) {
                         constexpr int k2 = K;
                         const int r = CT::out_pos(k1, k2);
-                        const float p = P[big_idx<N>(r, col, TILED)];
+                        const float p = elt(P, big_idx<N>(r, col, TILED));
                         kacc += p * p * (v[k2].x * v[k2].x + v[k2].y * v[k2].y);
                         v[k2] = cscale(v[k2], p * p * rs2);
                     });
@@ -413,9 +423,9 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                         float2 y[CH];
                         static_for<0, CH>([&](auto I) {
                             constexpr int k2 = C * CH + I;
-                            const long long o = big_idx<N>(CT::out_pos(k1, k2), col, TILED);
-                            w[I] = P[o];
-                            y[I] = a.add1[pb + o];
+                            const int o = big_idx<N>(CT::out_pos(k1, k2), col, TILED);
+                            w[I] = elt(P, o);
+                            y[I] = elt(a.add1 + pb, o);
                         });
                         static_for<0, CH>([&](auto I) {
                             constexpr int k2 = C * CH + I;
@@ -453,7 +463,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                 RegDFT<N1, true>::run(v);
                 static_for<0, N1>([&](auto K) {
                     constexpr int k1 = K;
-                    if constexpr (k1 > 0) v[k1] = cmulc(v[k1], a.tw2[k1 * N2 + j2]);
+                    if constexpr (k1 > 0) v[k1] = cmulc(v[k1], elt(a.tw2, k1 * N2 + j2));
                 });
             }
             __syncthreads();
@@ -492,7 +502,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                 const int ri = rp - lo;
                 if (ri >= 0 && ri < m) {
                     const float s = TWO ? CT::sign(rp) : CT::sign(rp) * a.rs;
-                    a.out[((long long)plane * m + ri) * N + col] = cscale(v[k2], s);
+                    elt(a.out + (long long)plane * m * N, ri * N + col) = cscale(v[k2], s);
                 }
             });
         } else {
@@ -509,24 +519,24 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                     float2 u1[CH], u2[CH], u3[CH];
                     static_for<0, CH>([&](auto I) {
                         constexpr int k2 = C * CH + I;
-                        const long long o = big_idx<N>(CT::out_pos(k1, k2), col, TILED);
-                        if constexpr (MODE == COL_PAD_FFT_P) w[I] = P[o];
-                        if constexpr (WINV_OUT || CGU) w[I] = a.winv[o];
+                        const int o = big_idx<N>(CT::out_pos(k1, k2), col, TILED);
+                        if constexpr (MODE == COL_PAD_FFT_P) w[I] = elt(P, o);
+                        if constexpr (WINV_OUT || CGU) w[I] = elt(a.winv, o);
                         if constexpr (MODE == COL_PAD_FFT_GPROD || CGU || (WINV_OUT && H1))
-                            u1[I] = a.add1[pbase + o];
-                        if constexpr (WINV_OUT && H2) u2[I] = a.add2[pbase + o];
+                            u1[I] = elt(a.add1 + pbase, o);
+                        if constexpr (WINV_OUT && H2) u2[I] = elt(a.add2 + pbase, o);
                         if constexpr (CGU) {
-                            u2[I] = a.out[pbase + o];    // r
-                            u3[I] = a.dx[pbase + o];
+                            u2[I] = elt(a.out + pbase, o);    // r
+                            u3[I] = elt(a.dx + pbase, o);
                         }
                     });
                     static_for<0, CH>([&](auto I) {
                         constexpr int k2 = C * CH + I;
                         const int rp = CT::out_pos(k1, k2);
-                        const long long o = big_idx<N>(rp, col, TILED);
+                        const int o = big_idx<N>(rp, col, TILED);
                         float2 x = v[k2];
                         if constexpr (MODE == COL_PAD_FFT_P) {
-                            a.out[pbase + o] = cscale(x, CT::sign(rp) * a.rs * w[I]);
+                            elt(a.out + pbase, o) = cscale(x, CT::sign(rp) * a.rs * w[I]);
                         } else if constexpr (CGU) {
                             x = cscale(x, CT::sign(rp) * a.rs * w[I]);
                             const float2 u = u1[I];                          // p
@@ -535,22 +545,22 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                             float2 r = u2[I];
                             r.x -= av * x.x;
                             r.y -= av * x.y;
-                            a.out[pbase + o] = r;
+                            elt(a.out + pbase, o) = r;
                             float2 d = u3[I];
                             d.x += av * u.x;
                             d.y += av * u.y;
-                            a.dx[pbase + o] = d;
+                            elt(a.dx + pbase, o) = d;
                             facc += r.x * r.x + r.y * r.y;
                         } else if constexpr (WINV_OUT) {
                             x = cscale(x, CT::sign(rp) * a.rs * w[I]);
                             if constexpr (H1) { x.x += s1 * u1[I].x; x.y += s1 * u1[I].y; }
                             if constexpr (H2) { x.x += s2 * u2[I].x; x.y += s2 * u2[I].y; }
-                            a.out[pbase + o] = x;
+                            elt(a.out + pbase, o) = x;
                             facc += x.x * x.x + x.y * x.y;
                         } else if constexpr (MODE == COL_PAD_FFT_GPROD) {
                             const float2 g = u1[I];
                             x = cscale(x, CT::sign(rp) * a.rs);
-                            reinterpret_cast<float*>(a.out)[pbase + o] = g.x * x.x + g.y * x.y;
+                            elt(reinterpret_cast<float*>(a.out) + pbase, o) = g.x * x.x + g.y * x.y;
                         }
                     });
                 });
@@ -636,7 +646,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
             if (line < a.nlines && q >= 0 && q < m) {
                 const int plane = line / m, i = line % m;
                 const int f = a.plane_frame ? a.plane_frame[plane] : 0;
-                z = cscale(cmul(a.rho[((long long)f * m + i) * m + q], a.c[((long long)plane * m + i) * m + q]),
+                z = cscale(cmul(elt(a.rho + (long long)f * m * m, i * m + q), elt(a.c + (long long)line0 * m, ll * m + q)),
                            CT::sign(pos));
             }
             buf[ll * N + pos] = z;
@@ -651,13 +661,14 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
             static_for<0, N1>([&](auto K) {
                 constexpr int k1 = K;
                 const int p = CT::in_pos(j2, k1);
-                v[k1] = line < a.nlines ? cscale(a.in[(long long)line * N + p], CT::sign(p)) : make_float2(0.f, 0.f);
+                v[k1] = line < a.nlines ? cscale(elt(a.in + (long long)line0 * N, ll * N + p), CT::sign(p))
+                                        : make_float2(0.f, 0.f);
             });
             RegDFT<N1, true>::run(v);
             static_for<0, N1>([&](auto K) {
                 constexpr int k1 = K;
                 float2 x = v[k1];
-                if constexpr (k1 > 0) x = cmulc(x, a.tw2[k1 * N2 + j2]);
+                if constexpr (k1 > 0) x = cmulc(x, elt(a.tw2, k1 * N2 + j2));
                 buf[(ll * N1 + k1) * S2 + j2] = x;
             });
         }
@@ -685,24 +696,27 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
                         const int pos = CT::out_pos(k1, k2);
                         const int q = pos - lo;
                         if (live && q >= 0 && q < m)
-                            a.c_out[((long long)plane * m + i) * m + q] = cscale(v[k2], CT::sign(pos) * a.rs);
+                            elt(a.c_out + (long long)line0 * m, (line_c - line0) * m + q) = cscale(v[k2], CT::sign(pos) * a.rs);
                     });
                 } else {
                     // the pointwise products, CH outputs at a time: the operands
                     // of a chunk are loaded (from a valid column for outputs
                     // outside Omega) before any of its results is formed
                     constexpr int CH = pointwise_chunk(N2, kRowChunk);
-                    const long long cbase = ((long long)plane * m + i) * m;
-                    const long long rbase = ((long long)f * m + i) * m;
+                    // this line's row of c and aux from the workgroup's base, and its frame's row of rho
+                    const int cofs = (line_c - line0) * m;
+                    const float2* crow = a.c + (long long)line0 * m;
+                    const float2* rrow = a.rho + ((long long)f * m + i) * m;
+                    const float2* drow = MODE == ROW_DERIV ? a.drho + ((long long)f * m + i) * m : nullptr;
                     static_for<0, N2 / CH>([&](auto C) {
                         float2 cv[CH], rv[CH], dv[CH];
                         static_for<0, CH>([&](auto I) {
                             constexpr int k2 = C * CH + I;
                             const int q = CT::out_pos(k1, k2) - lo;
                             const int qc = (q >= 0 && q < m) ? q : 0;
-                            cv[I] = a.c[cbase + qc];
-                            rv[I] = a.rho[rbase + qc];
-                            if constexpr (MODE == ROW_DERIV) dv[I] = a.drho[rbase + qc];
+                            cv[I] = elt(crow, cofs + qc);
+                            rv[I] = elt(rrow, qc);
+                            if constexpr (MODE == ROW_DERIV) dv[I] = elt(drow, qc);
                         });
                         static_for<0, CH>([&](auto I) {
                             constexpr int k2 = C * CH + I;
@@ -714,7 +728,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
                                 if constexpr (MODE == ROW_DERIV) {
                                     z = cadd(cmul(dv[I], cv[I]), cmul(rv[I], u));
                                 } else {  // ROW_ADJ
-                                    a.aux[cbase + q] = cconjmul(cv[I], u);
+                                    elt(a.aux + (long long)line0 * m, cofs + q) = cconjmul(cv[I], u);
                                     z = cconjmul(rv[I], u);
                                 }
                                 z = cscale(z, CT::sign(pos));
@@ -748,7 +762,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
             RegDFT<N1, false>::run(v);
             static_for<0, N1>([&](auto K) {
                 constexpr int k1 = K;
-                if constexpr (k1 > 0) v[k1] = cmul(v[k1], a.tw2[k1 * N2 + j2]);
+                if constexpr (k1 > 0) v[k1] = cmul(v[k1], elt(a.tw2, k1 * N2 + j2));
             });
         }
         __syncthreads();
@@ -774,7 +788,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
             static_for<0, N2>([&](auto K) {
                 constexpr int k2 = K;
                 const int pos = CT::out_pos(k1, k2);
-                a.out[(long long)line * N + pos] = cscale(v[k2], CT::sign(pos) * a.rs);
+                elt(a.out + (long long)line0 * N, ll * N + pos) = cscale(v[k2], CT::sign(pos) * a.rs);
             });
         }
     }
