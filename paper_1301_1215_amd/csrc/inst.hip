@@ -13,8 +13,11 @@ static hipError_t col_L(int mode, const ColArgs& a, int nplanes, hipStream_t s) 
     const int total = (N / L) * nplanes;
     const int extra = mode == COL_PAD_FFT_WINV_CG_UPD ? a.cs_blocks : 0;   // fused coil-sum workgroups
     const dim3 grid(8 * ((total + 7) / 8) + extra), block(pass_threads(N, L));
-#define NLINV_COL(MODE, T) hipLaunchKernelGGL((k_col<N, L, MODE, T>), grid, block, 0, s, a)
-    if (a.tiled) {   // inside a solve: every mode
+    const bool half = 2 * a.m == N && 4 * a.lo == N;
+#define NLINV_COL(MODE, T)                                                                   \
+    if (T && half) hipLaunchKernelGGL((k_col<N, L, MODE, T, T>), grid, block, 0, s, a);        \
+    else hipLaunchKernelGGL((k_col<N, L, MODE, T, false>), grid, block, 0, s, a)
+    if (a.tiled) {   // inside a solve: every mode, Omega = the centred half specialised
         switch (mode) {
             case COL_WINV_IFFT_CROP: NLINV_COL(COL_WINV_IFFT_CROP, true); break;
             case COL_P_IFFT_CROP: NLINV_COL(COL_P_IFFT_CROP, true); break;
@@ -45,13 +48,18 @@ static hipError_t col_L(int mode, const ColArgs& a, int nplanes, hipStream_t s) 
 template <int N, int L>
 static hipError_t row_L(int mode, const RowArgs& a, hipStream_t s) {
     const dim3 grid((a.nlines + L - 1) / L), block(pass_threads(N, L));
+    const bool half = 2 * a.m == N && 4 * a.lo == N;
+#define NLINV_ROW(MODE)                                                                   \
+    if (half) hipLaunchKernelGGL((k_row<N, L, MODE, true>), grid, block, 0, s, a);         \
+    else hipLaunchKernelGGL((k_row<N, L, MODE, false>), grid, block, 0, s, a)
     switch (mode) {
-        case ROW_CACHE: hipLaunchKernelGGL((k_row<N, L, ROW_CACHE>), grid, block, 0, s, a); break;
-        case ROW_FWD: hipLaunchKernelGGL((k_row<N, L, ROW_FWD>), grid, block, 0, s, a); break;
-        case ROW_DERIV: hipLaunchKernelGGL((k_row<N, L, ROW_DERIV>), grid, block, 0, s, a); break;
-        case ROW_ADJ: hipLaunchKernelGGL((k_row<N, L, ROW_ADJ>), grid, block, 0, s, a); break;
+        case ROW_CACHE: NLINV_ROW(ROW_CACHE); break;
+        case ROW_FWD: NLINV_ROW(ROW_FWD); break;
+        case ROW_DERIV: NLINV_ROW(ROW_DERIV); break;
+        case ROW_ADJ: NLINV_ROW(ROW_ADJ); break;
         default: return hipErrorInvalidValue;
     }
+#undef NLINV_ROW
     return hipGetLastError();
 }
 

@@ -186,7 +186,7 @@ __device__ __forceinline__ bool col_item(int ntiles, int nplanes, int& tile, int
 
 // TILED: the n x n operands are in the column-tiled solve layout (as
 // ColArgs::tiled, fixed at compile time so no access computes both forms).
-template <int N, int L, int MODE, bool TILED>
+template <int N, int L, int MODE, bool TILED, bool HALF>
 __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
     constexpr int NT = pass_threads(N, L);
     using CT = Centre<N>;
@@ -221,7 +221,9 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
     if (!col_item(N / L, a.nplanes, tile, plane)) return;
     const int col0 = tile * L;
     const int f = a.plane_frame ? a.plane_frame[plane] : 0;
-    const int m = a.m, lo = a.lo;
+    // HALF: Omega is the centred half of the grid (m = n/2, 2x oversampling),
+    // fixed at compile time so that every crop and pad test folds away
+    const int m = HALF ? N / 2 : a.m, lo = HALF ? N / 4 : a.lo;
     const float* P = a.P + (long long)f * a.p_stride;
     const long long pofs = (long long)plane * (IN_CROP ? m : N) * N;
     const float2* src = a.in + pofs;
@@ -622,7 +624,7 @@ struct RowArgs {
     Scalars sc;
 };
 
-template <int N, int L, int MODE>
+template <int N, int L, int MODE, bool HALF>
 __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
     using CT = Centre<N>;
     constexpr int N1 = CT::N1, N2 = CT::N2;
@@ -633,7 +635,9 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
     // the two transforms: every stage reads into registers, waits, then writes
     __shared__ float2 buf[L * N1 * S2];
     const int line0 = blockIdx.x * L;
-    const int m = a.m, lo = a.lo;
+    // HALF: Omega is the centred half of the grid (m = n/2, 2x oversampling),
+    // fixed at compile time so that every crop and pad test folds away
+    const int m = HALF ? N / 2 : a.m, lo = HALF ? N / 4 : a.lo;
     const int t = threadIdx.x;
     if constexpr (MODE == ROW_ADJ || MODE == ROW_CACHE) fold_scalar_step(a.fold, a.sc);
 
@@ -743,7 +747,9 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
             if (act) {
                 static_for<0, N2>([&](auto K) {
                     constexpr int k2 = K;
-                    buf[ll * N + CT::out_pos(k1, k2)] = v[k2];
+                    const int pos = CT::out_pos(k1, k2);
+                    // HALF: the positions outside Omega are never read below
+                    if (!HALF || (pos >= lo && pos < lo + m)) buf[ll * N + pos] = v[k2];
                 });
             }
         }
@@ -757,7 +763,9 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
         if (act) {
             static_for<0, N1>([&](auto K) {
                 constexpr int k1 = K;
-                v[k1] = buf[ll * N + CT::in_pos(j2, k1)];
+                const int pos = CT::in_pos(j2, k1);
+                // HALF: the zero padding outside Omega is known at compile time
+                v[k1] = (HALF && (pos < lo || pos >= lo + m)) ? make_float2(0.f, 0.f) : buf[ll * N + pos];
             });
             RegDFT<N1, false>::run(v);
             static_for<0, N1>([&](auto K) {
