@@ -248,7 +248,7 @@ def other_workload(a):
         run = lambda outs: pl.solve_series(data, prm, outs)
         outs = [pl._frame_out(pl.dims, prm) for _ in range(B)]
     else:
-        pl = Plan(frames=[(f.n, f.n_om, f.ncoils) for f in frames])
+        pl = Plan(frames=[(f.n, f.n_om, f.ncoils) for f in frames], branch_frames=a.branch_frames)
         run = lambda outs: pl.solve_batch(data, prm, outs)
         outs = [pl._frame_out(fd, prm) for fd in pl.frames]
     if not a.no_autotune:
@@ -266,7 +266,9 @@ def other_workload(a):
            "scaling": "weak", "vs_baseline": None, "dtype": "c64 (fp32), fp64 CG dots/scalars",
            "data": "synthetic", "config": {"workload": desc, "frames_per_step": B,
                                            "path": ("series" if a.workload == "series_512" else "batched")
-                                           + ("" if a.no_graph else "+hipGraph")},
+                                           + ("" if a.no_graph else "+hipGraph")
+                                           + (f", branches of {a.branch_frames} frames" if a.branch_frames
+                                              else "")},
            "roofline": None, "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 
@@ -285,6 +287,9 @@ def main():
     ap.add_argument("--applies", type=int, default=200)
     ap.add_argument("--cpu-newton", type=int, default=2, help="Newton steps of the CPU oracle sample (0: skip)")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--branch-frames", type=int, default=0,
+                    help="frames of one shape per concurrent branch (0: one branch per shape); the "
+                         "roofline kernel's launches then share the GPU with the other branches")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default pass variants")
     ap.add_argument("--kernel-class", default=None, help="kernel class for the roofline (default: dominant)")
     ap.add_argument("--stream-probe", action="store_true",
@@ -315,7 +320,7 @@ def main():
                                mask_frame=t + 1) for t in range(B)]
     data = [(torch.from_numpy(f.y).cuda(), torch.from_numpy(f.P).cuda()) for f in frames]
     prm = Plan.params(NEWTON, CG, use_graph=not a.no_graph)
-    pl = Plan(frames=[(N, N_OM, J)] * B)
+    pl = Plan(frames=[(N, N_OM, J)] * B, branch_frames=a.branch_frames)
     if not a.no_autotune:
         os.environ.setdefault("NLINV_TUNE_VERBOSE", "1")
         pl.autotune()
@@ -372,13 +377,15 @@ def main():
     log(f"bench: {ms_step:.2f} ms/step, {fps:.1f} frames/s; {kc}: {launches} launches, {kms:.3f} ms")
 
     extras = {}
-    if getattr(dominant_class, "totals", None):
+    if getattr(dominant_class, "totals", None) and not a.branch_frames:
         extras.update(apply_rates(dominant_class.totals, B))
     if a.compare:
         extras.update(compare_paths(a, data, outs, B))
 
     # roofline of the dominant kernel class
-    per_launch = kernel_bytes(kc, N, N_OM, J * B, B)
+    # with concurrent branches each launch covers one branch's frames
+    nbranch = -(-B // a.branch_frames) if a.branch_frames > 0 else 1
+    per_launch = kernel_bytes(kc, N, N_OM, J * B, B) / nbranch
     avg_ms = kms / max(launches, 1)
     achieved = per_launch / (avg_ms * 1e-3) / 1e9 if launches else None
     roof = {"bound": "hbm", "kernel": kc, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -396,7 +403,8 @@ def main():
         "dtype": "c64 (fp32), fp64 CG dots/scalars", "data": "synthetic",
         "config": {"workload": "realtime_384: 384x384 grid, Omega 192x192, 12 coils, 15 radial spokes, "
                                "7 Newton x 10 CG",
-                   "frames_per_step": B, "path": "batched" + ("" if a.no_graph else "+hipGraph")},
+                   "frames_per_step": B, "path": "batched" + ("" if a.no_graph else "+hipGraph")
+                   + (f", branches of {a.branch_frames} frames" if a.branch_frames else "")},
         **extras,
         "roofline": roof,
         "cpu_baseline": cpu,

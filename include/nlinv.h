@@ -109,6 +109,14 @@ typedef struct {
  * device memory here, on the current HIP device; compute calls allocate none.
  * The single-frame operators and nlinv_irgnm_solve act on frame 0's shape. */
 int nlinv_plan_create(nlinv_plan* out, const nlinv_dims* dims, int32_t nframes);
+/* As nlinv_plan_create, but frames of one shape are grouped in runs of at
+ * most `branch_frames` (<= 0: no limit, the same as nlinv_plan_create).  Each
+ * group runs its Newton loop as a concurrent branch (its own default-priority
+ * stream, forked from and joined into the caller's stream or graph), so
+ * groups overlap each other's memory- and VALU-bound passes: more frames/s
+ * on a batch, while every kernel shares the GPU with the other branches.
+ * Results are bitwise those of nlinv_plan_create. */
+int nlinv_plan_create_branched(nlinv_plan* out, const nlinv_dims* dims, int32_t nframes, int32_t branch_frames);
 int nlinv_plan_destroy(nlinv_plan plan);                  /* NULL-safe */
 
 /* c_j = E^H W^{-1} chat_j (Eq. 2: the weighted inverse transform of the

@@ -17,7 +17,7 @@ NLINV_OK, NLINV_EINVAL, NLINV_EUNSUPPORTED, NLINV_ENOMEM, NLINV_EHIP = 0, -1, -2
 NLINV_USE_GRAPH, NLINV_WARM_START = 1, 2
 
 EXPORTED = (
-    "nlinv_plan_create", "nlinv_plan_destroy", "nlinv_coil_maps", "nlinv_forward", "nlinv_deriv",
+    "nlinv_plan_create", "nlinv_plan_create_branched", "nlinv_plan_destroy", "nlinv_coil_maps", "nlinv_forward", "nlinv_deriv",
     "nlinv_adjoint", "nlinv_normal", "nlinv_mask_gradient", "nlinv_image", "nlinv_irgnm_solve",
     "nlinv_irgnm_solve_batch", "nlinv_irgnm_solve_series", "nlinv_plan_autotune", "nlinv_plan_variant",
     "nlinv_plan_set_variant", "nlinv_plan_timing_enable", "nlinv_plan_timing_read",
@@ -65,6 +65,7 @@ def load(path: str | None = None):
     vp, i32, f32 = C.c_void_p, C.c_int32, C.c_float
     sig = {
         "nlinv_plan_create": ([C.POINTER(vp), C.POINTER(nlinv_dims), i32], C.c_int),
+        "nlinv_plan_create_branched": ([C.POINTER(vp), C.POINTER(nlinv_dims), i32, i32], C.c_int),
         "nlinv_plan_destroy": ([vp], C.c_int),
         "nlinv_coil_maps": ([vp, vp, vp, vp], C.c_int),
         "nlinv_forward": ([vp, vp, vp, vp, vp, vp, vp], C.c_int),
@@ -143,8 +144,9 @@ def _f32(t, what):
 # entry points under their C names
 # ---------------------------------------------------------------------------
 
-def nlinv_plan_create(dims_list, nframes=None):
-    """dims_list: sequence of (n, n_om, ncoils[, a, l]) or nlinv_dims."""
+def nlinv_plan_create(dims_list, nframes=None, branch_frames=0):
+    """dims_list: sequence of (n, n_om, ncoils[, a, l]) or nlinv_dims;
+    branch_frames > 0 calls nlinv_plan_create_branched."""
     lib = load()
     arr = (nlinv_dims * len(dims_list))()
     for i, d in enumerate(dims_list):
@@ -155,8 +157,12 @@ def nlinv_plan_create(dims_list, nframes=None):
             l = d[4] if len(d) > 4 else 32.0
             arr[i] = nlinv_dims(int(d[0]), int(d[1]), int(d[2]), float(a), float(l))
     h = C.c_void_p()
-    check(lib.nlinv_plan_create(C.byref(h), arr, len(dims_list) if nframes is None else nframes),
-          "nlinv_plan_create")
+    nf = len(dims_list) if nframes is None else nframes
+    if branch_frames:
+        check(lib.nlinv_plan_create_branched(C.byref(h), arr, nf, int(branch_frames)),
+              "nlinv_plan_create_branched")
+    else:
+        check(lib.nlinv_plan_create(C.byref(h), arr, nf), "nlinv_plan_create")
     return h
 
 

@@ -178,7 +178,12 @@ struct nlinv_plan_s {
     std::vector<hipStream_t> lanes;
     hipEvent_t fork_ev = nullptr;
     std::vector<hipEvent_t> join_ev;
-    hipGraphExec_t gexec = nullptr;
+    // Two instances of the captured Newton loop, launched in turn: a launch
+    // of an instance whose previous launch is still running waits on the
+    // host for it, which would leave the GPU idle while the next launch is
+    // being submitted.
+    hipGraphExec_t gexec = nullptr, gexec2 = nullptr;
+    int gnext = 0;
     GraphKey gkey;
     // kernel timing
     bool timing[KC_NUM] = {};
@@ -279,7 +284,12 @@ void tend(nlinv_plan_s* p, int slot, hipStream_t s) {
 int drop_graph(nlinv_plan_s* p) {
     if (!p->gexec) return NLINV_OK;
     hipError_t e = hipGraphExecDestroy(p->gexec);
-    p->gexec = nullptr;
+    if (p->gexec2) {
+        const hipError_t e2 = hipGraphExecDestroy(p->gexec2);
+        if (e == hipSuccess) e = e2;
+    }
+    p->gexec = p->gexec2 = nullptr;
+    p->gnext = 0;
     for (auto& u : p->ev_used)
         if (u == 2) u = 0;
     HIPCHK(e);
@@ -968,11 +978,16 @@ int run_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s) {
         }
         HIPCHK(e);
         e = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
+        if (e == hipSuccess) e = hipGraphInstantiate(&p->gexec2, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
-        HIPCHK(e);
+        if (e != hipSuccess) {
+            (void)drop_graph(p);
+            HIPCHK(e);
+        }
         p->gkey = key;
     }
-    HIPCHK(hipGraphLaunch(p->gexec, s));
+    HIPCHK(hipGraphLaunch(p->gnext ? p->gexec2 : p->gexec, s));
+    p->gnext ^= 1;
     return NLINV_OK;
 }
 
@@ -1084,6 +1099,7 @@ int build_class(nlinv_plan_s* p, Class& C) {
 void free_plan(nlinv_plan_s* p) {
     if (!p) return;
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->gexec2) (void)hipGraphExecDestroy(p->gexec2);
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     for (hipStream_t q : p->lanes) (void)hipStreamDestroy(q);
@@ -1263,6 +1279,10 @@ const char* nlinv_kernel_class_name(int32_t kclass) {
 }
 
 int nlinv_plan_create(nlinv_plan* out, const nlinv_dims* dims, int32_t nframes) {
+    return nlinv_plan_create_branched(out, dims, nframes, 0);
+}
+
+int nlinv_plan_create_branched(nlinv_plan* out, const nlinv_dims* dims, int32_t nframes, int32_t branch_frames) {
     if (!out || !dims || nframes <= 0 || nframes > 4096) return NLINV_EINVAL;
     *out = nullptr;
     for (int f = 0; f < nframes; ++f) CHK(check_dims(dims[f]));
@@ -1276,12 +1296,14 @@ int nlinv_plan_create(nlinv_plan* out, const nlinv_dims* dims, int32_t nframes) 
     p->sob_a = dims[0].sobolev_a;
     p->sob_hl = 0.5f * dims[0].sobolev_l;
     p->loc.resize(nframes);
+    // frames of one shape share a class; with branch_frames > 0 a class
+    // takes at most that many, and the next frames of the shape open another
     std::map<std::pair<int, int>, int> cls;
     for (int f = 0; f < nframes; ++f) {
         const auto key = std::make_pair(dims[f].n, dims[f].n_om);
         auto it = cls.find(key);
         int ci;
-        if (it == cls.end()) {
+        if (it == cls.end() || (branch_frames > 0 && p->classes[it->second].nframes >= branch_frames)) {
             ci = (int)p->classes.size();
             cls[key] = ci;
             Class C;

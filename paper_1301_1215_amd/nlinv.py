@@ -20,16 +20,21 @@ class FrameDims:
 
 
 class Plan:
-    """Workspace for one frame shape, or for a batch of frames of uneven shapes."""
+    """Workspace for one frame shape, or for a batch of frames of uneven shapes.
 
-    def __init__(self, n=None, n_om=None, ncoils=None, sobolev_a=220.0, sobolev_l=32.0, frames=None):
+    branch_frames > 0: frames of one shape are grouped in runs of at most
+    that many, each group a concurrent branch of the solve (bitwise the same
+    results, more frames/s on a batch)."""
+
+    def __init__(self, n=None, n_om=None, ncoils=None, sobolev_a=220.0, sobolev_l=32.0, frames=None,
+                 branch_frames=0):
         import torch
         if frames is None:
             frames = [FrameDims(n, n_om, ncoils, sobolev_a, sobolev_l)]
         self.frames = [f if isinstance(f, FrameDims) else FrameDims(*f) for f in frames]
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.handle = N.nlinv_plan_create([(f.n, f.n_om, f.ncoils, f.sobolev_a, f.sobolev_l)
-                                           for f in self.frames])
+                                           for f in self.frames], branch_frames=branch_frames)
 
     # -- lifetime ----------------------------------------------------------
     def close(self):

@@ -46,6 +46,33 @@ def test_realtime_384_matches_oracle():
     assert np.allclose(got["stats"][2:9], ref.r0_norms, rtol=1e-4)
 
 
+def test_uneven_omega_matches_oracle():
+    """Omega neither the grid nor its centred half (n = 96, n_om = 40, crop
+    offset 28: no multiple of either FFT factor), so the passes take the
+    general crop and pad path, in a graph."""
+    fr = synth.make_frame(2, 5, 96, 40, 4, "radial", spokes=11)
+    ref = oracle_solve(fr, 3, 5)
+    got = gpu_solve(fr, 3, 5, use_graph=True)
+    assert rel(got["image"], ref.image) < NRMSE
+    assert rel(got["rho"], ref.rho) < NRMSE
+
+
+def test_branched_plan_is_bitwise_the_one_branch_plan():
+    """Frames of one shape split into concurrent branches (2 + 2 + 1 frames)
+    give exactly what one class of all five gives, in a graph."""
+    frames = [synth.make_frame(4, 200 + i, 64, 32, 4, "radial", spokes=9, mask_frame=i) for i in range(5)]
+    prm = Plan.params(3, 5, use_graph=True)
+    res = []
+    for bf in (0, 2):
+        with Plan(frames=[(f.n, f.n_om, f.ncoils) for f in frames], branch_frames=bf) as pl:
+            for _ in range(2):   # capture, then a replay
+                outs = pl.solve_batch([(dev(f.y), dev(f.P)) for f in frames], prm)
+            res.append([{k: host(v) for k, v in o.items()} for o in outs])
+    for a, b in zip(*res):
+        for k in ("rho", "chat", "image", "stats"):
+            assert np.array_equal(a[k], b[k]), k
+
+
 def test_graph_replay_is_bitwise_eager():
     fr = synth.make_frame(2, 3, 128, 64, 6, "radial", spokes=11)
     with Plan(fr.n, fr.n_om, fr.ncoils) as pl:
