@@ -186,6 +186,7 @@ __device__ __forceinline__ bool col_item(int ntiles, int nplanes, int& tile, int
 
 // TILED: the n x n operands are in the column-tiled solve layout (as
 // ColArgs::tiled, fixed at compile time so no access computes both forms).
+// HALF: Omega is the centred n/2 x n/2 block (a.m and a.lo are then ignored).
 template <int N, int L, int MODE, bool TILED, bool HALF>
 __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
     constexpr int NT = pass_threads(N, L);
