@@ -57,6 +57,17 @@ def test_uneven_omega_matches_oracle():
     assert rel(got["rho"], ref.rho) < NRMSE
 
 
+@pytest.mark.parametrize("n", [12, 24])
+def test_small_grids_match_oracle(n):
+    """The smallest grids with Omega the centred half: n = 12 splits as 3 x 4
+    (odd factor: the centring is the checkerboard sign), n = 24 as 4 x 6."""
+    fr = synth.make_frame(2, 7, n, n // 2, 2, "radial", spokes=5)
+    ref = oracle_solve(fr, 3, 4)
+    got = gpu_solve(fr, 3, 4, use_graph=True)
+    assert rel(got["image"], ref.image) < NRMSE
+    assert rel(got["rho"], ref.rho) < NRMSE
+
+
 def test_branched_plan_is_bitwise_the_one_branch_plan():
     """Frames of one shape split into concurrent branches (2 + 2 + 1 frames)
     give exactly what one class of all five gives, in a graph."""
