@@ -874,7 +874,10 @@ int setup_frames(nlinv_plan_s* p, const nlinv_frame* frames, const nlinv_irgnm_p
                                C.x_r, (long long)C.nframes * C.rplane(), make_float2(1.f, 0.f));
         }
         HIPCHK(hipGetLastError());
-        // x_ref
+        bool any_chat_ref = false;
+        for (int lf = 0; lf < C.nframes; ++lf) any_chat_ref = any_chat_ref || frames[C.frames[lf]].chat_ref;
+        C.chat_ref_zero = !warm && !any_chat_ref;   // x_ref = x0, whose chat part is 0
+        // x_ref (a zero chat part is not stored: the passes are not given it)
         for (int lf = 0; lf < C.nframes; ++lf) {
             const nlinv_frame& F = frames[C.frames[lf]];
             const size_t cb = (size_t)C.J[lf] * C.cplane() * sizeof(float2);
@@ -884,14 +887,13 @@ int setup_frames(nlinv_plan_s* p, const nlinv_frame* frames, const nlinv_irgnm_p
                 CHK(tile_copy(p, C, (const float2*)F.chat_ref, rc, C.J[lf], 1, s));
                 HIPCHK(hipMemcpyAsync(rr, F.rho_ref, C.rplane() * sizeof(float2), hipMemcpyDeviceToDevice, s));
             } else {
-                HIPCHK(hipMemcpyAsync(rc, C.x_c + (size_t)C.plane0[lf] * C.cplane(), cb, hipMemcpyDeviceToDevice, s));
+                if (!C.chat_ref_zero)
+                    HIPCHK(hipMemcpyAsync(rc, C.x_c + (size_t)C.plane0[lf] * C.cplane(), cb, hipMemcpyDeviceToDevice,
+                                          s));
                 HIPCHK(hipMemcpyAsync(rr, C.x_r + (size_t)lf * C.rplane(), C.rplane() * sizeof(float2),
                                       hipMemcpyDeviceToDevice, s));
             }
         }
-        bool any_chat_ref = false;
-        for (int lf = 0; lf < C.nframes; ++lf) any_chat_ref = any_chat_ref || frames[C.frames[lf]].chat_ref;
-        C.chat_ref_zero = !warm && !any_chat_ref;   // x_ref = x0, whose chat part is 0
         // a caller's x_ref is in data units: scale its rho part (x0-derived refs already are scaled)
         bool any_ref = false;
         for (int lf = 0; lf < C.nframes; ++lf) {
