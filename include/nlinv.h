@@ -111,10 +111,12 @@ typedef struct {
 int nlinv_plan_create(nlinv_plan* out, const nlinv_dims* dims, int32_t nframes);
 /* As nlinv_plan_create, but frames of one shape are grouped in runs of at
  * most `branch_frames` (<= 0: no limit, the same as nlinv_plan_create).  Each
- * group runs its Newton loop as a concurrent branch (its own default-priority
- * stream, forked from and joined into the caller's stream or graph), so
+ * group runs its Newton loop as a concurrent branch (on a default-priority
+ * stream of the plan, forked from and joined into the caller's stream or
+ * graph), so
  * groups overlap each other's memory- and VALU-bound passes: more frames/s
  * on a batch, while every kernel shares the GPU with the other branches.
+ * At most 8 streams are used; groups beyond that share them in turn.
  * Results are bitwise those of nlinv_plan_create. */
 int nlinv_plan_create_branched(nlinv_plan* out, const nlinv_dims* dims, int32_t nframes, int32_t branch_frames);
 int nlinv_plan_destroy(nlinv_plan plan);                  /* NULL-safe */

@@ -5,6 +5,7 @@
 // C ABI declared in include/nlinv.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -49,6 +50,7 @@ constexpr int kCoilSeg = kThreads;   // Omega pixels per coil-sum workgroup (one
 constexpr int kColModes = 9;         // ColMode values
 constexpr int kRowModes = 4;         // RowMode values
 constexpr int kTimingSlots = 8192;   // event pairs for kernel timing
+constexpr int kMaxLanes = 8;          // streams for concurrent shape classes
 
 bool size_supported(int n) {
     switch (n) {
@@ -172,9 +174,10 @@ struct nlinv_plan_s {
     float sob_a = 220.f, sob_hl = 16.f;
     std::vector<void*> allocs;
     hipStream_t cap_stream = nullptr;
-    // shape classes are independent: with more than one, each runs its Newton
-    // loop on a stream of its own (default priority), forked from and joined
-    // back into the caller's stream (as concurrent branches in a graph)
+    // shape classes are independent: with more than one, their Newton loops
+    // run on up to kMaxLanes streams of their own (default priority; class i
+    // on lane i mod lanes), forked from and joined back into the caller's
+    // stream (as concurrent branches in a graph)
     std::vector<hipStream_t> lanes;
     hipEvent_t fork_ev = nullptr;
     std::vector<hipEvent_t> join_ev;
@@ -803,16 +806,18 @@ int enqueue_class_newton(nlinv_plan_s* p, Class& C, const nlinv_irgnm_params& pr
 }
 
 int enqueue_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s) {
-    if (p->classes.size() == 1 || p->lanes.size() != p->classes.size()) {
+    const size_t nl = p->lanes.size();
+    if (p->classes.size() == 1 || nl == 0) {
         for (Class& C : p->classes) CHK(enqueue_class_newton(p, C, prm, s));
         return NLINV_OK;
     }
+    // class i on lane i mod nl (classes sharing a lane run one after another)
     HIPCHK(hipEventRecord(p->fork_ev, s));
-    for (size_t i = 0; i < p->classes.size(); ++i) {
-        HIPCHK(hipStreamWaitEvent(p->lanes[i], p->fork_ev, 0));
-        CHK(enqueue_class_newton(p, p->classes[i], prm, p->lanes[i]));
-        HIPCHK(hipEventRecord(p->join_ev[i], p->lanes[i]));
-        HIPCHK(hipStreamWaitEvent(s, p->join_ev[i], 0));
+    for (size_t l = 0; l < nl; ++l) HIPCHK(hipStreamWaitEvent(p->lanes[l], p->fork_ev, 0));
+    for (size_t i = 0; i < p->classes.size(); ++i) CHK(enqueue_class_newton(p, p->classes[i], prm, p->lanes[i % nl]));
+    for (size_t l = 0; l < nl; ++l) {
+        HIPCHK(hipEventRecord(p->join_ev[l], p->lanes[l]));
+        HIPCHK(hipStreamWaitEvent(s, p->join_ev[l], 0));
     }
     return NLINV_OK;
 }
@@ -1331,9 +1336,10 @@ int nlinv_plan_create_branched(nlinv_plan* out, const nlinv_dims* dims, int32_t 
     }
     e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) { g_last_hip = (int)e; free_plan(p); return NLINV_EHIP; }
-    if (p->classes.size() > 1) {   // one stream per shape class (default priority)
+    if (p->classes.size() > 1) {   // a stream per shape class, up to kMaxLanes (default priority)
         e = hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
-        for (size_t i = 0; e == hipSuccess && i < p->classes.size(); ++i) {
+        const size_t nl = std::min(p->classes.size(), (size_t)kMaxLanes);
+        for (size_t i = 0; e == hipSuccess && i < nl; ++i) {
             hipStream_t q = nullptr;
             hipEvent_t j = nullptr;
             e = hipStreamCreateWithFlags(&q, hipStreamNonBlocking);

@@ -84,6 +84,20 @@ def test_branched_plan_is_bitwise_the_one_branch_plan():
             assert np.array_equal(a[k], b[k]), k
 
 
+def test_more_branches_than_streams():
+    """Ten one-frame branches on the plan's eight streams (two streams run
+    two branches in turn): bitwise the single-frame plans."""
+    frames = [synth.make_frame(4, 300 + i, 32, 16, 2, "radial", spokes=5, mask_frame=i) for i in range(10)]
+    prm = Plan.params(2, 3, use_graph=True)
+    with Plan(frames=[(f.n, f.n_om, f.ncoils) for f in frames], branch_frames=1) as pl:
+        outs = pl.solve_batch([(dev(f.y), dev(f.P)) for f in frames], prm)
+        outs = [{k: host(v) for k, v in o.items()} for o in outs]
+    for f, o in zip(frames, outs):
+        single = gpu_solve(f, 2, 3)
+        for k in ("rho", "chat", "image", "stats"):
+            assert np.array_equal(o[k], single[k]), k
+
+
 def test_graph_replay_is_bitwise_eager():
     fr = synth.make_frame(2, 3, 128, 64, 6, "radial", spokes=11)
     with Plan(fr.n, fr.n_om, fr.ncoils) as pl:
