@@ -300,7 +300,7 @@ def main():
     a = ap.parse_args()
 
     if a.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {a.gpus} is not supported "
+        print(f"bench.py: this benchmark runs on one GPU; --gpus {a.gpus} is not supported "
               f"(the coil-split multi-GPU decomposition is designed, not built)", file=sys.stderr)
         sys.exit(2)
 
