@@ -134,6 +134,46 @@ __global__ __launch_bounds__(kThreads) void k_tile(const T* src, T* dst, int npl
     }
 }
 
+// The same conversion for up to kTileBatch frames in one launch: entry
+// blockIdx.y copies np[y] planes from src[y] to dst[y].
+constexpr int kTileBatch = 16;
+template <class T>
+struct TileBatch {
+    const T* src[kTileBatch];
+    T* dst[kTileBatch];
+    int np[kTileBatch];
+};
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_tile_batch(TileBatch<T> b, int n, int tw, int to_tiled) {
+    const T* src = b.src[blockIdx.y];
+    T* dst = b.dst[blockIdx.y];
+    const long long nn = (long long)n * n, tot = b.np[blockIdx.y] * nn;
+    for (long long g = (long long)blockIdx.x * kThreads + threadIdx.x; g < tot;
+         g += (long long)gridDim.x * kThreads) {
+        const long long pl = g / nn, e = g % nn;
+        const int r = (int)(e / n), c = (int)(e % n);
+        const long long t = pl * nn + ((long long)(c / tw) * n + r) * tw + (c % tw);
+        if (to_tiled) dst[t] = src[g];
+        else dst[g] = src[t];
+    }
+}
+
+// Up to kCopyBatch device-to-device copies of 8-byte words in one launch:
+// entry blockIdx.y copies n[y] words from src[y] to dst[y].
+constexpr int kCopyBatch = 48;
+struct CopyBatch {
+    const uint64_t* src[kCopyBatch];
+    uint64_t* dst[kCopyBatch];
+    long long n[kCopyBatch];
+};
+__global__ __launch_bounds__(kThreads) void k_copy_batch(CopyBatch b) {
+    const uint64_t* src = b.src[blockIdx.y];
+    uint64_t* dst = b.dst[blockIdx.y];
+    const long long n = b.n[blockIdx.y];
+    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads)
+        dst[i] = src[i];
+}
+
 // Bandwidth probe: a plain 16-byte-per-thread streaming copy (the practical
 // HBM ceiling, and the known-size copy that calibrates traffic counters).
 __global__ __launch_bounds__(kThreads) void k_stream_copy(const float4* __restrict__ src,

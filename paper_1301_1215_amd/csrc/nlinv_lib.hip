@@ -834,6 +834,33 @@ int tile_copy(nlinv_plan_s* p, const Class& C, const T* src, T* dst, int nplanes
     return NLINV_OK;
 }
 
+// Several such copies, one launch per kTileBatch entries: entry i copies
+// np[i] planes from src[i] to dst[i] (entries with np[i] <= 0 are skipped).
+template <class T>
+int tile_copy_batch(nlinv_plan_s* p, const Class& C, const std::vector<const T*>& src, const std::vector<T*>& dst,
+                    const std::vector<int>& np, int to_tiled, hipStream_t s) {
+    for (size_t i0 = 0; i0 < src.size(); i0 += kTileBatch) {
+        TileBatch<T> b{};
+        int cnt = 0, maxp = 0;
+        for (size_t i = i0; i < src.size() && i < i0 + kTileBatch; ++i) {
+            if (np[i] <= 0) continue;
+            b.src[cnt] = src[i];
+            b.dst[cnt] = dst[i];
+            b.np[cnt] = np[i];
+            maxp = std::max(maxp, np[i]);
+            ++cnt;
+        }
+        if (cnt == 0) continue;
+        const int slot = tbegin(p, KC_VEC_OTHER, s);
+        hipLaunchKernelGGL((k_tile_batch<T>), dim3(grid_for((long long)maxp * C.cplane()), cnt), dim3(kThreads), 0, s,
+                           b, C.n, C.tilew, to_tiled);
+        hipError_t e = hipGetLastError();
+        tend(p, slot, s);
+        HIPCHK(e);
+    }
+    return NLINV_OK;
+}
+
 int check_params(const nlinv_irgnm_params* prm) {
     if (!prm) return NLINV_EINVAL;
     if (prm->newton_steps < 0 || prm->newton_steps > kMaxNewton) return NLINV_EINVAL;
@@ -848,12 +875,23 @@ bool aligned(const void* q) { return ((uintptr_t)q & 15) == 0; }
 // Per-frame set-up: copy y and P into the class workspace, data scale, x0, x_ref.
 int setup_frames(nlinv_plan_s* p, const nlinv_frame* frames, const nlinv_irgnm_params& prm, hipStream_t s) {
     for (Class& C : p->classes) {
-        for (int lf = 0; lf < C.nframes; ++lf) {
-            const nlinv_frame& F = frames[C.frames[lf]];
-            const size_t cb = (size_t)C.J[lf] * C.cplane() * sizeof(float2);
-            (void)cb;
-            CHK(tile_copy(p, C, (const float2*)F.y, C.y + (size_t)C.plane0[lf] * C.cplane(), C.J[lf], 1, s));
-            CHK(tile_copy(p, C, F.P, C.P + (size_t)lf * C.cplane(), 1, 1, s));
+        {   // y and P of every frame into the solve layout, one launch each
+            std::vector<const float2*> ys;
+            std::vector<float2*> yd;
+            std::vector<const float*> ps;
+            std::vector<float*> pd;
+            std::vector<int> nj, one;
+            for (int lf = 0; lf < C.nframes; ++lf) {
+                const nlinv_frame& F = frames[C.frames[lf]];
+                ys.push_back((const float2*)F.y);
+                yd.push_back(C.y + (size_t)C.plane0[lf] * C.cplane());
+                nj.push_back(C.J[lf]);
+                ps.push_back(F.P);
+                pd.push_back(C.P + (size_t)lf * C.cplane());
+                one.push_back(1);
+            }
+            CHK(tile_copy_batch(p, C, ys, yd, nj, 1, s));
+            CHK(tile_copy_batch(p, C, ps, pd, one, 1, s));
         }
         CHK(run_vec<VEC_DOT>(p, C.geomC, vptrs(C.y, nullptr, C.y, nullptr), C.partial, s));
         CHK(run_scalar(p, C, SC_YNORM, C.geomC, prm.scale_norm, 0, s));
@@ -932,20 +970,43 @@ int finish_frames(nlinv_plan_s* p, const nlinv_frame* frames, const nlinv_irgnm_
         hipLaunchKernelGGL(k_scale_rho, dim3(grid_for((long long)C.nframes * C.rplane())), dim3(kThreads), 0, s,
                            C.dx_r, (const float2*)C.x_r, (const float*)C.sc.inv_s, C.nframes, (int)C.rplane(), 1);
         HIPCHK(hipGetLastError());
+        {   // chat of every frame back to the caller's row-major layout, one launch
+            std::vector<const float2*> cs;
+            std::vector<float2*> cd;
+            std::vector<int> nj;
+            for (int lf = 0; lf < C.nframes; ++lf) {
+                cs.push_back(C.x_c + (size_t)C.plane0[lf] * C.cplane());
+                cd.push_back((float2*)frames[C.frames[lf]].chat);
+                nj.push_back(C.J[lf]);
+            }
+            CHK(tile_copy_batch(p, C, cs, cd, nj, 0, s));
+        }
+        // rho, image and stats of every frame: one launch per kCopyBatch copies
+        CopyBatch b{};
+        int cnt = 0;
+        long long maxn = 0;
+        auto add = [&](const void* src, void* dst, long long words) {
+            b.src[cnt] = (const uint64_t*)src;
+            b.dst[cnt] = (uint64_t*)dst;
+            b.n[cnt] = words;
+            maxn = std::max(maxn, words);
+            ++cnt;
+        };
+        auto flush = [&]() -> hipError_t {
+            if (cnt == 0) return hipSuccess;
+            hipLaunchKernelGGL(k_copy_batch, dim3(grid_for(maxn), cnt), dim3(kThreads), 0, s, b);
+            cnt = 0;
+            maxn = 0;
+            return hipGetLastError();
+        };
         for (int lf = 0; lf < C.nframes; ++lf) {
             const nlinv_frame& F = frames[C.frames[lf]];
-            const size_t cb = (size_t)C.J[lf] * C.cplane() * sizeof(float2);
-            const size_t rb = C.rplane() * sizeof(float2);
-            HIPCHK(hipMemcpyAsync(F.rho, C.dx_r + (size_t)lf * C.rplane(), rb, hipMemcpyDeviceToDevice, s));
-            CHK(tile_copy(p, C, (const float2*)(C.x_c + (size_t)C.plane0[lf] * C.cplane()), (float2*)F.chat,
-                          C.J[lf], 0, s));
-            (void)cb;
-            if (F.image)
-                HIPCHK(hipMemcpyAsync(F.image, C.aux + (size_t)lf * C.rplane(), rb, hipMemcpyDeviceToDevice, s));
-            if (F.stats)
-                HIPCHK(hipMemcpyAsync(F.stats, C.sc.stats + (size_t)lf * kStatsCap, stats_len * sizeof(double),
-                                      hipMemcpyDeviceToDevice, s));
+            if (cnt + 3 > kCopyBatch) HIPCHK(flush());
+            add(C.dx_r + (size_t)lf * C.rplane(), F.rho, (long long)C.rplane());
+            if (F.image) add(C.aux + (size_t)lf * C.rplane(), F.image, (long long)C.rplane());
+            if (F.stats) add(C.sc.stats + (size_t)lf * kStatsCap, F.stats, stats_len);
         }
+        HIPCHK(flush());
     }
     return NLINV_OK;
 }
