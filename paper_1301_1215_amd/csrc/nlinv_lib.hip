@@ -897,17 +897,16 @@ int setup_frames(nlinv_plan_s* p, const nlinv_frame* frames, const nlinv_irgnm_p
         CHK(run_scalar(p, C, SC_YNORM, C.geomC, prm.scale_norm, 0, s));
         // x0: warm start copies the caller's x (rho scaled below); else rho = 1 (scaled units), chat = 0
         const bool warm = (prm.flags & NLINV_WARM_START) != 0;
-        for (int lf = 0; lf < C.nframes; ++lf) {
-            const nlinv_frame& F = frames[C.frames[lf]];
-            const size_t cb = (size_t)C.J[lf] * C.cplane() * sizeof(float2);
-            float2* xc = C.x_c + (size_t)C.plane0[lf] * C.cplane();
-            float2* xr = C.x_r + (size_t)lf * C.rplane();
-            if (warm) {
+        if (warm) {
+            for (int lf = 0; lf < C.nframes; ++lf) {
+                const nlinv_frame& F = frames[C.frames[lf]];
+                float2* xc = C.x_c + (size_t)C.plane0[lf] * C.cplane();
+                float2* xr = C.x_r + (size_t)lf * C.rplane();
                 CHK(tile_copy(p, C, (const float2*)F.chat, xc, C.J[lf], 1, s));
                 HIPCHK(hipMemcpyAsync(xr, F.rho, C.rplane() * sizeof(float2), hipMemcpyDeviceToDevice, s));
-            } else {
-                HIPCHK(hipMemsetAsync(xc, 0, cb, s));
             }
+        } else {   // the chat parts of all frames are contiguous: one fill
+            HIPCHK(hipMemsetAsync(C.x_c, 0, (size_t)C.nplanes * C.cplane() * sizeof(float2), s));
         }
         if (warm) {
             hipLaunchKernelGGL(k_scale_rho, dim3(grid_for((long long)C.nframes * C.rplane())), dim3(kThreads), 0, s,
@@ -921,7 +920,16 @@ int setup_frames(nlinv_plan_s* p, const nlinv_frame* frames, const nlinv_irgnm_p
         for (int lf = 0; lf < C.nframes; ++lf) any_chat_ref = any_chat_ref || frames[C.frames[lf]].chat_ref;
         C.chat_ref_zero = !warm && !any_chat_ref;   // x_ref = x0, whose chat part is 0
         // x_ref (a zero chat part is not stored: the passes are not given it)
-        for (int lf = 0; lf < C.nframes; ++lf) {
+        bool no_ref = true;
+        for (int lf = 0; lf < C.nframes; ++lf) no_ref = no_ref && !frames[C.frames[lf]].rho_ref;
+        if (no_ref) {   // x_ref = x0 for every frame: one copy of each contiguous part
+            HIPCHK(hipMemcpyAsync(C.xr_r, C.x_r, (size_t)C.nframes * C.rplane() * sizeof(float2),
+                                  hipMemcpyDeviceToDevice, s));
+            if (!C.chat_ref_zero)
+                HIPCHK(hipMemcpyAsync(C.xr_c, C.x_c, (size_t)C.nplanes * C.cplane() * sizeof(float2),
+                                      hipMemcpyDeviceToDevice, s));
+        }
+        for (int lf = 0; lf < C.nframes && !no_ref; ++lf) {
             const nlinv_frame& F = frames[C.frames[lf]];
             const size_t cb = (size_t)C.J[lf] * C.cplane() * sizeof(float2);
             float2* rc = C.xr_c + (size_t)C.plane0[lf] * C.cplane();
