@@ -98,12 +98,6 @@ __global__ __launch_bounds__(64) void k_scalar(ScalarStep ss, Scalars sc) {
     fold_scalar_step(ss, sc);
 }
 
-// per-frame: alpha[f] = value, alpha[F + f] = -value
-__global__ void k_set_alpha(float* alpha, int nframes, float value) {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f < nframes) { alpha[f] = value; alpha[nframes + f] = -value; }
-}
-
 // x[f][e] = s_f * src[f][e] (src nullable -> s_f * 1) on rho parts
 __global__ __launch_bounds__(kThreads) void k_scale_rho(float2* x, const float2* src, const float* s,
                                                         int nframes, int E, int use_inv) {

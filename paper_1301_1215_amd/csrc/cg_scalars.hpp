@@ -82,7 +82,6 @@ struct Scalars {
     float* a;          // [F] CG step a = rr / gamma
     float* beta;       // [F]
     int* brk;          // [F] breakdown in the current Newton step
-    float* alpha;      // [F] current alpha (and -alpha at alpha + F)
     float* s;          // [F] data scale
     float* inv_s;      // [F]
     double* stats;     // [F][stats_len]
@@ -102,13 +101,15 @@ enum ScalarOp : int {
 
 // Where a scalar op is applied: which op, geometry of its partials, indices
 // for the stats.  With `partial2` set the total is
-// sum(partial) + alpha_f * sum(partial2) (geometry g2).
+// sum(partial) + alpha * sum(partial2) (geometry g2; alpha is the Newton
+// step's, the same for every frame of a solve).
 struct ScalarStep {
     int op;
     SegGeom g;
     const double* partial;
     SegGeom g2;
     const double* partial2;
+    float alpha;
     const int* frame_plane0;
     const int* frame_planes;
     float scale_norm;
@@ -223,7 +224,7 @@ __device__ __forceinline__ void fold_scalar_step(const ScalarStep& ss, const Sca
         double t = frame_total_wave(ss.g, ss.partial, f, ss.frame_plane0, ss.frame_planes);
         if (ss.partial2) {
             const double t2 = frame_total_wave(ss.g2, ss.partial2, f, ss.frame_plane0, ss.frame_planes);
-            if (threadIdx.x == 0) t += (double)sc.alpha[f] * t2;
+            if (threadIdx.x == 0) t += (double)ss.alpha * t2;
         }
         if (threadIdx.x == 0) scalar_apply(ss, sc, f, t, fs);
     }

@@ -145,7 +145,6 @@ struct Class {
     double* partial = nullptr;   // general partials; in CG: |DF p|^2 of the PSF pass
     double* partial2 = nullptr;  // CG: |r|^2 after the update
     double* part_p = nullptr;    // CG: |p|^2 of the direction update
-    float* alpha = nullptr;      // [2F]: alpha, -alpha
     SegGeom geom{}, geomC{};
     Scalars sc{};
     bool chat_ref_zero = false;  // this solve's x_ref has chat = 0 in every frame (not read then)
@@ -648,7 +647,10 @@ SegGeom cg_rr_geom(const Class& C) {
     return g;
 }
 
-int seq_cg_iteration(nlinv_plan_s* p, Class& C, int step, int it, int nsteps, int ncg, hipStream_t s) {
+// alpha: the Newton step's regularisation weight (a kernel argument of the
+// passes that need it)
+int seq_cg_iteration(nlinv_plan_s* p, Class& C, int step, int it, int nsteps, int ncg, float alpha,
+                     hipStream_t s) {
     const Frames fr = class_frames(C);
     ColArgs a = col_args(p, C, fr.tiled);
     a.in = C.p_c;
@@ -694,6 +696,7 @@ int seq_cg_iteration(nlinv_plan_s* p, Class& C, int step, int it, int nsteps, in
         ss.g2.cseg = tp;
         ss.g2.rseg = tp;
         ss.partial2 = C.part_p;
+        ss.alpha = alpha;
         r.fold = ss;
         r.sc = C.sc;
     }
@@ -711,12 +714,13 @@ int seq_cg_iteration(nlinv_plan_s* p, Class& C, int step, int it, int nsteps, in
     e.dx = C.x_c;
     e.plane_frame = fr.plane_frame;
     e.add1 = C.p_c;
-    e.s1 = C.alpha;
+    e.s1 = nullptr;
+    e.c1 = alpha;
     e.cg_a = C.sc.a;
     e.partial = C.partial2;
     // the rho parts: the coil sum in its CG form, as extra workgroups of the
     // same launch (segments of one workgroup's size)
-    CoilSumArgs cs = coil_sum_args(C, fr, nullptr, C.p_r, nullptr, C.alpha, nullptr, 0.f, 0.f, C.partial2,
+    CoilSumArgs cs = coil_sum_args(C, fr, nullptr, C.p_r, nullptr, nullptr, nullptr, alpha, 0.f, C.partial2,
                                    (long long)C.nplanes * tu);
     cs.r_upd = C.r_r;
     cs.dx_upd = C.dx_r;
@@ -768,8 +772,6 @@ int enqueue_class_newton(nlinv_plan_s* p, Class& C, const nlinv_irgnm_params& pr
         {
             const Frames fr = class_frames(C);
             const long long ps = C.cplane();
-            hipLaunchKernelGGL(k_set_alpha, dim3((C.nframes + 63) / 64), dim3(64), 0, s, C.alpha, C.nframes, al);
-            HIPCHK(hipGetLastError());
             // linearisation cache c at x_n (with the previous step's rho
             // update and its last CG step's stats folded in)
             if (step > 0 && K > 0) {
@@ -787,12 +789,12 @@ int enqueue_class_newton(nlinv_plan_s* p, Class& C, const nlinv_irgnm_params& pr
                 const ScalarStep r0 = scalar_step(C, SC_R0NORM, g0, 0.f, step);
                 SegGeom gb{};
                 CHK(seq_adjoint_tail(p, C, fr, C.x_r, C.c, C.r_r, C.r_c, C.x_c, C.x_r,
-                                     C.chat_ref_zero ? nullptr : C.xr_c, C.xr_r, C.alpha + C.nframes, C.alpha,
-                                     0.f, 0.f, s, C.partial, &gb, &r0));
+                                     C.chat_ref_zero ? nullptr : C.xr_c, C.xr_r, nullptr, nullptr, -al, al, s,
+                                     C.partial, &gb, &r0));
                 (void)gb;   // the geometry rhs_geom() gives the first CG pass
             }
         }
-        for (int it = 0; it < K; ++it) CHK(seq_cg_iteration(p, C, step, it, N, K, s));
+        for (int it = 0; it < K; ++it) CHK(seq_cg_iteration(p, C, step, it, N, K, al, s));
         // the chat part of the step is already in x; rho += drho happens in
         // the next coil-map pass (dx_r is first written by CG iteration 0)
     }
@@ -1154,7 +1156,6 @@ int build_class(nlinv_plan_s* p, Class& C) {
     // into a column pass)
     const size_t tiles = (size_t)C.nplanes * (C.n / 4) + (size_t)C.nframes * ((rn + 63) / 64);
     CHK(dalloc(p, &C.partial, std::max<size_t>(tiles, (size_t)std::max(nseg(C.geom), nseg(C.geomC)))));
-    CHK(dalloc(p, &C.alpha, (size_t)2 * C.nframes));
     CHK(dalloc(p, &C.partial2, std::max<size_t>(tiles, (size_t)nseg(C.geom))));
     CHK(dalloc(p, &C.part_p, (size_t)(C.nplanes + C.nframes) * (C.n / 4)));
     CHK(dalloc(p, &C.sc.rr, (size_t)2 * C.nframes));
@@ -1164,7 +1165,6 @@ int build_class(nlinv_plan_s* p, Class& C) {
     CHK(dalloc(p, &C.sc.s, C.nframes));
     CHK(dalloc(p, &C.sc.inv_s, C.nframes));
     CHK(dalloc(p, &C.sc.stats, (size_t)C.nframes * kStatsCap));
-    C.sc.alpha = C.alpha;
     C.sc.nframes = C.nframes;
     C.sc.stats_len = kStatsCap;
     for (int& v : C.colv) v = default_col_variant(C.n);
@@ -1219,12 +1219,12 @@ ColArgs tune_col_args(nlinv_plan_s* p, Class& C, int mode) {
         case COL_PAD_FFT_P: a.out = C.q_c; break;
         case COL_RESID_P_IFFT: a.add1 = C.y; a.s1 = C.sc.s; break;   // in place on T
         case COL_PAD_FFT_WINV_ADD:
-            a.out = C.r_c; a.add1 = C.x_c; a.add2 = C.xr_c; a.s1 = C.alpha + C.nframes; a.s2 = C.alpha;
+            a.out = C.r_c; a.add1 = C.x_c; a.add2 = C.xr_c; a.c1 = -1.f; a.c2 = 1.f;
             break;
         case COL_PAD_FFT_WINV_CG_UPD:
             // q_c stands in for x (scratch: tuning must not touch the solution)
             a.out = C.r_c; a.dx = C.q_c; a.add1 = C.p_c;
-            a.s1 = C.alpha; a.cg_a = C.sc.a; a.partial = C.partial2;
+            a.c1 = 1.f; a.cg_a = C.sc.a; a.partial = C.partial2;
             break;
         default: break;
     }
