@@ -389,7 +389,9 @@ def main():
     avg_ms = kms / max(launches, 1)
     achieved = per_launch / (avg_ms * 1e-3) / 1e9 if launches else None
     roof = {"bound": "hbm", "kernel": kc, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBPS) if achieved else None, "traffic": pmc_traffic(kc, B),
+            "frac": (achieved / HBM_PEAK_GBPS) if achieved else None,
+            # the counters were taken on launches that cover all B frames
+            "traffic": None if a.branch_frames else pmc_traffic(kc, B),
             "bytes_per_launch": per_launch, "avg_launch_ms": avg_ms, "launches_timed": launches,
             "timing_stride": TIMING_STRIDE, "event_timing_on": timing_path}
 
