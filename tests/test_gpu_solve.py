@@ -68,6 +68,24 @@ def test_small_grids_match_oracle(n):
     assert rel(got["rho"], ref.rho) < NRMSE
 
 
+def test_batch_mixing_omega_shapes_matches_single_frames():
+    """One batch whose shape classes take different pass variants: Omega the
+    centred half, Omega the grid, and a general Omega (n = 48, n_om = 20)."""
+    shapes = [(64, 32, 3, 7), (64, 64, 2, 9), (48, 20, 2, 7), (64, 32, 2, 5)]
+    frames = [synth.make_frame(4, 400 + i, n, m, J, "radial", spokes=S, mask_frame=i)
+              for i, (n, m, J, S) in enumerate(shapes)]
+    prm = Plan.params(3, 4, use_graph=True)
+    with Plan(frames=[(f.n, f.n_om, f.ncoils) for f in frames]) as pl:
+        outs = pl.solve_batch([(dev(f.y), dev(f.P)) for f in frames], prm)
+        outs = [{k: host(v) for k, v in o.items()} for o in outs]
+    for f, o in zip(frames, outs):
+        single = gpu_solve(f, 3, 4)
+        for k in ("rho", "chat", "image", "stats"):
+            assert np.array_equal(o[k], single[k]), k
+        ref = oracle_solve(f, 3, 4)
+        assert rel(o["image"], ref.image) < NRMSE
+
+
 def test_branched_plan_is_bitwise_the_one_branch_plan():
     """Frames of one shape split into concurrent branches (2 + 2 + 1 frames)
     give exactly what one class of all five gives, in a graph."""
