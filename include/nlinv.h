@@ -214,6 +214,11 @@ int nlinv_plan_set_variant(nlinv_plan plan, int32_t n, int32_t col_variant, int3
  * resets. */
 int nlinv_plan_timing_enable(nlinv_plan plan, int32_t kclass, int32_t enable);
 int nlinv_plan_timing_read(nlinv_plan plan, int32_t* launches, double* total_ms);
+/* As nlinv_plan_timing_read, but only the bracketed launches of kernel class
+ * `kclass` (-1: every class, the same as nlinv_plan_timing_read); the other
+ * classes' brackets are kept for their own reads.  Several classes can be
+ * bracketed in one solve and read apart afterwards. */
+int nlinv_plan_timing_read_class(nlinv_plan plan, int32_t kclass, int32_t* launches, double* total_ms);
 const char* nlinv_kernel_class_name(int32_t kclass);   /* NULL past the last */
 
 /* ---- measurement ----------------------------------------------------------

@@ -21,6 +21,7 @@ EXPORTED = (
     "nlinv_adjoint", "nlinv_normal", "nlinv_mask_gradient", "nlinv_image", "nlinv_irgnm_solve",
     "nlinv_irgnm_solve_batch", "nlinv_irgnm_solve_series", "nlinv_plan_autotune", "nlinv_plan_variant",
     "nlinv_plan_set_variant", "nlinv_plan_timing_enable", "nlinv_plan_timing_read",
+    "nlinv_plan_timing_read_class",
     "nlinv_kernel_class_name", "nlinv_status_string", "nlinv_last_hip_error", "nlinv_bandwidth_probe",
 )
 
@@ -83,6 +84,7 @@ def load(path: str | None = None):
         "nlinv_plan_set_variant": ([vp, i32, i32, i32], C.c_int),
         "nlinv_plan_timing_enable": ([vp, i32, i32], C.c_int),
         "nlinv_plan_timing_read": ([vp, C.POINTER(i32), C.POINTER(C.c_double)], C.c_int),
+        "nlinv_plan_timing_read_class": ([vp, i32, C.POINTER(i32), C.POINTER(C.c_double)], C.c_int),
         "nlinv_kernel_class_name": ([i32], C.c_char_p),
         "nlinv_status_string": ([C.c_int], C.c_char_p),
         "nlinv_bandwidth_probe": ([vp, vp, C.c_size_t, vp], C.c_int),
@@ -141,6 +143,66 @@ def _f32(t, what):
 
 
 # ---------------------------------------------------------------------------
+# shape checks: every tensor is checked against the plan's frame shapes here,
+# before the library is called, so that a wrong-sized array never reaches a
+# kernel (the library only sees pointers)
+# ---------------------------------------------------------------------------
+
+_PLANS: dict = {}   # plan handle value -> [(n, n_om, ncoils)] per frame
+
+
+def _plan_dims(plan):
+    key = plan.value if isinstance(plan, C.c_void_p) else plan
+    dims = _PLANS.get(key)
+    if dims is None:
+        raise ValueError("unknown plan handle (not created by nlinv_plan_create, or destroyed)")
+    return dims
+
+
+def _expect(t, shape, what):
+    """Raise unless t (nullable) has exactly `shape`."""
+    if t is None:
+        return
+    got = tuple(getattr(t, "shape", ()))
+    if got != tuple(shape):
+        raise ValueError(f"{what}: expected shape {tuple(shape)}, got {got}")
+
+
+def _op_shapes(plan, **ts):
+    """Check operator arguments against frame 0's shape: names ending in
+    rho / image are Omega images, chat / y / dy / g k-space coil planes, c
+    Omega coil planes, P and gP the grid."""
+    n, m, J = _plan_dims(plan)[0]
+    for what, t in ts.items():
+        base = what.replace("_out", "").replace("_inout", "").replace("_ref", "")
+        if base in ("rho", "drho", "image"):
+            _expect(t, (m, m), what)
+        elif base in ("chat", "dchat", "y", "dy", "g"):
+            _expect(t, (J, n, n), what)
+        elif base == "c":
+            _expect(t, (J, m, m), what)
+        elif base in ("P", "gP"):
+            _expect(t, (n, n), what)
+        else:
+            raise KeyError(what)
+
+
+def _frame_shapes(fd, f, prm, where):
+    n, m, J = fd
+    for k in ("y", "chat", "chat_ref"):
+        _expect(f.get(k), (J, n, n), f"{where} {k}")
+    for k in ("rho", "rho_ref", "image"):
+        _expect(f.get(k), (m, m), f"{where} {k}")
+    _expect(f.get("P"), (n, n), f"{where} P")
+    st = f.get("stats")
+    if st is not None:
+        need = stats_len(prm.newton_steps, prm.cg_iters)
+        if st.dim() != 1 or st.numel() < need:
+            raise ValueError(f"{where} stats: expected a vector of at least {need} doubles, "
+                             f"got shape {tuple(st.shape)}")
+
+
+# ---------------------------------------------------------------------------
 # entry points under their C names
 # ---------------------------------------------------------------------------
 
@@ -163,36 +225,44 @@ def nlinv_plan_create(dims_list, nframes=None, branch_frames=0):
               "nlinv_plan_create_branched")
     else:
         check(lib.nlinv_plan_create(C.byref(h), arr, nf), "nlinv_plan_create")
+    _PLANS[h.value] = [(arr[i].n, arr[i].n_om, arr[i].ncoils) for i in range(nf)]
     return h
 
 
 def nlinv_plan_destroy(plan):
     check(load().nlinv_plan_destroy(plan), "nlinv_plan_destroy")
+    _PLANS.pop(plan.value if isinstance(plan, C.c_void_p) else plan, None)
 
 
 def nlinv_coil_maps(plan, chat, c_out, stream=None):
+    _op_shapes(plan, chat=chat, c_out=c_out)
     check(load().nlinv_coil_maps(plan, _c64(chat, "chat"), _c64(c_out, "c_out"), _stream(stream)),
           "nlinv_coil_maps")
 
 
 def nlinv_forward(plan, rho, chat, P, y_out, c_out=None, stream=None):
+    _op_shapes(plan, rho=rho, chat=chat, P=P, y_out=y_out, c_out=c_out)
     check(load().nlinv_forward(plan, _c64(rho, "rho"), _c64(chat, "chat"), _f32(P, "P"),
                                _c64(y_out, "y_out"), _c64(c_out, "c_out"), _stream(stream)), "nlinv_forward")
 
 
 def nlinv_deriv(plan, rho, chat, c, P, drho, dchat, dy_out, stream=None):
+    _op_shapes(plan, rho=rho, chat=chat, c=c, P=P, drho=drho, dchat=dchat, dy_out=dy_out)
     check(load().nlinv_deriv(plan, _c64(rho, "rho"), _c64(chat, "chat"), _c64(c, "c"), _f32(P, "P"),
                              _c64(drho, "drho"), _c64(dchat, "dchat"), _c64(dy_out, "dy_out"),
                              _stream(stream)), "nlinv_deriv")
 
 
 def nlinv_adjoint(plan, rho, chat, c, P, dy, drho_out, dchat_out, stream=None):
+    _op_shapes(plan, rho=rho, chat=chat, c=c, P=P, dy=dy, drho_out=drho_out, dchat_out=dchat_out)
     check(load().nlinv_adjoint(plan, _c64(rho, "rho"), _c64(chat, "chat"), _c64(c, "c"), _f32(P, "P"),
                                _c64(dy, "dy"), _c64(drho_out, "drho_out"), _c64(dchat_out, "dchat_out"),
                                _stream(stream)), "nlinv_adjoint")
 
 
 def nlinv_normal(plan, rho, chat, c, P, alpha, drho, dchat, drho_out, dchat_out, stream=None):
+    _op_shapes(plan, rho=rho, chat=chat, c=c, P=P, drho=drho, dchat=dchat, drho_out=drho_out,
+               dchat_out=dchat_out)
     check(load().nlinv_normal(plan, _c64(rho, "rho"), _c64(chat, "chat"), _c64(c, "c"), _f32(P, "P"),
                               float(alpha), _c64(drho, "drho"), _c64(dchat, "dchat"),
                               _c64(drho_out, "drho_out"), _c64(dchat_out, "dchat_out"), _stream(stream)),
@@ -200,12 +270,14 @@ def nlinv_normal(plan, rho, chat, c, P, alpha, drho, dchat, drho_out, dchat_out,
 
 
 def nlinv_mask_gradient(plan, rho, chat, c, g, gP_out, stream=None):
+    _op_shapes(plan, rho=rho, chat=chat, c=c, g=g, gP_out=gP_out)
     check(load().nlinv_mask_gradient(plan, _c64(rho, "rho"), _c64(chat, "chat"), _c64(c, "c"),
                                      _c64(g, "g"), _f32(gP_out, "gP_out"), _stream(stream)),
           "nlinv_mask_gradient")
 
 
 def nlinv_image(plan, rho, c, image_out, stream=None):
+    _op_shapes(plan, rho=rho, c=c, image_out=image_out)
     check(load().nlinv_image(plan, _c64(rho, "rho"), _c64(c, "c"), _c64(image_out, "image_out"),
                              _stream(stream)), "nlinv_image")
 
@@ -219,6 +291,11 @@ def make_params(newton_steps=7, cg_iters=10, alpha0=1.0, alpha_q=0.5, alpha_min=
 def nlinv_irgnm_solve(plan, y, P, prm, rho_inout, chat_inout, rho_ref=None, chat_ref=None, image_out=None,
                       stats_out=None, stream=None):
     import torch
+    dims = _plan_dims(plan)
+    if len(dims) != 1:
+        raise ValueError("nlinv_irgnm_solve: the plan holds more than one frame (use the batch call)")
+    _frame_shapes(dims[0], dict(y=y, P=P, rho=rho_inout, chat=chat_inout, rho_ref=rho_ref, chat_ref=chat_ref,
+                                image=image_out, stats=stats_out), prm, "nlinv_irgnm_solve")
     check(load().nlinv_irgnm_solve(plan, _c64(y, "y"), _f32(P, "P"), C.byref(prm),
                                    _c64(rho_inout, "rho_inout"), _c64(chat_inout, "chat_inout"),
                                    _c64(rho_ref, "rho_ref"), _c64(chat_ref, "chat_ref"),
@@ -238,11 +315,22 @@ def _frames(frames):
 
 
 def nlinv_irgnm_solve_batch(plan, frames, prm, stream=None):
+    dims = _plan_dims(plan)
+    if len(frames) != len(dims):
+        raise ValueError(f"nlinv_irgnm_solve_batch: {len(frames)} frame descriptors for a plan of "
+                         f"{len(dims)} frames")
+    for i, (fd, f) in enumerate(zip(dims, frames)):
+        _frame_shapes(fd, f, prm, f"nlinv_irgnm_solve_batch frame {i}")
     arr = _frames(frames)
     check(load().nlinv_irgnm_solve_batch(plan, arr, C.byref(prm), _stream(stream)), "nlinv_irgnm_solve_batch")
 
 
 def nlinv_irgnm_solve_series(plan, frames, prm, stream=None):
+    dims = _plan_dims(plan)
+    if len(dims) != 1:
+        raise ValueError("nlinv_irgnm_solve_series: the plan must hold one frame shape")
+    for i, f in enumerate(frames):
+        _frame_shapes(dims[0], f, prm, f"nlinv_irgnm_solve_series frame {i}")
     arr = _frames(frames)
     check(load().nlinv_irgnm_solve_series(plan, len(frames), arr, C.byref(prm), _stream(stream)),
           "nlinv_irgnm_solve_series")
@@ -287,6 +375,15 @@ def nlinv_plan_timing_enable(plan, kclass, enable=True):
 def nlinv_plan_timing_read(plan):
     n, ms = C.c_int32(), C.c_double()
     check(load().nlinv_plan_timing_read(plan, C.byref(n), C.byref(ms)), "nlinv_plan_timing_read")
+    return n.value, ms.value
+
+
+def nlinv_plan_timing_read_class(plan, kclass):
+    if isinstance(kclass, str):
+        kclass = nlinv_kernel_class_names().index(kclass)
+    n, ms = C.c_int32(), C.c_double()
+    check(load().nlinv_plan_timing_read_class(plan, int(kclass), C.byref(n), C.byref(ms)),
+          "nlinv_plan_timing_read_class")
     return n.value, ms.value
 
 

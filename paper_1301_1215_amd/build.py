@@ -40,18 +40,48 @@ def _run(cmd):
     return out
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
+def _deps(src):
+    """Sources an object depends on: the .hip file, the headers it includes
+    from csrc/ (transitively) and include/nlinv.h."""
+    import re
+    seen, todo = set(), [src]
+    while todo:
+        f = todo.pop()
+        if f in seen or not os.path.exists(f):
+            continue
+        seen.add(f)
+        for inc in re.findall(r'#include\s+"([^"]+)"', open(f).read()):
+            for d in (CSRC, INCLUDE):
+                if os.path.exists(os.path.join(d, inc)):
+                    todo.append(os.path.join(d, inc))
+    return seen
+
+
+def _stale(obj, src):
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in _deps(src))
+
+
+def build(jobs: int | None = None, verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every object and link the library; with `incremental`, only
+    objects older than one of their sources."""
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(8, os.cpu_count() or 4)
     objs = []
     cmds = []
+    inst = os.path.join(CSRC, "inst.hip")
     for n in SIZES:
         o = os.path.join(BUILD, f"inst_{n}.o")
         objs.append(o)
-        cmds.append([HIPCC, *FLAGS, f"-DNLINV_SIZE={n}", "-c", os.path.join(CSRC, "inst.hip"), "-o", o])
+        if not incremental or _stale(o, inst):
+            cmds.append([HIPCC, *FLAGS, f"-DNLINV_SIZE={n}", "-c", inst, "-o", o])
+    lib_src = os.path.join(CSRC, "nlinv_lib.hip")
     lib_o = os.path.join(BUILD, "nlinv_lib.o")
     objs.append(lib_o)
-    cmds.append([HIPCC, *FLAGS, "-c", os.path.join(CSRC, "nlinv_lib.hip"), "-o", lib_o])
+    if not incremental or _stale(lib_o, lib_src):
+        cmds.append([HIPCC, *FLAGS, "-c", lib_src, "-o", lib_o])
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         for out in ex.map(_run, cmds):
             if verbose and out.strip():
@@ -66,8 +96,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("-j", "--jobs", type=int, default=None)
     ap.add_argument("-v", "--verbose", action="store_true")
+    ap.add_argument("-i", "--incremental", action="store_true", help="rebuild only stale objects")
     a = ap.parse_args()
-    print(build(a.jobs, a.verbose))
+    print(build(a.jobs, a.verbose, a.incremental))
 
 
 if __name__ == "__main__":

@@ -168,12 +168,29 @@ __global__ __launch_bounds__(kThreads) void k_copy_batch(CopyBatch b) {
         dst[i] = src[i];
 }
 
-// Bandwidth probe: a plain 16-byte-per-thread streaming copy (the practical
-// HBM ceiling, and the known-size copy that calibrates traffic counters).
-__global__ __launch_bounds__(kThreads) void k_stream_copy(const float4* __restrict__ src,
-                                                          float4* __restrict__ dst, long long n16) {
-    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n16; i += (long long)gridDim.x * kThreads)
-        dst[i] = src[i];
+// Bandwidth probe: a streaming copy (the practical HBM ceiling, and the
+// known-size copy that calibrates traffic counters).  Each thread moves
+// kProbeUnroll 16-byte words per round, all loads issued before the stores
+// (one wavefront keeps 4 KiB in flight), with non-temporal hints: the data
+// are touched once.
+constexpr int kProbeUnroll = 4;
+typedef float probe_v4 __attribute__((ext_vector_type(4)));   // a native 16-byte vector
+__global__ __launch_bounds__(kThreads) void k_stream_copy(const probe_v4* __restrict__ src,
+                                                          probe_v4* __restrict__ dst, long long n16) {
+    const long long step = (long long)gridDim.x * kThreads * kProbeUnroll;
+    for (long long b = (long long)blockIdx.x * kThreads * kProbeUnroll + threadIdx.x; b < n16; b += step) {
+        probe_v4 v[kProbeUnroll];
+#pragma unroll
+        for (int u = 0; u < kProbeUnroll; ++u) {
+            const long long i = b + (long long)u * kThreads;
+            if (i < n16) v[u] = __builtin_nontemporal_load(src + i);
+        }
+#pragma unroll
+        for (int u = 0; u < kProbeUnroll; ++u) {
+            const long long i = b + (long long)u * kThreads;
+            if (i < n16) __builtin_nontemporal_store(v[u], dst + i);
+        }
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void k_fill(float2* x, long long n, float2 v) {

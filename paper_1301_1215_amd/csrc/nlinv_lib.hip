@@ -51,6 +51,7 @@ constexpr int kColModes = 9;         // ColMode values
 constexpr int kRowModes = 4;         // RowMode values
 constexpr int kTimingSlots = 8192;   // event pairs for kernel timing
 constexpr int kMaxLanes = 8;          // streams for concurrent shape classes
+constexpr int kMaxGraphs = 4;         // captured Newton loops kept per plan (by key)
 
 bool size_supported(int n) {
     switch (n) {
@@ -180,19 +181,30 @@ struct nlinv_plan_s {
     std::vector<hipStream_t> lanes;
     hipEvent_t fork_ev = nullptr;
     std::vector<hipEvent_t> join_ev;
-    // Two instances of the captured Newton loop, launched in turn: a launch
-    // of an instance whose previous launch is still running waits on the
-    // host for it, which would leave the GPU idle while the next launch is
-    // being submitted.
-    hipGraphExec_t gexec = nullptr, gexec2 = nullptr;
-    int gnext = 0;
-    GraphKey gkey;
+    // Captured Newton loops, one per key (a temporal series alternates
+    // between a cold first frame and warm-started ones), least recently used
+    // dropped beyond kMaxGraphs.  Each has two instances launched in turn: a
+    // launch of an instance whose previous launch is still running waits on
+    // the host for it, which would leave the GPU idle while the next launch
+    // is being submitted.
+    struct GraphEntry {
+        GraphKey key;
+        hipGraphExec_t exec[2] = {nullptr, nullptr};
+        int next = 0;
+        long long used = 0;
+        long long id = 0;             // owner id of its timing slots
+    };
+    std::vector<GraphEntry> graphs;
+    long long graph_clock = 0;
     // kernel timing
     bool timing[KC_NUM] = {};
     int timing_stride[KC_NUM] = {};   // bracket every stride-th launch of the class
     long long timing_count[KC_NUM] = {};
     std::vector<hipEvent_t> ev;
     std::vector<unsigned char> ev_used;
+    std::vector<int> ev_class;          // kernel class of each slot
+    std::vector<long long> ev_owner;    // graph id of a slot owned by a captured graph
+    long long capture_id = 0;
     int ev_next = 0;
     bool capturing = false;
     bool timing_failed = false;
@@ -275,23 +287,37 @@ int tbegin(nlinv_plan_s* p, int kc, hipStream_t s) {
         p->ev_next = (p->ev_next + 1) % kTimingSlots;
         if (p->ev_used[slot] == 2) continue;
         if (record_event(p, p->ev[2 * slot], s) != hipSuccess) return -1;
+        p->ev_class[slot] = kc;
         return slot;
     }
     return -1;
 }
 void tend(nlinv_plan_s* p, int slot, hipStream_t s) {
     if (slot < 0) return;
-    if (record_event(p, p->ev[2 * slot + 1], s) == hipSuccess) p->ev_used[slot] = p->capturing ? 2 : 1;
+    if (record_event(p, p->ev[2 * slot + 1], s) == hipSuccess) {
+        p->ev_used[slot] = p->capturing ? 2 : 1;
+        p->ev_owner[slot] = p->capturing ? p->capture_id : 0;
+    }
 }
+hipError_t destroy_entry(nlinv_plan_s::GraphEntry& g) {
+    hipError_t e = hipSuccess;
+    for (hipGraphExec_t& x : g.exec) {
+        if (!x) continue;
+        const hipError_t e2 = hipGraphExecDestroy(x);
+        if (e == hipSuccess) e = e2;
+        x = nullptr;
+    }
+    return e;
+}
+// Drop every captured graph (and free the timing slots they own).
 int drop_graph(nlinv_plan_s* p) {
-    if (!p->gexec) return NLINV_OK;
-    hipError_t e = hipGraphExecDestroy(p->gexec);
-    if (p->gexec2) {
-        const hipError_t e2 = hipGraphExecDestroy(p->gexec2);
+    if (p->graphs.empty()) return NLINV_OK;
+    hipError_t e = hipSuccess;
+    for (auto& g : p->graphs) {
+        const hipError_t e2 = destroy_entry(g);
         if (e == hipSuccess) e = e2;
     }
-    p->gexec = p->gexec2 = nullptr;
-    p->gnext = 0;
+    p->graphs.clear();
     for (auto& u : p->ev_used)
         if (u == 2) u = 0;
     HIPCHK(e);
@@ -1041,8 +1067,21 @@ int run_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s) {
     if (!(prm.flags & NLINV_USE_GRAPH)) return enqueue_newton(p, prm, s);
     GraphKey key{prm.newton_steps, prm.cg_iters, prm.alpha0, prm.alpha_q, prm.alpha_min, {}};
     for (const Class& C : p->classes) key.zero_ref.push_back(C.chat_ref_zero);
-    if (!p->gexec || !(p->gkey == key)) {
-        CHK(drop_graph(p));
+    nlinv_plan_s::GraphEntry* ent = nullptr;
+    for (auto& g : p->graphs)
+        if (g.key == key) ent = &g;
+    if (!ent) {
+        if ((int)p->graphs.size() >= kMaxGraphs) {   // drop the least recently used
+            size_t lru = 0;
+            for (size_t i = 1; i < p->graphs.size(); ++i)
+                if (p->graphs[i].used < p->graphs[lru].used) lru = i;
+            for (size_t k = 0; k < p->ev_used.size(); ++k)   // free the timing slots it owned
+                if (p->ev_used[k] == 2 && p->ev_owner[k] == p->graphs[lru].id) p->ev_used[k] = 0;
+            HIPCHK(destroy_entry(p->graphs[lru]));
+            p->graphs.erase(p->graphs.begin() + lru);
+        }
+        nlinv_plan_s::GraphEntry fresh;
+        fresh.id = ++p->capture_id;
         HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
         p->capturing = true;
         for (long long& c : p->timing_count) c = 0;   // the graph's brackets start at launch 0
@@ -1055,17 +1094,20 @@ int run_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s) {
             return st;
         }
         HIPCHK(e);
-        e = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
-        if (e == hipSuccess) e = hipGraphInstantiate(&p->gexec2, g, nullptr, nullptr, 0);
+        e = hipGraphInstantiate(&fresh.exec[0], g, nullptr, nullptr, 0);
+        if (e == hipSuccess) e = hipGraphInstantiate(&fresh.exec[1], g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (e != hipSuccess) {
-            (void)drop_graph(p);
+            (void)destroy_entry(fresh);
             HIPCHK(e);
         }
-        p->gkey = key;
+        fresh.key = key;
+        p->graphs.push_back(fresh);
+        ent = &p->graphs.back();
     }
-    HIPCHK(hipGraphLaunch(p->gnext ? p->gexec2 : p->gexec, s));
-    p->gnext ^= 1;
+    ent->used = ++p->graph_clock;
+    HIPCHK(hipGraphLaunch(ent->exec[ent->next], s));
+    ent->next ^= 1;
     return NLINV_OK;
 }
 
@@ -1174,8 +1216,7 @@ int build_class(nlinv_plan_s* p, Class& C) {
 
 void free_plan(nlinv_plan_s* p) {
     if (!p) return;
-    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
-    if (p->gexec2) (void)hipGraphExecDestroy(p->gexec2);
+    for (auto& g : p->graphs) (void)destroy_entry(g);
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     for (hipStream_t q : p->lanes) (void)hipStreamDestroy(q);
@@ -1341,10 +1382,11 @@ int nlinv_last_hip_error(void) { return g_last_hip; }
 int nlinv_bandwidth_probe(const void* src, void* dst, size_t bytes, void* stream) {
     if (!src || !dst || !aligned(src) || !aligned(dst) || (bytes & 15)) return NLINV_EINVAL;
     const long long n16 = (long long)(bytes / 16);
-    const int blocks = (int)std::min<long long>((n16 + kThreads - 1) / kThreads, 8 * 256 * 8);
+    const long long per = (long long)kThreads * kProbeUnroll;
+    const int blocks = (int)std::min<long long>((n16 + per - 1) / per, 8 * 256 * 16);
     if (n16 == 0) return NLINV_OK;
     hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(kThreads), 0, (hipStream_t)stream,
-                       (const float4*)src, (float4*)dst, n16);
+                       (const probe_v4*)src, (probe_v4*)dst, n16);
     HIPCHK(hipGetLastError());
     return NLINV_OK;
 }
@@ -1706,6 +1748,8 @@ int nlinv_plan_timing_enable(nlinv_plan p, int32_t kclass, int32_t enable) {
     if (enable && p->ev.empty()) {
         p->ev.resize(2 * kTimingSlots);
         p->ev_used.assign(kTimingSlots, 0);
+        p->ev_class.assign(kTimingSlots, -1);
+        p->ev_owner.assign(kTimingSlots, 0);
         // timing-only events: no system-scope fence (cache writeback) at
         // each record, which would stall the kernels around the bracket;
         // their times are read after the stream has been synchronised
@@ -1719,7 +1763,11 @@ int nlinv_plan_timing_enable(nlinv_plan p, int32_t kclass, int32_t enable) {
 }
 
 int nlinv_plan_timing_read(nlinv_plan p, int32_t* launches, double* total_ms) {
-    if (!p || !launches || !total_ms) return NLINV_EINVAL;
+    return nlinv_plan_timing_read_class(p, -1, launches, total_ms);
+}
+
+int nlinv_plan_timing_read_class(nlinv_plan p, int32_t kclass, int32_t* launches, double* total_ms) {
+    if (!p || !launches || !total_ms || kclass < -1 || kclass >= KC_NUM) return NLINV_EINVAL;
     if (p->timing_failed) {
         p->timing_failed = false;
         return NLINV_EHIP;
@@ -1727,7 +1775,7 @@ int nlinv_plan_timing_read(nlinv_plan p, int32_t* launches, double* total_ms) {
     int cnt = 0;
     double tot = 0.0;
     for (int k = 0; k < (int)p->ev_used.size(); ++k) {
-        if (!p->ev_used[k]) continue;
+        if (!p->ev_used[k] || (kclass >= 0 && p->ev_class[k] != kclass)) continue;
         HIPCHK(hipEventSynchronize(p->ev[2 * k + 1]));
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, p->ev[2 * k], p->ev[2 * k + 1]));

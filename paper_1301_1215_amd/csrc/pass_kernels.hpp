@@ -310,7 +310,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
     for (int t = threadIdx.x; t < L * N2; t += NT) {
         const int l = t % L, j2 = t / L, col = col0 + l;
         float2 v[N1];
-        float pacc = 0.f;
+        double pacc = 0.0;   // FP64 from the first term: these sums feed the CG scalars
         if constexpr (PUPD) {
             // p = r + beta p, written back; the operands of a chunk of
             // elements are loaded before its p values are stored (see the
@@ -345,7 +345,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                             x.y += b * pv[I].y;
                         }
                         elt(a.p_out + pofs, o) = x;
-                        pacc += x.x * x.x + x.y * x.y;
+                        pacc += (double)(x.x * x.x + x.y * x.y);
                         v[k1] = cscale(x, CT::sign(r) * w[I]);
                     });
                 });
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                 v[k1] = x;
             });
         }
-        if constexpr (PUPD) acc += (double)pacc;
+        if constexpr (PUPD) acc += pacc;
         RegDFT<N1, INV1>::run(v);
         static_for<0, N1>([&](auto K) {
             constexpr int k1 = K;
@@ -407,20 +407,20 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                 });
                 RegDFT<N2, false>::run(v);
                 if constexpr (PSF) {   // times P^2 and 1/n
-                    float kacc = 0.f;
+                    double kacc = 0.0;
                     static_for<0, N2>([&](auto K) {
                         constexpr int k2 = K;
                         const int r = CT::out_pos(k1, k2);
                         const float p = elt(P, big_idx<N>(r, col, TILED));
-                        kacc += p * p * (v[k2].x * v[k2].x + v[k2].y * v[k2].y);
+                        kacc += (double)(p * p * (v[k2].x * v[k2].x + v[k2].y * v[k2].y));
                         v[k2] = cscale(v[k2], p * p * rs2);
                     });
-                    acc += (double)kacc * (double)rs2;   // |P K|^2 with K = rs . v (unitary DFT)
+                    acc += kacc * (double)rs2;   // |P K|^2 with K = rs . v (unitary DFT)
                 } else {               // residual q = s y - P K, then P q
                     const long long pb = (long long)plane * N * N;
                     const float sy = a.s1 ? a.s1[f] : a.c1;
                     constexpr int CH = pointwise_chunk(N2);
-                    float racc = 0.f;
+                    double racc = 0.0;
                     static_for<0, N2 / CH>([&](auto C) {
                         float w[CH];
                         float2 y[CH];
@@ -435,11 +435,11 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                             const float sg = CT::sign(CT::out_pos(k1, k2));
                             const float pk = w[I] * sg * a.rs;           // P times the forward's factors
                             const float2 q = make_float2(sy * y[I].x - pk * v[k2].x, sy * y[I].y - pk * v[k2].y);
-                            racc += q.x * q.x + q.y * q.y;
+                            racc += (double)(q.x * q.x + q.y * q.y);
                             v[k2] = cscale(q, w[I] * sg * a.rs);
                         });
                     });
-                    acc += (double)racc;
+                    acc += racc;
                 }
             }
             __syncthreads();
@@ -494,7 +494,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
             v[j2] = bufA[k1 * RS + j2 * L + l];
         });
         RegDFT<N2, INV2>::run(v);
-        float facc = 0.f;
+        double facc = 0.0;
         if constexpr (OUT_CROP) {
             static_for<0, N2>([&](auto K) {
                 constexpr int k2 = K;
@@ -553,13 +553,13 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                             d.x += av * u.x;
                             d.y += av * u.y;
                             elt(a.dx + pbase, o) = d;
-                            facc += r.x * r.x + r.y * r.y;
+                            facc += (double)(r.x * r.x + r.y * r.y);
                         } else if constexpr (WINV_OUT) {
                             x = cscale(x, CT::sign(rp) * a.rs * w[I]);
                             if constexpr (H1) { x.x += s1 * u1[I].x; x.y += s1 * u1[I].y; }
                             if constexpr (H2) { x.x += s2 * u2[I].x; x.y += s2 * u2[I].y; }
                             elt(a.out + pbase, o) = x;
-                            facc += x.x * x.x + x.y * x.y;
+                            facc += (double)(x.x * x.x + x.y * x.y);
                         } else if constexpr (MODE == COL_PAD_FFT_GPROD) {
                             const float2 g = u1[I];
                             x = cscale(x, CT::sign(rp) * a.rs);
@@ -577,7 +577,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                 chunks(std::true_type{}, std::true_type{});
             }
         }
-        acc += (double)facc;
+        acc += facc;
     }
     if constexpr (RED) {
         if (a.partial) {   // uniform over the workgroup

@@ -133,8 +133,12 @@ class Plan:
 
     def solve_batch(self, data, prm, outs=None):
         """data: list of (y, P) per plan frame.  Returns one dict per frame."""
+        if len(data) != len(self.frames):
+            raise ValueError(f"solve_batch: {len(data)} (y, P) pairs for a plan of {len(self.frames)} frames")
         if outs is None:
             outs = [self._frame_out(fd, prm) for fd in self.frames]
+        if len(outs) != len(data):
+            raise ValueError(f"solve_batch: {len(outs)} outputs for {len(data)} frames")
         frames = [dict(y=y, P=P, **o) for (y, P), o in zip(data, outs)]
         N.nlinv_irgnm_solve_batch(self.handle, frames, prm)
         return outs
@@ -143,6 +147,8 @@ class Plan:
         """data: list of (y, P) frames of frame 0's shape, solved in order."""
         if outs is None:
             outs = [self._frame_out(self.dims, prm) for _ in data]
+        if len(outs) != len(data):
+            raise ValueError(f"solve_series: {len(outs)} outputs for {len(data)} frames")
         frames = [dict(y=y, P=P, **o) for (y, P), o in zip(data, outs)]
         N.nlinv_irgnm_solve_series(self.handle, frames, prm)
         return outs
@@ -160,5 +166,8 @@ class Plan:
     def timing_enable(self, kclass, enable=True):
         N.nlinv_plan_timing_enable(self.handle, kclass, enable)
 
-    def timing_read(self):
-        return N.nlinv_plan_timing_read(self.handle)
+    def timing_read(self, kclass=None):
+        """(bracketed launches, total ms): of every class, or of one class."""
+        if kclass is None:
+            return N.nlinv_plan_timing_read(self.handle)
+        return N.nlinv_plan_timing_read_class(self.handle, kclass)

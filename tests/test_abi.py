@@ -73,3 +73,54 @@ def test_every_supported_size_passes_the_host_checks(n):
     HIP call; a supported size gets past them (to NLINV_OK on a GPU, or to a
     HIP error where there is none)."""
     assert _create(n, n // 2, 4) in (N.NLINV_OK, N.NLINV_EHIP)
+
+
+# ---- the binding's shape checks (run before any library call, no GPU needed)
+
+@pytest.fixture
+def fake_plan():
+    """A handle registered with frame shapes, as nlinv_plan_create would; the
+    library is never called with it (every check below fails first)."""
+    h = ctypes.c_void_p(0x1000)
+    N._PLANS[h.value] = [(16, 8, 2)]
+    yield h
+    N._PLANS.pop(h.value, None)
+
+
+def _t(*shape, dtype=None):
+    import torch
+    return torch.zeros(shape, dtype=dtype or torch.complex64)
+
+
+def test_operator_shapes_are_checked_before_the_call(fake_plan):
+    import torch
+    good = dict(rho=_t(8, 8), chat=_t(2, 16, 16), c=_t(2, 8, 8), P=_t(16, 16, dtype=torch.float32))
+    with pytest.raises(ValueError, match="drho"):
+        N.nlinv_normal(fake_plan, good["rho"], good["chat"], good["c"], good["P"], 1.0, _t(16, 16),
+                       _t(2, 16, 16), _t(8, 8), _t(2, 16, 16))
+    with pytest.raises(ValueError, match="dchat_out"):
+        N.nlinv_adjoint(fake_plan, good["rho"], good["chat"], None, good["P"], _t(2, 16, 16), _t(8, 8),
+                        _t(3, 16, 16))
+    with pytest.raises(ValueError, match="P"):
+        N.nlinv_forward(fake_plan, good["rho"], good["chat"], _t(8, 8, dtype=torch.float32), _t(2, 16, 16))
+    with pytest.raises(ValueError, match="c_out"):
+        N.nlinv_coil_maps(fake_plan, good["chat"], _t(2, 16, 16))
+    with pytest.raises(ValueError, match="gP_out"):
+        N.nlinv_mask_gradient(fake_plan, good["rho"], good["chat"], None, _t(2, 16, 16), _t(8, 8))
+
+
+def test_solve_shapes_and_frame_counts_are_checked(fake_plan):
+    import torch
+    prm = N.make_params(2, 3)
+    f = dict(y=_t(2, 16, 16), P=_t(16, 16, dtype=torch.float32), rho=_t(8, 8), chat=_t(2, 16, 16),
+             stats=torch.zeros(N.stats_len(2, 3), dtype=torch.float64))
+    with pytest.raises(ValueError, match="2 frame descriptors for a plan of 1"):
+        N.nlinv_irgnm_solve_batch(fake_plan, [f, f], prm)
+    with pytest.raises(ValueError, match="stats"):
+        N.nlinv_irgnm_solve_batch(fake_plan, [dict(f, stats=torch.zeros(3, dtype=torch.float64))], prm)
+    with pytest.raises(ValueError, match="chat_ref"):
+        N.nlinv_irgnm_solve(fake_plan, f["y"], f["P"], prm, f["rho"], f["chat"], _t(8, 8), _t(2, 8, 8))
+    with pytest.raises(ValueError, match="frame 1 y"):
+        N.nlinv_irgnm_solve_series(fake_plan, [f, dict(f, y=_t(2, 16, 8))], prm)
+    with pytest.raises(ValueError, match="unknown plan"):
+        N.nlinv_normal(ctypes.c_void_p(0x2000), *[None] * 9)

@@ -38,9 +38,10 @@ def test_batched_realtime_384_as_benchmarked():
 
 @pytest.mark.timeout(900)
 def test_ragged_batch_64_frames_sampled():
-    """All 64 uneven frames in one batched, graph-replayed solve; three
-    sampled frames (the smallest grid, a 32-coil frame, a 384 grid) against
-    the oracle, every frame finite and converging."""
+    """All 64 uneven frames in one batched, graph-replayed solve; sampled
+    frames (the smallest grid, a 32-coil frame, a 384 grid and a 192 grid, the
+    radix-3 size whose passes split 12 x 16) against the oracle, every frame
+    finite and converging."""
     frames = synth.ragged_batch(64)
     with Plan(frames=[(f.n, f.n_om, f.ncoils) for f in frames]) as pl:
         pl.autotune()
@@ -52,21 +53,25 @@ def test_ragged_batch_64_frames_sampled():
         assert st[2 + 6] < st[2]        # residual falls over the Newton steps
     picks = {min(range(64), key=lambda i: frames[i].n),
              next(i for i in range(64) if frames[i].ncoils == 32),
-             next(i for i in range(64) if frames[i].n == 384)}
+             next(i for i in range(64) if frames[i].n == 384),
+             next(i for i in range(64) if frames[i].n == 192)}
     for i in sorted(picks):
         assert rel(res[i]["image"], _oracle(frames[i]).image) < NRMSE, i
 
 
 @pytest.mark.timeout(900)
 def test_temporal_series_512_first_frames():
-    """512x512, 32 coils, 13 golden-angle spokes: frames 0..1 of the series,
-    each warm-started from the previous, against the oracle's series."""
+    """512x512, 32 coils, 13 golden-angle spokes: frames 0..7 of the series
+    (the benchmark's step), each warm-started from the previous, against the
+    oracle's series, so that FP32 drift along the chain of references is
+    measured frame by frame."""
     ph = synth.temporal_phantom()
-    frames = [synth.temporal_frame(t, ph) for t in range(2)]
+    frames = [synth.temporal_frame(t, ph) for t in range(8)]
     with Plan(512, 256, 32) as pl:
         outs = pl.solve_series([(dev(f.y), dev(f.P)) for f in frames], Plan.params(7, 10, use_graph=True))
         imgs = [host(o["image"]) for o in outs]
     _workers()
     ref = O.irgnm_series([f.y for f in frames], [f.P for f in frames], O.Dims(512, 256, 32), O.IRGNMParams(7, 10))
-    for img, r in zip(imgs, ref):
-        assert rel(img, r.image) < NRMSE
+    errs = [rel(img, r.image) for img, r in zip(imgs, ref)]
+    print("series_512 image NRMSE per frame:", " ".join(f"{e:.2e}" for e in errs))
+    assert max(errs) < NRMSE, errs

@@ -239,3 +239,26 @@ def test_breakdown_on_zero_data():
         assert int(st[1]) & 1
         assert np.all(st[2 + 2:] == -1.0)
         assert np.all(host(out["chat"]) == 0) and np.all(host(out["rho"]) == 1)
+
+
+@pytest.mark.parametrize("n,n_om", [(16, 8), (12, 12)])
+@pytest.mark.parametrize("K", [1, 3])
+def test_no_sampling_lands_on_the_reference(n, n_om, K):
+    """P = 0: F and DF vanish and Eq. 3 reduces to dx = x_ref - x_n, so the
+    solve must return the caller's x_ref (data units, s != 1) to FP32 rounding
+    in both blocks; the oracle's closed form of the same case is pinned on the
+    CPU."""
+    rng = np.random.default_rng([5, n, K])
+    y = (rng.standard_normal((2, n, n)) + 1j * rng.standard_normal((2, n, n))).astype(np.complex64)
+    P = np.zeros((n, n), np.float32)
+    def rc(*s):
+        return (rng.standard_normal(s) + 1j * rng.standard_normal(s)).astype(np.complex64)
+    rho0, chat0, rref, cref = rc(n_om, n_om), rc(2, n, n), rc(n_om, n_om), rc(2, n, n)
+    with Plan(n, n_om, 2) as pl:
+        for use_graph in (False, True):
+            out = pl.solve(dev(y), dev(P), Plan.params(2, K, use_graph=use_graph, warm_start=True),
+                           rho0=dev(rho0), chat0=dev(chat0), rho_ref=dev(rref), chat_ref=dev(cref))
+            got = {k: host(v) for k, v in out.items()}
+            assert abs(got["stats"][0] - 1.0) > 0.5
+            assert rel(got["rho"], rref) < 1e-5
+            assert rel(got["chat"], cref) < 1e-5

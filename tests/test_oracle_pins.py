@@ -299,6 +299,29 @@ def test_noiseless_full_sampling_recovery():
     assert np.linalg.norm(rss - truth) / np.linalg.norm(truth) < 0.15
 
 
+@pytest.mark.parametrize("n,n_om", [(16, 8), (12, 12)])
+@pytest.mark.parametrize("K", [1, 3])
+def test_no_sampling_lands_on_the_reference(n, n_om, K):
+    """P = 0 makes F and DF vanish, so Eq. 3 reads alpha dx = -alpha (x_n - x_ref):
+    the normal operator is alpha I, the right-hand side -alpha (x_n - x_ref),
+    and the first CG step already gives dx = x_ref - x_n.  With y != 0 the data
+    scale s differs from 1, and x0, x_ref are given in data units (their rho
+    parts scaled by s inside the solve), so the result must be x_ref exactly:
+    both blocks of the regularisation term and the scaling of rho_ref count."""
+    d = O.Dims(n, n_om, 2)
+    y = crand(2, n, n)                                  # ||y|| far from 100: s != 1
+    P = np.zeros((n, n))
+    rho0, chat0 = crand(n_om, n_om), crand(2, n, n)
+    rho_ref, chat_ref = crand(n_om, n_om), crand(2, n, n)
+    res = O.irgnm(y, P, d, O.IRGNMParams(newton_steps=2, cg_iters=K), rho0=rho0, chat0=chat0,
+                  rho_ref=rho_ref, chat_ref=chat_ref)
+    assert abs(res.scale - 1.0) > 0.5
+    assert relerr(res.rho, rho_ref) < 1e-12
+    assert relerr(res.chat, chat_ref) < 1e-12
+    # and the residual of step 0 is the scaled data itself (F(x) = 0)
+    assert math.isclose(res.r0_norms[0], 100.0, rel_tol=1e-12)
+
+
 def test_series_warm_start_uses_previous_result():
     """Frame 1 with the same data as frame 0 starts at frame 0's result: its first
     residual is ||s y - F(s rho_prev, chat_prev)||."""
