@@ -36,6 +36,7 @@
 #ifndef NLINV_H
 #define NLINV_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -76,7 +77,8 @@ enum {
     NLINV_EINVAL = -1,
     NLINV_EUNSUPPORTED = -2,
     NLINV_ENOMEM = -3,
-    NLINV_EHIP = -4
+    NLINV_EHIP = -4,
+    NLINV_ESCRATCH = -5     /* nlinv_normal_noalloc: the frame needs more than its static scratch */
 };
 
 enum {
@@ -148,6 +150,26 @@ int nlinv_normal(nlinv_plan plan, const nlinv_c32* rho, const nlinv_c32* chat,
                  const nlinv_c32* c, const float* P, float alpha,
                  const nlinv_c32* drho, const nlinv_c32* dchat,
                  nlinv_c32* drho_out, nlinv_c32* dchat_out, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the normal
+ * operator of nlinv_normal for one frame of shape *dims, without a plan.  It
+ * allocates nothing: its workspace is a static device array of
+ * NLINV_NOALLOC_SCRATCH_BYTES per GPU (held until the process ends), which
+ * must hold the twiddles (8 n B), the inverse weight table (4 n^2 B), the
+ * coil products (8 J n_om^2 B), the pass intermediate (8 J n_om n B) and,
+ * when c is NULL, the sensitivities (8 J n_om^2 B), each rounded up to
+ * 256 B; larger frames are refused with NLINV_ESCRATCH before anything is
+ * enqueued (512 x 512, n_om 256, 32 coils fits; every smaller shape does).
+ * Arguments, layouts and the result are those of nlinv_normal (default pass
+ * variants).  Every call on a GPU reuses that GPU's array and rebuilds what it
+ * needs in it, so calls that overlap on one GPU (other streams or threads)
+ * race and give wrong results; serialise them. */
+#define NLINV_NOALLOC_SCRATCH_BYTES ((size_t)80 << 20)
+int nlinv_normal_noalloc(const nlinv_dims* dims, const nlinv_c32* rho, const nlinv_c32* chat,
+                         const nlinv_c32* c, const float* P, float alpha,
+                         const nlinv_c32* drho, const nlinv_c32* dchat,
+                         nlinv_c32* drho_out, nlinv_c32* dchat_out, void* stream);
 
 /* Gradient with respect to P of a loss of y = F(x; P), given
  * g = dL/dRe(y) + i dL/dIm(y) [J][n][n]:  gP = Re sum_j conj(g_j) . DTFT(E(rho . c_j)).

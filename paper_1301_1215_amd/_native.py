@@ -13,12 +13,14 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnlinv.so")
 
-NLINV_OK, NLINV_EINVAL, NLINV_EUNSUPPORTED, NLINV_ENOMEM, NLINV_EHIP = 0, -1, -2, -3, -4
+NLINV_OK, NLINV_EINVAL, NLINV_EUNSUPPORTED, NLINV_ENOMEM, NLINV_EHIP, NLINV_ESCRATCH = 0, -1, -2, -3, -4, -5
+# bytes of the static device scratch of nlinv_normal_noalloc (NLINV_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 80 << 20
 NLINV_USE_GRAPH, NLINV_WARM_START = 1, 2
 
 EXPORTED = (
     "nlinv_plan_create", "nlinv_plan_create_branched", "nlinv_plan_destroy", "nlinv_coil_maps", "nlinv_forward", "nlinv_deriv",
-    "nlinv_adjoint", "nlinv_normal", "nlinv_mask_gradient", "nlinv_image", "nlinv_irgnm_solve",
+    "nlinv_adjoint", "nlinv_normal", "nlinv_normal_noalloc", "nlinv_mask_gradient", "nlinv_image", "nlinv_irgnm_solve",
     "nlinv_irgnm_solve_batch", "nlinv_irgnm_solve_series", "nlinv_plan_autotune", "nlinv_plan_variant",
     "nlinv_plan_set_variant", "nlinv_plan_timing_enable", "nlinv_plan_timing_read",
     "nlinv_plan_timing_read_class",
@@ -73,6 +75,7 @@ def load(path: str | None = None):
         "nlinv_deriv": ([vp, vp, vp, vp, vp, vp, vp, vp, vp], C.c_int),
         "nlinv_adjoint": ([vp, vp, vp, vp, vp, vp, vp, vp, vp], C.c_int),
         "nlinv_normal": ([vp, vp, vp, vp, vp, f32, vp, vp, vp, vp, vp], C.c_int),
+        "nlinv_normal_noalloc": ([C.POINTER(nlinv_dims), vp, vp, vp, vp, f32, vp, vp, vp, vp, vp], C.c_int),
         "nlinv_mask_gradient": ([vp, vp, vp, vp, vp, vp, vp], C.c_int),
         "nlinv_image": ([vp, vp, vp, vp, vp], C.c_int),
         "nlinv_irgnm_solve": ([vp, vp, vp, C.POINTER(nlinv_irgnm_params), vp, vp, vp, vp, vp, vp, vp], C.c_int),
@@ -267,6 +270,31 @@ def nlinv_normal(plan, rho, chat, c, P, alpha, drho, dchat, drho_out, dchat_out,
                               float(alpha), _c64(drho, "drho"), _c64(dchat, "dchat"),
                               _c64(drho_out, "drho_out"), _c64(dchat_out, "dchat_out"), _stream(stream)),
           "nlinv_normal")
+
+
+def noalloc_scratch_need(n, n_om, ncoils, with_c):
+    """Scratch bytes nlinv_normal_noalloc needs for a frame (its header's formula)."""
+    r = lambda b: (b + 255) // 256 * 256
+    om = r(8 * ncoils * n_om * n_om)
+    return r(8 * n) + r(4 * n * n) + om + r(8 * ncoils * n_om * n) + (0 if with_c else om)
+
+
+def nlinv_normal_noalloc(dims, rho, chat, c, P, alpha, drho, dchat, drho_out, dchat_out, stream=None):
+    """dims: (n, n_om, ncoils[, a, l]) of the one frame; no plan."""
+    n, m, J = int(dims[0]), int(dims[1]), int(dims[2])
+    a = float(dims[3]) if len(dims) > 3 else 220.0
+    l = float(dims[4]) if len(dims) > 4 else 32.0
+    for what, t in dict(rho=rho, drho=drho, drho_out=drho_out).items():
+        _expect(t, (m, m), what)
+    for what, t in dict(chat=chat, dchat=dchat, dchat_out=dchat_out).items():
+        _expect(t, (J, n, n), what)
+    _expect(c, (J, m, m), "c")
+    _expect(P, (n, n), "P")
+    d = nlinv_dims(n, m, J, a, l)
+    check(load().nlinv_normal_noalloc(C.byref(d), _c64(rho, "rho"), _c64(chat, "chat"), _c64(c, "c"),
+                                      _f32(P, "P"), float(alpha), _c64(drho, "drho"), _c64(dchat, "dchat"),
+                                      _c64(drho_out, "drho_out"), _c64(dchat_out, "dchat_out"),
+                                      _stream(stream)), "nlinv_normal_noalloc")
 
 
 def nlinv_mask_gradient(plan, rho, chat, c, g, gP_out, stream=None):

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <string>
@@ -1373,6 +1374,7 @@ const char* nlinv_status_string(int status) {
         case NLINV_EUNSUPPORTED: return "unsupported size";
         case NLINV_ENOMEM: return "out of device memory";
         case NLINV_EHIP: return "HIP error";
+        case NLINV_ESCRATCH: return "frame too large for the static scratch of nlinv_normal_noalloc";
         default: return "unknown status";
     }
 }
@@ -1789,3 +1791,121 @@ int nlinv_plan_timing_read_class(nlinv_plan p, int32_t kclass, int32_t* launches
 }
 
 }  // extern "C"
+
+// =============================================================================
+// The normal operator without a plan and without allocation
+// =============================================================================
+//
+// nlinv_normal_noalloc runs the kernels of nlinv_normal on workspace taken
+// from `scratch`, a static device array of kNoallocScratchBytes: the line-FFT
+// twiddles, the inverse Sobolev weight table, the sensitivities (when the
+// caller passes none), the coil products and the pass intermediate T.  The
+// tables are rebuilt by a kernel at every call (they depend on the frame's
+// n, a and l), so a call depends on nothing an earlier call left.  Each GPU
+// holds its own copy of the array; calls that overlap on one GPU race on it.
+
+static __device__ __align__(256) unsigned char scratch[NLINV_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr size_t kNoallocScratchBytes = NLINV_NOALLOC_SCRATCH_BYTES;
+
+// Device address of `scratch` on each device, looked up once per device
+// with that device current (in host code the array's name is only a
+// host-side stand-in and must never be handed to a kernel).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_ptr(unsigned char** out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return NLINV_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* q = nullptr;
+        HIPCHK(hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)));
+        if (!q) return NLINV_EHIP;
+        g_scratch_ptr[dev] = q;
+    }
+    *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+    return NLINV_OK;
+}
+
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// tw2[k1][j2] = exp(-2 pi i k1 j2 / n) and 1/w = (1 + a |k|^2)^(-hl) on the
+// row-major grid, both evaluated in FP64 and rounded once to FP32 (the
+// plan's host tables are made the same way)
+__global__ __launch_bounds__(kThreads) void k_noalloc_tables(float2* tw, float* winv, int n, int n1, double a,
+                                                             double hl) {
+    const int n2 = n / n1;
+    const long long tot = (long long)n * n;
+    for (long long g = (long long)blockIdx.x * kThreads + threadIdx.x; g < tot;
+         g += (long long)gridDim.x * kThreads) {
+        const int r = (int)(g / n), c = (int)(g % n);
+        const double k0 = (double)(r - n / 2) / n, k1 = (double)(c - n / 2) / n;
+        winv[g] = (float)pow(1.0 + a * (k0 * k0 + k1 * k1), -hl);
+        if (g < n) {
+            const int kk1 = (int)g / n2, j2 = (int)g % n2;
+            const double ang = -2.0 * 3.14159265358979323846 * (double)(kk1 * j2) / (double)n;
+            tw[g] = make_float2((float)cos(ang), (float)sin(ang));
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" int nlinv_normal_noalloc(const nlinv_dims* dims, const nlinv_c32* rho, const nlinv_c32* chat,
+                                    const nlinv_c32* c, const float* P, float alpha, const nlinv_c32* drho,
+                                    const nlinv_c32* dchat, nlinv_c32* drho_out, nlinv_c32* dchat_out,
+                                    void* stream) {
+    if (!dims || !rho || !P || !drho || !dchat || !drho_out || !dchat_out || (!c && !chat)) return NLINV_EINVAL;
+    if (!aligned(rho) || !aligned(P) || !aligned(drho) || !aligned(dchat) || !aligned(drho_out) ||
+        !aligned(dchat_out) || (c && !aligned(c)) || (chat && !aligned(chat)))
+        return NLINV_EINVAL;
+    CHK(check_dims(*dims));
+    const int n = dims->n, m = dims->n_om, J = dims->ncoils;
+    // scratch layout: tw | winv | aux | T | c (c only when the caller gives none)
+    const size_t b_tw = round256((size_t)n * sizeof(float2));
+    const size_t b_w = round256((size_t)n * n * sizeof(float));
+    const size_t b_om = round256((size_t)J * m * m * sizeof(float2));
+    const size_t b_T = round256((size_t)J * m * n * sizeof(float2));
+    const size_t need = b_tw + b_w + b_om + b_T + (c ? 0 : b_om);
+    if (need > kNoallocScratchBytes) return NLINV_ESCRATCH;
+    unsigned char* base = nullptr;
+    CHK(scratch_ptr(&base));
+    const hipStream_t s = (hipStream_t)stream;
+
+    // a plan-shaped description of the frame on the scratch (no allocation:
+    // the plan's containers stay empty and timing stays off)
+    nlinv_plan_s pl;
+    pl.sob_a = dims->sobolev_a;
+    pl.sob_hl = 0.5f * dims->sobolev_l;
+    Class C;
+    C.n = n;
+    C.m = m;
+    C.lo = n / 2 - m / 2;
+    C.nframes = 1;
+    C.nplanes = J;
+    C.tilew = plane_tile_width(n);
+    C.tw = reinterpret_cast<float2*>(base);
+    C.winv = reinterpret_cast<float*>(base + b_tw);
+    C.aux = reinterpret_cast<float2*>(base + b_tw + b_w);
+    C.T = reinterpret_cast<float2*>(base + b_tw + b_w + b_om);
+    C.c = c ? nullptr : reinterpret_cast<float2*>(base + b_tw + b_w + b_om + b_T);
+    for (int& v : C.colv) v = default_col_variant(n);
+    for (int& v : C.rowv) v = default_row_variant(n);
+
+    hipLaunchKernelGGL(k_noalloc_tables, dim3(grid_for((long long)n * n)), dim3(kThreads), 0, s, C.tw, C.winv, n,
+                       split_n1(n), (double)pl.sob_a, (double)pl.sob_hl);
+    HIPCHK(hipGetLastError());
+    const Frames fr = single_frame(J);
+    const float2* cc = (const float2*)c;
+    if (!cc) {
+        CHK(seq_coil_maps(&pl, C, fr, (const float2*)chat, C.c, s));
+        cc = C.c;
+    }
+    return seq_normal(&pl, C, fr, (const float2*)rho, cc, P, 0, nullptr, alpha, (const float2*)drho,
+                      (const float2*)dchat, (float2*)drho_out, (float2*)dchat_out, s);
+}

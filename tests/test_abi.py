@@ -124,3 +124,21 @@ def test_solve_shapes_and_frame_counts_are_checked(fake_plan):
         N.nlinv_irgnm_solve_series(fake_plan, [f, dict(f, y=_t(2, 16, 8))], prm)
     with pytest.raises(ValueError, match="unknown plan"):
         N.nlinv_normal(ctypes.c_void_p(0x2000), *[None] * 9)
+
+
+def test_noalloc_normal_refuses_before_touching_a_gpu():
+    """NULL arguments, bad dims and frames larger than the static scratch are
+    refused before any HIP call (the pointers here are never dereferenced)."""
+    lib = N.load()
+    fake = ctypes.c_void_p(1 << 20)     # aligned, never read: the call returns first
+    def call(n, m, J, c=fake, rho=fake):
+        d = N.nlinv_dims(n, m, J, 220.0, 32.0)
+        return lib.nlinv_normal_noalloc(ctypes.byref(d), rho, fake, c, fake, 1.0, fake, fake, fake, fake, None)
+    assert call(512, 256, 32, rho=None) == N.NLINV_EINVAL
+    assert call(100, 50, 4) == N.NLINV_EUNSUPPORTED
+    assert call(1024, 1024, 16) == N.NLINV_ESCRATCH
+    # 512 x 512, Omega 256, 32 coils fits with and without a caller's c
+    assert N.noalloc_scratch_need(512, 256, 32, with_c=False) <= N.NOALLOC_SCRATCH_BYTES
+    assert N.noalloc_scratch_need(1024, 512, 16, with_c=False) > N.NOALLOC_SCRATCH_BYTES
+    assert call(1024, 512, 16, c=None) == N.NLINV_ESCRATCH
+    assert lib.nlinv_status_string(N.NLINV_ESCRATCH).decode().startswith("frame too large")
