@@ -67,42 +67,57 @@ def log(*a):
 # byte models
 # ---------------------------------------------------------------------------
 
-def normal_bytes(n, m, J):
+def normal_bytes(n, m, J, kb=None):
     """B_normal: compulsory bytes of one (DF^H DF + alpha) apply on one frame:
-    read h (chat and rho parts), the linearisation point (c on Omega, rho) and
-    P; write N h.  complex64 = 8 B, P float32 = 4 B."""
-    N_, NO = n * n, m * m
-    return 8 * (J * N_ + NO) + 8 * (J * NO + NO) + 4 * N_ + 8 * (J * N_ + NO)
+    read h (its sensitivity part and its image part), the linearisation point
+    (c on Omega, rho) and P; write N h.  complex64 = 8 B, P float32 = 4 B.
+    The sensitivity part counts the kb x kb band of k-space the solve keeps
+    (kb = n: every component, the dense count)."""
+    N_, NO, K = n * n, m * m, (kb or n) ** 2
+    return 8 * (J * K + NO) + 8 * (J * NO + NO) + 4 * N_ + 8 * (J * K + NO)
 
 
-def cg_bytes(n, m, J):
+def cg_bytes(n, m, J, kb=None):
     """B_cg = B_normal + 7 V: one CG iteration with the apply fused with the
     vector updates (read r, q / write r; read x, p, r / write x, p; the read
-    of p shared with the apply), V = 8 (J n^2 + m^2) bytes per vector."""
-    V = 8 * (J * n * n + m * m)
-    return normal_bytes(n, m, J) + 7 * V
+    of p shared with the apply), V = 8 (J kb^2 + m^2) bytes per vector."""
+    V = 8 * (J * (kb or n) ** 2 + m * m)
+    return normal_bytes(n, m, J, kb) + 7 * V
 
 
-def schedule_bytes(kc: str, n: int, m: int, planes: int, frames: int) -> float:
+def fft_flops(n, m, J, kb):
+    """Line-FFT work of one CG iteration on one frame, 5 L log2 L flops per
+    transform of length L = n: the first column pass transforms the kb band
+    columns, each row pass 2 transforms of the m Omega rows, the PSF column
+    pass 2 transforms of all n columns, the last column pass the kb band
+    columns; per coil plane."""
+    import math
+    t = 5.0 * n * math.log2(n)
+    return J * t * (kb + 2 * m + 2 * n + 2 * m + kb)
+
+
+def schedule_bytes(kc: str, n: int, m: int, planes: int, frames: int, kb: int) -> float:
     """Bytes one launch of pass class `kc` moves in the build's pass schedule
-    (its operands and results, the T intermediate between the two axes
-    included), for `planes` coil planes of `frames` frames; the 1/w table
-    (shared by every plane, L2-resident) is not counted."""
-    c, mn, mm, nn = 8.0, float(m * n), float(m * m), float(n * n)
+    inside a solve (its operands and results, the intermediates between the
+    two axes included: T [m][n], and [m][kb] on the band side), for `planes`
+    coil planes of `frames` frames, with the sensitivity vectors on the
+    kb x kb band; the 1/w table (shared by every plane, L2-resident) is not
+    counted."""
+    c, mn, mm, nn, mk, kk = 8.0, float(m * n), float(m * m), float(n * n), float(m * kb), float(kb * kb)
     per = {
-        "col_winv_ifft": planes * c * (nn + mn),
-        "col_pupd_winv_ifft": planes * c * (3 * nn + mn) + frames * 3 * c * mm,   # read r, p; write p, T
+        "col_winv_ifft": planes * c * (kk + mk),
+        "col_pupd_winv_ifft": planes * c * (3 * kk + mk) + frames * 3 * c * mm,   # read r, p; write p, T
         "col_p_ifft": planes * c * (nn + mn) + frames * 4 * nn,
         "col_fft_p": planes * c * (mn + nn) + frames * 4 * nn,
         "col_resid_p_ifft": planes * c * (2 * mn + nn) + frames * 4 * nn,
         "col_psf": planes * c * (2 * mn) + frames * 4 * nn,
-        "col_fft_winv_add": planes * c * (mn + 3 * nn),
+        "col_fft_winv_add": planes * c * (mk + 3 * kk),
         # read T, p, r, x (chat) and the coil products; write r, x; rho parts: read p, r, dx; write r, dx
-        "col_fft_winv_cg_update": planes * c * (mn + 5 * nn + mm) + frames * 5 * c * mm,
-        "row_cache": planes * c * (mn + mm),
+        "col_fft_winv_cg_update": planes * c * (mk + 5 * kk + mm) + frames * 5 * c * mm,
+        "row_cache": planes * c * (mk + mm),
         "row_fwd": planes * c * (mm + mn) + frames * c * mm,
-        "row_deriv": planes * c * (2 * mn + mm) + frames * 2 * c * mm,
-        "row_adj": planes * c * (2 * mn + 2 * mm) + frames * c * mm,
+        "row_deriv": planes * c * (mk + mn + mm) + frames * 2 * c * mm,
+        "row_adj": planes * c * (mn + mk + 2 * mm) + frames * c * mm,
         "coil_sum": planes * c * mm + frames * 3 * c * mm,
         "vec_dot": (planes * nn + frames * mm) * 2 * c,
     }
@@ -241,20 +256,30 @@ def timed_steps(pl, run, steps, classes):
     return dt, per
 
 
-def roofline_record(workload, n, m, J, frames_per_launch, per, traffic):
-    """The CG iteration against the HBM roofline: B_cg x frames per launch over
-    the sum of the five classes' average launch durations."""
+def roofline_record(workload, n, m, J, kb, frames_per_launch, per, traffic):
+    """The CG iteration against the HBM roofline: B_cg (with the sensitivity
+    vectors on the kb x kb band the solve keeps) x frames per launch over the
+    sum of the five classes' average launch durations."""
     avg = {k: (ms / cnt if cnt else float("nan")) for k, (cnt, ms) in per.items()}
     sum_ms = sum(avg[k] for k in CG_CLASSES)
-    B = cg_bytes(n, m, J) * frames_per_launch
-    sched = {k: schedule_bytes(k, n, m, J * frames_per_launch, frames_per_launch) for k in CG_CLASSES}
+    B = cg_bytes(n, m, J, kb) * frames_per_launch
+    B_dense = cg_bytes(n, m, J) * frames_per_launch
+    sched = {k: schedule_bytes(k, n, m, J * frames_per_launch, frames_per_launch, kb) for k in CG_CLASSES}
     achieved = B / (sum_ms * 1e-3) / 1e9
+    flops = fft_flops(n, m, J, kb) * frames_per_launch
     rec = {"bound": "hbm",
            "kernel": "CG iteration = " + " + ".join(CG_CLASSES),
            "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
            "traffic": None,
            "algorithmic_bytes_per_launch": B,
-           "algorithmic_bytes_note": f"B_cg = B_normal + 7V per frame x {frames_per_launch} frame(s) per launch",
+           "algorithmic_bytes_note": f"B_cg = B_normal + 7V per frame x {frames_per_launch} frame(s) per launch, "
+                                     f"sensitivity vectors on the {kb}x{kb} band of the {n}x{n} grid that the "
+                                     f"solve keeps (1/w > 2^-40 inside)",
+           "band": kb,
+           "dense_chat_bytes_per_launch": B_dense,
+           "dense_chat_GBps": B_dense / (sum_ms * 1e-3) / 1e9,
+           "fft_flops_per_launch": flops,
+           "fft_TFLOPs": flops / (sum_ms * 1e-3) / 1e12,
            "avg_launch_ms": {k: avg[k] for k in CG_CLASSES},
            "sum_avg_launch_ms": sum_ms,
            "launches_timed": {k: per[k][0] for k in CG_CLASSES},
@@ -295,7 +320,7 @@ def series_bench(a, NAT, torch):
     ms_step = 1e3 * dt / a.steps
     fps = F * a.steps / dt
     log(f"bench: {ms_step:.2f} ms/step, {fps:.2f} frames/s")
-    roof = roofline_record("series_512", n, m, J, 1, per, pmc_traffic("series_512"))
+    roof = roofline_record("series_512", n, m, J, pl.band()[0], 1, per, pmc_traffic("series_512"))
     extras = {"kernel_class_ms_per_step": {k: v[0] for k, v in totals.items()}}
     img_last = outs[-1]["image"].clone()
 
@@ -360,7 +385,7 @@ def realtime_bench(a, NAT, torch, steps=None, quiet=False):
     torch.cuda.synchronize()
     dt, per = timed_steps(pl, run, steps or a.steps, CG_CLASSES)
     k = steps or a.steps
-    roof = roofline_record("realtime_384", n, m, J, F, per, None)
+    roof = roofline_record("realtime_384", n, m, J, pl.band()[0], F, per, None)
     pl.close()
     del outs, data
     torch.cuda.empty_cache()

@@ -221,6 +221,18 @@ int nlinv_plan_autotune(nlinv_plan plan, void* stream);
  * CG loop. */
 int nlinv_plan_variant(nlinv_plan plan, int32_t n, int32_t* col_variant, int32_t* row_variant);
 
+/* The band of k-space the solves keep of the sensitivities for grid size n:
+ * rows and columns [*kb_lo, *kb_lo + *kb).  Outside it every Sobolev weight
+ * has 1/w <= 2^-40, so those components of chat reach c = E^H W^{-1} chat
+ * only far below single-precision rounding: the solves treat them as
+ * untouched by DF (there the normal operator of Eq. 3 is alpha I, which CG
+ * follows exactly through a few per-frame scalars) and write them once, at
+ * the end.  *kb = n (the whole grid) for small grids, flat weights, or when
+ * the environment variable NLINV_FULL_CHAT=1 was set at plan creation.  The
+ * operator entry points always act on the whole grid.  NLINV_EINVAL if n is
+ * not in the plan. */
+int nlinv_plan_band(nlinv_plan plan, int32_t n, int32_t* kb, int32_t* kb_lo);
+
 /* Force one variant on every column / row pass of grid size n (for tests):
  * returns NLINV_EINVAL for an index that is not valid for n. */
 int nlinv_plan_set_variant(nlinv_plan plan, int32_t n, int32_t col_variant, int32_t row_variant);

@@ -21,7 +21,7 @@ NLINV_USE_GRAPH, NLINV_WARM_START = 1, 2
 EXPORTED = (
     "nlinv_plan_create", "nlinv_plan_create_branched", "nlinv_plan_destroy", "nlinv_coil_maps", "nlinv_forward", "nlinv_deriv",
     "nlinv_adjoint", "nlinv_normal", "nlinv_normal_noalloc", "nlinv_mask_gradient", "nlinv_image", "nlinv_irgnm_solve",
-    "nlinv_irgnm_solve_batch", "nlinv_irgnm_solve_series", "nlinv_plan_autotune", "nlinv_plan_variant",
+    "nlinv_irgnm_solve_batch", "nlinv_irgnm_solve_series", "nlinv_plan_autotune", "nlinv_plan_variant", "nlinv_plan_band",
     "nlinv_plan_set_variant", "nlinv_plan_timing_enable", "nlinv_plan_timing_read",
     "nlinv_plan_timing_read_class",
     "nlinv_kernel_class_name", "nlinv_status_string", "nlinv_last_hip_error", "nlinv_bandwidth_probe",
@@ -85,6 +85,7 @@ def load(path: str | None = None):
         "nlinv_plan_autotune": ([vp, vp], C.c_int),
         "nlinv_plan_variant": ([vp, i32, C.POINTER(i32), C.POINTER(i32)], C.c_int),
         "nlinv_plan_set_variant": ([vp, i32, i32, i32], C.c_int),
+        "nlinv_plan_band": ([vp, i32, C.POINTER(i32), C.POINTER(i32)], C.c_int),
         "nlinv_plan_timing_enable": ([vp, i32, i32], C.c_int),
         "nlinv_plan_timing_read": ([vp, C.POINTER(i32), C.POINTER(C.c_double)], C.c_int),
         "nlinv_plan_timing_read_class": ([vp, i32, C.POINTER(i32), C.POINTER(C.c_double)], C.c_int),
@@ -372,6 +373,13 @@ def nlinv_plan_variant(plan, n):
     cv, rv = C.c_int32(), C.c_int32()
     check(load().nlinv_plan_variant(plan, int(n), C.byref(cv), C.byref(rv)), "nlinv_plan_variant")
     return cv.value, rv.value
+
+
+def nlinv_plan_band(plan, n):
+    """(kb, kb_lo): the band of k-space the solves keep of the sensitivities."""
+    kb, lo = C.c_int32(), C.c_int32()
+    check(load().nlinv_plan_band(plan, int(n), C.byref(kb), C.byref(lo)), "nlinv_plan_band")
+    return kb.value, lo.value
 
 
 def nlinv_plan_set_variant(plan, n, col_variant, row_variant):

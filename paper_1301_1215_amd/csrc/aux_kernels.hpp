@@ -168,6 +168,113 @@ __global__ __launch_bounds__(kThreads) void k_copy_batch(CopyBatch b) {
         dst[i] = src[i];
 }
 
+// ---------------------------------------------------------------------------
+// the band of the sensitivities a solve keeps (rows and columns
+// [klo, klo + kb) of k-space), against the caller's whole [n][n] planes
+// ---------------------------------------------------------------------------
+
+// Up to kTileBatch frames per launch; entry blockIdx.y covers np[y] planes.
+struct BandBatch {
+    const float2* src[kTileBatch];   // k_band_in: caller planes [np][n][n]
+    const float2* band[kTileBatch];  // k_chat_out: band planes (solve layout)
+    float2* dst[kTileBatch];         // k_band_in: band planes; k_chat_out: caller planes
+    const float2* x0[kTileBatch];    // k_chat_out / k_inert_dist: the start x0 (nullable: 0)
+    const float2* ref[kTileBatch];   // the caller's x_ref (nullable: x_ref = x0)
+    int np[kTileBatch];
+    int plane0[kTileBatch];          // k_inert_dist: class plane of the entry's first plane
+    int frame[kTileBatch];           // k_chat_out: class frame of the entry
+};
+
+// band of caller planes -> solve layout [kb/tw][kb][tw] per plane
+__global__ __launch_bounds__(kThreads) void k_band_in(BandBatch b, int n, int klo, int kb, int tw) {
+    const float2* src = b.src[blockIdx.y];
+    float2* dst = b.dst[blockIdx.y];
+    const long long kk = (long long)kb * kb, tot = b.np[blockIdx.y] * kk;
+    for (long long g = (long long)blockIdx.x * kThreads + threadIdx.x; g < tot;
+         g += (long long)gridDim.x * kThreads) {
+        const long long pl = g / kk, e = g % kk;
+        const int r = (int)(e / kb), c = (int)(e % kb);
+        dst[pl * kk + ((long long)(c / tw) * kb + r) * tw + (c % tw)] =
+            src[pl * (long long)n * n + (long long)(klo + r) * n + klo + c];
+    }
+}
+
+// The caller's planes of the result: the band from the solve layout, the
+// rest x_ref + theta (x0 - x_ref) (x_ref = x0 when ref is null, x0 = 0 when
+// x0 is null); theta = inert[frame][1].  x0 or ref may alias dst (each
+// element is read before it is written, by the same thread).
+__global__ __launch_bounds__(kThreads) void k_chat_out(BandBatch b, const double* inert, int n, int klo, int kb,
+                                                      int tw) {
+    const float2* band = b.band[blockIdx.y];
+    const float2* x0 = b.x0[blockIdx.y];
+    const float2* ref = b.ref[blockIdx.y];
+    float2* dst = b.dst[blockIdx.y];
+    const float th = (float)inert[(long long)b.frame[blockIdx.y] * kInertLen + 1];
+    const long long nn = (long long)n * n, kk = (long long)kb * kb, tot = b.np[blockIdx.y] * nn;
+    for (long long g = (long long)blockIdx.x * kThreads + threadIdx.x; g < tot;
+         g += (long long)gridDim.x * kThreads) {
+        const long long pl = g / nn, e = g % nn;
+        const int r = (int)(e / n) - klo, c = (int)(e % n) - klo;
+        float2 v;
+        if ((unsigned)r < (unsigned)kb && (unsigned)c < (unsigned)kb) {
+            v = band[pl * kk + ((long long)(c / tw) * kb + r) * tw + (c % tw)];
+        } else {
+            const float2 x = x0 ? x0[g] : make_float2(0.f, 0.f);
+            if (ref) {
+                const float2 q = ref[g];
+                v = make_float2(q.x + th * (x.x - q.x), q.y + th * (x.y - q.y));
+            } else {
+                v = x;
+            }
+        }
+        dst[g] = v;
+    }
+}
+
+// partial[plane0 + p] = |x0 - ref|^2 over plane p outside the band (x0 null:
+// 0; ref null: 0), in FP64, one workgroup per plane, a fixed order
+__global__ __launch_bounds__(kThreads) void k_inert_dist(BandBatch b, double* partial, int n, int klo, int kb) {
+    __shared__ double red[kThreads / 64];
+    const int y = blockIdx.y, pl = blockIdx.x;
+    if (pl >= b.np[y]) return;
+    const float2* x0 = b.x0[y];
+    const float2* ref = b.ref[y];
+    const long long nn = (long long)n * n;
+    double acc = 0.0;
+    if (ref) {
+        for (long long e = threadIdx.x; e < nn; e += kThreads) {
+            const int r = (int)(e / n) - klo, c = (int)(e % n) - klo;
+            if ((unsigned)r < (unsigned)kb && (unsigned)c < (unsigned)kb) continue;
+            const float2 x = x0 ? x0[pl * nn + e] : make_float2(0.f, 0.f);
+            const float2 q = ref[pl * nn + e];
+            const double dx = (double)x.x - q.x, dy = (double)x.y - q.y;
+            acc += dx * dx + dy * dy;
+        }
+    }
+    const double t = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[b.plane0[y] + pl] = t;
+}
+
+// Start of a solve: the record of the components outside the band for every
+// frame of a class (D from the per-plane partials in plane order, or 0 when
+// partial is null; theta = 1)
+__global__ __launch_bounds__(kThreads) void k_inert_init(double* inert, const double* partial,
+                                                        const int* frame_plane0, const int* frame_planes,
+                                                        int nplanes, int nframes) {
+    for (int f = blockIdx.x * kThreads + threadIdx.x; f < nframes; f += gridDim.x * kThreads) {
+        double d = 0.0;
+        if (partial) {
+            const int p0 = frame_plane0 ? frame_plane0[f] : 0;
+            const int np = frame_planes ? frame_planes[f] : nplanes;
+            for (int p = 0; p < np; ++p) d += partial[p0 + p];
+        }
+        double* in = inert + (long long)f * kInertLen;
+        in[0] = d;
+        in[1] = 1.0;
+        for (int k = 2; k < kInertLen; ++k) in[k] = 0.0;
+    }
+}
+
 // Bandwidth probe: a streaming copy (the practical HBM ceiling, and the
 // known-size copy that calibrates traffic counters).  Each thread moves
 // kProbeUnroll 16-byte words per round, all loads issued before the stores

@@ -75,6 +75,25 @@ __device__ __forceinline__ double wg_sum(double v, double* red) {
     return t;
 }
 
+// Sensitivity components outside the band of k-space that the solve keeps
+// (where 1/w is below 2^-40) do not reach DF in single precision: there the
+// normal operator is alpha I, and CG moves them along a fixed direction.
+// With e = x_n - x_ref on those components and b = -alpha e, every CG vector
+// there is a real multiple of b: r = rho_k b, p = pi_k b, dx = xi_k b, with
+// rho_0 = pi_0 = 1, xi_0 = 0 and, for the step a_k and direction weight
+// beta_k of the whole vector,
+//   rho_{k+1} = rho_k - a_k alpha pi_k,   xi_{k+1} = xi_k + a_k pi_k,
+//   pi_{k+1} = rho_{k+1} + beta_{k+1} pi_k;
+// they add rho_k^2 |b|^2 to <r, r> and alpha pi_k^2 |b|^2 to Re<p, N p>, and
+// after the Newton step e <- (1 - alpha xi_K) e.  So only |e_0|^2 = D (set
+// when the solve starts) and theta (e_n = theta e_0) are kept per frame; the
+// components themselves are written once, at the end: x_ref + theta e_0.
+// Per-frame record: [0] D, [1] theta, [2] |b|^2 of the current Newton step,
+// then (rho, pi, xi) in two slots by the parity of the CG iteration (a step
+// folded into a pass reads one slot while its first workgroup writes the
+// other).
+constexpr int kInertLen = 9;
+
 // CG and Newton scalars of every frame of a class, all on the device.
 struct Scalars {
     double* rr;        // [2][F] <r, r>, by the parity of the CG iteration it belongs to
@@ -85,6 +104,7 @@ struct Scalars {
     float* s;          // [F] data scale
     float* inv_s;      // [F]
     double* stats;     // [F][stats_len]
+    double* inert;     // [F][kInertLen]: the components outside the band (see above)
     int stats_len;
     int nframes;       // F
 };
@@ -101,8 +121,9 @@ enum ScalarOp : int {
 
 // Where a scalar op is applied: which op, geometry of its partials, indices
 // for the stats.  With `partial2` set the total is
-// sum(partial) + alpha * sum(partial2) (geometry g2; alpha is the Newton
-// step's, the same for every frame of a solve).
+// sum(partial) + alpha * sum(partial2) (geometry g2).  alpha is the Newton
+// step's regularisation weight (the same for every frame of a solve); SC_RR0,
+// SC_GAMMA and SC_RR use it for the components outside the band.
 struct ScalarStep {
     int op;
     SegGeom g;
@@ -121,20 +142,41 @@ struct ScalarStep {
 struct FrameScalars {
     double rr, flags;
     int brk;
+    float a;                     // the CG step of this iteration (0 after a breakdown)
+    double B2, irho, ipi, ixi;   // components outside the band: |b|^2 and this iteration's slot
 };
 // <r, r> of CG iteration `it` of frame f
 __device__ __forceinline__ double* rr_of(const Scalars& sc, int it, int f) {
     return sc.rr + (long long)(it & 1) * sc.nframes + f;
 }
+// slot of (rho, pi, xi) at the start of CG iteration `it`
+__device__ __forceinline__ double* inert_slot(const Scalars& sc, int f, int it) {
+    return sc.inert + (long long)f * kInertLen + 3 + 3 * (it & 1);
+}
 __device__ __forceinline__ FrameScalars load_frame_scalars(const ScalarStep& ss, const Scalars& sc, int f) {
-    return FrameScalars{*rr_of(sc, ss.op == SC_RR0 ? 0 : ss.it, f), sc.stats[(long long)f * sc.stats_len + 1],
-                        sc.brk[f]};
+    const int it = ss.op == SC_RR0 ? 0 : ss.it;
+    const double* in = sc.inert + (long long)f * kInertLen;
+    const double* sl = inert_slot(sc, f, it);
+    return FrameScalars{*rr_of(sc, it, f), sc.stats[(long long)f * sc.stats_len + 1], sc.brk[f], sc.a[f],
+                        in[2], sl[0], sl[1], sl[2]};
 }
 
-// beta of the direction after CG iteration ss.it, from the total t of
-// <r, r> (what SC_RR records)
-__device__ __forceinline__ float cg_beta(const FrameScalars& fs, double t) {
-    return fs.brk ? 0.f : (float)(t / fs.rr);
+// After CG iteration ss.it: the coefficients of r and dx outside the band,
+// and the total <r, r> with their share added to t (the band's total).
+__device__ __forceinline__ double rr_after(const ScalarStep& ss, const FrameScalars& fs, double t, double& rho1,
+                                           double& xi1) {
+    const double a = (double)fs.a;
+    rho1 = fs.irho - a * (double)ss.alpha * fs.ipi;
+    xi1 = fs.ixi + a * fs.ipi;
+    return t + rho1 * rho1 * fs.B2;
+}
+
+// beta of the direction after CG iteration ss.it, from the band's total t of
+// <r, r> (SC_RR records the same total)
+__device__ __forceinline__ float cg_beta(const ScalarStep& ss, const FrameScalars& fs, double t) {
+    double rho1, xi1;
+    const double tt = rr_after(ss, fs, t, rho1, xi1);
+    return fs.brk ? 0.f : (float)(tt / fs.rr);
 }
 
 // The scalar logic for frame f given the total t and the frame's scalars
@@ -155,9 +197,19 @@ __device__ __forceinline__ void scalar_apply(const ScalarStep& ss, const Scalars
         st[2 + ss.step] = sqrt(t);
         if (!isfinite(t)) st[1] = (double)((int)fs.flags | 2);
     } else if (op == SC_RR0) {
-        *rr_of(sc, 0, f) = t;
+        // b = -alpha e outside the band: |b|^2 = alpha^2 theta^2 D
+        double* in = sc.inert + (long long)f * kInertLen;
+        const double al = (double)ss.alpha, th = in[1];
+        const double B2 = al * al * th * th * in[0];
+        in[2] = B2;
+        double* sl = inert_slot(sc, f, 0);
+        sl[0] = 1.0;
+        sl[1] = 1.0;
+        sl[2] = 0.0;
+        *rr_of(sc, 0, f) = t + B2;
         sc.brk[f] = 0;
     } else if (op == SC_GAMMA) {
+        t += (double)ss.alpha * fs.ipi * fs.ipi * fs.B2;   // alpha |p|^2 outside the band
         const double rr = fs.rr;
         if (fs.brk || rr == 0.0 || !(t > 0.0) || !isfinite(rr)) {
             if (!fs.brk) {
@@ -172,14 +224,25 @@ __device__ __forceinline__ void scalar_apply(const ScalarStep& ss, const Scalars
         }
     } else if (op == SC_RR) {
         double* slot = st + 2 + ss.nsteps + ss.step * ss.ncg + ss.it;
+        double rho1, xi1;
+        const double tt = rr_after(ss, fs, t, rho1, xi1);
+        float beta = 0.f;
         if (fs.brk) {
-            sc.beta[f] = 0.f;
             *slot = -1.0;
         } else {
-            if (!isfinite(t)) st[1] = (double)((int)fs.flags | 2);
-            sc.beta[f] = cg_beta(fs, t);
-            *rr_of(sc, ss.it + 1, f) = t;
-            *slot = t;
+            if (!isfinite(tt)) st[1] = (double)((int)fs.flags | 2);
+            beta = (float)(tt / fs.rr);
+            *rr_of(sc, ss.it + 1, f) = tt;
+            *slot = tt;
+        }
+        sc.beta[f] = beta;
+        double* nx = inert_slot(sc, f, ss.it + 1);
+        nx[0] = rho1;
+        nx[1] = rho1 + (double)beta * fs.ipi;
+        nx[2] = xi1;
+        if (ss.it == ss.ncg - 1) {   // end of the Newton step: e <- (1 - alpha xi_K) e
+            double* in = sc.inert + (long long)f * kInertLen;
+            in[1] *= 1.0 - (double)ss.alpha * xi1;
         }
     }
 }

@@ -9,8 +9,15 @@ namespace nlinv {
 
 template <int N, int L>
 static hipError_t col_L(int mode, const ColArgs& a, int nplanes, hipStream_t s) {
+    // the sensitivity-side modes run over the kb columns of the band
+    const bool chat = mode == COL_WINV_IFFT_CROP || mode == COL_PUPD_WINV_IFFT_CROP ||
+                      mode == COL_PAD_FFT_WINV_ADD || mode == COL_PAD_FFT_WINV_CG_UPD;
+    if (chat && (a.kb <= 0 || a.kb > N || a.kb % L != 0 || a.kb % plane_tile<N>() != 0 || a.kb_lo < 0 ||
+                 a.kb_lo + a.kb > N))
+        return hipErrorInvalidValue;
+    const int ncols = chat ? a.kb : N;
     // 1D grid, a multiple of 8 blocks: the kernel deals work items to XCDs
-    const int total = (N / L) * nplanes;
+    const int total = (ncols / L) * nplanes;
     const int extra = mode == COL_PAD_FFT_WINV_CG_UPD ? a.cs_blocks : 0;   // fused coil-sum workgroups
     const dim3 grid(8 * ((total + 7) / 8) + extra), block(pass_threads(N, L));
     const bool half = 2 * a.m == N && 4 * a.lo == N;
@@ -47,6 +54,9 @@ static hipError_t col_L(int mode, const ColArgs& a, int nplanes, hipStream_t s) 
 
 template <int N, int L>
 static hipError_t row_L(int mode, const RowArgs& a, hipStream_t s) {
+    if ((mode == ROW_CACHE || mode == ROW_DERIV || mode == ROW_ADJ) &&
+        (a.kb <= 0 || a.kb > N || a.kb_lo < 0 || a.kb_lo + a.kb > N))
+        return hipErrorInvalidValue;
     const dim3 grid((a.nlines + L - 1) / L), block(pass_threads(N, L));
     const bool half = 2 * a.m == N && 4 * a.lo == N;
 #define NLINV_ROW(MODE)                                                                   \

@@ -121,10 +121,11 @@ int row_kclass(int mode) {
 }
 
 // One shape class: frames of a plan that share n and n_om.  Every CG vector
-// of the class is stored contiguously: chat parts [planes][n*n], rho parts
-// [frames][m*m].
+// of the class is stored contiguously: chat parts [planes][kb*kb] (the band
+// of k-space the solve keeps, column-tiled), rho parts [frames][m*m].
 struct Class {
     int n = 0, m = 0, lo = 0;
+    int kb = 0, kb_lo = 0;       // band [kb_lo, kb_lo + kb)^2 of the sensitivities the solve keeps
     int nframes = 0, nplanes = 0;
     std::vector<int> frames;     // plan frame index of each class frame
     std::vector<int> J, plane0;
@@ -136,14 +137,15 @@ struct Class {
     int* frame_planes = nullptr;
     float2* tw = nullptr;
     float* winv = nullptr;       // [n][n] 1/w, row-major
-    float* winv_t = nullptr;     // the same, column-tiled (solve layout)
+    float* winv_t = nullptr;     // its band [kb][kb], column-tiled (solve layout)
     int tilew = 8;               // tile width of the solve layout
     float2 *x_c = nullptr, *x_r = nullptr, *dx_r = nullptr;   // the chat part of dx goes into x_c
     float2 *r_c = nullptr, *r_r = nullptr, *p_c = nullptr, *p_r = nullptr;
-    float2 *q_c = nullptr, *q_r = nullptr, *xr_c = nullptr, *xr_r = nullptr;
+    float2 *q_c = nullptr, *q_r = nullptr, *xr_c = nullptr, *xr_r = nullptr;   // q_c: grid-sized scratch
     float2* y = nullptr;
     float* P = nullptr;
     float2 *c = nullptr, *T = nullptr, *aux = nullptr;
+    float2* T2 = nullptr;        // band-side intermediate [planes][m][kb] (when kb < n)
     double* partial = nullptr;   // general partials; in CG: |DF p|^2 of the PSF pass
     double* partial2 = nullptr;  // CG: |r|^2 after the update
     double* part_p = nullptr;    // CG: |p|^2 of the direction update
@@ -153,6 +155,7 @@ struct Class {
 
     long long cplane() const { return (long long)n * n; }
     long long rplane() const { return (long long)m * m; }
+    long long kplane() const { return (long long)kb * kb; }
 };
 
 struct GraphKey {
@@ -325,29 +328,61 @@ int drop_graph(nlinv_plan_s* p) {
     return NLINV_OK;
 }
 
+struct Frames {               // which planes / frames a sequence acts on
+    int nplanes, nframes;
+    const int* plane_frame;   // nullable
+    const int* frame_plane0;  // nullable
+    const int* frame_planes;  // nullable
+    int tiled;                // planes in the column-tiled solve layout
+    int kb, kb_lo;            // band of the sensitivity side (the whole grid for the operators)
+};
+
+// the operator entry points: one frame, caller's row-major arrays, whole grid
+Frames single_frame(const Class& C, int J) { return Frames{J, 1, nullptr, nullptr, nullptr, 0, C.n, 0}; }
+// inside a solve: every frame of the class, solve layout, the class's band
+Frames class_frames(const Class& C) {
+    return Frames{C.nplanes, C.nframes, C.plane_frame, C.frame_plane0, C.frame_planes, 1, C.kb, C.kb_lo};
+}
+// band-side intermediate: T itself when the band is the whole grid (the row
+// passes then work in place), else the separate [planes][m][kb] buffer
+float2* band_T(const Class& C, const Frames& fr) { return fr.kb < C.n ? C.T2 : C.T; }
+
 // ---- launch helpers -----------------------------------------------------------
 
-ColArgs col_args(const nlinv_plan_s* p, const Class& C, int tiled) {
+ColArgs col_args(const nlinv_plan_s* p, const Class& C, const Frames& fr) {
     ColArgs a{};
-    a.tiled = tiled;
+    a.tiled = fr.tiled;
     a.m = C.m;
     a.lo = C.lo;
+    a.kb = fr.kb;
+    a.kb_lo = fr.kb_lo;
     a.rs = (float)(1.0 / std::sqrt((double)C.n));
     a.tw2 = C.tw;
-    a.winv = tiled ? C.winv_t : C.winv;
+    a.winv = fr.tiled ? C.winv_t : C.winv;
     a.fold.op = SC_NONE;
     (void)p;
     return a;
 }
 
-RowArgs row_args(const Class& C) {
+RowArgs row_args(const Class& C, const Frames& fr) {
     RowArgs a{};
     a.m = C.m;
     a.lo = C.lo;
+    a.kb = fr.kb;
+    a.kb_lo = fr.kb_lo;
     a.rs = (float)(1.0 / std::sqrt((double)C.n));
     a.tw2 = C.tw;
     a.fold.op = SC_NONE;
     return a;
+}
+
+bool col_mode_on_band(int mode) {
+    return mode == COL_WINV_IFFT_CROP || mode == COL_PUPD_WINV_IFFT_CROP || mode == COL_PAD_FFT_WINV_ADD ||
+           mode == COL_PAD_FFT_WINV_CG_UPD;
+}
+// column tiles per plane of a launch of `mode` with its class variant
+int col_tiles(const Class& C, const Frames& fr, int mode) {
+    return (col_mode_on_band(mode) ? fr.kb : C.n) / kColL[C.colv[mode]];
 }
 
 // Every operand a pass mode reads or writes unconditionally must be set: a
@@ -467,18 +502,6 @@ VecPtrs vptrs(float2* c0, float2* r0, float2* c1 = nullptr, float2* r1 = nullptr
 
 
 
-struct Frames {               // which planes / frames a sequence acts on
-    int nplanes, nframes;
-    const int* plane_frame;   // nullable
-    const int* frame_plane0;  // nullable
-    const int* frame_planes;  // nullable
-    int tiled;                // n x n planes in the column-tiled solve layout
-};
-
-Frames single_frame(int J) { return Frames{J, 1, nullptr, nullptr, nullptr, 0}; }
-Frames class_frames(const Class& C) {
-    return Frames{C.nplanes, C.nframes, C.plane_frame, C.frame_plane0, C.frame_planes, 1};
-}
 
 
 // one workgroup per (frame, segment of up to kCoilSeg Omega pixels)
@@ -511,17 +534,17 @@ CoilSumArgs coil_sum_args(const Class& C, const Frames& fr, float2* out, const f
 // and its last CG scalar step folded into the two passes)
 int seq_coil_maps(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2* chat, float2* c_out,
                   hipStream_t s, bool rho_update = false, const ScalarStep* fold = nullptr) {
-    ColArgs a = col_args(p, C, fr.tiled);
+    ColArgs a = col_args(p, C, fr);
     a.in = chat;
-    a.out = C.T;
+    a.out = band_T(C, fr);
     a.plane_frame = fr.plane_frame;
     if (rho_update) {
         a.rho_acc = C.x_r;
         a.rho_step = C.dx_r;
     }
     CHK(run_col(p, C, COL_WINV_IFFT_CROP, a, fr.nplanes, s));
-    RowArgs r = row_args(C);
-    r.in = C.T;
+    RowArgs r = row_args(C, fr);
+    r.in = band_T(C, fr);
     r.c_out = c_out;
     r.plane_frame = fr.plane_frame;
     r.nlines = fr.nplanes * C.m;
@@ -535,14 +558,14 @@ int seq_coil_maps(nlinv_plan_s* p, const Class& C, const Frames& fr, const float
 // out = P . DFT(E(rho . c))
 int seq_forward(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2* rho, const float2* c,
                 const float* P, long long p_stride, float2* out, hipStream_t s) {
-    RowArgs r = row_args(C);
+    RowArgs r = row_args(C, fr);
     r.c = c;
     r.rho = rho;
     r.out = C.T;
     r.plane_frame = fr.plane_frame;
     r.nlines = fr.nplanes * C.m;
     CHK(run_row(p, C, ROW_FWD, r, s));
-    ColArgs a = col_args(p, C, fr.tiled);
+    ColArgs a = col_args(p, C, fr);
     a.in = C.T;
     a.out = out;
     a.P = P;
@@ -556,14 +579,14 @@ int seq_forward(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2*
 // |r0|^2 partials into `partial`, `g` receives their geometry.
 int seq_residual_head(nlinv_plan_s* p, const Class& C, const Frames& fr, double* partial, SegGeom* g,
                       hipStream_t s) {
-    RowArgs r = row_args(C);
+    RowArgs r = row_args(C, fr);
     r.c = C.c;
     r.rho = C.x_r;
     r.out = C.T;
     r.plane_frame = fr.plane_frame;
     r.nlines = fr.nplanes * C.m;
     CHK(run_row(p, C, ROW_FWD, r, s));
-    ColArgs a = col_args(p, C, fr.tiled);
+    ColArgs a = col_args(p, C, fr);
     a.in = C.T;
     a.out = C.T;
     a.P = C.P;
@@ -574,7 +597,7 @@ int seq_residual_head(nlinv_plan_s* p, const Class& C, const Frames& fr, double*
     a.c1 = 1.f;
     a.partial = partial;
     *g = C.geom;
-    g->cseg = C.n / kColL[C.colv[COL_RESID_P_IFFT]];
+    g->cseg = col_tiles(C, fr, COL_RESID_P_IFFT);
     g->rseg = 0;
     return run_col(p, C, COL_RESID_P_IFFT, a, fr.nplanes, s);
 }
@@ -582,13 +605,13 @@ int seq_residual_head(nlinv_plan_s* p, const Class& C, const Frames& fr, double*
 // T = row-DFT(E(drho . c + rho . E^H W^{-1} dchat))   (first half of DF)
 int seq_deriv_head(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2* rho, const float2* c,
                    const float2* drho, const float2* dchat, hipStream_t s) {
-    ColArgs a = col_args(p, C, fr.tiled);
+    ColArgs a = col_args(p, C, fr);
     a.in = dchat;
-    a.out = C.T;
+    a.out = band_T(C, fr);
     a.plane_frame = fr.plane_frame;
     CHK(run_col(p, C, COL_WINV_IFFT_CROP, a, fr.nplanes, s));
-    RowArgs r = row_args(C);
-    r.in = C.T;
+    RowArgs r = row_args(C, fr);
+    r.in = band_T(C, fr);
     r.out = C.T;
     r.c = c;
     r.rho = rho;
@@ -607,9 +630,9 @@ int seq_adjoint_tail(nlinv_plan_s* p, const Class& C, const Frames& fr, const fl
                      const float2* add2c, const float2* add2r, const float* s1, const float* s2,
                      float c1, float c2, hipStream_t s, double* partial = nullptr, SegGeom* g = nullptr,
                      const ScalarStep* fold = nullptr) {
-    RowArgs r = row_args(C);
+    RowArgs r = row_args(C, fr);
     r.in = C.T;
-    r.out = C.T;
+    r.out = band_T(C, fr);
     r.c = c;
     r.rho = rho;
     r.aux = C.aux;
@@ -620,8 +643,8 @@ int seq_adjoint_tail(nlinv_plan_s* p, const Class& C, const Frames& fr, const fl
     r.plane_frame = fr.plane_frame;
     r.nlines = fr.nplanes * C.m;
     CHK(run_row(p, C, ROW_ADJ, r, s));
-    ColArgs a = col_args(p, C, fr.tiled);
-    a.in = C.T;
+    ColArgs a = col_args(p, C, fr);
+    a.in = band_T(C, fr);
     a.out = dchat_out;
     a.plane_frame = fr.plane_frame;
     a.add1 = add1c;
@@ -632,7 +655,7 @@ int seq_adjoint_tail(nlinv_plan_s* p, const Class& C, const Frames& fr, const fl
     a.c2 = c2;
     a.partial = partial;
     CHK(run_col(p, C, COL_PAD_FFT_WINV_ADD, a, fr.nplanes, s));
-    const int nt = C.n / kColL[C.colv[COL_PAD_FFT_WINV_ADD]];
+    const int nt = col_tiles(C, fr, COL_PAD_FFT_WINV_ADD);
     CoilSumArgs cs = coil_sum_args(C, fr, drho_out, add1r, add2r, s1, s2, c1, c2, partial,
                                    (long long)fr.nplanes * nt);
     cs.self_dot = partial != nullptr;
@@ -658,7 +681,7 @@ int seq_adjoint_tail(nlinv_plan_s* p, const Class& C, const Frames& fr, const fl
 // seq_adjoint_tail reports them).
 SegGeom rhs_geom(const Class& C) {
     SegGeom g = C.geom;
-    g.cseg = C.n / kColL[C.colv[COL_PAD_FFT_WINV_ADD]];
+    g.cseg = col_tiles(C, class_frames(C), COL_PAD_FFT_WINV_ADD);
     g.rseg = (int)((C.rplane() + kCoilSeg - 1) / kCoilSeg);
     return g;
 }
@@ -669,7 +692,7 @@ SegGeom cg_rr_geom(const Class& C) {
     SegGeom g = C.geom;
     const int L = kColL[C.colv[COL_PAD_FFT_WINV_CG_UPD]];
     const int wg = pass_threads(C.n, L);
-    g.cseg = C.n / L;
+    g.cseg = col_tiles(C, class_frames(C), COL_PAD_FFT_WINV_CG_UPD);
     g.rseg = (int)((C.rplane() + wg - 1) / wg);
     return g;
 }
@@ -679,9 +702,10 @@ SegGeom cg_rr_geom(const Class& C) {
 int seq_cg_iteration(nlinv_plan_s* p, Class& C, int step, int it, int nsteps, int ncg, float alpha,
                      hipStream_t s) {
     const Frames fr = class_frames(C);
-    ColArgs a = col_args(p, C, fr.tiled);
+    float2* TB = band_T(C, fr);
+    ColArgs a = col_args(p, C, fr);
     a.in = C.p_c;
-    a.out = C.T;
+    a.out = TB;
     a.plane_frame = fr.plane_frame;
     a.r_in = C.r_c;
     a.p_out = C.p_c;
@@ -693,10 +717,11 @@ int seq_cg_iteration(nlinv_plan_s* p, Class& C, int step, int it, int nsteps, in
     // it == 0: <b, b> of the right-hand side recorded by it
     a.fold = it > 0 ? scalar_step(C, SC_RR, cg_rr_geom(C), 0.f, step, it - 1, nsteps, ncg, C.partial2)
                     : scalar_step(C, SC_RR0, rhs_geom(C), 0.f, step, 0, nsteps, ncg, C.partial);
+    a.fold.alpha = alpha;
     a.sc = C.sc;
     CHK(run_col(p, C, COL_PUPD_WINV_IFFT_CROP, a, fr.nplanes, s));
-    RowArgs r = row_args(C);
-    r.in = C.T;
+    RowArgs r = row_args(C, fr);
+    r.in = TB;
     r.out = C.T;
     r.c = C.c;
     r.rho = C.x_r;
@@ -704,7 +729,7 @@ int seq_cg_iteration(nlinv_plan_s* p, Class& C, int step, int it, int nsteps, in
     r.plane_frame = fr.plane_frame;
     r.nlines = fr.nplanes * C.m;
     CHK(run_row(p, C, ROW_DERIV, r, s));
-    ColArgs b = col_args(p, C, fr.tiled);
+    ColArgs b = col_args(p, C, fr);
     b.in = C.T;
     b.out = C.T;
     b.P = C.P;
@@ -714,8 +739,8 @@ int seq_cg_iteration(nlinv_plan_s* p, Class& C, int step, int it, int nsteps, in
     CHK(run_col(p, C, COL_PAD_FFT_P2_IFFT, b, fr.nplanes, s));
     // a = <r,r> / (|DF p|^2 + alpha |p|^2) per frame, folded into the adjoint row pass
     {
-        const int tp = C.n / kColL[C.colv[COL_PUPD_WINV_IFFT_CROP]];
-        const int tg = C.n / kColL[C.colv[COL_PAD_FFT_P2_IFFT]];
+        const int tp = col_tiles(C, fr, COL_PUPD_WINV_IFFT_CROP);
+        const int tg = col_tiles(C, fr, COL_PAD_FFT_P2_IFFT);
         ScalarStep ss = scalar_step(C, SC_GAMMA, C.geom, 0.f, step, it, nsteps, ncg, C.partial);
         ss.g.cseg = tg;
         ss.g.rseg = 0;
@@ -729,10 +754,12 @@ int seq_cg_iteration(nlinv_plan_s* p, Class& C, int step, int it, int nsteps, in
     }
     r.aux = C.aux;
     r.drho = nullptr;
+    r.in = C.T;
+    r.out = TB;
     CHK(run_row(p, C, ROW_ADJ, r, s));
-    const int tu = C.n / kColL[C.colv[COL_PAD_FFT_WINV_CG_UPD]];
-    ColArgs e = col_args(p, C, fr.tiled);
-    e.in = C.T;
+    const int tu = col_tiles(C, fr, COL_PAD_FFT_WINV_CG_UPD);
+    ColArgs e = col_args(p, C, fr);
+    e.in = TB;
     e.out = C.r_c;
     // the step's chat part goes straight into x: x's chat part is not read
     // during CG (the linearisation uses the cached sensitivities c, and the
@@ -771,7 +798,7 @@ int seq_normal(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2* 
                const float2* drho, const float2* dchat, float2* drho_out, float2* dchat_out,
                hipStream_t s) {
     CHK(seq_deriv_head(p, C, fr, rho, c, drho, dchat, s));
-    ColArgs a = col_args(p, C, fr.tiled);
+    ColArgs a = col_args(p, C, fr);
     a.in = C.T;
     a.out = C.T;
     a.P = P;
@@ -802,7 +829,8 @@ int enqueue_class_newton(nlinv_plan_s* p, Class& C, const nlinv_irgnm_params& pr
             // linearisation cache c at x_n (with the previous step's rho
             // update and its last CG step's stats folded in)
             if (step > 0 && K > 0) {
-                const ScalarStep last = scalar_step(C, SC_RR, cg_rr_geom(C), 0.f, step - 1, K - 1, N, K, C.partial2);
+                ScalarStep last = scalar_step(C, SC_RR, cg_rr_geom(C), 0.f, step - 1, K - 1, N, K, C.partial2);
+                last.alpha = alpha_of(prm, step - 1);
                 CHK(seq_coil_maps(p, C, fr, C.x_c, C.c, s, true, &last));
             } else {
                 CHK(seq_coil_maps(p, C, fr, C.x_c, C.c, s));
@@ -828,7 +856,8 @@ int enqueue_class_newton(nlinv_plan_s* p, Class& C, const nlinv_irgnm_params& pr
     // sensitivities of the final x (for the image), with the last step's
     // rho update and last CG stats
     if (N > 0 && K > 0) {
-        const ScalarStep last = scalar_step(C, SC_RR, cg_rr_geom(C), 0.f, N - 1, K - 1, N, K, C.partial2);
+        ScalarStep last = scalar_step(C, SC_RR, cg_rr_geom(C), 0.f, N - 1, K - 1, N, K, C.partial2);
+        last.alpha = alpha_of(prm, N - 1);
         return seq_coil_maps(p, C, class_frames(C), C.x_c, C.c, s, true, &last);
     }
     return seq_coil_maps(p, C, class_frames(C), C.x_c, C.c, s);
@@ -901,8 +930,59 @@ int check_params(const nlinv_irgnm_params* prm) {
 
 bool aligned(const void* q) { return ((uintptr_t)q & 15) == 0; }
 
-// Per-frame set-up: copy y and P into the class workspace, data scale, x0, x_ref.
-int setup_frames(nlinv_plan_s* p, const nlinv_frame* frames, const nlinv_irgnm_params& prm, hipStream_t s) {
+// Where a warm start reads x0 (data units): the frame's own rho / chat
+// arrays unless given here (a temporal series starts frame t from frame
+// t - 1's results).
+struct FrameSrc {
+    const float2* rho0;
+    const float2* chat0;
+};
+
+const float2* chat0_of(const nlinv_frame& F, const FrameSrc* src, int f) {
+    return src && src[f].chat0 ? src[f].chat0 : (const float2*)F.chat;
+}
+const float2* rho0_of(const nlinv_frame& F, const FrameSrc* src, int f) {
+    return src && src[f].rho0 ? src[f].rho0 : (const float2*)F.rho;
+}
+
+// Frames of class C in runs of at most kTileBatch: fn(first class frame, count)
+template <class Fn>
+int for_frame_batches(const Class& C, Fn&& fn) {
+    for (int f0 = 0; f0 < C.nframes; f0 += kTileBatch) CHK(fn(f0, std::min(kTileBatch, C.nframes - f0)));
+    return NLINV_OK;
+}
+
+// the band of caller planes into the solve layout, for every frame of C
+// whose source is non-null
+int band_in(nlinv_plan_s* p, const Class& C, const std::vector<const float2*>& src, float2* dst, hipStream_t s) {
+    return for_frame_batches(C, [&](int f0, int cnt) -> int {
+        BandBatch b{};
+        int k = 0, maxp = 1;
+        for (int i = 0; i < cnt; ++i) {
+            const int lf = f0 + i;
+            if (!src[lf]) continue;
+            b.src[k] = src[lf];
+            b.dst[k] = dst + (size_t)C.plane0[lf] * C.kplane();
+            b.np[k] = C.J[lf];
+            maxp = std::max(maxp, C.J[lf]);
+            ++k;
+        }
+        if (k == 0) return NLINV_OK;
+        const int slot = tbegin(p, KC_VEC_OTHER, s);
+        hipLaunchKernelGGL(k_band_in, dim3(grid_for((long long)maxp * C.kplane()), k), dim3(kThreads), 0, s, b, C.n,
+                           C.kb_lo, C.kb, C.tilew);
+        hipError_t e = hipGetLastError();
+        tend(p, slot, s);
+        HIPCHK(e);
+        return NLINV_OK;
+    });
+}
+
+// Per-frame set-up: copy y and P into the class workspace, data scale, x0,
+// x_ref (the band of the sensitivities), the record of the components
+// outside the band.
+int setup_frames(nlinv_plan_s* p, const nlinv_frame* frames, const nlinv_irgnm_params& prm, hipStream_t s,
+                 const FrameSrc* src) {
     for (Class& C : p->classes) {
         {   // y and P of every frame into the solve layout, one launch each
             std::vector<const float2*> ys;
@@ -924,78 +1004,91 @@ int setup_frames(nlinv_plan_s* p, const nlinv_frame* frames, const nlinv_irgnm_p
         }
         CHK(run_vec<VEC_DOT>(p, C.geomC, vptrs(C.y, nullptr, C.y, nullptr), C.partial, s));
         CHK(run_scalar(p, C, SC_YNORM, C.geomC, prm.scale_norm, 0, s));
-        // x0: warm start copies the caller's x (rho scaled below); else rho = 1 (scaled units), chat = 0
+        // x0: warm start takes the caller's x (rho scaled below); else rho = 1 (scaled units), chat = 0
         const bool warm = (prm.flags & NLINV_WARM_START) != 0;
         if (warm) {
+            std::vector<const float2*> c0(C.nframes);
             for (int lf = 0; lf < C.nframes; ++lf) {
                 const nlinv_frame& F = frames[C.frames[lf]];
-                float2* xc = C.x_c + (size_t)C.plane0[lf] * C.cplane();
-                float2* xr = C.x_r + (size_t)lf * C.rplane();
-                CHK(tile_copy(p, C, (const float2*)F.chat, xc, C.J[lf], 1, s));
-                HIPCHK(hipMemcpyAsync(xr, F.rho, C.rplane() * sizeof(float2), hipMemcpyDeviceToDevice, s));
+                c0[lf] = chat0_of(F, src, C.frames[lf]);
+                HIPCHK(hipMemcpyAsync(C.x_r + (size_t)lf * C.rplane(), rho0_of(F, src, C.frames[lf]),
+                                      C.rplane() * sizeof(float2), hipMemcpyDeviceToDevice, s));
             }
-        } else {   // the chat parts of all frames are contiguous: one fill
-            HIPCHK(hipMemsetAsync(C.x_c, 0, (size_t)C.nplanes * C.cplane() * sizeof(float2), s));
-        }
-        if (warm) {
+            CHK(band_in(p, C, c0, C.x_c, s));
             hipLaunchKernelGGL(k_scale_rho, dim3(grid_for((long long)C.nframes * C.rplane())), dim3(kThreads), 0, s,
                                C.x_r, (const float2*)C.x_r, (const float*)C.sc.s, C.nframes, (int)C.rplane(), 0);
-        } else {
+        } else {   // the chat parts of all frames are contiguous: one fill
+            HIPCHK(hipMemsetAsync(C.x_c, 0, (size_t)C.nplanes * C.kplane() * sizeof(float2), s));
             hipLaunchKernelGGL(k_fill, dim3(grid_for((long long)C.nframes * C.rplane())), dim3(kThreads), 0, s,
                                C.x_r, (long long)C.nframes * C.rplane(), make_float2(1.f, 0.f));
         }
         HIPCHK(hipGetLastError());
-        bool any_chat_ref = false;
-        for (int lf = 0; lf < C.nframes; ++lf) any_chat_ref = any_chat_ref || frames[C.frames[lf]].chat_ref;
-        C.chat_ref_zero = !warm && !any_chat_ref;   // x_ref = x0, whose chat part is 0
+        bool any_ref = false;
+        for (int lf = 0; lf < C.nframes; ++lf) any_ref = any_ref || frames[C.frames[lf]].chat_ref;
+        C.chat_ref_zero = !warm && !any_ref;   // x_ref = x0, whose chat part is 0
         // x_ref (a zero chat part is not stored: the passes are not given it)
-        bool no_ref = true;
-        for (int lf = 0; lf < C.nframes; ++lf) no_ref = no_ref && !frames[C.frames[lf]].rho_ref;
-        if (no_ref) {   // x_ref = x0 for every frame: one copy of each contiguous part
+        if (!any_ref) {   // x_ref = x0 for every frame: one copy of each contiguous part
             HIPCHK(hipMemcpyAsync(C.xr_r, C.x_r, (size_t)C.nframes * C.rplane() * sizeof(float2),
                                   hipMemcpyDeviceToDevice, s));
             if (!C.chat_ref_zero)
-                HIPCHK(hipMemcpyAsync(C.xr_c, C.x_c, (size_t)C.nplanes * C.cplane() * sizeof(float2),
+                HIPCHK(hipMemcpyAsync(C.xr_c, C.x_c, (size_t)C.nplanes * C.kplane() * sizeof(float2),
                                       hipMemcpyDeviceToDevice, s));
-        }
-        for (int lf = 0; lf < C.nframes && !no_ref; ++lf) {
-            const nlinv_frame& F = frames[C.frames[lf]];
-            const size_t cb = (size_t)C.J[lf] * C.cplane() * sizeof(float2);
-            float2* rc = C.xr_c + (size_t)C.plane0[lf] * C.cplane();
-            float2* rr = C.xr_r + (size_t)lf * C.rplane();
-            if (F.rho_ref && F.chat_ref) {
-                CHK(tile_copy(p, C, (const float2*)F.chat_ref, rc, C.J[lf], 1, s));
-                HIPCHK(hipMemcpyAsync(rr, F.rho_ref, C.rplane() * sizeof(float2), hipMemcpyDeviceToDevice, s));
-            } else {
-                if (!C.chat_ref_zero)
-                    HIPCHK(hipMemcpyAsync(rc, C.x_c + (size_t)C.plane0[lf] * C.cplane(), cb, hipMemcpyDeviceToDevice,
-                                          s));
-                HIPCHK(hipMemcpyAsync(rr, C.x_r + (size_t)lf * C.rplane(), C.rplane() * sizeof(float2),
-                                      hipMemcpyDeviceToDevice, s));
-            }
-        }
-        // a caller's x_ref is in data units: scale its rho part (x0-derived refs already are scaled)
-        bool any_ref = false;
-        for (int lf = 0; lf < C.nframes; ++lf) {
-            const nlinv_frame& F = frames[C.frames[lf]];
-            if (F.rho_ref && F.chat_ref) any_ref = true;
-        }
-        if (any_ref) {
+        } else {
+            std::vector<const float2*> cr(C.nframes, nullptr);
             for (int lf = 0; lf < C.nframes; ++lf) {
                 const nlinv_frame& F = frames[C.frames[lf]];
-                if (!(F.rho_ref && F.chat_ref)) continue;
                 float2* rr = C.xr_r + (size_t)lf * C.rplane();
-                hipLaunchKernelGGL(k_scale_rho, dim3(grid_for(C.rplane())), dim3(kThreads), 0, s, rr,
-                                   (const float2*)rr, (const float*)(C.sc.s + lf), 1, (int)C.rplane(), 0);
-                HIPCHK(hipGetLastError());
+                if (F.rho_ref && F.chat_ref) {
+                    cr[lf] = (const float2*)F.chat_ref;
+                    HIPCHK(hipMemcpyAsync(rr, F.rho_ref, C.rplane() * sizeof(float2), hipMemcpyDeviceToDevice, s));
+                    // a caller's x_ref is in data units: scale its rho part
+                    hipLaunchKernelGGL(k_scale_rho, dim3(grid_for(C.rplane())), dim3(kThreads), 0, s, rr,
+                                       (const float2*)rr, (const float*)(C.sc.s + lf), 1, (int)C.rplane(), 0);
+                    HIPCHK(hipGetLastError());
+                } else {
+                    HIPCHK(hipMemcpyAsync(C.xr_c + (size_t)C.plane0[lf] * C.kplane(),
+                                          C.x_c + (size_t)C.plane0[lf] * C.kplane(),
+                                          (size_t)C.J[lf] * C.kplane() * sizeof(float2), hipMemcpyDeviceToDevice, s));
+                    HIPCHK(hipMemcpyAsync(rr, C.x_r + (size_t)lf * C.rplane(), C.rplane() * sizeof(float2),
+                                          hipMemcpyDeviceToDevice, s));
+                }
             }
+            CHK(band_in(p, C, cr, C.xr_c, s));
         }
+        // components outside the band: D = |x0 - x_ref|^2 there (nonzero only
+        // for a caller's x_ref), theta = 1
+        const double* dpart = nullptr;
+        if (any_ref && C.kb < C.n) {
+            CHK(for_frame_batches(C, [&](int f0, int cnt) -> int {
+                BandBatch b{};
+                int maxp = 1;
+                for (int i = 0; i < cnt; ++i) {
+                    const int lf = f0 + i;
+                    const nlinv_frame& F = frames[C.frames[lf]];
+                    b.x0[i] = warm ? chat0_of(F, src, C.frames[lf]) : nullptr;
+                    b.ref[i] = (F.rho_ref && F.chat_ref) ? (const float2*)F.chat_ref : nullptr;
+                    b.np[i] = C.J[lf];
+                    b.plane0[i] = C.plane0[lf];
+                    maxp = std::max(maxp, C.J[lf]);
+                }
+                hipLaunchKernelGGL(k_inert_dist, dim3(maxp, cnt), dim3(kThreads), 0, s, b, C.partial, C.n, C.kb_lo,
+                                   C.kb);
+                HIPCHK(hipGetLastError());
+                return NLINV_OK;
+            }));
+            dpart = C.partial;
+        }
+        hipLaunchKernelGGL(k_inert_init, dim3(grid_for(C.nframes)), dim3(kThreads), 0, s, C.sc.inert, dpart,
+                           (const int*)C.frame_plane0, (const int*)C.frame_planes, C.nplanes, C.nframes);
+        HIPCHK(hipGetLastError());
     }
     return NLINV_OK;
 }
 
-int finish_frames(nlinv_plan_s* p, const nlinv_frame* frames, const nlinv_irgnm_params& prm, hipStream_t s) {
+int finish_frames(nlinv_plan_s* p, const nlinv_frame* frames, const nlinv_irgnm_params& prm, hipStream_t s,
+                  const FrameSrc* src) {
     const int stats_len = 2 + prm.newton_steps + prm.newton_steps * prm.cg_iters;
+    const bool warm = (prm.flags & NLINV_WARM_START) != 0;
     for (Class& C : p->classes) {
         // image (uses rho in scaled units times 1/s) into aux, rho / s into dx_r
         const int slot = tbegin(p, KC_IMAGE, s);
@@ -1007,23 +1100,36 @@ int finish_frames(nlinv_plan_s* p, const nlinv_frame* frames, const nlinv_irgnm_
         hipLaunchKernelGGL(k_scale_rho, dim3(grid_for((long long)C.nframes * C.rplane())), dim3(kThreads), 0, s,
                            C.dx_r, (const float2*)C.x_r, (const float*)C.sc.inv_s, C.nframes, (int)C.rplane(), 1);
         HIPCHK(hipGetLastError());
-        {   // chat of every frame back to the caller's row-major layout, one launch
-            std::vector<const float2*> cs;
-            std::vector<float2*> cd;
-            std::vector<int> nj;
-            for (int lf = 0; lf < C.nframes; ++lf) {
-                cs.push_back(C.x_c + (size_t)C.plane0[lf] * C.cplane());
-                cd.push_back((float2*)frames[C.frames[lf]].chat);
-                nj.push_back(C.J[lf]);
+        // chat of every frame into the caller's planes: the band from the
+        // solve layout, the rest x_ref + theta (x0 - x_ref)
+        CHK(for_frame_batches(C, [&](int f0, int cnt) -> int {
+            BandBatch b{};
+            int maxp = 1;
+            for (int i = 0; i < cnt; ++i) {
+                const int lf = f0 + i;
+                const nlinv_frame& F = frames[C.frames[lf]];
+                b.band[i] = C.x_c + (size_t)C.plane0[lf] * C.kplane();
+                b.x0[i] = warm ? chat0_of(F, src, C.frames[lf]) : nullptr;
+                b.ref[i] = (F.rho_ref && F.chat_ref) ? (const float2*)F.chat_ref : nullptr;
+                b.dst[i] = (float2*)F.chat;
+                b.np[i] = C.J[lf];
+                b.frame[i] = lf;
+                maxp = std::max(maxp, C.J[lf]);
             }
-            CHK(tile_copy_batch(p, C, cs, cd, nj, 0, s));
-        }
+            const int sl = tbegin(p, KC_VEC_OTHER, s);
+            hipLaunchKernelGGL(k_chat_out, dim3(grid_for((long long)maxp * C.cplane()), cnt), dim3(kThreads), 0, s, b,
+                               (const double*)C.sc.inert, C.n, C.kb_lo, C.kb, C.tilew);
+            hipError_t e = hipGetLastError();
+            tend(p, sl, s);
+            HIPCHK(e);
+            return NLINV_OK;
+        }));
         // rho, image and stats of every frame: one launch per kCopyBatch copies
         CopyBatch b{};
         int cnt = 0;
         long long maxn = 0;
-        auto add = [&](const void* src, void* dst, long long words) {
-            b.src[cnt] = (const uint64_t*)src;
+        auto add = [&](const void* src_, void* dst, long long words) {
+            b.src[cnt] = (const uint64_t*)src_;
             b.dst[cnt] = (uint64_t*)dst;
             b.n[cnt] = words;
             maxn = std::max(maxn, words);
@@ -1112,10 +1218,11 @@ int run_newton(nlinv_plan_s* p, const nlinv_irgnm_params& prm, hipStream_t s) {
     return NLINV_OK;
 }
 
-int solve_all(nlinv_plan_s* p, const nlinv_frame* frames, const nlinv_irgnm_params& prm, hipStream_t s) {
-    CHK(setup_frames(p, frames, prm, s));
+int solve_all(nlinv_plan_s* p, const nlinv_frame* frames, const nlinv_irgnm_params& prm, hipStream_t s,
+              const FrameSrc* src = nullptr) {
+    CHK(setup_frames(p, frames, prm, s, src));
     CHK(run_newton(p, prm, s));
-    return finish_frames(p, frames, prm, s);
+    return finish_frames(p, frames, prm, s, src);
 }
 
 // ---- twiddles -------------------------------------------------------------------
@@ -1134,9 +1241,11 @@ int make_twiddles(nlinv_plan_s* p, Class& C) {
     return NLINV_OK;
 }
 
-int default_col_variant(int n) {
+// a column variant valid for the grid and for `ncols` columns per plane
+bool col_ok_cols(int n, int ncols, int v) { return col_ok(n, v) && ncols % kColL[v] == 0; }
+int default_col_variant(int n, int ncols) {
     for (int v = 0; v < kNumColVariants; ++v)
-        if (col_ok(n, v)) return v;
+        if (col_ok_cols(n, ncols, v)) return v;
     return -1;
 }
 int default_row_variant(int n) {
@@ -1156,21 +1265,45 @@ int make_weight_table(nlinv_plan_s* p, Class& C) {
         }
     CHK(dalloc(p, &C.winv, h.size()));
     HIPCHK(hipMemcpy(C.winv, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
-    std::vector<float> t(h.size());
-    for (int r = 0; r < C.n; ++r)
-        for (int c = 0; c < C.n; ++c)
-            t[((size_t)(c / C.tilew) * C.n + r) * C.tilew + (c % C.tilew)] = h[(size_t)r * C.n + c];
+    // the band [kb_lo, kb_lo + kb)^2 in the solve layout [kb/tw][kb][tw]
+    std::vector<float> t((size_t)C.kb * C.kb);
+    for (int r = 0; r < C.kb; ++r)
+        for (int c = 0; c < C.kb; ++c)
+            t[((size_t)(c / C.tilew) * C.kb + r) * C.tilew + (c % C.tilew)] =
+                h[(size_t)(C.kb_lo + r) * C.n + C.kb_lo + c];
     CHK(dalloc(p, &C.winv_t, t.size()));
     HIPCHK(hipMemcpy(C.winv_t, t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice));
     return NLINV_OK;
 }
 
+// Half-width h of the band of k-space the solve keeps of the sensitivities:
+// outside [n/2 - h, n/2 + h)^2 every weight has 1/w <= 2^-40 (there
+// |k|^2 >= (h/n)^2 and (1 + a (h/n)^2)^(l/2) >= 2^40), so those components
+// of chat reach c = DTFT^{-1}(chat / w) only below 2^-40 of their size, far
+// under single-precision rounding.  h is a multiple of 16 (the band side a
+// multiple of 32: whole column tiles of every pass variant); h = n/2 (the
+// whole grid) when the weight is too flat for a narrower band, or with
+// NLINV_FULL_CHAT=1 set.
+int band_half(int n, double a, double l) {
+    const char* full = std::getenv("NLINV_FULL_CHAT");
+    if ((full && full[0] == '1') || !(a > 0.0) || !(l > 0.0)) return n / 2;
+    const double k = std::sqrt((std::pow(2.0, 80.0 / l) - 1.0) / a);   // |k| where 1/w = 2^-40
+    int h = (int)std::ceil(k * n - 1e-9);
+    h = (h + 15) / 16 * 16;
+    return 2 * h >= n ? n / 2 : h;
+}
+
 int build_class(nlinv_plan_s* p, Class& C) {
     C.tilew = plane_tile_width(C.n);
+    {
+        const int h = band_half(C.n, (double)p->sob_a, 2.0 * (double)p->sob_hl);
+        C.kb = 2 * h;
+        C.kb_lo = C.n / 2 - h;
+    }
     CHK(make_twiddles(p, C));
     CHK(make_weight_table(p, C));
     const long long cn = C.cplane(), rn = C.rplane();
-    const size_t cv = (size_t)C.nplanes * cn, rv = (size_t)C.nframes * rn;
+    const size_t cv = (size_t)C.nplanes * cn, rv = (size_t)C.nframes * rn, kv = (size_t)C.nplanes * C.kplane();
     std::vector<int> pf(C.nplanes), fp0(C.nframes), fpn(C.nframes);
     for (int lf = 0; lf < C.nframes; ++lf) {
         fp0[lf] = C.plane0[lf];
@@ -1183,14 +1316,18 @@ int build_class(nlinv_plan_s* p, Class& C) {
     HIPCHK(hipMemcpy(C.plane_frame, pf.data(), pf.size() * sizeof(int), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(C.frame_plane0, fp0.data(), fp0.size() * sizeof(int), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(C.frame_planes, fpn.data(), fpn.size() * sizeof(int), hipMemcpyHostToDevice));
-    float2** cvecs[] = {&C.x_c, &C.r_c, &C.p_c, &C.q_c, &C.xr_c, &C.y};
-    for (float2** v : cvecs) CHK(dalloc(p, v, cv));
+    // CG vectors: the band of the sensitivities; q_c (grid-sized scratch) and y: whole planes
+    float2** kvecs[] = {&C.x_c, &C.r_c, &C.p_c, &C.xr_c};
+    for (float2** v : kvecs) CHK(dalloc(p, v, kv));
+    CHK(dalloc(p, &C.q_c, cv));
+    CHK(dalloc(p, &C.y, cv));
     float2** rvecs[] = {&C.x_r, &C.dx_r, &C.r_r, &C.p_r, &C.q_r, &C.xr_r};
     for (float2** v : rvecs) CHK(dalloc(p, v, rv));
     CHK(dalloc(p, &C.P, (size_t)C.nframes * cn));
     CHK(dalloc(p, &C.c, (size_t)C.nplanes * rn));
     CHK(dalloc(p, &C.aux, (size_t)C.nplanes * rn));
     CHK(dalloc(p, &C.T, (size_t)C.nplanes * C.m * C.n));
+    if (C.kb < C.n) CHK(dalloc(p, &C.T2, (size_t)C.nplanes * C.m * C.kb));
     make_geom(C.geom, C.nplanes, C.nframes, cn, rn, true, C.plane_frame);
     make_geom(C.geomC, C.nplanes, C.nframes, cn, rn, false, C.plane_frame);
     // partials: the segment geometries, or (column tiles of the narrowest
@@ -1208,10 +1345,13 @@ int build_class(nlinv_plan_s* p, Class& C) {
     CHK(dalloc(p, &C.sc.s, C.nframes));
     CHK(dalloc(p, &C.sc.inv_s, C.nframes));
     CHK(dalloc(p, &C.sc.stats, (size_t)C.nframes * kStatsCap));
+    CHK(dalloc(p, &C.sc.inert, (size_t)C.nframes * kInertLen));
     C.sc.nframes = C.nframes;
     C.sc.stats_len = kStatsCap;
-    for (int& v : C.colv) v = default_col_variant(C.n);
+    for (int m = 0; m < kColModes; ++m) C.colv[m] = default_col_variant(C.n, col_mode_on_band(m) ? C.kb : C.n);
     for (int& v : C.rowv) v = default_row_variant(C.n);
+    for (int m = 0; m < kColModes; ++m)
+        if (C.colv[m] < 0) return NLINV_EUNSUPPORTED;
     return NLINV_OK;
 }
 
@@ -1230,7 +1370,7 @@ void free_plan(nlinv_plan_s* p) {
 int check_dims(const nlinv_dims& d) {
     if (d.n <= 0 || d.n_om <= 0 || d.ncoils <= 0) return NLINV_EINVAL;
     if (!size_supported(d.n) || !supported_len(d.n)) return NLINV_EUNSUPPORTED;
-    if (default_col_variant(d.n) < 0 || default_row_variant(d.n) < 0) return NLINV_EUNSUPPORTED;
+    if (default_col_variant(d.n, d.n) < 0 || default_row_variant(d.n) < 0) return NLINV_EUNSUPPORTED;
     if ((d.n_om & 1) || d.n_om > d.n) return NLINV_EUNSUPPORTED;
     if (d.ncoils > 64) return NLINV_EUNSUPPORTED;
     if (!(d.sobolev_a >= 0.f) || !(d.sobolev_l >= 0.f)) return NLINV_EINVAL;
@@ -1244,28 +1384,29 @@ Class* class0(nlinv_plan_s* p) { return &p->classes[p->loc[0].first]; }
 // everything from its inputs).
 ColArgs tune_col_args(nlinv_plan_s* p, Class& C, int mode) {
     const Frames fr = class_frames(C);
-    ColArgs a = col_args(p, C, fr.tiled);
+    float2* TB = band_T(C, fr);
+    ColArgs a = col_args(p, C, fr);
     a.plane_frame = fr.plane_frame;
     a.P = C.P;
     a.p_stride = C.cplane();
     a.in = C.T;
     a.out = C.T;
     switch (mode) {
-        case COL_WINV_IFFT_CROP: a.in = C.x_c; break;
+        case COL_WINV_IFFT_CROP: a.in = C.x_c; a.out = TB; break;
         case COL_PUPD_WINV_IFFT_CROP:
-            a.in = C.p_c; a.r_in = C.r_c; a.p_out = C.p_c; a.beta = C.sc.beta; a.pr = C.p_r; a.rr = C.r_r;
-            a.partial = C.part_p;
+            a.in = C.p_c; a.out = TB; a.r_in = C.r_c; a.p_out = C.p_c; a.beta = C.sc.beta; a.pr = C.p_r;
+            a.rr = C.r_r; a.partial = C.part_p;
             break;
         case COL_PAD_FFT_P2_IFFT: a.partial = C.partial; break;
         case COL_P_IFFT_CROP: a.in = C.q_c; break;
         case COL_PAD_FFT_P: a.out = C.q_c; break;
         case COL_RESID_P_IFFT: a.add1 = C.y; a.s1 = C.sc.s; break;   // in place on T
         case COL_PAD_FFT_WINV_ADD:
-            a.out = C.r_c; a.add1 = C.x_c; a.add2 = C.xr_c; a.c1 = -1.f; a.c2 = 1.f;
+            a.in = TB; a.out = C.r_c; a.add1 = C.x_c; a.add2 = C.xr_c; a.c1 = -1.f; a.c2 = 1.f;
             break;
         case COL_PAD_FFT_WINV_CG_UPD:
             // q_c stands in for x (scratch: tuning must not touch the solution)
-            a.out = C.r_c; a.dx = C.q_c; a.add1 = C.p_c;
+            a.in = TB; a.out = C.r_c; a.dx = C.q_c; a.add1 = C.p_c;
             a.c1 = 1.f; a.cg_a = C.sc.a; a.partial = C.partial2;
             break;
         default: break;
@@ -1275,9 +1416,12 @@ ColArgs tune_col_args(nlinv_plan_s* p, Class& C, int mode) {
 
 RowArgs tune_row_args(Class& C, int mode) {
     const Frames fr = class_frames(C);
-    RowArgs r = row_args(C);
+    float2* TB = band_T(C, fr);
+    RowArgs r = row_args(C, fr);
     r.in = C.T;
     r.out = C.T;
+    if (mode == ROW_CACHE || mode == ROW_DERIV) r.in = TB;
+    if (mode == ROW_ADJ) r.out = TB;
     r.c = C.c;
     r.rho = C.x_r;
     r.drho = C.p_r;
@@ -1285,7 +1429,6 @@ RowArgs tune_row_args(Class& C, int mode) {
     r.c_out = C.c;
     r.plane_frame = fr.plane_frame;
     r.nlines = fr.nplanes * C.m;
-    (void)mode;
     return r;
 }
 
@@ -1318,7 +1461,7 @@ int tune_class(nlinv_plan_s* p, Class& C, hipStream_t s) {
         for (int v = 0; v < kNumColVariants; ++v) {
             // fewer lines than the tile width would split cache lines between
             // workgroups: cheap when timed warm here, not in a solve
-            if (!col_ok(C.n, v) || kColL[v] < C.tilew) continue;
+            if (!col_ok_cols(C.n, col_mode_on_band(mode) ? C.kb : C.n, v) || kColL[v] < C.tilew) continue;
             C.colv[mode] = v;
             float ms = 0.f;
             CHK(timeit([&] { return run_col(p, C, mode, a, nplanes, s); }, ms));
@@ -1478,7 +1621,7 @@ int nlinv_plan_destroy(nlinv_plan plan) {
 int nlinv_coil_maps(nlinv_plan p, const nlinv_c32* chat, nlinv_c32* c_out, void* stream) {
     if (!p || !chat || !c_out || !aligned(chat) || !aligned(c_out)) return NLINV_EINVAL;
     Class& C = *class0(p);
-    return seq_coil_maps(p, C, single_frame(p->dims[0].ncoils), (const float2*)chat, (float2*)c_out,
+    return seq_coil_maps(p, C, single_frame(C, p->dims[0].ncoils), (const float2*)chat, (float2*)c_out,
                          (hipStream_t)stream);
 }
 
@@ -1489,7 +1632,7 @@ int nlinv_forward(nlinv_plan p, const nlinv_c32* rho, const nlinv_c32* chat, con
         return NLINV_EINVAL;
     Class& C = *class0(p);
     const hipStream_t s = (hipStream_t)stream;
-    const Frames fr = single_frame(p->dims[0].ncoils);
+    const Frames fr = single_frame(C, p->dims[0].ncoils);
     float2* c = c_out ? (float2*)c_out : C.c;
     CHK(seq_coil_maps(p, C, fr, (const float2*)chat, c, s));
     return seq_forward(p, C, fr, (const float2*)rho, c, P, 0, (float2*)y_out, s);
@@ -1504,14 +1647,14 @@ int nlinv_deriv(nlinv_plan p, const nlinv_c32* rho, const nlinv_c32* chat, const
         return NLINV_EINVAL;
     Class& C = *class0(p);
     const hipStream_t s = (hipStream_t)stream;
-    const Frames fr = single_frame(p->dims[0].ncoils);
+    const Frames fr = single_frame(C, p->dims[0].ncoils);
     const float2* cc = (const float2*)c;
     if (!cc) {
         CHK(seq_coil_maps(p, C, fr, (const float2*)chat, C.c, s));
         cc = C.c;
     }
     CHK(seq_deriv_head(p, C, fr, (const float2*)rho, cc, (const float2*)drho, (const float2*)dchat, s));
-    ColArgs a = col_args(p, C, fr.tiled);
+    ColArgs a = col_args(p, C, fr);
     a.in = C.T;
     a.out = (float2*)dy_out;
     a.P = P;
@@ -1527,13 +1670,13 @@ int nlinv_adjoint(nlinv_plan p, const nlinv_c32* rho, const nlinv_c32* chat, con
         return NLINV_EINVAL;
     Class& C = *class0(p);
     const hipStream_t s = (hipStream_t)stream;
-    const Frames fr = single_frame(p->dims[0].ncoils);
+    const Frames fr = single_frame(C, p->dims[0].ncoils);
     const float2* cc = (const float2*)c;
     if (!cc) {
         CHK(seq_coil_maps(p, C, fr, (const float2*)chat, C.c, s));
         cc = C.c;
     }
-    ColArgs a = col_args(p, C, fr.tiled);
+    ColArgs a = col_args(p, C, fr);
     a.in = (const float2*)dy;
     a.out = C.T;
     a.P = P;
@@ -1551,7 +1694,7 @@ int nlinv_normal(nlinv_plan p, const nlinv_c32* rho, const nlinv_c32* chat, cons
         return NLINV_EINVAL;
     Class& C = *class0(p);
     const hipStream_t s = (hipStream_t)stream;
-    const Frames fr = single_frame(p->dims[0].ncoils);
+    const Frames fr = single_frame(C, p->dims[0].ncoils);
     const float2* cc = (const float2*)c;
     if (!cc) {
         CHK(seq_coil_maps(p, C, fr, (const float2*)chat, C.c, s));
@@ -1569,19 +1712,19 @@ int nlinv_mask_gradient(nlinv_plan p, const nlinv_c32* rho, const nlinv_c32* cha
     Class& C = *class0(p);
     const hipStream_t s = (hipStream_t)stream;
     const int J = p->dims[0].ncoils;
-    const Frames fr = single_frame(J);
+    const Frames fr = single_frame(C, J);
     const float2* cc = (const float2*)c;
     if (!cc) {
         CHK(seq_coil_maps(p, C, fr, (const float2*)chat, C.c, s));
         cc = C.c;
     }
-    RowArgs r = row_args(C);
+    RowArgs r = row_args(C, fr);
     r.c = cc;
     r.rho = (const float2*)rho;
     r.out = C.T;
     r.nlines = J * C.m;
     CHK(run_row(p, C, ROW_FWD, r, s));
-    ColArgs a = col_args(p, C, fr.tiled);
+    ColArgs a = col_args(p, C, fr);
     a.in = C.T;
     a.out = C.q_c;                  // real products Re(conj g . S) [J][n][n] as floats
     a.add1 = (const float2*)g;
@@ -1646,18 +1789,17 @@ int nlinv_irgnm_solve_series(nlinv_plan p, int32_t count, const nlinv_frame* fra
     for (int t = 0; t < count; ++t) {
         nlinv_frame f = frames[t];
         nlinv_irgnm_params q = *prm;
-        if (t > 0) {
-            // x0 = x_ref = the previous frame's result, in data units
-            q.flags |= NLINV_WARM_START;
-            HIPCHK(hipMemcpyAsync(f.rho, frames[t - 1].rho, class0(p)->rplane() * sizeof(float2),
-                                  hipMemcpyDeviceToDevice, s));
-            HIPCHK(hipMemcpyAsync(f.chat, frames[t - 1].chat,
-                                  (size_t)p->dims[0].ncoils * class0(p)->cplane() * sizeof(float2),
-                                  hipMemcpyDeviceToDevice, s));
-            f.rho_ref = frames[t - 1].rho;
-            f.chat_ref = frames[t - 1].chat;
+        if (t == 0) {
+            CHK(solve_all(p, &f, q, s));
+            continue;
         }
-        CHK(solve_all(p, &f, q, s));
+        // x0 = x_ref = the previous frame's result, in data units: read from
+        // its arrays (x_ref = x0 needs no arrays of its own)
+        q.flags |= NLINV_WARM_START;
+        f.rho_ref = nullptr;
+        f.chat_ref = nullptr;
+        const FrameSrc src{(const float2*)frames[t - 1].rho, (const float2*)frames[t - 1].chat};
+        CHK(solve_all(p, &f, q, s, &src));
     }
     return NLINV_OK;
 }
@@ -1667,7 +1809,7 @@ int nlinv_plan_autotune(nlinv_plan p, void* stream) {
     const hipStream_t s = (hipStream_t)stream;
     const std::string arch = arch_name(p->device);
     const char* path = std::getenv("NLINV_TUNE_CACHE");
-    // cache lines: arch n planes <kColModes column variants> <kRowModes row variants>
+    // cache lines: arch n planes kb <kColModes column variants> <kRowModes row variants>
     std::map<std::string, std::vector<int>> cache;
     if (path) {
         std::ifstream in(path);
@@ -1675,26 +1817,27 @@ int nlinv_plan_autotune(nlinv_plan p, void* stream) {
         while (std::getline(in, line)) {
             std::istringstream ls(line);
             std::string a;
-            int n, np;
-            if (!(ls >> a >> n >> np)) continue;
+            int n, np, kb;
+            if (!(ls >> a >> n >> np >> kb)) continue;
             std::vector<int> v;
             int x;
             while (ls >> x) v.push_back(x);
             if ((int)v.size() != kColModes + kRowModes) continue;
             std::ostringstream k;
-            k << a << ' ' << n << ' ' << np;
+            k << a << ' ' << n << ' ' << np << ' ' << kb;
             cache[k.str()] = v;
         }
     }
     bool changed = false;
     for (Class& C : p->classes) {
         std::ostringstream k;
-        k << arch << ' ' << C.n << ' ' << C.nplanes;
+        k << arch << ' ' << C.n << ' ' << C.nplanes << ' ' << C.kb;
         auto it = cache.find(k.str());
         bool ok = it != cache.end();
         if (ok)
             for (int i = 0; i < kColModes + kRowModes; ++i)
-                ok = ok && (i < kColModes ? col_ok(C.n, it->second[i]) : row_ok(C.n, it->second[i]));
+                ok = ok && (i < kColModes ? col_ok_cols(C.n, col_mode_on_band(i) ? C.kb : C.n, it->second[i])
+                                          : row_ok(C.n, it->second[i]));
         if (ok) {
             for (int i = 0; i < kColModes; ++i) C.colv[i] = it->second[i];
             for (int i = 0; i < kRowModes; ++i) C.rowv[i] = it->second[kColModes + i];
@@ -1727,6 +1870,18 @@ int nlinv_plan_variant(nlinv_plan p, int32_t n, int32_t* col_variant, int32_t* r
             return NLINV_OK;
         }
     *col_variant = *row_variant = -1;
+    return NLINV_EINVAL;
+}
+
+int nlinv_plan_band(nlinv_plan p, int32_t n, int32_t* kb, int32_t* kb_lo) {
+    if (!p || !kb || !kb_lo) return NLINV_EINVAL;
+    for (Class& C : p->classes)
+        if (C.n == n) {
+            *kb = C.kb;
+            *kb_lo = C.kb_lo;
+            return NLINV_OK;
+        }
+    *kb = *kb_lo = -1;
     return NLINV_EINVAL;
 }
 
@@ -1886,6 +2041,8 @@ extern "C" int nlinv_normal_noalloc(const nlinv_dims* dims, const nlinv_c32* rho
     C.n = n;
     C.m = m;
     C.lo = n / 2 - m / 2;
+    C.kb = n;
+    C.kb_lo = 0;
     C.nframes = 1;
     C.nplanes = J;
     C.tilew = plane_tile_width(n);
@@ -1894,13 +2051,13 @@ extern "C" int nlinv_normal_noalloc(const nlinv_dims* dims, const nlinv_c32* rho
     C.aux = reinterpret_cast<float2*>(base + b_tw + b_w);
     C.T = reinterpret_cast<float2*>(base + b_tw + b_w + b_om);
     C.c = c ? nullptr : reinterpret_cast<float2*>(base + b_tw + b_w + b_om + b_T);
-    for (int& v : C.colv) v = default_col_variant(n);
+    for (int& v : C.colv) v = default_col_variant(n, n);
     for (int& v : C.rowv) v = default_row_variant(n);
 
     hipLaunchKernelGGL(k_noalloc_tables, dim3(grid_for((long long)n * n)), dim3(kThreads), 0, s, C.tw, C.winv, n,
                        split_n1(n), (double)pl.sob_a, (double)pl.sob_hl);
     HIPCHK(hipGetLastError());
-    const Frames fr = single_frame(J);
+    const Frames fr = single_frame(C, J);
     const float2* cc = (const float2*)c;
     if (!cc) {
         CHK(seq_coil_maps(&pl, C, fr, (const float2*)chat, C.c, s));

@@ -125,10 +125,16 @@ struct ColArgs {
     const float* s2;
     float c1, c2;
     int m, lo;
+    // The sensitivity-side modes (COL_WINV_IFFT_CROP, COL_PUPD_WINV_IFFT_CROP,
+    // COL_PAD_FFT_WINV_ADD, COL_PAD_FFT_WINV_CG_UPD) act on the kb columns and
+    // rows [kb_lo, kb_lo + kb) of k-space only: their chat-like operands and
+    // 1/w are kb x kb arrays of that centred square, their T is [m][kb].
+    // kb = n, kb_lo = 0 is the whole grid.
+    int kb, kb_lo;
     int nplanes;
     float rs;                 // 1/sqrt(n)
     const float2* tw2;        // [N1][N2]: exp(-2 pi i k1 j2 / n)
-    const float* winv;        // [n][n]: 1/w, the inverse Sobolev weight
+    const float* winv;        // [kb][kb]: 1/w, the inverse Sobolev weight on the band
     // COL_PUPD_WINV_IFFT_CROP: the direction update p = r + beta_f p is done
     // at load (in = p is rewritten); beta == nullptr means p = r.
     const float2* r_in;       // chat part of r (nullable: no update)
@@ -203,6 +209,9 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
     constexpr bool CGU = (MODE == COL_PAD_FFT_WINV_CG_UPD);
     constexpr bool WINV_OUT = (MODE == COL_PAD_FFT_WINV_ADD) || CGU;
     constexpr bool RED = CGU || PUPD || TWO || (MODE == COL_PAD_FFT_WINV_ADD);  // can write partial sums
+    // sensitivity-side modes work on the band of k-space (see ColArgs)
+    constexpr bool CHAT = WINV_IN || WINV_OUT;
+    constexpr int TW = plane_tile<N>();
     // Exchange buffer [k1][j2][l] (slot j2 + N2 k1 of line l), each k1 row
     // padded by L entries: the L-line groups of one wavefront then fall on
     // different LDS banks in every access pattern below.
@@ -211,22 +220,32 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
     __shared__ double red[RED ? NT / 64 : 1];
     static_assert(NT % 64 == 0 && NT <= 1024, "pass workgroup size");
 
+    const int kb = CHAT ? a.kb : N, klo = CHAT ? a.kb_lo : 0;
+    const int ncols = kb;                          // columns of this pass
+    // element (grid row r, band column col) of a band-side array; whether
+    // grid row r lies in the band
+    auto cidx = [&](int r, int col) -> int {
+        const int rc = r - klo;
+        return TILED ? ((col / TW) * kb + rc) * TW + (col % TW) : rc * kb + col;
+    };
+    auto in_band = [&](int r) -> bool { return !CHAT || (unsigned)(r - klo) < (unsigned)kb; };
     if constexpr (CGU) {
-        const int ncol = 8 * ((N / L * a.nplanes + 7) / 8);
+        const int ncol = 8 * ((ncols / L * a.nplanes + 7) / 8);
         if ((int)blockIdx.x >= ncol) {
             coil_sum_block<NT>(a.cs, (int)blockIdx.x - ncol, red);
             return;
         }
     }
     int tile, plane;
-    if (!col_item(N / L, a.nplanes, tile, plane)) return;
+    if (!col_item(ncols / L, a.nplanes, tile, plane)) return;
     const int col0 = tile * L;
     const int f = a.plane_frame ? a.plane_frame[plane] : 0;
     // HALF: Omega is the centred half of the grid (m = n/2, 2x oversampling),
     // fixed at compile time so that every crop and pad test folds away
     const int m = HALF ? N / 2 : a.m, lo = HALF ? N / 4 : a.lo;
     const float* P = a.P + (long long)f * a.p_stride;
-    const long long pofs = (long long)plane * (IN_CROP ? m : N) * N;
+    // plane offset of the input: T [m][ncols], a band array [kb][kb] or a grid plane
+    const long long pofs = (long long)plane * (IN_CROP ? (long long)m * ncols : (long long)kb * kb);
     const float2* src = a.in + pofs;
     double acc = 0.0;     // this thread's share of the workgroup's partial sum
     double acc_rho = 0.0;
@@ -241,7 +260,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
     float w0[CHP];
     if constexpr (MODE == COL_WINV_IFFT_CROP) {
         if (a.rho_acc && (plane == 0 || (a.plane_frame && a.plane_frame[plane - 1] != f))) {
-            const int E = m * m, ntiles = N / L;
+            const int E = m * m, ntiles = ncols / L;
             const int chunk = (E + ntiles - 1) / ntiles;
             const int e0 = tile * chunk, e1 = min(E, e0 + chunk);
             float2* x = a.rho_acc + (long long)f * E;
@@ -259,10 +278,18 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
             const int l = threadIdx.x % L, j2 = threadIdx.x / L, col = col0 + l;
             static_for<0, CHP>([&](auto I) {
                 constexpr int k1 = I;
-                const int o = big_idx<N>(CT::in_pos(j2, k1), col, TILED);
-                rv0[I] = elt(a.r_in + pofs, o);
-                pv0[I] = has_beta ? elt(src, o) : make_float2(0.f, 0.f);
-                w0[I] = elt(a.winv, o);
+                const int r = CT::in_pos(j2, k1);
+                const float2 z = make_float2(0.f, 0.f);
+                if (in_band(r)) {
+                    const int o = cidx(r, col);
+                    rv0[I] = elt(a.r_in + pofs, o);
+                    pv0[I] = has_beta ? elt(src, o) : z;
+                    w0[I] = elt(a.winv, o);
+                } else {
+                    rv0[I] = z;
+                    pv0[I] = z;
+                    w0[I] = 0.f;
+                }
             });
         }
         first_plane = plane == 0 || (a.plane_frame && a.plane_frame[plane - 1] != f);
@@ -279,7 +306,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                     const double t = frame_total_wave(a.fold.g, a.fold.partial, f, a.fold.frame_plane0,
                                                       a.fold.frame_planes);
                     if (threadIdx.x == 0) {
-                        beta_sh = rr0 ? 0.f : cg_beta(fs, t);
+                        beta_sh = rr0 ? 0.f : cg_beta(a.fold, fs, t);
                         if (designated) scalar_apply(a.fold, a.sc, f, t, fs);
                     }
                 }
@@ -291,7 +318,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
         }
         // rho part of the direction update, done by the first plane of each frame
         if (first_plane) {
-            const int E = m * m, ntiles = N / L;
+            const int E = m * m, ntiles = ncols / L;
             const int chunk = (E + ntiles - 1) / ntiles;
             const int e0 = tile * chunk, e1 = min(E, e0 + chunk);
             const float bf = beta;
@@ -329,23 +356,30 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                             pv[I] = pv0[I];
                             w[I] = w0[I];
                         } else {
-                            const int o = big_idx<N>(CT::in_pos(j2, k1), col, TILED);
-                            rv[I] = elt(a.r_in + pofs, o);
-                            if constexpr (HB) pv[I] = elt(src, o);
-                            w[I] = elt(a.winv, o);
+                            const int r = CT::in_pos(j2, k1);
+                            rv[I] = make_float2(0.f, 0.f);
+                            pv[I] = rv[I];
+                            w[I] = 0.f;
+                            if (in_band(r)) {
+                                const int o = cidx(r, col);
+                                rv[I] = elt(a.r_in + pofs, o);
+                                if constexpr (HB) pv[I] = elt(src, o);
+                                w[I] = elt(a.winv, o);
+                            }
                         }
                     });
                     static_for<0, CH>([&](auto I) {
                         constexpr int k1 = C * CH + I;
                         const int r = CT::in_pos(j2, k1);
-                        const int o = big_idx<N>(r, col, TILED);
                         float2 x = rv[I];
                         if constexpr (HB) {
                             x.x += b * pv[I].x;
                             x.y += b * pv[I].y;
                         }
-                        elt(a.p_out + pofs, o) = x;
-                        pacc += (double)(x.x * x.x + x.y * x.y);
+                        if (in_band(r)) {
+                            elt(a.p_out + pofs, cidx(r, col)) = x;
+                            pacc += (double)(x.x * x.x + x.y * x.y);
+                        }
                         v[k1] = cscale(x, CT::sign(r) * w[I]);
                     });
                 });
@@ -359,14 +393,15 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                 float2 x = make_float2(0.f, 0.f);
                 if constexpr (IN_CROP) {
                     const int ri = r - lo;
-                    if (ri >= 0 && ri < m) x = cscale(elt(src, ri * N + col), CT::sign(r));
-                } else {
-                    const int o = big_idx<N>(r, col, TILED);
-                    if constexpr (WINV_IN) {
+                    if (ri >= 0 && ri < m) x = cscale(elt(src, ri * ncols + col), CT::sign(r));
+                } else if constexpr (WINV_IN) {
+                    if (in_band(r)) {
+                        const int o = cidx(r, col);
                         x = cscale(elt(src, o), CT::sign(r) * elt(a.winv, o));
-                    } else {   // COL_P_IFFT_CROP
-                        x = cscale(elt(src, o), CT::sign(r) * elt(P, o));
                     }
+                } else {   // COL_P_IFFT_CROP
+                    const int o = big_idx<N>(r, col, TILED);
+                    x = cscale(elt(src, o), CT::sign(r) * elt(P, o));
                 }
                 v[k1] = x;
             });
@@ -482,7 +517,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
 
     // ---- stage 2 of the last transform, straight to HBM
     constexpr bool INV2 = INV1 || TWO;
-    const long long pbase = (long long)plane * N * N;
+    const long long pbase = (long long)plane * kb * kb;   // band or grid plane of the outputs
     const float s1 = a.s1 ? a.s1[f] : a.c1;
     const float s2 = a.s2 ? a.s2[f] : a.c2;
     const float av = CGU ? a.cg_a[f] : 0.f;
@@ -505,7 +540,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                 const int ri = rp - lo;
                 if (ri >= 0 && ri < m) {
                     const float s = TWO ? CT::sign(rp) : CT::sign(rp) * a.rs;
-                    elt(a.out + (long long)plane * m * N, ri * N + col) = cscale(v[k2], s);
+                    elt(a.out + (long long)plane * m * ncols, ri * ncols + col) = cscale(v[k2], s);
                 }
             });
         } else {
@@ -522,21 +557,25 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                     float2 u1[CH], u2[CH], u3[CH];
                     static_for<0, CH>([&](auto I) {
                         constexpr int k2 = C * CH + I;
-                        const int o = big_idx<N>(CT::out_pos(k1, k2), col, TILED);
-                        if constexpr (MODE == COL_PAD_FFT_P) w[I] = elt(P, o);
-                        if constexpr (WINV_OUT || CGU) w[I] = elt(a.winv, o);
-                        if constexpr (MODE == COL_PAD_FFT_GPROD || CGU || (WINV_OUT && H1))
-                            u1[I] = elt(a.add1 + pbase, o);
-                        if constexpr (WINV_OUT && H2) u2[I] = elt(a.add2 + pbase, o);
-                        if constexpr (CGU) {
-                            u2[I] = elt(a.out + pbase, o);    // r
-                            u3[I] = elt(a.dx + pbase, o);
+                        const int rp = CT::out_pos(k1, k2);
+                        if (in_band(rp)) {
+                            const int o = CHAT ? cidx(rp, col) : big_idx<N>(rp, col, TILED);
+                            if constexpr (MODE == COL_PAD_FFT_P) w[I] = elt(P, o);
+                            if constexpr (WINV_OUT || CGU) w[I] = elt(a.winv, o);
+                            if constexpr (MODE == COL_PAD_FFT_GPROD || CGU || (WINV_OUT && H1))
+                                u1[I] = elt(a.add1 + pbase, o);
+                            if constexpr (WINV_OUT && H2) u2[I] = elt(a.add2 + pbase, o);
+                            if constexpr (CGU) {
+                                u2[I] = elt(a.out + pbase, o);    // r
+                                u3[I] = elt(a.dx + pbase, o);
+                            }
                         }
                     });
                     static_for<0, CH>([&](auto I) {
                         constexpr int k2 = C * CH + I;
                         const int rp = CT::out_pos(k1, k2);
-                        const int o = big_idx<N>(rp, col, TILED);
+                        if (!in_band(rp)) return;         // outside the band: not stored
+                        const int o = CHAT ? cidx(rp, col) : big_idx<N>(rp, col, TILED);
                         float2 x = v[k2];
                         if constexpr (MODE == COL_PAD_FFT_P) {
                             elt(a.out + pbase, o) = cscale(x, CT::sign(rp) * a.rs * w[I]);
@@ -581,7 +620,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
     }
     if constexpr (RED) {
         if (a.partial) {   // uniform over the workgroup
-            constexpr long long ntiles = N / L;
+            const long long ntiles = ncols / L;
             const double t = wg_sum<NT>(acc, red);
             if (threadIdx.x == 0) a.partial[(long long)plane * ntiles + tile] = t;
             if constexpr (PUPD) {
@@ -606,8 +645,9 @@ enum RowMode : int {
 };
 
 struct RowArgs {
-    const float2* in;        // T [planes][m][n]
-    float2* out;             // T (may equal in)
+    const float2* in;        // T [planes][m][n], or [planes][m][kb] (ROW_CACHE, ROW_DERIV)
+    float2* out;             // T [planes][m][n], or [planes][m][kb] (ROW_ADJ); may equal
+                             // in when both have the same row length
     const float2* c;         // [planes][m][m]
     float2* c_out;           // ROW_CACHE output
     const float2* rho;       // [frames][m][m]
@@ -616,6 +656,10 @@ struct RowArgs {
     const int* plane_frame;
     int nlines;              // planes * m
     int m, lo;
+    // band of k-space columns [kb_lo, kb_lo + kb) on the sensitivity side:
+    // ROW_CACHE and ROW_DERIV read only those columns of their input (the
+    // rest is zero), ROW_ADJ writes only those of its output
+    int kb, kb_lo;
     float rs;
     const float2* tw2;       // [N1][N2]
     // ROW_ADJ, ROW_CACHE: a per-frame scalar step folded into the launch (op
@@ -640,6 +684,9 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
     // fixed at compile time so that every crop and pad test folds away
     const int m = HALF ? N / 2 : a.m, lo = HALF ? N / 4 : a.lo;
     const int t = threadIdx.x;
+    constexpr bool IN_BAND = MODE == ROW_CACHE || MODE == ROW_DERIV;   // input rows [kb]
+    constexpr bool OUT_BAND = MODE == ROW_ADJ;                          // output rows [kb]
+    const int kb = a.kb, klo = a.kb_lo;
     if constexpr (MODE == ROW_ADJ || MODE == ROW_CACHE) fold_scalar_step(a.fold, a.sc);
 
     if constexpr (MODE == ROW_FWD) {
@@ -666,8 +713,14 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
             static_for<0, N1>([&](auto K) {
                 constexpr int k1 = K;
                 const int p = CT::in_pos(j2, k1);
-                v[k1] = line < a.nlines ? cscale(elt(a.in + (long long)line0 * N, ll * N + p), CT::sign(p))
-                                        : make_float2(0.f, 0.f);
+                v[k1] = make_float2(0.f, 0.f);
+                if constexpr (IN_BAND) {
+                    const int pc = p - klo;
+                    if (line < a.nlines && (unsigned)pc < (unsigned)kb)
+                        v[k1] = cscale(elt(a.in + (long long)line0 * kb, ll * kb + pc), CT::sign(p));
+                } else {
+                    if (line < a.nlines) v[k1] = cscale(elt(a.in + (long long)line0 * N, ll * N + p), CT::sign(p));
+                }
             });
             RegDFT<N1, true>::run(v);
             static_for<0, N1>([&](auto K) {
@@ -797,7 +850,13 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
             static_for<0, N2>([&](auto K) {
                 constexpr int k2 = K;
                 const int pos = CT::out_pos(k1, k2);
-                elt(a.out + (long long)line0 * N, ll * N + pos) = cscale(v[k2], CT::sign(pos) * a.rs);
+                if constexpr (OUT_BAND) {
+                    const int pc = pos - klo;
+                    if ((unsigned)pc < (unsigned)kb)
+                        elt(a.out + (long long)line0 * kb, ll * kb + pc) = cscale(v[k2], CT::sign(pos) * a.rs);
+                } else {
+                    elt(a.out + (long long)line0 * N, ll * N + pos) = cscale(v[k2], CT::sign(pos) * a.rs);
+                }
             });
         }
     }

@@ -160,6 +160,11 @@ class Plan:
     def variant(self, n):
         return N.nlinv_plan_variant(self.handle, n)
 
+    def band(self, n=None):
+        """(kb, kb_lo): rows and columns [kb_lo, kb_lo + kb) of k-space the
+        solves keep of the sensitivities of grid size n (default frame 0's)."""
+        return N.nlinv_plan_band(self.handle, self.dims.n if n is None else n)
+
     def set_variant(self, n, col_variant, row_variant):
         N.nlinv_plan_set_variant(self.handle, n, col_variant, row_variant)
 

@@ -1,0 +1,70 @@
+"""The solve keeps the sensitivities only on the centred band of k-space
+where the Sobolev weight has 1/w > 2^-40 (Eq. 2: W^{-1} chat = DTFT^{-1}(chat / w)).
+These CPU tests check that reading on the FP64 oracle's operators: the
+components outside the band change DF and the normal operator of Eq. 3 by
+less than 2^-40 of their size, so that there the normal operator is
+alpha I; and the band half-widths the library uses at the workload sizes
+follow from the weight alone."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import nlinv_oracle as O
+
+A, L = 220.0, 32.0
+
+
+def band_half(n, a=A, l=L):
+    """Smallest multiple of 16, h, with (1 + a (h/n)^2)^(l/2) >= 2^40 (every
+    k outside [n/2 - h, n/2 + h)^2 has |k| >= h/n), or n/2 if none is narrower."""
+    for h in range(16, n // 2, 16):
+        if (1.0 + a * (h / n) ** 2) ** (l / 2) >= 2.0 ** 40:
+            return h
+    return n // 2
+
+
+@pytest.mark.parametrize("n,h", [(32, 16), (64, 16), (128, 32), (192, 32), (256, 48), (384, 64), (512, 80)])
+def test_band_half_widths(n, h):
+    assert band_half(n) == h
+    d = O.Dims(n, n // 2, 1)
+    winv = 1.0 / O.sobolev_weight(d)
+    out = np.ones((n, n), bool)
+    out[n // 2 - h:n // 2 + h, n // 2 - h:n // 2 + h] = False
+    if out.any():
+        assert winv[out].max() <= 2.0 ** -40
+    assert winv[~out].max() == 1.0
+
+
+def _outside(n, h):
+    m = np.ones((n, n), bool)
+    m[n // 2 - h:n // 2 + h, n // 2 - h:n // 2 + h] = False
+    return m
+
+
+@pytest.mark.parametrize("n,n_om,J", [(64, 32, 3), (128, 64, 2), (128, 128, 2)])
+def test_components_outside_the_band_do_not_reach_df(n, n_om, J):
+    """DF and DF^H DF + alpha of a direction whose sensitivity part is spread
+    evenly over the whole grid: dropping that part outside the band changes
+    DF by < 2^-40 relative, and the normal operator there is alpha I to the
+    same bound; the band's own components are unaffected to the same bound."""
+    rng = np.random.default_rng([41, n, n_om, J])
+    d = O.Dims(n, n_om, J)
+    h = band_half(n)
+    out = _outside(n, h)
+    rc = lambda *s: rng.standard_normal(s) + 1j * rng.standard_normal(s)
+    rho = 1.0 + 0.1 * rc(n_om, n_om)
+    chat = 0.1 * rc(J, n, n) * (~out)
+    P = (rng.uniform(size=(n, n)) < 0.3).astype(np.float64)
+    drho, dchat = rc(n_om, n_om), rc(J, n, n)
+    dchat_band = dchat * (~out)
+    y_full = O.deriv(rho, chat, P, drho, dchat, d)
+    y_band = O.deriv(rho, chat, P, drho, dchat_band, d)
+    assert np.linalg.norm(y_full - y_band) <= 2.0 ** -40 * np.linalg.norm(dchat)
+    alpha = 0.25
+    nr, nc = O.normal(rho, chat, P, alpha, drho, dchat, d)
+    br, bc = O.normal(rho, chat, P, alpha, drho, dchat_band, d)
+    bc = bc + alpha * dchat * out            # alpha I outside the band
+    scale = np.linalg.norm(dchat) + np.linalg.norm(drho)
+    assert np.linalg.norm(nr - br) <= 2.0 ** -40 * scale
+    assert np.linalg.norm(nc - bc) <= 2.0 ** -40 * scale

@@ -204,7 +204,8 @@ def test_autotune_picks_valid_variants_and_keeps_parity(tmp_path, monkeypatch):
         nr, nc = map(host, pl.normal(dev(rho), dev(chat), dev(P), 0.5, dev(drho), dev(dchat)))
         assert rel(nr, ref[0]) < TOL and rel(nc, ref[1]) < TOL
     line = (tmp_path / "tune.txt").read_text().split()
-    assert line[1:3] == ["192", str(J)] and len(line) == 3 + 9 + 4
+    # arch, n, planes, the side of the band the solve keeps (64 at n = 192), 9 + 4 variants
+    assert line[1:4] == ["192", str(J), "64"] and len(line) == 4 + 9 + 4
     with Plan(n, n_om, J) as pl2:    # served from the cache file
         pl2.autotune()
         assert pl2.variant(n) == (cv, rv)

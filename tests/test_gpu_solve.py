@@ -241,7 +241,7 @@ def test_breakdown_on_zero_data():
         assert np.all(host(out["chat"]) == 0) and np.all(host(out["rho"]) == 1)
 
 
-@pytest.mark.parametrize("n,n_om", [(16, 8), (12, 12)])
+@pytest.mark.parametrize("n,n_om", [(16, 8), (12, 12), (64, 32)])
 @pytest.mark.parametrize("K", [1, 3])
 def test_no_sampling_lands_on_the_reference(n, n_om, K):
     """P = 0: F and DF vanish and Eq. 3 reduces to dx = x_ref - x_n, so the
@@ -249,7 +249,8 @@ def test_no_sampling_lands_on_the_reference(n, n_om, K):
     in both blocks; the oracle's closed form of the same case is pinned on the
     CPU."""
     rng = np.random.default_rng([5, n, K])
-    y = (rng.standard_normal((2, n, n)) + 1j * rng.standard_normal((2, n, n))).astype(np.complex64)
+    # |y| about 20, so that the data scale s = 100 / |y| is far from 1
+    y = ((10.0 / n) * (rng.standard_normal((2, n, n)) + 1j * rng.standard_normal((2, n, n)))).astype(np.complex64)
     P = np.zeros((n, n), np.float32)
     def rc(*s):
         return (rng.standard_normal(s) + 1j * rng.standard_normal(s)).astype(np.complex64)
@@ -262,3 +263,27 @@ def test_no_sampling_lands_on_the_reference(n, n_om, K):
             assert abs(got["stats"][0] - 1.0) > 0.5
             assert rel(got["rho"], rref) < 1e-5
             assert rel(got["chat"], cref) < 1e-5
+
+
+def test_band_solve_matches_whole_grid_solve(monkeypatch):
+    """The solve keeps only the band of the sensitivities where 1/w > 2^-40
+    (64 x 64 of 128 x 128 here); the same solve over every sensitivity
+    component (NLINV_FULL_CHAT=1) gives the same image and sensitivities to
+    single-precision rounding, and both match the oracle."""
+    fr = synth.make_frame(2, 7, 128, 64, 4, "radial", spokes=11)
+    ref = oracle_solve(fr, 4, 6)
+    band = gpu_solve(fr, 4, 6, use_graph=True)
+    monkeypatch.setenv("NLINV_FULL_CHAT", "1")
+    full = gpu_solve(fr, 4, 6, use_graph=True)
+    assert rel(band["image"], full["image"]) < 1e-5
+    assert rel(band["chat"], full["chat"]) < 1e-5
+    # outside the band the cold start's zeros stay: the whole-grid solve
+    # moves those components only below 2^-40 of the band's
+    out = np.ones((128, 128), bool)
+    out[32:96, 32:96] = False
+    assert np.all(band["chat"][:, out] == 0)
+    assert np.abs(full["chat"][:, out]).max() < 1e-9 * np.abs(full["chat"]).max()
+    for got in (band, full):
+        assert rel(got["image"], ref.image) < NRMSE
+        np.testing.assert_allclose(got["stats"][2:6], ref.r0_norms, rtol=1e-4)
+
