@@ -253,6 +253,8 @@ int nlinv_plan_timing_read(nlinv_plan plan, int32_t* launches, double* total_ms)
  * classes' brackets are kept for their own reads.  Several classes can be
  * bracketed in one solve and read apart afterwards. */
 int nlinv_plan_timing_read_class(nlinv_plan plan, int32_t kclass, int32_t* launches, double* total_ms);
+/* Names of the kernel classes, by index; the class "cg_iteration" brackets a
+ * whole CG iteration (its five launches) as one. */
 const char* nlinv_kernel_class_name(int32_t kclass);   /* NULL past the last */
 
 /* ---- measurement ----------------------------------------------------------

@@ -231,34 +231,40 @@ __global__ __launch_bounds__(kThreads) void k_chat_out(BandBatch b, const double
     }
 }
 
-// partial[plane0 + p] = |x0 - ref|^2 over plane p outside the band (x0 null:
-// 0; ref null: 0), in FP64, one workgroup per plane, a fixed order
-__global__ __launch_bounds__(kThreads) void k_inert_dist(BandBatch b, double* partial, int n, int klo, int kb) {
+// partial[(plane0 + p) * segs + g] = |x0 - ref|^2 over rows g*rows..(g+1)*rows
+// of plane p, outside the band (x0 null: 0; ref null: 0), in FP64; one
+// workgroup per (plane, row segment), a fixed order
+__global__ __launch_bounds__(kThreads) void k_inert_dist(BandBatch b, double* partial, int n, int klo, int kb,
+                                                        int segs) {
     __shared__ double red[kThreads / 64];
-    const int y = blockIdx.y, pl = blockIdx.x;
+    const int y = blockIdx.y, pl = blockIdx.x / segs, g = blockIdx.x % segs;
     if (pl >= b.np[y]) return;
     const float2* x0 = b.x0[y];
     const float2* ref = b.ref[y];
-    const long long nn = (long long)n * n;
+    const long long base = (long long)pl * n * n;
+    const int rows = (n + segs - 1) / segs, r0 = g * rows, r1 = min(n, r0 + rows);
     double acc = 0.0;
     if (ref) {
-        for (long long e = threadIdx.x; e < nn; e += kThreads) {
-            const int r = (int)(e / n) - klo, c = (int)(e % n) - klo;
-            if ((unsigned)r < (unsigned)kb && (unsigned)c < (unsigned)kb) continue;
-            const float2 x = x0 ? x0[pl * nn + e] : make_float2(0.f, 0.f);
-            const float2 q = ref[pl * nn + e];
-            const double dx = (double)x.x - q.x, dy = (double)x.y - q.y;
-            acc += dx * dx + dy * dy;
+        for (int r = r0; r < r1; ++r) {
+            const bool rin = (unsigned)(r - klo) < (unsigned)kb;
+            for (int c = threadIdx.x; c < n; c += kThreads) {
+                if (rin && (unsigned)(c - klo) < (unsigned)kb) continue;
+                const long long e = base + (long long)r * n + c;
+                const float2 x = x0 ? x0[e] : make_float2(0.f, 0.f);
+                const float2 q = ref[e];
+                const double dx = (double)x.x - q.x, dy = (double)x.y - q.y;
+                acc += dx * dx + dy * dy;
+            }
         }
     }
     const double t = block_sum(acc, red);
-    if (threadIdx.x == 0) partial[b.plane0[y] + pl] = t;
+    if (threadIdx.x == 0) partial[(long long)(b.plane0[y] + pl) * segs + g] = t;
 }
 
 // Start of a solve: the record of the components outside the band for every
-// frame of a class (D from the per-plane partials in plane order, or 0 when
-// partial is null; theta = 1)
-__global__ __launch_bounds__(kThreads) void k_inert_init(double* inert, const double* partial,
+// frame of a class (D from the per-plane partials, `segs` per plane, in
+// order, or 0 when partial is null; theta = 1)
+__global__ __launch_bounds__(kThreads) void k_inert_init(double* inert, const double* partial, int segs,
                                                         const int* frame_plane0, const int* frame_planes,
                                                         int nplanes, int nframes) {
     for (int f = blockIdx.x * kThreads + threadIdx.x; f < nframes; f += gridDim.x * kThreads) {
@@ -266,7 +272,7 @@ __global__ __launch_bounds__(kThreads) void k_inert_init(double* inert, const do
         if (partial) {
             const int p0 = frame_plane0 ? frame_plane0[f] : 0;
             const int np = frame_planes ? frame_planes[f] : nplanes;
-            for (int p = 0; p < np; ++p) d += partial[p0 + p];
+            for (long long i = (long long)p0 * segs; i < (long long)(p0 + np) * segs; ++i) d += partial[i];
         }
         double* in = inert + (long long)f * kInertLen;
         in[0] = d;

@@ -90,13 +90,15 @@ enum KClass : int {
     KC_COL_WINV_IFFT = 0, KC_COL_P_IFFT, KC_COL_FFT_P, KC_COL_RESID_P_IFFT, KC_COL_PSF,
     KC_COL_FFT_WINV_ADD, KC_COL_FFT_GPROD, KC_COL_PUPD_WINV_IFFT, KC_COL_FFT_WINV_CG_UPD,
     KC_ROW_CACHE, KC_ROW_FWD, KC_ROW_DERIV, KC_ROW_ADJ,
-    KC_COIL_SUM, KC_VEC_DOT, KC_VEC_OTHER, KC_SCALAR, KC_IMAGE, KC_NUM
+    KC_COIL_SUM, KC_VEC_DOT, KC_VEC_OTHER, KC_SCALAR, KC_IMAGE,
+    KC_CG_ITER,   // one whole CG iteration (its five launches), bracketed as one
+    KC_NUM
 };
 const char* kKClassNames[KC_NUM] = {
     "col_winv_ifft", "col_p_ifft", "col_fft_p", "col_resid_p_ifft", "col_psf",
     "col_fft_winv_add", "col_fft_gprod", "col_pupd_winv_ifft", "col_fft_winv_cg_update",
     "row_cache", "row_fwd", "row_deriv", "row_adj",
-    "coil_sum", "vec_dot", "vec_other", "scalar", "image"};
+    "coil_sum", "vec_dot", "vec_other", "scalar", "image", "cg_iteration"};
 
 int col_kclass(int mode) {
     switch (mode) {
@@ -703,6 +705,7 @@ int seq_cg_iteration(nlinv_plan_s* p, Class& C, int step, int it, int nsteps, in
                      hipStream_t s) {
     const Frames fr = class_frames(C);
     float2* TB = band_T(C, fr);
+    const int iter_slot = tbegin(p, KC_CG_ITER, s);
     ColArgs a = col_args(p, C, fr);
     a.in = C.p_c;
     a.out = TB;
@@ -786,6 +789,7 @@ int seq_cg_iteration(nlinv_plan_s* p, Class& C, int step, int it, int nsteps, in
     e.cs = cs;
     e.cs_blocks = C.nframes * cs.segs;
     CHK(run_col(p, C, COL_PAD_FFT_WINV_CG_UPD, e, fr.nplanes, s));
+    tend(p, iter_slot, s);
     // beta = <r,r>' / <r,r> from the |r|^2 partials: inside the next
     // iteration's first pass; after the last iteration (only its stats are
     // left) inside the next coil-map pass (the caller does that)
@@ -1058,6 +1062,7 @@ int setup_frames(nlinv_plan_s* p, const nlinv_frame* frames, const nlinv_irgnm_p
         // components outside the band: D = |x0 - x_ref|^2 there (nonzero only
         // for a caller's x_ref), theta = 1
         const double* dpart = nullptr;
+        const int dsegs = std::min(16, C.n / 4);   // row segments per plane (partials fit C.partial)
         if (any_ref && C.kb < C.n) {
             CHK(for_frame_batches(C, [&](int f0, int cnt) -> int {
                 BandBatch b{};
@@ -1071,14 +1076,14 @@ int setup_frames(nlinv_plan_s* p, const nlinv_frame* frames, const nlinv_irgnm_p
                     b.plane0[i] = C.plane0[lf];
                     maxp = std::max(maxp, C.J[lf]);
                 }
-                hipLaunchKernelGGL(k_inert_dist, dim3(maxp, cnt), dim3(kThreads), 0, s, b, C.partial, C.n, C.kb_lo,
-                                   C.kb);
+                hipLaunchKernelGGL(k_inert_dist, dim3(maxp * dsegs, cnt), dim3(kThreads), 0, s, b, C.partial, C.n,
+                                   C.kb_lo, C.kb, dsegs);
                 HIPCHK(hipGetLastError());
                 return NLINV_OK;
             }));
             dpart = C.partial;
         }
-        hipLaunchKernelGGL(k_inert_init, dim3(grid_for(C.nframes)), dim3(kThreads), 0, s, C.sc.inert, dpart,
+        hipLaunchKernelGGL(k_inert_init, dim3(grid_for(C.nframes)), dim3(kThreads), 0, s, C.sc.inert, dpart, dsegs,
                            (const int*)C.frame_plane0, (const int*)C.frame_planes, C.nplanes, C.nframes);
         HIPCHK(hipGetLastError());
     }
