@@ -7,6 +7,23 @@
 
 namespace nlinv {
 
+// One column mode: the Omega-half and compile-time-band variants when the
+// launch's geometry is theirs.
+template <int N, int L, int MODE, bool T>
+static void col_mode(const ColArgs& a, dim3 grid, dim3 block, hipStream_t s, bool half, bool bandc) {
+    constexpr bool CHAT = MODE == COL_WINV_IFFT_CROP || MODE == COL_PUPD_WINV_IFFT_CROP ||
+                          MODE == COL_PAD_FFT_WINV_ADD || MODE == COL_PAD_FFT_WINV_CG_UPD;
+    if constexpr (T && CHAT && Band<N>::OK) {
+        if (bandc) {
+            if (half) hipLaunchKernelGGL((k_col<N, L, MODE, true, true, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_col<N, L, MODE, true, false, true>), grid, block, 0, s, a);
+            return;
+        }
+    }
+    if (T && half) hipLaunchKernelGGL((k_col<N, L, MODE, T, T>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_col<N, L, MODE, T, false>), grid, block, 0, s, a);
+}
+
 template <int N, int L>
 static hipError_t col_L(int mode, const ColArgs& a, int nplanes, hipStream_t s) {
     // the sensitivity-side modes run over the kb columns of the band
@@ -21,9 +38,8 @@ static hipError_t col_L(int mode, const ColArgs& a, int nplanes, hipStream_t s) 
     const int extra = mode == COL_PAD_FFT_WINV_CG_UPD ? a.cs_blocks : 0;   // fused coil-sum workgroups
     const dim3 grid(8 * ((total + 7) / 8) + extra), block(pass_threads(N, L));
     const bool half = 2 * a.m == N && 4 * a.lo == N;
-#define NLINV_COL(MODE, T)                                                                   \
-    if (T && half) hipLaunchKernelGGL((k_col<N, L, MODE, T, T>), grid, block, 0, s, a);        \
-    else hipLaunchKernelGGL((k_col<N, L, MODE, T, false>), grid, block, 0, s, a)
+    const bool bandc = chat && a.kb == Band<N>::KB && a.kb_lo == Band<N>::KLO;
+#define NLINV_COL(MODE, T) col_mode<N, L, MODE, T>(a, grid, block, s, half, bandc)
     if (a.tiled) {   // inside a solve: every mode, Omega = the centred half specialised
         switch (mode) {
             case COL_WINV_IFFT_CROP: NLINV_COL(COL_WINV_IFFT_CROP, true); break;

@@ -44,6 +44,79 @@ struct Centre {
         return PERM ? k1 + N1 * ((k2 + N2 / 2) % N2) : k1 + N1 * k2;
     }
     static __device__ __forceinline__ float sign(int pos) { return PERM ? 1.0f : sgn(pos); }
+    // With the permutation, N2 a multiple of 4 and N/4 a multiple of N1, the
+    // stage-2 output slot k2 of every thread (any k1) lies in the centred half
+    // [N/4, 3N/4) of the line exactly when k2' = (k2 + N2/2) mod N2 is in
+    // [N2/4, 3 N2/4): which outputs fall in Omega = the centred half is then
+    // known at compile time.
+    static constexpr bool HALF_BY_K2 = PERM && N2 % 4 == 0 && (N / 4) % N1 == 0;
+    static constexpr bool half_k2(int k2) {
+        const int k = (k2 + N2 / 2) % N2;
+        return k >= N2 / 4 && k < 3 * N2 / 4;
+    }
+    // the i-th output slot in the centred half (N2/2 of them)
+    static constexpr int half_k2_at(int i) {
+        for (int k2 = 0; k2 < N2; ++k2)
+            if (half_k2(k2) && i-- == 0) return k2;
+        return -1;
+    }
+    // The same for the stage-1 input slots: with N1 a multiple of 4 and N/4
+    // a multiple of N2, slot k1 (positions j2 + N2 k1', any j2) lies in the
+    // centred half exactly when k1' = (k1 + N1/2) mod N1 is in [N1/4, 3 N1/4).
+    static constexpr bool HALF_BY_K1 = PERM && N1 % 4 == 0 && (N / 4) % N2 == 0;
+    static constexpr bool half_k1(int k1) {
+        const int k = (k1 + N1 / 2) % N1;
+        return k >= N1 / 4 && k < 3 * N1 / 4;
+    }
+};
+
+// The band the solves keep of the sensitivities for the default weight
+// (a = 220, l = 32): its side per grid size (the whole grid below 48).  The
+// host derives the band from the weight itself; a CPU test checks that this
+// table agrees, and a launch uses the compile-time geometry below only when
+// its band is this one.
+constexpr int default_band(int n) {
+    switch (n) {
+        case 48: case 64: case 96: return 32;
+        case 128: case 192: return 64;
+        case 256: return 96;
+        case 384: return 128;
+        case 512: return 160;
+        case 768: return 224;
+        case 1024: return 320;
+        default: return n;
+    }
+}
+
+// Compile-time geometry of the default band [KLO, KLO + KB) on a line of N
+// (with the centring permutation and the bounds multiples of N1): stage-2
+// output slot k2 of any thread lies in it exactly when k2' = (k2 + N2/2) mod
+// N2 is in [KLO/N1, (KLO + KB)/N1); stage-1 input slot k1 (positions
+// j2 + N2 k1') is wholly in it, wholly outside, or split by j2.
+template <int N>
+struct Band {
+    using CT = Centre<N>;
+    static constexpr int N1 = CT::N1, N2 = CT::N2;
+    static constexpr int KB = default_band(N), KLO = (N - KB) / 2;
+    static constexpr bool OK = CT::PERM && KB < N && KLO % N1 == 0 && KB % N1 == 0;
+    static constexpr bool out_k2(int k2) {
+        const int k = (k2 + N2 / 2) % N2;
+        return k >= KLO / N1 && k < (KLO + KB) / N1;
+    }
+    static constexpr int NOUT = KB / N1;    // output slots per thread in the band
+    static constexpr int out_k2_at(int i) {
+        for (int k2 = 0; k2 < N2; ++k2)
+            if (out_k2(k2) && i-- == 0) return k2;
+        return -1;
+    }
+    // 0: every position of input slot k1 outside the band, 1: every one
+    // inside, 2: split (decided per j2)
+    static constexpr int in_k1(int k1) {
+        const int r0 = N2 * ((k1 + N1 / 2) % N1), r1 = r0 + N2;
+        if (r1 <= KLO || r0 >= KLO + KB) return 0;
+        if (r0 >= KLO && r1 <= KLO + KB) return 1;
+        return 2;
+    }
 };
 
 // Inside a solve the n x n planes (CG vectors, data, P, 1/w) are stored
@@ -193,7 +266,10 @@ __device__ __forceinline__ bool col_item(int ntiles, int nplanes, int& tile, int
 // TILED: the n x n operands are in the column-tiled solve layout (as
 // ColArgs::tiled, fixed at compile time so no access computes both forms).
 // HALF: Omega is the centred n/2 x n/2 block (a.m and a.lo are then ignored).
-template <int N, int L, int MODE, bool TILED, bool HALF>
+// BANDC: a sensitivity-side mode on the default band of Band<N> (a.kb and
+// a.kb_lo are then ignored): which loads, stores and transform outputs fall
+// in the band is known at compile time.
+template <int N, int L, int MODE, bool TILED, bool HALF, bool BANDC = false>
 __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
     constexpr int NT = pass_threads(N, L);
     using CT = Centre<N>;
@@ -220,7 +296,9 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
     __shared__ double red[RED ? NT / 64 : 1];
     static_assert(NT % 64 == 0 && NT <= 1024, "pass workgroup size");
 
-    const int kb = CHAT ? a.kb : N, klo = CHAT ? a.kb_lo : 0;
+    using BD = Band<N>;
+    static_assert(!BANDC || (CHAT && TILED && BD::OK), "compile-time band");
+    const int kb = CHAT ? (BANDC ? BD::KB : a.kb) : N, klo = CHAT ? (BANDC ? BD::KLO : a.kb_lo) : 0;
     const int ncols = kb;                          // columns of this pass
     // element (grid row r, band column col) of a band-side array; whether
     // grid row r lies in the band
@@ -229,6 +307,18 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
         return TILED ? ((col / TW) * kb + rc) * TW + (col % TW) : rc * kb + col;
     };
     auto in_band = [&](int r) -> bool { return !CHAT || (unsigned)(r - klo) < (unsigned)kb; };
+    // whether position r of stage-1 input slot K1 lies in the band (decided
+    // at compile time with BANDC unless the slot is split by the band's edge)
+    auto in_band_k1 = [&](auto K1, int r) -> bool {
+        if constexpr (BANDC) {
+            constexpr int st = BD::in_k1(decltype(K1)::value);
+            if constexpr (st == 0) return false;
+            else if constexpr (st == 1) return true;
+            else return in_band(r);
+        } else {
+            return in_band(r);
+        }
+    };
     if constexpr (CGU) {
         const int ncol = 8 * ((ncols / L * a.nplanes + 7) / 8);
         if ((int)blockIdx.x >= ncol) {
@@ -255,7 +345,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
     float beta = 0.f;
     // PUPD: the first chunk of this thread's stage-1 operands, loaded before
     // beta is formed so that their latency overlaps the scalar fold
-    constexpr int CHP = PUPD ? pointwise_chunk(N1) : 1;
+    constexpr int CHP = PUPD ? (BANDC ? N1 : pointwise_chunk(N1)) : 1;
     float2 rv0[CHP], pv0[CHP];
     float w0[CHP];
     if constexpr (MODE == COL_WINV_IFFT_CROP) {
@@ -280,7 +370,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                 constexpr int k1 = I;
                 const int r = CT::in_pos(j2, k1);
                 const float2 z = make_float2(0.f, 0.f);
-                if (in_band(r)) {
+                if (in_band_k1(std::integral_constant<int, k1>{}, r)) {
                     const int o = cidx(r, col);
                     rv0[I] = elt(a.r_in + pofs, o);
                     pv0[I] = has_beta ? elt(src, o) : z;
@@ -360,7 +450,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                             rv[I] = make_float2(0.f, 0.f);
                             pv[I] = rv[I];
                             w[I] = 0.f;
-                            if (in_band(r)) {
+                            if (in_band_k1(std::integral_constant<int, k1>{}, r)) {
                                 const int o = cidx(r, col);
                                 rv[I] = elt(a.r_in + pofs, o);
                                 if constexpr (HB) pv[I] = elt(src, o);
@@ -376,7 +466,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                             x.x += b * pv[I].x;
                             x.y += b * pv[I].y;
                         }
-                        if (in_band(r)) {
+                        if (in_band_k1(std::integral_constant<int, k1>{}, r)) {
                             elt(a.p_out + pofs, cidx(r, col)) = x;
                             pacc += (double)(x.x * x.x + x.y * x.y);
                         }
@@ -391,11 +481,14 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                 constexpr int k1 = K;
                 const int r = CT::in_pos(j2, k1);
                 float2 x = make_float2(0.f, 0.f);
-                if constexpr (IN_CROP) {
+                if constexpr (IN_CROP && HALF && CT::HALF_BY_K1) {
+                    // Omega rows by slot, known at compile time
+                    if constexpr (CT::half_k1(k1)) x = cscale(elt(src, (r - lo) * ncols + col), CT::sign(r));
+                } else if constexpr (IN_CROP) {
                     const int ri = r - lo;
                     if (ri >= 0 && ri < m) x = cscale(elt(src, ri * ncols + col), CT::sign(r));
                 } else if constexpr (WINV_IN) {
-                    if (in_band(r)) {
+                    if (in_band_k1(std::integral_constant<int, k1>{}, r)) {
                         const int o = cidx(r, col);
                         x = cscale(elt(src, o), CT::sign(r) * elt(a.winv, o));
                     }
@@ -533,14 +626,17 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
         if constexpr (OUT_CROP) {
             static_for<0, N2>([&](auto K) {
                 constexpr int k2 = K;
-                // TWO: the forward pass left slots in place, so the inverse's
-                // output slot s sits at position s; its pre-shift is in the
-                // input slots (P^2 was applied at the shifted positions)
-                const int rp = CT::out_pos(k1, k2);
-                const int ri = rp - lo;
-                if (ri >= 0 && ri < m) {
-                    const float s = TWO ? CT::sign(rp) : CT::sign(rp) * a.rs;
-                    elt(a.out + (long long)plane * m * ncols, ri * ncols + col) = cscale(v[k2], s);
+                // HALF: the slots outside Omega are known at compile time
+                if constexpr (!HALF || !CT::HALF_BY_K2 || CT::half_k2(k2)) {
+                    // TWO: the forward pass left slots in place, so the inverse's
+                    // output slot s sits at position s; its pre-shift is in the
+                    // input slots (P^2 was applied at the shifted positions)
+                    const int rp = CT::out_pos(k1, k2);
+                    const int ri = rp - lo;
+                    if (ri >= 0 && ri < m) {
+                        const float s = TWO ? CT::sign(rp) : CT::sign(rp) * a.rs;
+                        elt(a.out + (long long)plane * m * ncols, ri * ncols + col) = cscale(v[k2], s);
+                    }
                 }
             });
         } else {
@@ -549,16 +645,18 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
             // stored.  (A store may alias a later operand as far as the
             // compiler can tell, so output-by-output code waits for each
             // output's loads in turn.)
-            constexpr int CH = pointwise_chunk(N2, CGU ? kCgChunk : 8);
+            // BANDC: only the output slots in the band, all in one round
+            constexpr int NOUT = BANDC ? BD::NOUT : N2;
+            constexpr int CH = BANDC ? NOUT : pointwise_chunk(N2, CGU ? kCgChunk : 8);
             auto chunks = [&](auto HAS1, auto HAS2) {
                 constexpr bool H1 = decltype(HAS1)::value, H2 = decltype(HAS2)::value;
-                static_for<0, N2 / CH>([&](auto C) {
+                static_for<0, NOUT / CH>([&](auto C) {
                     float w[CH];
                     float2 u1[CH], u2[CH], u3[CH];
                     static_for<0, CH>([&](auto I) {
-                        constexpr int k2 = C * CH + I;
+                        constexpr int k2 = BANDC ? BD::out_k2_at(C * CH + I) : C * CH + I;
                         const int rp = CT::out_pos(k1, k2);
-                        if (in_band(rp)) {
+                        if (BANDC || in_band(rp)) {
                             const int o = CHAT ? cidx(rp, col) : big_idx<N>(rp, col, TILED);
                             if constexpr (MODE == COL_PAD_FFT_P) w[I] = elt(P, o);
                             if constexpr (WINV_OUT || CGU) w[I] = elt(a.winv, o);
@@ -572,9 +670,9 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                         }
                     });
                     static_for<0, CH>([&](auto I) {
-                        constexpr int k2 = C * CH + I;
+                        constexpr int k2 = BANDC ? BD::out_k2_at(C * CH + I) : C * CH + I;
                         const int rp = CT::out_pos(k1, k2);
-                        if (!in_band(rp)) return;         // outside the band: not stored
+                        if (!BANDC && !in_band(rp)) return;   // outside the band: not stored
                         const int o = CHAT ? cidx(rp, col) : big_idx<N>(rp, col, TILED);
                         float2 x = v[k2];
                         if constexpr (MODE == COL_PAD_FFT_P) {
@@ -751,10 +849,51 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
                 if constexpr (MODE == ROW_CACHE) {
                     static_for<0, N2>([&](auto K) {
                         constexpr int k2 = K;
-                        const int pos = CT::out_pos(k1, k2);
-                        const int q = pos - lo;
-                        if (live && q >= 0 && q < m)
-                            elt(a.c_out + (long long)line0 * m, (line_c - line0) * m + q) = cscale(v[k2], CT::sign(pos) * a.rs);
+                        if constexpr (!HALF || !CT::HALF_BY_K2 || CT::half_k2(k2)) {
+                            const int pos = CT::out_pos(k1, k2);
+                            const int q = pos - lo;
+                            if (live && q >= 0 && q < m)
+                                elt(a.c_out + (long long)line0 * m, (line_c - line0) * m + q) =
+                                    cscale(v[k2], CT::sign(pos) * a.rs);
+                        }
+                    });
+                } else if constexpr (HALF && CT::HALF_BY_K2) {
+                    // Omega = the centred half, its output slots known at
+                    // compile time (N2/2 of them): their operands are loaded
+                    // in one round (two for the derivative's three operands)
+                    // before any product is formed or stored
+                    constexpr int NO = N2 / 2;
+                    constexpr int RCH = MODE == ROW_DERIV ? (NO % 2 == 0 ? NO / 2 : NO) : NO;
+                    const int cofs = (line_c - line0) * m;
+                    const float2* crow = a.c + (long long)line0 * m;
+                    const float2* rrow = a.rho + ((long long)f * m + i) * m;
+                    const float2* drow = MODE == ROW_DERIV ? a.drho + ((long long)f * m + i) * m : nullptr;
+                    static_for<0, N2>([&](auto K) {
+                        constexpr int k2 = K;
+                        if constexpr (!CT::half_k2(k2)) v[k2] = make_float2(0.f, 0.f);
+                    });
+                    static_for<0, NO / RCH>([&](auto R) {
+                        float2 cv[RCH], rv[RCH], dv[RCH];
+                        static_for<0, RCH>([&](auto I) {
+                            constexpr int k2 = CT::half_k2_at(decltype(R)::value * RCH + I);
+                            const int q = CT::out_pos(k1, k2) - lo;     // in [0, m)
+                            cv[I] = elt(crow, cofs + q);
+                            rv[I] = elt(rrow, q);
+                            if constexpr (MODE == ROW_DERIV) dv[I] = elt(drow, q);
+                        });
+                        static_for<0, RCH>([&](auto I) {
+                            constexpr int k2 = CT::half_k2_at(decltype(R)::value * RCH + I);
+                            const int pos = CT::out_pos(k1, k2);
+                            const float2 u = cscale(v[k2], CT::sign(pos) * a.rs);
+                            float2 z;
+                            if constexpr (MODE == ROW_DERIV) {
+                                z = cadd(cmul(dv[I], cv[I]), cmul(rv[I], u));
+                            } else {  // ROW_ADJ
+                                if (live) elt(a.aux + (long long)line0 * m, cofs + (pos - lo)) = cconjmul(cv[I], u);
+                                z = cconjmul(rv[I], u);
+                            }
+                            v[k2] = live ? cscale(z, CT::sign(pos)) : make_float2(0.f, 0.f);
+                        });
                     });
                 } else {
                     // the pointwise products, CH outputs at a time: the operands
@@ -801,9 +940,11 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
             if (act) {
                 static_for<0, N2>([&](auto K) {
                     constexpr int k2 = K;
-                    const int pos = CT::out_pos(k1, k2);
-                    // HALF: the positions outside Omega are never read below
-                    if (!HALF || (pos >= lo && pos < lo + m)) buf[ll * N + pos] = v[k2];
+                    if constexpr (!HALF || !CT::HALF_BY_K2 || CT::half_k2(k2)) {
+                        const int pos = CT::out_pos(k1, k2);
+                        // HALF: the positions outside Omega are never read below
+                        if (!HALF || (pos >= lo && pos < lo + m)) buf[ll * N + pos] = v[k2];
+                    }
                 });
             }
         }

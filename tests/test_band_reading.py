@@ -68,3 +68,21 @@ def test_components_outside_the_band_do_not_reach_df(n, n_om, J):
     scale = np.linalg.norm(dchat) + np.linalg.norm(drho)
     assert np.linalg.norm(nr - br) <= 2.0 ** -40 * scale
     assert np.linalg.norm(nc - bc) <= 2.0 ** -40 * scale
+
+
+def test_compile_time_band_table_is_the_weights_band():
+    """The kernels' compile-time band geometry for the default weight
+    (default_band in the pass kernels' source) is the band the weight
+    defines, at every grid size the library is built for."""
+    import os
+    import re
+    src = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1301_1215_amd",
+                            "csrc", "pass_kernels.hpp")).read()
+    body = src[src.index("constexpr int default_band(int n)"):]
+    body = body[:body.index("\n}\n")]
+    table = {}
+    for cases, val in re.findall(r"((?:case \d+: )+)return (\d+);", body):
+        for c in re.findall(r"case (\d+):", cases):
+            table[int(c)] = int(val)
+    for n in (8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024):
+        assert table.get(n, n) == 2 * band_half(n), n
