@@ -863,7 +863,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
                     // in one round (two for the derivative's three operands)
                     // before any product is formed or stored
                     constexpr int NO = N2 / 2;
-                    constexpr int RCH = MODE == ROW_DERIV ? (NO % 2 == 0 ? NO / 2 : NO) : NO;
+                    constexpr int RCH = NO % 2 == 0 ? NO / 2 : NO;
                     const int cofs = (line_c - line0) * m;
                     const float2* crow = a.c + (long long)line0 * m;
                     const float2* rrow = a.rho + ((long long)f * m + i) * m;
@@ -872,6 +872,10 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
                         constexpr int k2 = K;
                         if constexpr (!CT::half_k2(k2)) v[k2] = make_float2(0.f, 0.f);
                     });
+                    // ROW_ADJ: the coil products of every round are stored
+                    // after the last round's loads (a store between two load
+                    // rounds would hold the second one back)
+                    float2 aux[MODE == ROW_ADJ ? NO : 1];
                     static_for<0, NO / RCH>([&](auto R) {
                         float2 cv[RCH], rv[RCH], dv[RCH];
                         static_for<0, RCH>([&](auto I) {
@@ -882,19 +886,28 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
                             if constexpr (MODE == ROW_DERIV) dv[I] = elt(drow, q);
                         });
                         static_for<0, RCH>([&](auto I) {
-                            constexpr int k2 = CT::half_k2_at(decltype(R)::value * RCH + I);
+                            constexpr int o = decltype(R)::value * RCH + I;
+                            constexpr int k2 = CT::half_k2_at(o);
                             const int pos = CT::out_pos(k1, k2);
                             const float2 u = cscale(v[k2], CT::sign(pos) * a.rs);
                             float2 z;
                             if constexpr (MODE == ROW_DERIV) {
                                 z = cadd(cmul(dv[I], cv[I]), cmul(rv[I], u));
                             } else {  // ROW_ADJ
-                                if (live) elt(a.aux + (long long)line0 * m, cofs + (pos - lo)) = cconjmul(cv[I], u);
+                                aux[o] = cconjmul(cv[I], u);
                                 z = cconjmul(rv[I], u);
                             }
                             v[k2] = live ? cscale(z, CT::sign(pos)) : make_float2(0.f, 0.f);
                         });
                     });
+                    if constexpr (MODE == ROW_ADJ) {
+                        if (live) {
+                            static_for<0, NO>([&](auto O) {
+                                constexpr int k2 = CT::half_k2_at(O);
+                                elt(a.aux + (long long)line0 * m, cofs + (CT::out_pos(k1, k2) - lo)) = aux[O];
+                            });
+                        }
+                    }
                 } else {
                     // the pointwise products, CH outputs at a time: the operands
                     // of a chunk are loaded (from a valid column for outputs
