@@ -257,6 +257,32 @@ int nlinv_plan_timing_read_class(nlinv_plan plan, int32_t kclass, int32_t* launc
  * whole CG iteration (its five launches) as one. */
 const char* nlinv_kernel_class_name(int32_t kclass);   /* NULL past the last */
 
+/* ---- gridding of radial samples -------------------------------------------
+ * The step before the reconstruction (Sec. 3.1: the non-Cartesian samples
+ * are interpolated to the grid; Sec. 3.2: on a grid doubled for the
+ * interpolation's accuracy): convolution gridding with a separable
+ * Kaiser-Bessel window, and its adjoint.  Spoke s (angle angles[s], radians)
+ * carries R samples at radii r_i = i - floor(R/2) (grid units), at
+ * k_si = (n/2 + r_i cos angles[s], n/2 + r_i sin angles[s]) (DC at n/2 along
+ * both axes); the window is kb(d0) kb(d1) with
+ * kb(d) = I0(beta sqrt(1 - (2d/width)^2)) / I0(beta) for |d| <= width/2, and
+ * a window that crosses the grid's edge wraps around.  dcf [R] (nullable:
+ * all 1) weights the samples by radius (density compensation).
+ *   nlinv_grid_radial:   grid_out[j][u][v] = sum_{s,i} dcf[i] data[j][s][i] window(u, v; k_si)
+ *   nlinv_degrid_radial: data_out[j][s][i] = dcf[i] sum_{u,v} window(u, v; k_si) grid[j][u][v]
+ * data [J][S][R] and grids [J][n][n] complex; angles [S] and dcf [R] float32;
+ * all device pointers (complex arrays 8-byte, float arrays 4-byte aligned).
+ * Gridding all-ones data (J = 1) gives the sampling density, the k-space
+ * weights P of the reconstruction.  Every output element is written by one
+ * thread in a fixed order (deterministic); positions, window membership and
+ * the window are evaluated in double precision, the sums in single.
+ * NLINV_EINVAL for S outside 1..1024, width outside (0, n), negative beta,
+ * NULL or misaligned pointers.  No plan, no allocation. */
+int nlinv_grid_radial(int32_t n, int32_t J, int32_t S, int32_t R, const float* angles, const float* dcf,
+                      float width, float beta, const nlinv_c32* data, nlinv_c32* grid_out, void* stream);
+int nlinv_degrid_radial(int32_t n, int32_t J, int32_t S, int32_t R, const float* angles, const float* dcf,
+                        float width, float beta, const nlinv_c32* grid, nlinv_c32* data_out, void* stream);
+
 /* ---- measurement ----------------------------------------------------------
  * Bandwidth probe: copy `bytes` (a multiple of 16) from src to dst (device,
  * 16-byte aligned, not overlapping) with a plain streaming kernel.  It gives

@@ -25,6 +25,7 @@ EXPORTED = (
     "nlinv_plan_set_variant", "nlinv_plan_timing_enable", "nlinv_plan_timing_read",
     "nlinv_plan_timing_read_class",
     "nlinv_kernel_class_name", "nlinv_status_string", "nlinv_last_hip_error", "nlinv_bandwidth_probe",
+    "nlinv_grid_radial", "nlinv_degrid_radial",
 )
 
 
@@ -92,6 +93,8 @@ def load(path: str | None = None):
         "nlinv_kernel_class_name": ([i32], C.c_char_p),
         "nlinv_status_string": ([C.c_int], C.c_char_p),
         "nlinv_bandwidth_probe": ([vp, vp, C.c_size_t, vp], C.c_int),
+        "nlinv_grid_radial": ([i32, i32, i32, i32, vp, vp, f32, f32, vp, vp, vp], C.c_int),
+        "nlinv_degrid_radial": ([i32, i32, i32, i32, vp, vp, f32, f32, vp, vp, vp], C.c_int),
         "nlinv_last_hip_error": ([], C.c_int),
     }
     for name, (args, res) in sig.items():
@@ -427,3 +430,39 @@ def nlinv_bandwidth_probe(src, dst, nbytes=None, stream=None):
     nbytes = src.numel() * src.element_size() if nbytes is None else int(nbytes)
     check(load().nlinv_bandwidth_probe(_ptr(src, None, "src"), _ptr(dst, None, "dst"), nbytes, _stream(stream)),
           "nlinv_bandwidth_probe")
+
+
+def nlinv_grid_radial(n, angles, data, width, beta, dcf=None, grid_out=None, stream=None):
+    """data [J, S, R] complex64, angles [S] float32 (radians), dcf [R] float32
+    or None -> grid [J, n, n] complex64 (allocated when grid_out is None)."""
+    import torch
+    if data.dim() != 3:
+        raise ValueError(f"data: expected [J, S, R], got shape {tuple(data.shape)}")
+    J, S, R = data.shape
+    _expect(angles, (S,), "angles")
+    _expect(dcf, (R,), "dcf")
+    if grid_out is None:
+        grid_out = torch.empty((J, n, n), dtype=torch.complex64, device=data.device)
+    _expect(grid_out, (J, n, n), "grid_out")
+    check(load().nlinv_grid_radial(int(n), J, S, R, _f32(angles, "angles"), _f32(dcf, "dcf"), float(width),
+                                   float(beta), _c64(data, "data"), _c64(grid_out, "grid_out"), _stream(stream)),
+          "nlinv_grid_radial")
+    return grid_out
+
+
+def nlinv_degrid_radial(grid, angles, R, width, beta, dcf=None, data_out=None, stream=None):
+    """grid [J, n, n] complex64 -> samples [J, S, R] complex64."""
+    import torch
+    if grid.dim() != 3 or grid.shape[1] != grid.shape[2]:
+        raise ValueError(f"grid: expected [J, n, n], got shape {tuple(grid.shape)}")
+    J, n = grid.shape[0], grid.shape[1]
+    S = angles.shape[0]
+    _expect(dcf, (R,), "dcf")
+    if data_out is None:
+        data_out = torch.empty((J, S, R), dtype=torch.complex64, device=grid.device)
+    _expect(data_out, (J, S, R), "data_out")
+    check(load().nlinv_degrid_radial(int(n), J, S, int(R), _f32(angles, "angles"), _f32(dcf, "dcf"), float(width),
+                                     float(beta), _c64(grid, "grid"), _c64(data_out, "data_out"), _stream(stream)),
+          "nlinv_degrid_radial")
+    return data_out
+

@@ -20,6 +20,7 @@
 
 #include "nlinv.h"
 #include "aux_kernels.hpp"
+#include "gridding.hpp"
 #include "launch.hpp"
 
 using namespace nlinv;
@@ -1537,6 +1538,42 @@ int nlinv_bandwidth_probe(const void* src, void* dst, size_t bytes, void* stream
     if (n16 == 0) return NLINV_OK;
     hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(kThreads), 0, (hipStream_t)stream,
                        (const probe_v4*)src, (probe_v4*)dst, n16);
+    HIPCHK(hipGetLastError());
+    return NLINV_OK;
+}
+
+// ---- gridding of radial samples (Sec. 3.1-3.2) ------------------------------
+
+static int grid_check(int32_t n, int32_t J, int32_t S, int32_t R, const float* angles, const float* dcf, float width,
+                      float beta, const void* in, const void* out) {
+    if (n < 1 || n > 65536 || J < 1 || J > 65535 * kGridCoilChunk || S < 1 || S > kMaxSpokes || R < 1) return NLINV_EINVAL;
+    if ((long long)S * R > (1LL << 30)) return NLINV_EINVAL;
+    if (!(width > 0.f) || !(width < (float)n) || !(beta >= 0.f) || !std::isfinite(beta)) return NLINV_EINVAL;
+    if (!angles || !in || !out || ((uintptr_t)angles & 3) || (dcf && ((uintptr_t)dcf & 3)) ||
+        ((uintptr_t)in & 7) || ((uintptr_t)out & 7))
+        return NLINV_EINVAL;
+    return NLINV_OK;
+}
+
+int nlinv_grid_radial(int32_t n, int32_t J, int32_t S, int32_t R, const float* angles, const float* dcf, float width,
+                      float beta, const nlinv_c32* data, nlinv_c32* grid_out, void* stream) {
+    CHK(grid_check(n, J, S, R, angles, dcf, width, beta, data, grid_out));
+    GridArgs g{n, J, S, R, angles, dcf, (double)width, (double)beta, (const float2*)data, (float2*)grid_out,
+               nullptr};
+    const long long nn = (long long)n * n;
+    hipLaunchKernelGGL(k_grid_radial, dim3((unsigned)((nn + kThreads - 1) / kThreads), (J + kGridCoilChunk - 1) / kGridCoilChunk),
+                       dim3(kThreads), 0, (hipStream_t)stream, g);
+    HIPCHK(hipGetLastError());
+    return NLINV_OK;
+}
+
+int nlinv_degrid_radial(int32_t n, int32_t J, int32_t S, int32_t R, const float* angles, const float* dcf,
+                        float width, float beta, const nlinv_c32* grid, nlinv_c32* data_out, void* stream) {
+    CHK(grid_check(n, J, S, R, angles, dcf, width, beta, grid, data_out));
+    GridArgs g{n, J, S, R, angles, dcf, (double)width, (double)beta, nullptr, (float2*)data_out, (const float2*)grid};
+    const long long ns = (long long)S * R;
+    hipLaunchKernelGGL(k_degrid_radial, dim3((unsigned)((ns + kThreads - 1) / kThreads), (J + kGridCoilChunk - 1) / kGridCoilChunk),
+                       dim3(kThreads), 0, (hipStream_t)stream, g);
     HIPCHK(hipGetLastError());
     return NLINV_OK;
 }

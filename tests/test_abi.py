@@ -142,3 +142,18 @@ def test_noalloc_normal_refuses_before_touching_a_gpu():
     assert N.noalloc_scratch_need(1024, 512, 16, with_c=False) > N.NOALLOC_SCRATCH_BYTES
     assert call(1024, 512, 16, c=None) == N.NLINV_ESCRATCH
     assert lib.nlinv_status_string(N.NLINV_ESCRATCH).decode().startswith("frame too large")
+
+
+def test_gridding_refuses_bad_arguments_before_touching_a_gpu():
+    lib = N.load()
+    fake = ctypes.c_void_p(1 << 20)
+    def call(n=64, J=2, S=3, R=64, width=4.0, beta=9.0, angles=fake, data=fake, dcf=None):
+        return lib.nlinv_grid_radial(n, J, S, R, angles, dcf, width, beta, data, fake, None)
+    assert call(width=64.0) == N.NLINV_EINVAL          # window as wide as the grid
+    assert call(width=0.0) == N.NLINV_EINVAL
+    assert call(beta=-1.0) == N.NLINV_EINVAL
+    assert call(S=0) == N.NLINV_EINVAL
+    assert call(S=1025) == N.NLINV_EINVAL
+    assert call(angles=None) == N.NLINV_EINVAL
+    assert call(data=ctypes.c_void_p((1 << 20) + 4)) == N.NLINV_EINVAL   # complex data 8-byte aligned
+    assert lib.nlinv_degrid_radial(64, 2, 3, 64, fake, None, 4.0, 9.0, fake, None, None) == N.NLINV_EINVAL
