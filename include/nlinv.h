@@ -283,6 +283,26 @@ int nlinv_grid_radial(int32_t n, int32_t J, int32_t S, int32_t R, const float* a
 int nlinv_degrid_radial(int32_t n, int32_t J, int32_t S, int32_t R, const float* angles, const float* dcf,
                         float width, float beta, const nlinv_c32* grid, nlinv_c32* data_out, void* stream);
 
+/* ---- PCA channel compression ---------------------------------------------
+ * Sec. 3.2: the receive channels are compressed by a principal component
+ * analysis before the reconstruction (32 to 8-12 in the paper).  y [J][M]
+ * holds every channel's M samples (e.g. M = n*n k-space grid points; zeros
+ * add nothing).  The channel covariance A[i][k] = sum_m y_i[m] conj(y_k[m])
+ * (products of the single-precision samples summed in double precision) is
+ * decomposed A = V diag(lambda) V^H (cyclic Jacobi in double precision on
+ * the GPU), lambda descending, each eigenvector scaled so that its
+ * largest-magnitude entry is real and positive (the first on a tie); then
+ * y_out[k][m] = sum_j conj(V[j][k]) y[j][m] for the K kept virtual channels.
+ * eigvals_out [J] (double) and basis_out [J][K] (complex64, column k the k-th
+ * eigenvector) are nullable.  The caller provides `workspace` (device, 16-byte
+ * aligned) of at least nlinv_coil_compress_workspace(J, M) bytes (0 for bad
+ * J or M); the call allocates nothing.  NLINV_EINVAL for J outside 1..64, K
+ * outside 1..J, M < 1, a small workspace, NULL or misaligned pointers. */
+size_t nlinv_coil_compress_workspace(int32_t J, int64_t M);
+int nlinv_coil_compress(int32_t J, int64_t M, int32_t K, const nlinv_c32* y, nlinv_c32* y_out,
+                        double* eigvals_out, nlinv_c32* basis_out, void* workspace, size_t workspace_bytes,
+                        void* stream);
+
 /* ---- measurement ----------------------------------------------------------
  * Bandwidth probe: copy `bytes` (a multiple of 16) from src to dst (device,
  * 16-byte aligned, not overlapping) with a plain streaming kernel.  It gives

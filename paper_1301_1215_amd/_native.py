@@ -25,7 +25,7 @@ EXPORTED = (
     "nlinv_plan_set_variant", "nlinv_plan_timing_enable", "nlinv_plan_timing_read",
     "nlinv_plan_timing_read_class",
     "nlinv_kernel_class_name", "nlinv_status_string", "nlinv_last_hip_error", "nlinv_bandwidth_probe",
-    "nlinv_grid_radial", "nlinv_degrid_radial",
+    "nlinv_grid_radial", "nlinv_degrid_radial", "nlinv_coil_compress_workspace", "nlinv_coil_compress",
 )
 
 
@@ -94,6 +94,8 @@ def load(path: str | None = None):
         "nlinv_status_string": ([C.c_int], C.c_char_p),
         "nlinv_bandwidth_probe": ([vp, vp, C.c_size_t, vp], C.c_int),
         "nlinv_grid_radial": ([i32, i32, i32, i32, vp, vp, f32, f32, vp, vp, vp], C.c_int),
+        "nlinv_coil_compress_workspace": ([i32, C.c_int64], C.c_size_t),
+        "nlinv_coil_compress": ([i32, C.c_int64, i32, vp, vp, vp, vp, vp, C.c_size_t, vp], C.c_int),
         "nlinv_degrid_radial": ([i32, i32, i32, i32, vp, vp, f32, f32, vp, vp, vp], C.c_int),
         "nlinv_last_hip_error": ([], C.c_int),
     }
@@ -465,4 +467,24 @@ def nlinv_degrid_radial(grid, angles, R, width, beta, dcf=None, data_out=None, s
                                      float(beta), _c64(grid, "grid"), _c64(data_out, "data_out"), _stream(stream)),
           "nlinv_degrid_radial")
     return data_out
+
+
+def nlinv_coil_compress(y, K, stream=None):
+    """y [J, ...] complex64 (each channel's samples) -> (y' [K, ...] complex64,
+    eigenvalues [J] float64 descending, basis [J, K] complex64); the
+    workspace is allocated here with torch (the caller side of the ABI)."""
+    import torch
+    J = y.shape[0]
+    M = y.numel() // J
+    ws_bytes = load().nlinv_coil_compress_workspace(int(J), int(M))
+    if ws_bytes == 0:
+        raise ValueError(f"nlinv_coil_compress: unsupported J = {J} or M = {M}")
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=y.device)
+    out = torch.empty((int(K),) + tuple(y.shape[1:]), dtype=torch.complex64, device=y.device)
+    lam = torch.empty(J, dtype=torch.float64, device=y.device)
+    V = torch.empty((J, int(K)), dtype=torch.complex64, device=y.device)
+    check(load().nlinv_coil_compress(int(J), int(M), int(K), _c64(y, "y"), _c64(out, "y_out"),
+                                     _ptr(lam, torch.float64, "eigvals"), _c64(V, "basis"), ws.data_ptr(), ws_bytes,
+                                     _stream(stream)), "nlinv_coil_compress")
+    return out, lam, V
 

@@ -20,6 +20,7 @@
 
 #include "nlinv.h"
 #include "aux_kernels.hpp"
+#include "coil_pca.hpp"
 #include "gridding.hpp"
 #include "launch.hpp"
 
@@ -1574,6 +1575,68 @@ int nlinv_degrid_radial(int32_t n, int32_t J, int32_t S, int32_t R, const float*
     const long long ns = (long long)S * R;
     hipLaunchKernelGGL(k_degrid_radial, dim3((unsigned)((ns + kThreads - 1) / kThreads), (J + kGridCoilChunk - 1) / kGridCoilChunk),
                        dim3(kThreads), 0, (hipStream_t)stream, g);
+    HIPCHK(hipGetLastError());
+    return NLINV_OK;
+}
+
+// ---- PCA channel compression (Sec. 3.2) ---------------------------------------
+
+static void pca_layout(int32_t J, int64_t M, long long* chunk, int* G, size_t* off_A, size_t* off_l, size_t* off_V,
+                       size_t* total) {
+    long long c = std::max<long long>(kPcaChunk, (M + kPcaMaxPartials - 1) / kPcaMaxPartials);
+    c = (c + kPcaTile - 1) / kPcaTile * kPcaTile;
+    *chunk = c;
+    *G = (int)((M + c - 1) / c);
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t jj = (size_t)J * J;
+    *off_A = up((size_t)*G * jj * sizeof(double2));
+    *off_l = *off_A + up(jj * sizeof(double2));
+    *off_V = *off_l + up((size_t)J * sizeof(double));
+    *total = *off_V + up(jj * sizeof(float2));
+}
+
+size_t nlinv_coil_compress_workspace(int32_t J, int64_t M) {
+    if (J < 1 || J > kPcaMaxJ || M < 1) return 0;
+    long long chunk;
+    int G;
+    size_t a, l, v, t;
+    pca_layout(J, M, &chunk, &G, &a, &l, &v, &t);
+    return t;
+}
+
+int nlinv_coil_compress(int32_t J, int64_t M, int32_t K, const nlinv_c32* y, nlinv_c32* y_out, double* eigvals_out,
+                        nlinv_c32* basis_out, void* workspace, size_t workspace_bytes, void* stream) {
+    if (J < 1 || J > kPcaMaxJ || K < 1 || K > J || M < 1) return NLINV_EINVAL;
+    if (!y || !y_out || !workspace || ((uintptr_t)y & 7) || ((uintptr_t)y_out & 7) || ((uintptr_t)workspace & 15) ||
+        (eigvals_out && ((uintptr_t)eigvals_out & 7)) || (basis_out && ((uintptr_t)basis_out & 7)))
+        return NLINV_EINVAL;
+    long long chunk;
+    int G;
+    size_t oA, ol, oV, total;
+    pca_layout(J, M, &chunk, &G, &oA, &ol, &oV, &total);
+    if (workspace_bytes < total) return NLINV_EINVAL;
+    unsigned char* ws = static_cast<unsigned char*>(workspace);
+    PcaArgs a{};
+    a.J = J;
+    a.K = K;
+    a.M = M;
+    a.G = G;
+    a.chunk = chunk;
+    a.y = (const float2*)y;
+    a.partial = reinterpret_cast<double2*>(ws);
+    a.A = reinterpret_cast<double2*>(ws + oA);
+    a.lambda = eigvals_out ? eigvals_out : reinterpret_cast<double*>(ws + ol);
+    a.V = basis_out ? (float2*)basis_out : reinterpret_cast<float2*>(ws + oV);
+    a.y_out = (float2*)y_out;
+    const hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_pca_cov_partial, dim3(G), dim3(kThreads), 0, s, a);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_pca_cov_reduce, dim3((J * J + kThreads - 1) / kThreads), dim3(kThreads), 0, s, a);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_pca_eig, dim3(1), dim3(kThreads), 0, s, a);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_pca_compress, dim3((unsigned)((M + kThreads - 1) / kThreads), (K + kPcaCompressK - 1) / kPcaCompressK),
+                       dim3(kThreads), 0, s, a);
     HIPCHK(hipGetLastError());
     return NLINV_OK;
 }

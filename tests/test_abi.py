@@ -157,3 +157,19 @@ def test_gridding_refuses_bad_arguments_before_touching_a_gpu():
     assert call(angles=None) == N.NLINV_EINVAL
     assert call(data=ctypes.c_void_p((1 << 20) + 4)) == N.NLINV_EINVAL   # complex data 8-byte aligned
     assert lib.nlinv_degrid_radial(64, 2, 3, 64, fake, None, 4.0, 9.0, fake, None, None) == N.NLINV_EINVAL
+
+
+def test_coil_compression_refuses_bad_arguments_before_touching_a_gpu():
+    lib = N.load()
+    fake = ctypes.c_void_p(1 << 20)
+    assert lib.nlinv_coil_compress_workspace(0, 100) == 0
+    assert lib.nlinv_coil_compress_workspace(65, 100) == 0
+    need = lib.nlinv_coil_compress_workspace(8, 4096)
+    assert need > 0
+    def call(J=8, M=4096, K=3, ws=need, y=fake):
+        return lib.nlinv_coil_compress(J, M, K, y, fake, None, None, fake, ws, None)
+    assert call(K=0) == N.NLINV_EINVAL
+    assert call(K=9) == N.NLINV_EINVAL
+    assert call(ws=need - 1) == N.NLINV_EINVAL
+    assert call(y=None) == N.NLINV_EINVAL
+    assert call(J=65) == N.NLINV_EINVAL
