@@ -207,6 +207,32 @@ int nlinv_irgnm_solve_batch(nlinv_plan plan, const nlinv_frame* frames,
 int nlinv_irgnm_solve_series(nlinv_plan plan, int32_t count, const nlinv_frame* frames,
                              const nlinv_irgnm_params* prm, void* stream);
 
+/* ---- differentiation through a Gauss-Newton step --------------------------
+ * The regularised Gauss-Newton step of Eq. 3 as a differentiable map, its
+ * linearisation point x_n held fixed: x_{n+1} = x_n + dx with
+ *   (DF^H DF + alpha I) dx = DF^H (y - F x_n) - alpha (x_n - x_ref)
+ * (forward: nlinv_irgnm_solve with newton_steps = 1, alpha0 = alpha,
+ * scale_norm = 0, NLINV_WARM_START, x0 = x_n, the references x_ref).  Given
+ * g = dL/dx_{n+1} (g_rho [n_om][n_om], g_chat [J][n][n]; complex gradients
+ * as dL/dRe + i dL/dIm), with lambda = (DF^H DF + alpha I)^{-1} g solved by
+ * cg_iters CG iterations of the same solver:
+ *   grad_y        = DF lambda                                  [J][n][n]
+ *   grad_*_ref    = alpha lambda                               (both or neither)
+ *   grad_alpha    = -Re<lambda, x_{n+1} - x_ref>               (one device double)
+ *   grad_P        = Re sum_j conj(u_j) (y_j - 2 P w_j)         [n][n] float32
+ *                   u = A lambda, w = A (x_{n+1} - x_n / 2), A = DF at x_n with P = 1
+ * (F is bilinear, so F(x_n) + A dx = A (x_{n+1} - x_n / 2)).  rho_next,
+ * chat_next: the forward's result.  Every output is nullable.  The caller
+ * provides `workspace` (device, 16-byte aligned) of at least
+ * nlinv_gn_step_vjp_workspace(plan) bytes.  Plans of one frame only. */
+size_t nlinv_gn_step_vjp_workspace(nlinv_plan plan);
+int nlinv_gn_step_vjp(nlinv_plan plan, const nlinv_c32* rho_n, const nlinv_c32* chat_n, const nlinv_c32* y,
+                      const float* P, float alpha, const nlinv_c32* rho_next, const nlinv_c32* chat_next,
+                      const nlinv_c32* rho_ref, const nlinv_c32* chat_ref, const nlinv_c32* g_rho,
+                      const nlinv_c32* g_chat, int32_t cg_iters, nlinv_c32* grad_y, nlinv_c32* grad_rho_ref,
+                      nlinv_c32* grad_chat_ref, float* grad_P, double* grad_alpha, void* workspace,
+                      size_t workspace_bytes, void* stream);
+
 /* ---- autotuning -----------------------------------------------------------
  * Time the FFT pass variants (lines per workgroup) of every pass mode for
  * every shape class of the plan on `stream` (which must not be capturing),

@@ -26,6 +26,7 @@ EXPORTED = (
     "nlinv_plan_timing_read_class",
     "nlinv_kernel_class_name", "nlinv_status_string", "nlinv_last_hip_error", "nlinv_bandwidth_probe",
     "nlinv_grid_radial", "nlinv_degrid_radial", "nlinv_coil_compress_workspace", "nlinv_coil_compress",
+    "nlinv_gn_step_vjp_workspace", "nlinv_gn_step_vjp",
 )
 
 
@@ -95,6 +96,9 @@ def load(path: str | None = None):
         "nlinv_bandwidth_probe": ([vp, vp, C.c_size_t, vp], C.c_int),
         "nlinv_grid_radial": ([i32, i32, i32, i32, vp, vp, f32, f32, vp, vp, vp], C.c_int),
         "nlinv_coil_compress_workspace": ([i32, C.c_int64], C.c_size_t),
+        "nlinv_gn_step_vjp_workspace": ([vp], C.c_size_t),
+        "nlinv_gn_step_vjp": ([vp, vp, vp, vp, vp, f32, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp,
+                               C.c_size_t, vp], C.c_int),
         "nlinv_coil_compress": ([i32, C.c_int64, i32, vp, vp, vp, vp, vp, C.c_size_t, vp], C.c_int),
         "nlinv_degrid_radial": ([i32, i32, i32, i32, vp, vp, f32, f32, vp, vp, vp], C.c_int),
         "nlinv_last_hip_error": ([], C.c_int),
@@ -183,7 +187,9 @@ def _op_shapes(plan, **ts):
     Omega coil planes, P and gP the grid."""
     n, m, J = _plan_dims(plan)[0]
     for what, t in ts.items():
-        base = what.replace("_out", "").replace("_inout", "").replace("_ref", "")
+        base = what.replace("_out", "").replace("_inout", "").replace("_ref", "").replace("_next", "")
+        base = base.replace("_n", "") if base.endswith("_n") else base
+        base = base.replace("_g", "") if base.endswith("_g") else base
         if base in ("rho", "drho", "image"):
             _expect(t, (m, m), what)
         elif base in ("chat", "dchat", "y", "dy", "g"):
@@ -487,4 +493,35 @@ def nlinv_coil_compress(y, K, stream=None):
                                      _ptr(lam, torch.float64, "eigvals"), _c64(V, "basis"), ws.data_ptr(), ws_bytes,
                                      _stream(stream)), "nlinv_coil_compress")
     return out, lam, V
+
+
+def nlinv_gn_step_vjp(plan, rho_n, chat_n, y, P, alpha, rho_next, chat_next, rho_ref, chat_ref, g_rho, g_chat,
+                      cg_iters, want_y=True, want_ref=True, want_P=True, want_alpha=True, stream=None):
+    """Gradients of a loss of x_{n+1} = GN step(x_n; y, P, alpha, x_ref) given
+    g = dL/dx_{n+1}: dict with 'y', 'rho_ref', 'chat_ref', 'P', 'alpha' (the
+    requested ones; the workspace allocated here with torch)."""
+    import torch
+    _op_shapes(plan, rho=rho_n, chat=chat_n, y=y, P=P, rho_next=rho_next, chat_next=chat_next, rho_ref=rho_ref,
+               chat_ref=chat_ref, rho_g=g_rho, chat_g=g_chat)
+    lib = load()
+    dev = y.device
+    ws_bytes = lib.nlinv_gn_step_vjp_workspace(plan)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    out = {}
+    if want_y:
+        out["y"] = torch.empty_like(y)
+    if want_ref:
+        out["rho_ref"], out["chat_ref"] = torch.empty_like(rho_ref), torch.empty_like(chat_ref)
+    if want_P:
+        out["P"] = torch.empty_like(P)
+    if want_alpha:
+        out["alpha"] = torch.zeros((), dtype=torch.float64, device=dev)
+    check(lib.nlinv_gn_step_vjp(plan, _c64(rho_n, "rho_n"), _c64(chat_n, "chat_n"), _c64(y, "y"), _f32(P, "P"),
+                                float(alpha), _c64(rho_next, "rho_next"), _c64(chat_next, "chat_next"),
+                                _c64(rho_ref, "rho_ref"), _c64(chat_ref, "chat_ref"), _c64(g_rho, "g_rho"),
+                                _c64(g_chat, "g_chat"), int(cg_iters), _c64(out.get("y"), "grad_y"),
+                                _c64(out.get("rho_ref"), "grad_rho_ref"), _c64(out.get("chat_ref"), "grad_chat_ref"),
+                                _f32(out.get("P"), "grad_P"), _ptr(out.get("alpha"), torch.float64, "grad_alpha"),
+                                ws.data_ptr(), ws_bytes, _stream(stream)), "nlinv_gn_step_vjp")
+    return out
 

@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import torch
 
+from . import _native as N
 from .nlinv import Plan
 
 
@@ -34,6 +35,50 @@ class NlinvForward(torch.autograd.Function):
         if ctx.needs_input_grad[2]:
             gP = plan.mask_gradient(rho, chat, g, c=c)
         return grho, gchat, gP, None
+
+
+class GaussNewtonStep(torch.autograd.Function):
+    """x_{n+1} = x_n + dx, (DF^H DF + alpha I) dx = DF^H (y - F x_n) - alpha (x_n - x_ref)
+    (Eq. 3), differentiable with respect to the data y, the sampling weights P,
+    the regularisation weight alpha and the references x_ref, with the
+    linearisation point x_n held fixed (implicit differentiation: the
+    backward solves the same normal equations for g on the GPU,
+    nlinv_gn_step_vjp).  Forward and backward run cg_iters CG iterations."""
+
+    @staticmethod
+    def forward(ctx, y, P, alpha, rho_ref, chat_ref, rho_n, chat_n, plan: Plan, cg_iters: int):
+        if rho_n.requires_grad or chat_n.requires_grad:
+            raise ValueError("GaussNewtonStep holds the linearisation point x_n fixed: it must not require grad")
+        a = float(alpha)
+        prm = plan.params(1, cg_iters, alpha0=a, alpha_q=1.0, scale_norm=0.0, warm_start=True)
+        y, P, rho_ref, chat_ref = y.contiguous(), P.contiguous(), rho_ref.contiguous(), chat_ref.contiguous()
+        out = plan.solve(y, P, prm, rho0=rho_n.contiguous(), chat0=chat_n.contiguous(), rho_ref=rho_ref,
+                         chat_ref=chat_ref)
+        ctx.save_for_backward(y, P, rho_ref, chat_ref, rho_n, chat_n, out["rho"], out["chat"])
+        ctx.plan, ctx.alpha, ctx.cg_iters = plan, a, cg_iters
+        ctx.alpha_dtype = alpha.dtype if torch.is_tensor(alpha) else torch.float32
+        return out["rho"], out["chat"]
+
+    @staticmethod
+    def backward(ctx, g_rho, g_chat):
+        y, P, rho_ref, chat_ref, rho_n, chat_n, rho1, chat1 = ctx.saved_tensors
+        if g_rho is None:
+            g_rho = torch.zeros_like(rho1)
+        if g_chat is None:
+            g_chat = torch.zeros_like(chat1)
+        need = ctx.needs_input_grad
+        gr = N.nlinv_gn_step_vjp(ctx.plan.handle, rho_n, chat_n, y, P, ctx.alpha, rho1, chat1, rho_ref, chat_ref,
+                                 g_rho.contiguous(), g_chat.contiguous(), ctx.cg_iters, want_y=need[0],
+                                 want_ref=need[3] or need[4], want_P=need[1], want_alpha=need[2])
+        ga = gr.get("alpha")
+        return (gr.get("y"), gr.get("P"), None if ga is None else ga.to(ctx.alpha_dtype),
+                gr.get("rho_ref"), gr.get("chat_ref"), None, None, None, None)
+
+
+def gauss_newton_step(y, P, alpha, rho_ref, chat_ref, rho_n, chat_n, plan: Plan, cg_iters: int = 30):
+    """Differentiable regularised Gauss-Newton step (Eq. 3) from x_n = (rho_n,
+    chat_n); alpha a float or a 0-dim real tensor.  Returns (rho_{n+1}, chat_{n+1})."""
+    return GaussNewtonStep.apply(y, P, alpha, rho_ref, chat_ref, rho_n, chat_n, plan, cg_iters)
 
 
 def nlinv_F(rho, chat, P, plan: Plan):

@@ -21,6 +21,7 @@
 #include "nlinv.h"
 #include "aux_kernels.hpp"
 #include "coil_pca.hpp"
+#include "gn_vjp.hpp"
 #include "gridding.hpp"
 #include "launch.hpp"
 
@@ -1905,6 +1906,124 @@ int nlinv_irgnm_solve_series(nlinv_plan p, int32_t count, const nlinv_frame* fra
         f.chat_ref = nullptr;
         const FrameSrc src{(const float2*)frames[t - 1].rho, (const float2*)frames[t - 1].chat};
         CHK(solve_all(p, &f, q, s, &src));
+    }
+    return NLINV_OK;
+}
+
+// ---- implicit derivative of a Gauss-Newton step (Eq. 3) ---------------------
+
+namespace {
+struct GnLayout {
+    size_t lam_r, lam_c, ref_r, ref_c, yp, out_r, out_c, h_r, h_c, u, w, ones, part, total;
+};
+GnLayout gn_layout(const nlinv_dims& d) {
+    const size_t cn = (size_t)d.ncoils * d.n * d.n * sizeof(float2), rn = (size_t)d.n_om * d.n_om * sizeof(float2);
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    GnLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t b) { const size_t at = o; o += up(b); return at; };
+    L.lam_r = take(rn); L.lam_c = take(cn);
+    L.ref_r = take(rn); L.ref_c = take(cn);
+    L.yp = take(cn);
+    L.out_r = take(rn); L.out_c = take(cn);
+    L.h_r = take(rn); L.h_c = take(cn);
+    L.u = take(cn); L.w = take(cn);
+    L.ones = take((size_t)d.n * d.n * sizeof(float) + 8);
+    L.part = take(2 * kDotBlocks * sizeof(double));
+    L.total = o;
+    return L;
+}
+int axpby(float2* z, float a, const float2* x, float b, const float2* y, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(kThreads), 0, s, z, a, x, b, y, n);
+    HIPCHK(hipGetLastError());
+    return NLINV_OK;
+}
+}  // namespace
+
+size_t nlinv_gn_step_vjp_workspace(nlinv_plan p) {
+    if (!p || p->dims.size() != 1) return 0;
+    return gn_layout(p->dims[0]).total;
+}
+
+int nlinv_gn_step_vjp(nlinv_plan p, const nlinv_c32* rho_n, const nlinv_c32* chat_n, const nlinv_c32* y,
+                      const float* P, float alpha, const nlinv_c32* rho_next, const nlinv_c32* chat_next,
+                      const nlinv_c32* rho_ref, const nlinv_c32* chat_ref, const nlinv_c32* g_rho,
+                      const nlinv_c32* g_chat, int32_t cg_iters, nlinv_c32* grad_y, nlinv_c32* grad_rho_ref,
+                      nlinv_c32* grad_chat_ref, float* grad_P, double* grad_alpha, void* workspace,
+                      size_t workspace_bytes, void* stream) {
+    if (!p || p->dims.size() != 1 || !(alpha > 0.f) || cg_iters < 0 || cg_iters > kMaxCG) return NLINV_EINVAL;
+    const void* need[] = {rho_n, chat_n, y, P, rho_next, chat_next, rho_ref, chat_ref, g_rho, g_chat, workspace};
+    for (const void* q : need)
+        if (!q || !aligned(q)) return NLINV_EINVAL;
+    const void* opt[] = {grad_y, grad_rho_ref, grad_chat_ref, grad_P, grad_alpha};
+    for (const void* q : opt)
+        if (q && !aligned(q) && q != (const void*)grad_alpha) return NLINV_EINVAL;
+    if (grad_alpha && ((uintptr_t)grad_alpha & 7)) return NLINV_EINVAL;
+    if ((grad_rho_ref == nullptr) != (grad_chat_ref == nullptr)) return NLINV_EINVAL;
+    const nlinv_dims& d = p->dims[0];
+    const GnLayout L = gn_layout(d);
+    if (workspace_bytes < L.total) return NLINV_EINVAL;
+    unsigned char* ws = static_cast<unsigned char*>(workspace);
+    auto W = [&](size_t off) { return reinterpret_cast<float2*>(ws + off); };
+    const hipStream_t s = (hipStream_t)stream;
+    const long long cn = (long long)d.ncoils * d.n * d.n, rn = (long long)d.n_om * d.n_om;
+    const float2 *xr = (const float2*)rho_n, *xc = (const float2*)chat_n;
+    // lambda = N_alpha^{-1} g by one Newton step of the solve on data whose
+    // residual vanishes (y' = F(x_n), no scaling) towards x_ref' = x_n + g/alpha:
+    // its right-hand side is -alpha (x_n - x_ref') = g, so it returns x_n + lambda
+    CHK(nlinv_forward(p, rho_n, chat_n, P, (nlinv_c32*)W(L.yp), nullptr, stream));
+    CHK(axpby(W(L.ref_r), 1.f, xr, 1.f / alpha, (const float2*)g_rho, rn, s));
+    CHK(axpby(W(L.ref_c), 1.f, xc, 1.f / alpha, (const float2*)g_chat, cn, s));
+    HIPCHK(hipMemcpyAsync(W(L.out_r), xr, rn * sizeof(float2), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(W(L.out_c), xc, cn * sizeof(float2), hipMemcpyDeviceToDevice, s));
+    nlinv_irgnm_params prm{1, cg_iters, alpha, 1.f, 0.f, 0.f, NLINV_WARM_START};
+    nlinv_frame f{};
+    f.y = (const nlinv_c32*)W(L.yp);
+    f.P = P;
+    f.rho = (nlinv_c32*)W(L.out_r);
+    f.chat = (nlinv_c32*)W(L.out_c);
+    f.rho_ref = (const nlinv_c32*)W(L.ref_r);
+    f.chat_ref = (const nlinv_c32*)W(L.ref_c);
+    CHK(solve_all(p, &f, prm, s));
+    CHK(axpby(W(L.lam_r), 1.f, W(L.out_r), -1.f, xr, rn, s));
+    CHK(axpby(W(L.lam_c), 1.f, W(L.out_c), -1.f, xc, cn, s));
+    const nlinv_c32 *lam_r = (const nlinv_c32*)W(L.lam_r), *lam_c = (const nlinv_c32*)W(L.lam_c);
+    // dL/dy = DF lambda
+    if (grad_y) CHK(nlinv_deriv(p, rho_n, chat_n, nullptr, P, lam_r, lam_c, grad_y, stream));
+    // dL/dx_ref = alpha lambda
+    if (grad_rho_ref) {
+        CHK(axpby((float2*)grad_rho_ref, alpha, W(L.lam_r), 0.f, nullptr, rn, s));
+        CHK(axpby((float2*)grad_chat_ref, alpha, W(L.lam_c), 0.f, nullptr, cn, s));
+    }
+    // dL/dalpha = -Re<lambda, x_{n+1} - x_ref>
+    if (grad_alpha) {
+        CHK(axpby(W(L.h_r), 1.f, (const float2*)rho_next, -1.f, (const float2*)rho_ref, rn, s));
+        CHK(axpby(W(L.h_c), 1.f, (const float2*)chat_next, -1.f, (const float2*)chat_ref, cn, s));
+        double* part = reinterpret_cast<double*>(ws + L.part);
+        hipLaunchKernelGGL(k_dot_re, dim3(kDotBlocks), dim3(kThreads), 0, s, (const float2*)W(L.lam_r),
+                           (const float2*)W(L.h_r), rn, part);
+        hipLaunchKernelGGL(k_dot_re, dim3(kDotBlocks), dim3(kThreads), 0, s, (const float2*)W(L.lam_c),
+                           (const float2*)W(L.h_c), cn, part + kDotBlocks);
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, (const double*)part, 2 * kDotBlocks, -1.0,
+                           grad_alpha);
+        HIPCHK(hipGetLastError());
+    }
+    // dL/dP = Re sum_j conj(u_j) (y_j - 2 P w_j), u = A lambda, w = A (x_{n+1} - x_n / 2),
+    // A = DF at x_n with P = 1
+    if (grad_P) {
+        float* ones = reinterpret_cast<float*>(ws + L.ones);
+        const long long nn = (long long)d.n * d.n;
+        hipLaunchKernelGGL(k_fill, dim3(grid_for((nn + 1) / 2)), dim3(kThreads), 0, s, reinterpret_cast<float2*>(ones),
+                           (nn + 1) / 2, make_float2(1.f, 1.f));
+        HIPCHK(hipGetLastError());
+        CHK(axpby(W(L.h_r), 1.f, (const float2*)rho_next, -0.5f, xr, rn, s));
+        CHK(axpby(W(L.h_c), 1.f, (const float2*)chat_next, -0.5f, xc, cn, s));
+        CHK(nlinv_deriv(p, rho_n, chat_n, nullptr, ones, lam_r, lam_c, (nlinv_c32*)W(L.u), stream));
+        CHK(nlinv_deriv(p, rho_n, chat_n, nullptr, ones, (const nlinv_c32*)W(L.h_r), (const nlinv_c32*)W(L.h_c),
+                        (nlinv_c32*)W(L.w), stream));
+        hipLaunchKernelGGL(k_gn_grad_P, dim3(grid_for(nn)), dim3(kThreads), 0, s, (const float2*)W(L.u),
+                           (const float2*)y, (const float2*)W(L.w), P, grad_P, d.ncoils, nn);
+        HIPCHK(hipGetLastError());
     }
     return NLINV_OK;
 }
