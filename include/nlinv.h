@@ -329,6 +329,22 @@ int nlinv_coil_compress(int32_t J, int64_t M, int32_t K, const nlinv_c32* y, nli
                         double* eigvals_out, nlinv_c32* basis_out, void* workspace, size_t workspace_bytes,
                         void* stream);
 
+/* ---- host-side check of the launch arguments ------------------------------
+ * For callers' and the library's tests (no GPU needed, nothing allocated on a
+ * device, no HIP call): builds the launch arguments of a solve's whole Newton
+ * loop (newton x cg iterations, nframes frames of the shape n, n_om, ncoils
+ * with the default weight) and of the autotuner's trial launch of every pass
+ * mode, exactly as a solve would, with placeholder device pointers, and
+ * checks each launch's operands the way a real launch is checked before it
+ * is enqueued.  drop_mode >= 0 plants an omission in the tuner's launch of
+ * that column mode (its operands are cleared, as a dropped argument line
+ * would leave them).  *launches: the number of launches checked;
+ * *first_bad: the kernel class (nlinv_kernel_class_name) of the first
+ * launch with a missing operand, or -1.  NLINV_OK when every launch is
+ * complete, NLINV_EINVAL otherwise (or for bad arguments). */
+int nlinv_check_launch_args(int32_t n, int32_t n_om, int32_t ncoils, int32_t nframes, int32_t newton,
+                            int32_t cg, int32_t drop_mode, int64_t* launches, int32_t* first_bad);
+
 /* ---- measurement ----------------------------------------------------------
  * Bandwidth probe: copy `bytes` (a multiple of 16) from src to dst (device,
  * 16-byte aligned, not overlapping) with a plain streaming kernel.  It gives

@@ -26,7 +26,7 @@ EXPORTED = (
     "nlinv_plan_timing_read_class",
     "nlinv_kernel_class_name", "nlinv_status_string", "nlinv_last_hip_error", "nlinv_bandwidth_probe",
     "nlinv_grid_radial", "nlinv_degrid_radial", "nlinv_coil_compress_workspace", "nlinv_coil_compress",
-    "nlinv_gn_step_vjp_workspace", "nlinv_gn_step_vjp",
+    "nlinv_gn_step_vjp_workspace", "nlinv_gn_step_vjp", "nlinv_check_launch_args",
 )
 
 
@@ -97,6 +97,8 @@ def load(path: str | None = None):
         "nlinv_grid_radial": ([i32, i32, i32, i32, vp, vp, f32, f32, vp, vp, vp], C.c_int),
         "nlinv_coil_compress_workspace": ([i32, C.c_int64], C.c_size_t),
         "nlinv_gn_step_vjp_workspace": ([vp], C.c_size_t),
+        "nlinv_check_launch_args": ([i32, i32, i32, i32, i32, i32, i32, C.POINTER(C.c_int64), C.POINTER(i32)],
+                                    C.c_int),
         "nlinv_gn_step_vjp": ([vp, vp, vp, vp, vp, f32, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp,
                                C.c_size_t, vp], C.c_int),
         "nlinv_coil_compress": ([i32, C.c_int64, i32, vp, vp, vp, vp, vp, C.c_size_t, vp], C.c_int),
@@ -524,4 +526,13 @@ def nlinv_gn_step_vjp(plan, rho_n, chat_n, y, P, alpha, rho_next, chat_next, rho
                                 _f32(out.get("P"), "grad_P"), _ptr(out.get("alpha"), torch.float64, "grad_alpha"),
                                 ws.data_ptr(), ws_bytes, _stream(stream)), "nlinv_gn_step_vjp")
     return out
+
+
+def nlinv_check_launch_args(n, n_om, ncoils, nframes=1, newton=2, cg=3, drop_mode=-1, lib=None):
+    """(status, launches checked, kernel class of the first incomplete launch or -1)."""
+    lib = lib or load()
+    cnt, bad = C.c_int64(), C.c_int32()
+    st = lib.nlinv_check_launch_args(int(n), int(n_om), int(ncoils), int(nframes), int(newton), int(cg),
+                                     int(drop_mode), C.byref(cnt), C.byref(bad))
+    return st, cnt.value, bad.value
 

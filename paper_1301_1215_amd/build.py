@@ -92,13 +92,51 @@ def build(jobs: int | None = None, verbose: bool = False, incremental: bool = Fa
     return LIB
 
 
+SAN_LIB = os.path.join(PKG, "libnlinv_san.so")
+# host code only: each sanitizer flag applies to the host compilation (the
+# GPU code objects are the same as the library's)
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def asan_runtime() -> str:
+    """The ASan runtime of the host compiler (to preload into a process that
+    loads the sanitised library)."""
+    import glob
+    root = os.path.dirname(os.path.dirname(os.path.realpath(HIPCC)))
+    hits = sorted(glob.glob(os.path.join(root, "llvm", "lib", "clang", "*", "lib", "linux",
+                                         "libclang_rt.asan-x86_64.so")) +
+                  glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not hits:
+        raise FileNotFoundError("libclang_rt.asan-x86_64.so not found")
+    return hits[-1]
+
+
+def build_sanitized(jobs: int | None = None) -> str:
+    """libnlinv_san.so: the host library compiled with AddressSanitizer and
+    UndefinedBehaviorSanitizer (the pass-kernel objects of build() reused)."""
+    build(jobs, incremental=True)
+    lib_o = os.path.join(BUILD, "nlinv_lib_san.o")
+    _run([HIPCC, *FLAGS, *SAN_FLAGS, "-c", os.path.join(CSRC, "nlinv_lib.hip"), "-o", lib_o])
+    objs = [os.path.join(BUILD, f"inst_{n}.o") for n in SIZES] + [lib_o]
+    tmp = SAN_LIB + ".tmp"
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Xarch_host", "-fsanitize=address",
+          "-Xarch_host", "-fsanitize=undefined", "-shared-libsan", "-o", tmp, *objs])
+    os.replace(tmp, SAN_LIB)
+    return SAN_LIB
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("-j", "--jobs", type=int, default=None)
     ap.add_argument("-v", "--verbose", action="store_true")
     ap.add_argument("-i", "--incremental", action="store_true", help="rebuild only stale objects")
+    ap.add_argument("--sanitize", action="store_true",
+                    help="also build libnlinv_san.so (host code under ASan and UBSan)")
     a = ap.parse_args()
     print(build(a.jobs, a.verbose, a.incremental))
+    if a.sanitize:
+        print(build_sanitized(a.jobs))
 
 
 if __name__ == "__main__":

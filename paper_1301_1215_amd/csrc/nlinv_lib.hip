@@ -217,6 +217,11 @@ struct nlinv_plan_s {
     int ev_next = 0;
     bool capturing = false;
     bool timing_failed = false;
+    // dry run (nlinv_check_launch_args): launches only check their operands
+    // and are counted; nothing reaches the GPU
+    bool dry_run = false;
+    long long dry_launches = 0;
+    int dry_first_bad = -1;       // kernel class of the first launch with a missing operand
 };
 
 namespace {
@@ -419,7 +424,15 @@ bool row_operands_ok(int mode, const RowArgs& a) {
     }
 }
 
+// dry run: count the launch, remember the first one that would be refused
+int dry_launch(nlinv_plan_s* p, bool ok, int kc) {
+    ++p->dry_launches;
+    if (!ok && p->dry_first_bad < 0) p->dry_first_bad = kc;
+    return ok ? NLINV_OK : NLINV_EINVAL;
+}
+
 int run_col(nlinv_plan_s* p, const Class& C, int mode, const ColArgs& a0, int nplanes, hipStream_t s) {
+    if (p->dry_run) return dry_launch(p, col_operands_ok(mode, a0), col_kclass(mode));
     if (!col_operands_ok(mode, a0)) return NLINV_EINVAL;
     ColArgs a = a0;
     a.nplanes = nplanes;
@@ -431,6 +444,7 @@ int run_col(nlinv_plan_s* p, const Class& C, int mode, const ColArgs& a0, int np
 }
 
 int run_row(nlinv_plan_s* p, const Class& C, int mode, const RowArgs& a, hipStream_t s) {
+    if (p->dry_run) return dry_launch(p, row_operands_ok(mode, a), row_kclass(mode));
     if (!row_operands_ok(mode, a)) return NLINV_EINVAL;
     const int slot = tbegin(p, row_kclass(mode), s);
     hipError_t e = row_dispatch(C.n, mode, C.rowv[mode], a, s);
@@ -447,7 +461,9 @@ int grid_for(long long n, int per = kThreads) {
 }
 
 int run_coil_sum(nlinv_plan_s* p, const CoilSumArgs& a, hipStream_t s) {
-    if (!a.aux || (a.r_upd ? !(a.add1 && a.dx_upd && a.cg_a) : !a.out)) return NLINV_EINVAL;
+    const bool ok = a.aux && (a.r_upd ? (a.add1 && a.dx_upd && a.cg_a) : a.out != nullptr);
+    if (p->dry_run) return dry_launch(p, ok, KC_COIL_SUM);
+    if (!ok) return NLINV_EINVAL;
     const int slot = tbegin(p, KC_COIL_SUM, s);
     hipLaunchKernelGGL(k_coil_sum, dim3(a.nframes * a.segs), dim3(kThreads), 0, s, a);
     hipError_t e = hipGetLastError();
@@ -458,6 +474,7 @@ int run_coil_sum(nlinv_plan_s* p, const CoilSumArgs& a, hipStream_t s) {
 
 template <int OP>
 int run_vec(nlinv_plan_s* p, const SegGeom& g, const VecPtrs& v, double* partial, hipStream_t s) {
+    if (p->dry_run) return dry_launch(p, v.c0 && (OP != VEC_DOT || partial), OP == VEC_DOT ? KC_VEC_DOT : KC_VEC_OTHER);
     const int kc = OP == VEC_DOT ? KC_VEC_DOT : KC_VEC_OTHER;
     const int slot = tbegin(p, kc, s);
     hipLaunchKernelGGL((k_vec<OP>), dim3(nseg(g)), dim3(kThreads), 0, s, g, v, partial);
@@ -484,6 +501,7 @@ ScalarStep scalar_step(const Class& C, int op, const SegGeom& g, float scale_nor
 }
 
 int launch_scalar(nlinv_plan_s* p, Class& C, const ScalarStep& ss, hipStream_t s) {
+    if (p->dry_run) return dry_launch(p, ss.partial != nullptr, KC_SCALAR);
     const int slot = tbegin(p, KC_SCALAR, s);
     hipLaunchKernelGGL(k_scalar, dim3(C.nframes), dim3(64), 0, s, ss, C.sc);
     hipError_t e = hipGetLastError();
@@ -2026,6 +2044,84 @@ int nlinv_gn_step_vjp(nlinv_plan p, const nlinv_c32* rho_n, const nlinv_c32* cha
         HIPCHK(hipGetLastError());
     }
     return NLINV_OK;
+}
+
+// ---- host-side check of the launch arguments ----------------------------------
+
+int nlinv_check_launch_args(int32_t n, int32_t n_om, int32_t ncoils, int32_t nframes, int32_t newton, int32_t cg,
+                            int32_t drop_mode, int64_t* launches, int32_t* first_bad) {
+    if (!launches || !first_bad || nframes < 1 || nframes > 64 || newton < 0 || newton > kMaxNewton || cg < 0 ||
+        cg > kMaxCG)
+        return NLINV_EINVAL;
+    nlinv_dims d{n, n_om, ncoils, 220.f, 32.f};
+    CHK(check_dims(d));
+    // a plan whose device pointers are placeholders: in a dry run they are
+    // never dereferenced and no HIP call is made
+    nlinv_plan_s pl;
+    pl.dry_run = true;
+    pl.dims.assign((size_t)nframes, d);
+    Class C;
+    C.n = n;
+    C.m = n_om;
+    C.lo = n / 2 - n_om / 2;
+    {
+        const int h = band_half(n, 220.0, 32.0);
+        C.kb = 2 * h;
+        C.kb_lo = n / 2 - h;
+    }
+    C.tilew = plane_tile_width(n);
+    for (int f = 0; f < nframes; ++f) {
+        C.frames.push_back(f);
+        C.J.push_back(ncoils);
+        C.plane0.push_back(C.nplanes);
+        C.nplanes += ncoils;
+        C.nframes += 1;
+    }
+    uintptr_t fake = 0x10000;
+    auto ptr = [&](auto*& q) { q = reinterpret_cast<std::remove_reference_t<decltype(q)>>(fake += 0x10000); };
+    ptr(C.plane_frame); ptr(C.frame_plane0); ptr(C.frame_planes); ptr(C.tw); ptr(C.winv); ptr(C.winv_t);
+    ptr(C.x_c); ptr(C.x_r); ptr(C.dx_r); ptr(C.r_c); ptr(C.r_r); ptr(C.p_c); ptr(C.p_r); ptr(C.q_c); ptr(C.q_r);
+    ptr(C.xr_c); ptr(C.xr_r); ptr(C.y); ptr(C.P); ptr(C.c); ptr(C.T); ptr(C.aux); ptr(C.partial); ptr(C.partial2);
+    ptr(C.part_p);
+    if (C.kb < C.n) ptr(C.T2);
+    ptr(C.sc.rr); ptr(C.sc.a); ptr(C.sc.beta); ptr(C.sc.brk); ptr(C.sc.s); ptr(C.sc.inv_s); ptr(C.sc.stats);
+    ptr(C.sc.inert);
+    C.sc.nframes = C.nframes;
+    C.sc.stats_len = kStatsCap;
+    const long long cn = C.cplane(), rn = C.rplane();
+    make_geom(C.geom, C.nplanes, C.nframes, cn, rn, true, C.plane_frame);
+    make_geom(C.geomC, C.nplanes, C.nframes, cn, rn, false, C.plane_frame);
+    for (int m = 0; m < kColModes; ++m) C.colv[m] = default_col_variant(n, col_mode_on_band(m) ? C.kb : n);
+    for (int& v : C.rowv) v = default_row_variant(n);
+    // a planted omission (tests): the tuner's launch of column mode drop_mode
+    // loses its last operand set, as a dropped argument line would
+    pl.classes.push_back(C);
+    Class& K = pl.classes[0];
+    pl.loc.assign((size_t)nframes, {0, 0});
+    nlinv_irgnm_params prm{newton, cg, 1.f, 0.5f, 0.f, 100.f, NLINV_USE_GRAPH};
+    int st = enqueue_newton(&pl, prm, nullptr);
+    // the tuner's representative launch of every mode
+    const int col_modes[] = {COL_WINV_IFFT_CROP, COL_PUPD_WINV_IFFT_CROP, COL_P_IFFT_CROP, COL_PAD_FFT_P,
+                             COL_RESID_P_IFFT, COL_PAD_FFT_P2_IFFT, COL_PAD_FFT_WINV_ADD, COL_PAD_FFT_WINV_CG_UPD};
+    for (int mode : col_modes) {
+        ColArgs a = tune_col_args(&pl, K, mode);
+        if (mode == drop_mode) {   // what a swallowed argument line leaves
+            a.cg_a = nullptr;
+            a.r_in = nullptr;
+            a.add1 = nullptr;
+            a.winv = nullptr;
+            a.P = nullptr;
+        }
+        const int s2 = run_col(&pl, K, mode, a, K.nplanes, nullptr);
+        if (st == NLINV_OK) st = s2;
+    }
+    for (int mode : {ROW_CACHE, ROW_FWD, ROW_DERIV, ROW_ADJ}) {
+        const int s2 = run_row(&pl, K, mode, tune_row_args(K, mode), nullptr);
+        if (st == NLINV_OK) st = s2;
+    }
+    *launches = pl.dry_launches;
+    *first_bad = pl.dry_first_bad;
+    return st;
 }
 
 int nlinv_plan_autotune(nlinv_plan p, void* stream) {
