@@ -208,8 +208,8 @@ int nlinv_irgnm_solve_series(nlinv_plan plan, int32_t count, const nlinv_frame* 
                              const nlinv_irgnm_params* prm, void* stream);
 
 /* ---- differentiation through a Gauss-Newton step --------------------------
- * The regularised Gauss-Newton step of Eq. 3 as a differentiable map, its
- * linearisation point x_n held fixed: x_{n+1} = x_n + dx with
+ * The regularised Gauss-Newton step of Eq. 3 as a differentiable map:
+ * x_{n+1} = x_n + dx with
  *   (DF^H DF + alpha I) dx = DF^H (y - F x_n) - alpha (x_n - x_ref)
  * (forward: nlinv_irgnm_solve with newton_steps = 1, alpha0 = alpha,
  * scale_norm = 0, NLINV_WARM_START, x0 = x_n, the references x_ref).  Given
@@ -221,8 +221,14 @@ int nlinv_irgnm_solve_series(nlinv_plan plan, int32_t count, const nlinv_frame* 
  *   grad_alpha    = -Re<lambda, x_{n+1} - x_ref>               (one device double)
  *   grad_P        = Re sum_j conj(u_j) (y_j - 2 P w_j)         [n][n] float32
  *                   u = A lambda, w = A (x_{n+1} - x_n / 2), A = DF at x_n with P = 1
- * (F is bilinear, so F(x_n) + A dx = A (x_{n+1} - x_n / 2)).  rho_next,
- * chat_next: the forward's result.  Every output is nullable.  The caller
+ * (F is bilinear, so F(x_n) + A dx = A (x_{n+1} - x_n / 2)), and for the
+ * linearisation point itself (both or neither)
+ *   grad_*_n      = DF_lambda^H (y - DF (x_{n+1} - x_n / 2)) - DF_dx^H (DF lambda)
+ * where DF is the derivative at x_n, DF_v the derivative at the point v, and
+ * dx = x_{n+1} - x_n (F bilinear: DF_h k = DF_k h;
+ * the normal equations' N lambda = g cancel the direct terms), so that an
+ * N-step solve can be differentiated step by step from its stored iterates.
+ * rho_next, chat_next: the forward's result.  Every output is nullable.  The caller
  * provides `workspace` (device, 16-byte aligned) of at least
  * nlinv_gn_step_vjp_workspace(plan) bytes.  Plans of one frame only. */
 size_t nlinv_gn_step_vjp_workspace(nlinv_plan plan);
@@ -230,8 +236,8 @@ int nlinv_gn_step_vjp(nlinv_plan plan, const nlinv_c32* rho_n, const nlinv_c32* 
                       const float* P, float alpha, const nlinv_c32* rho_next, const nlinv_c32* chat_next,
                       const nlinv_c32* rho_ref, const nlinv_c32* chat_ref, const nlinv_c32* g_rho,
                       const nlinv_c32* g_chat, int32_t cg_iters, nlinv_c32* grad_y, nlinv_c32* grad_rho_ref,
-                      nlinv_c32* grad_chat_ref, float* grad_P, double* grad_alpha, void* workspace,
-                      size_t workspace_bytes, void* stream);
+                      nlinv_c32* grad_chat_ref, float* grad_P, double* grad_alpha, nlinv_c32* grad_rho_n,
+                      nlinv_c32* grad_chat_n, void* workspace, size_t workspace_bytes, void* stream);
 
 /* ---- autotuning -----------------------------------------------------------
  * Time the FFT pass variants (lines per workgroup) of every pass mode for

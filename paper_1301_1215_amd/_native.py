@@ -99,8 +99,8 @@ def load(path: str | None = None):
         "nlinv_gn_step_vjp_workspace": ([vp], C.c_size_t),
         "nlinv_check_launch_args": ([i32, i32, i32, i32, i32, i32, i32, C.POINTER(C.c_int64), C.POINTER(i32)],
                                     C.c_int),
-        "nlinv_gn_step_vjp": ([vp, vp, vp, vp, vp, f32, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp,
-                               C.c_size_t, vp], C.c_int),
+        "nlinv_gn_step_vjp": ([vp, vp, vp, vp, vp, f32, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp,
+                               vp, C.c_size_t, vp], C.c_int),
         "nlinv_coil_compress": ([i32, C.c_int64, i32, vp, vp, vp, vp, vp, C.c_size_t, vp], C.c_int),
         "nlinv_degrid_radial": ([i32, i32, i32, i32, vp, vp, f32, f32, vp, vp, vp], C.c_int),
         "nlinv_last_hip_error": ([], C.c_int),
@@ -498,10 +498,12 @@ def nlinv_coil_compress(y, K, stream=None):
 
 
 def nlinv_gn_step_vjp(plan, rho_n, chat_n, y, P, alpha, rho_next, chat_next, rho_ref, chat_ref, g_rho, g_chat,
-                      cg_iters, want_y=True, want_ref=True, want_P=True, want_alpha=True, stream=None):
+                      cg_iters, want_y=True, want_ref=True, want_P=True, want_alpha=True, want_x_n=False,
+                      stream=None):
     """Gradients of a loss of x_{n+1} = GN step(x_n; y, P, alpha, x_ref) given
-    g = dL/dx_{n+1}: dict with 'y', 'rho_ref', 'chat_ref', 'P', 'alpha' (the
-    requested ones; the workspace allocated here with torch)."""
+    g = dL/dx_{n+1}: dict with 'y', 'rho_ref', 'chat_ref', 'P', 'alpha',
+    'rho_n', 'chat_n' (the requested ones; the workspace allocated here with
+    torch)."""
     import torch
     _op_shapes(plan, rho=rho_n, chat=chat_n, y=y, P=P, rho_next=rho_next, chat_next=chat_next, rho_ref=rho_ref,
                chat_ref=chat_ref, rho_g=g_rho, chat_g=g_chat)
@@ -518,12 +520,15 @@ def nlinv_gn_step_vjp(plan, rho_n, chat_n, y, P, alpha, rho_next, chat_next, rho
         out["P"] = torch.empty_like(P)
     if want_alpha:
         out["alpha"] = torch.zeros((), dtype=torch.float64, device=dev)
+    if want_x_n:
+        out["rho_n"], out["chat_n"] = torch.empty_like(rho_n), torch.empty_like(chat_n)
     check(lib.nlinv_gn_step_vjp(plan, _c64(rho_n, "rho_n"), _c64(chat_n, "chat_n"), _c64(y, "y"), _f32(P, "P"),
                                 float(alpha), _c64(rho_next, "rho_next"), _c64(chat_next, "chat_next"),
                                 _c64(rho_ref, "rho_ref"), _c64(chat_ref, "chat_ref"), _c64(g_rho, "g_rho"),
                                 _c64(g_chat, "g_chat"), int(cg_iters), _c64(out.get("y"), "grad_y"),
                                 _c64(out.get("rho_ref"), "grad_rho_ref"), _c64(out.get("chat_ref"), "grad_chat_ref"),
                                 _f32(out.get("P"), "grad_P"), _ptr(out.get("alpha"), torch.float64, "grad_alpha"),
+                                _c64(out.get("rho_n"), "grad_rho_n"), _c64(out.get("chat_n"), "grad_chat_n"),
                                 ws.data_ptr(), ws_bytes, _stream(stream)), "nlinv_gn_step_vjp")
     return out
 

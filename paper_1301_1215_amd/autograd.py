@@ -40,20 +40,18 @@ class NlinvForward(torch.autograd.Function):
 class GaussNewtonStep(torch.autograd.Function):
     """x_{n+1} = x_n + dx, (DF^H DF + alpha I) dx = DF^H (y - F x_n) - alpha (x_n - x_ref)
     (Eq. 3), differentiable with respect to the data y, the sampling weights P,
-    the regularisation weight alpha and the references x_ref, with the
-    linearisation point x_n held fixed (implicit differentiation: the
-    backward solves the same normal equations for g on the GPU,
+    the regularisation weight alpha, the references x_ref and the
+    linearisation point x_n (implicit differentiation: the backward solves the
+    same normal equations for the incoming gradient on the GPU,
     nlinv_gn_step_vjp).  Forward and backward run cg_iters CG iterations."""
 
     @staticmethod
     def forward(ctx, y, P, alpha, rho_ref, chat_ref, rho_n, chat_n, plan: Plan, cg_iters: int):
-        if rho_n.requires_grad or chat_n.requires_grad:
-            raise ValueError("GaussNewtonStep holds the linearisation point x_n fixed: it must not require grad")
         a = float(alpha)
         prm = plan.params(1, cg_iters, alpha0=a, alpha_q=1.0, scale_norm=0.0, warm_start=True)
         y, P, rho_ref, chat_ref = y.contiguous(), P.contiguous(), rho_ref.contiguous(), chat_ref.contiguous()
-        out = plan.solve(y, P, prm, rho0=rho_n.contiguous(), chat0=chat_n.contiguous(), rho_ref=rho_ref,
-                         chat_ref=chat_ref)
+        rho_n, chat_n = rho_n.contiguous(), chat_n.contiguous()
+        out = plan.solve(y, P, prm, rho0=rho_n, chat0=chat_n, rho_ref=rho_ref, chat_ref=chat_ref)
         ctx.save_for_backward(y, P, rho_ref, chat_ref, rho_n, chat_n, out["rho"], out["chat"])
         ctx.plan, ctx.alpha, ctx.cg_iters = plan, a, cg_iters
         ctx.alpha_dtype = alpha.dtype if torch.is_tensor(alpha) else torch.float32
@@ -69,16 +67,37 @@ class GaussNewtonStep(torch.autograd.Function):
         need = ctx.needs_input_grad
         gr = N.nlinv_gn_step_vjp(ctx.plan.handle, rho_n, chat_n, y, P, ctx.alpha, rho1, chat1, rho_ref, chat_ref,
                                  g_rho.contiguous(), g_chat.contiguous(), ctx.cg_iters, want_y=need[0],
-                                 want_ref=need[3] or need[4], want_P=need[1], want_alpha=need[2])
+                                 want_ref=need[3] or need[4], want_P=need[1], want_alpha=need[2],
+                                 want_x_n=need[5] or need[6])
         ga = gr.get("alpha")
         return (gr.get("y"), gr.get("P"), None if ga is None else ga.to(ctx.alpha_dtype),
-                gr.get("rho_ref"), gr.get("chat_ref"), None, None, None, None)
+                gr.get("rho_ref"), gr.get("chat_ref"), gr.get("rho_n"), gr.get("chat_n"), None, None)
 
 
 def gauss_newton_step(y, P, alpha, rho_ref, chat_ref, rho_n, chat_n, plan: Plan, cg_iters: int = 30):
     """Differentiable regularised Gauss-Newton step (Eq. 3) from x_n = (rho_n,
     chat_n); alpha a float or a 0-dim real tensor.  Returns (rho_{n+1}, chat_{n+1})."""
     return GaussNewtonStep.apply(y, P, alpha, rho_ref, chat_ref, rho_n, chat_n, plan, cg_iters)
+
+
+def irgnm_unrolled(y, P, rho0, chat0, plan: Plan, newton_steps: int = 7, cg_iters: int = 30, alpha0=1.0,
+                   alpha_q: float = 0.5, alpha_min: float = 0.0, rho_ref=None, chat_ref=None):
+    """The Newton loop of Eq. 3 as a chain of differentiable steps:
+    x_{k+1} = step(x_k; y, P, alpha_k, x_ref) with alpha_k = max(alpha0 q^k,
+    alpha_min) and x_ref = x0 unless given, all in the units of y (no data
+    scaling).  Gradients reach y, P, x0, x_ref and alpha0 (a float or a 0-dim
+    real tensor) through every step; autograd keeps the iterates.  Returns
+    (rho_N, chat_N)."""
+    if rho_ref is None:
+        rho_ref, chat_ref = rho0, chat0
+    rho, chat = rho0, chat0
+    for k in range(newton_steps):
+        if torch.is_tensor(alpha0):
+            a = torch.clamp_min(alpha0 * alpha_q ** k, alpha_min)
+        else:
+            a = max(alpha0 * alpha_q ** k, alpha_min)
+        rho, chat = GaussNewtonStep.apply(y, P, a, rho_ref, chat_ref, rho, chat, plan, cg_iters)
+    return rho, chat
 
 
 def nlinv_F(rho, chat, P, plan: Plan):

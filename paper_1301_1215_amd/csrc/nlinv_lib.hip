@@ -1967,9 +1967,11 @@ int nlinv_gn_step_vjp(nlinv_plan p, const nlinv_c32* rho_n, const nlinv_c32* cha
                       const float* P, float alpha, const nlinv_c32* rho_next, const nlinv_c32* chat_next,
                       const nlinv_c32* rho_ref, const nlinv_c32* chat_ref, const nlinv_c32* g_rho,
                       const nlinv_c32* g_chat, int32_t cg_iters, nlinv_c32* grad_y, nlinv_c32* grad_rho_ref,
-                      nlinv_c32* grad_chat_ref, float* grad_P, double* grad_alpha, void* workspace,
-                      size_t workspace_bytes, void* stream) {
+                      nlinv_c32* grad_chat_ref, float* grad_P, double* grad_alpha, nlinv_c32* grad_rho_n,
+                      nlinv_c32* grad_chat_n, void* workspace, size_t workspace_bytes, void* stream) {
     if (!p || p->dims.size() != 1 || !(alpha > 0.f) || cg_iters < 0 || cg_iters > kMaxCG) return NLINV_EINVAL;
+    if ((grad_rho_n == nullptr) != (grad_chat_n == nullptr)) return NLINV_EINVAL;
+    if (grad_rho_n && (!aligned(grad_rho_n) || !aligned(grad_chat_n))) return NLINV_EINVAL;
     const void* need[] = {rho_n, chat_n, y, P, rho_next, chat_next, rho_ref, chat_ref, g_rho, g_chat, workspace};
     for (const void* q : need)
         if (!q || !aligned(q)) return NLINV_EINVAL;
@@ -2006,8 +2008,10 @@ int nlinv_gn_step_vjp(nlinv_plan p, const nlinv_c32* rho_n, const nlinv_c32* cha
     CHK(axpby(W(L.lam_r), 1.f, W(L.out_r), -1.f, xr, rn, s));
     CHK(axpby(W(L.lam_c), 1.f, W(L.out_c), -1.f, xc, cn, s));
     const nlinv_c32 *lam_r = (const nlinv_c32*)W(L.lam_r), *lam_c = (const nlinv_c32*)W(L.lam_c);
-    // dL/dy = DF lambda
-    if (grad_y) CHK(nlinv_deriv(p, rho_n, chat_n, nullptr, P, lam_r, lam_c, grad_y, stream));
+    // dL/dy = DF lambda (kept in the data-sized scratch when grad_y is not wanted
+    // but the linearisation point's gradient is)
+    nlinv_c32* dfl = grad_y ? grad_y : (nlinv_c32*)W(L.yp);
+    if (grad_y || grad_rho_n) CHK(nlinv_deriv(p, rho_n, chat_n, nullptr, P, lam_r, lam_c, dfl, stream));
     // dL/dx_ref = alpha lambda
     if (grad_rho_ref) {
         CHK(axpby((float2*)grad_rho_ref, alpha, W(L.lam_r), 0.f, nullptr, rn, s));
@@ -2042,6 +2046,25 @@ int nlinv_gn_step_vjp(nlinv_plan p, const nlinv_c32* rho_n, const nlinv_c32* cha
         hipLaunchKernelGGL(k_gn_grad_P, dim3(grid_for(nn)), dim3(kThreads), 0, s, (const float2*)W(L.u),
                            (const float2*)y, (const float2*)W(L.w), P, grad_P, d.ncoils, nn);
         HIPCHK(hipGetLastError());
+    }
+    // dL/dx_n = DF_lambda^H (y - F(x_n) - DF dx) - DF_dx^H (DF lambda): the step's
+    // dependence on its linearisation point (F bilinear: DF_h k = DF_k h, and
+    // the normal equations' N lambda = g cancel the direct terms);
+    // y - F(x_n) - DF dx = y - DF (x_{n+1} - x_n / 2)
+    if (grad_rho_n) {
+        CHK(axpby(W(L.ref_r), 1.f, (const float2*)rho_next, -0.5f, xr, rn, s));
+        CHK(axpby(W(L.ref_c), 1.f, (const float2*)chat_next, -0.5f, xc, cn, s));
+        CHK(nlinv_deriv(p, rho_n, chat_n, nullptr, P, (const nlinv_c32*)W(L.ref_r), (const nlinv_c32*)W(L.ref_c),
+                        (nlinv_c32*)W(L.u), stream));
+        CHK(axpby(W(L.u), 1.f, (const float2*)y, -1.f, W(L.u), cn, s));              // linearised residual
+        CHK(nlinv_adjoint(p, lam_r, lam_c, nullptr, P, (const nlinv_c32*)W(L.u), (nlinv_c32*)W(L.ref_r),
+                          (nlinv_c32*)W(L.ref_c), stream));                          // DF_lambda^H (...)
+        CHK(axpby(W(L.h_r), 1.f, (const float2*)rho_next, -1.f, xr, rn, s));        // dx
+        CHK(axpby(W(L.h_c), 1.f, (const float2*)chat_next, -1.f, xc, cn, s));
+        CHK(nlinv_adjoint(p, (const nlinv_c32*)W(L.h_r), (const nlinv_c32*)W(L.h_c), nullptr, P, dfl,
+                          (nlinv_c32*)W(L.out_r), (nlinv_c32*)W(L.out_c), stream));  // DF_dx^H (DF lambda)
+        CHK(axpby((float2*)grad_rho_n, 1.f, W(L.ref_r), -1.f, W(L.out_r), rn, s));
+        CHK(axpby((float2*)grad_chat_n, 1.f, W(L.ref_c), -1.f, W(L.out_c), cn, s));
     }
     return NLINV_OK;
 }
