@@ -514,21 +514,22 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
     __syncthreads();
 
     if constexpr (TWO) {
-        // Every stage has at most one task per thread, so the intermediate
-        // stays in bufA: read into registers, barrier, write back.
+        // The forward's stage 2, the pointwise step and the inverse's first
+        // stage in one task: the inverse is the adjoint of the forward's
+        // stages taken in reverse order (an N2-point inverse DFT over k2 in
+        // the same registers), so the task writes its results back to the
+        // very slots it read (no barrier in between); the last stage applies
+        // the conjugate twiddle and the adjoint of stage 1 (tasks j2, outputs
+        // at the stage-1 input positions).  The forward's raw outputs carry the
+        // centring sign of their position on both sides of the pointwise
+        // step, which the real pointwise factors leave unchanged.
         static_assert(L * N1 <= NT && L * N2 <= NT, "one task per thread");
-        // stage 2 of the forward transform, then the pointwise step at each
-        // output position, kept in slot order (the inverse reads the same
-        // slots).  What is handed to the inverse carries the centring sign of
-        // its position, as the forward's raw outputs do, and the inverse's
-        // 1/sqrt(n).
         const float rs2 = a.rs * a.rs;
         {
             const int t = threadIdx.x;
-            const bool act = t < L * N1;
-            const int l = t % L, k1 = t / L, col = col0 + l;
-            float2 v[N2];
-            if (act) {
+            if (t < L * N1) {
+                const int l = t % L, k1 = t / L, col = col0 + l;
+                float2 v[N2];
                 static_for<0, N2>([&](auto J) {
                     constexpr int j2 = J;
                     v[j2] = bufA[k1 * RS + j2 * L + l];
@@ -569,52 +570,48 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                     });
                     acc += racc;
                 }
-            }
-            __syncthreads();
-            if (act) {
-                static_for<0, N2>([&](auto K) {
-                    constexpr int k2 = K;
-                    const int sl = k1 + N1 * k2;           // slot sl = j2' + N2 k1'
-                    bufA[(sl / N2) * RS + (sl % N2) * L + l] = v[k2];
+                RegDFT<N2, true>::run(v);
+                static_for<0, N2>([&](auto J) {
+                    constexpr int j2 = J;
+                    bufA[k1 * RS + j2 * L + l] = v[j2];
                 });
             }
         }
         __syncthreads();
-        // stage 1 of the inverse transform, slots j2 + N2 k1
-        {
-            const int t = threadIdx.x;
-            const bool act = t < L * N2;
-            const int l = t % L, j2 = t / L;
+        // the conjugate twiddle, then the adjoint of stage 1: an N1-point
+        // inverse DFT per j2, outputs at the positions the forward's stage-1
+        // inputs came from
+        const long long obase = (long long)plane * m * ncols;
+        for (int t = threadIdx.x; t < L * N2; t += NT) {
+            const int l = t % L, j2 = t / L, col = col0 + l;
             float2 v[N1];
-            if (act) {
-                static_for<0, N1>([&](auto K) {
-                    constexpr int k1 = K;
-                    v[k1] = bufA[k1 * RS + j2 * L + l];
-                });
-                RegDFT<N1, true>::run(v);
-                static_for<0, N1>([&](auto K) {
-                    constexpr int k1 = K;
-                    if constexpr (k1 > 0) v[k1] = cmulc(v[k1], elt(a.tw2, k1 * N2 + j2));
-                });
-            }
-            __syncthreads();
-            if (act) {
-                static_for<0, N1>([&](auto K) {
-                    constexpr int k1 = K;
-                    bufA[k1 * RS + j2 * L + l] = v[k1];
-                });
-            }
+            static_for<0, N1>([&](auto K) {
+                constexpr int k1 = K;
+                v[k1] = bufA[k1 * RS + j2 * L + l];
+                if constexpr (k1 > 0) v[k1] = cmulc(v[k1], elt(a.tw2, k1 * N2 + j2));
+            });
+            RegDFT<N1, true>::run(v);
+            static_for<0, N1>([&](auto K) {
+                constexpr int k1 = K;
+                const int r = CT::in_pos(j2, k1);
+                if constexpr (HALF && CT::HALF_BY_K1) {
+                    if constexpr (CT::half_k1(k1)) elt(a.out + obase, (r - lo) * ncols + col) = cscale(v[k1], CT::sign(r));
+                } else {
+                    const int ri = r - lo;
+                    if (ri >= 0 && ri < m) elt(a.out + obase, ri * ncols + col) = cscale(v[k1], CT::sign(r));
+                }
+            });
         }
-        __syncthreads();
     }
 
-    // ---- stage 2 of the last transform, straight to HBM
-    constexpr bool INV2 = INV1 || TWO;
+    // ---- stage 2 of the last transform, straight to HBM (not in TWO modes,
+    // which end above)
+    constexpr bool INV2 = INV1;
     const long long pbase = (long long)plane * kb * kb;   // band or grid plane of the outputs
     const float s1 = a.s1 ? a.s1[f] : a.c1;
     const float s2 = a.s2 ? a.s2[f] : a.c2;
     const float av = CGU ? a.cg_a[f] : 0.f;
-    for (int t = threadIdx.x; t < L * N1; t += NT) {
+    if constexpr (!TWO) for (int t = threadIdx.x; t < L * N1; t += NT) {
         const int l = t % L, k1 = t / L, col = col0 + l;
         float2 v[N2];
         static_for<0, N2>([&](auto J) {
@@ -628,14 +625,11 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                 constexpr int k2 = K;
                 // HALF: the slots outside Omega are known at compile time
                 if constexpr (!HALF || !CT::HALF_BY_K2 || CT::half_k2(k2)) {
-                    // TWO: the forward pass left slots in place, so the inverse's
-                    // output slot s sits at position s; its pre-shift is in the
-                    // input slots (P^2 was applied at the shifted positions)
                     const int rp = CT::out_pos(k1, k2);
                     const int ri = rp - lo;
                     if (ri >= 0 && ri < m) {
-                        const float s = TWO ? CT::sign(rp) : CT::sign(rp) * a.rs;
-                        elt(a.out + (long long)plane * m * ncols, ri * ncols + col) = cscale(v[k2], s);
+                        elt(a.out + (long long)plane * m * ncols, ri * ncols + col) =
+                            cscale(v[k2], CT::sign(rp) * a.rs);
                     }
                 }
             });
