@@ -68,7 +68,7 @@ static hipError_t col_L(int mode, const ColArgs& a, int nplanes, hipStream_t s) 
     return hipGetLastError();
 }
 
-template <int N, int L>
+template <int N, int L, bool SW>
 static hipError_t row_L(int mode, const RowArgs& a, hipStream_t s) {
     if ((mode == ROW_CACHE || mode == ROW_DERIV || mode == ROW_ADJ) &&
         (a.kb <= 0 || a.kb > N || a.kb_lo < 0 || a.kb_lo + a.kb > N))
@@ -76,8 +76,8 @@ static hipError_t row_L(int mode, const RowArgs& a, hipStream_t s) {
     const dim3 grid((a.nlines + L - 1) / L), block(pass_threads(N, L));
     const bool half = 2 * a.m == N && 4 * a.lo == N;
 #define NLINV_ROW(MODE)                                                                   \
-    if (half) hipLaunchKernelGGL((k_row<N, L, MODE, true>), grid, block, 0, s, a);         \
-    else hipLaunchKernelGGL((k_row<N, L, MODE, false>), grid, block, 0, s, a)
+    if (half) hipLaunchKernelGGL((k_row<N, L, MODE, true, SW>), grid, block, 0, s, a);     \
+    else hipLaunchKernelGGL((k_row<N, L, MODE, false, SW>), grid, block, 0, s, a)
     switch (mode) {
         case ROW_CACHE: NLINV_ROW(ROW_CACHE); break;
         case ROW_FWD: NLINV_ROW(ROW_FWD); break;
@@ -102,10 +102,12 @@ hipError_t launch_col(int mode, int variant, const ColArgs& a, int nplanes, hipS
 template <int N>
 hipError_t launch_row(int mode, int variant, const RowArgs& a, hipStream_t s) {
     if (a.nlines <= 0) return hipSuccess;
-    if constexpr (row_variant_ok(N, 0)) { if (variant == 0) return row_L<N, kRowL[0]>(mode, a, s); }
-    if constexpr (row_variant_ok(N, 1)) { if (variant == 1) return row_L<N, kRowL[1]>(mode, a, s); }
-    if constexpr (row_variant_ok(N, 2)) { if (variant == 2) return row_L<N, kRowL[2]>(mode, a, s); }
-    if constexpr (row_variant_ok(N, 3)) { if (variant == 3) return row_L<N, kRowL[3]>(mode, a, s); }
+#define NLINV_RV(V)                                                                          \
+    if constexpr (row_variant_ok(N, V)) {                                                    \
+        if (variant == V) return row_L<N, row_lines(V), row_swapped(V)>(mode, a, s);         \
+    }
+    NLINV_RV(0) NLINV_RV(1) NLINV_RV(2) NLINV_RV(3) NLINV_RV(4) NLINV_RV(5) NLINV_RV(6) NLINV_RV(7)
+#undef NLINV_RV
     return hipErrorInvalidValue;
 }
 

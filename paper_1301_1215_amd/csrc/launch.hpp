@@ -17,13 +17,18 @@ namespace nlinv {
 constexpr int kColL[] = {16, 8, 32, 4};
 constexpr int kRowL[] = {8, 16, 4, 2};
 constexpr int kNumColVariants = 4;
-constexpr int kNumRowVariants = 4;
+constexpr int kNumRowVariants = 8;
 
 constexpr bool col_variant_ok(int n, int v) {
     return v >= 0 && v < kNumColVariants && n % kColL[v] == 0 && n * kColL[v] <= 8192;
 }
+// Row variant v takes kRowL[v & 3] lines per workgroup; v >= 4 also
+// transposes the line FFT's split N1 x N2 (only where N1 != N2).
+constexpr int row_lines(int v) { return kRowL[v & 3]; }
+constexpr bool row_swapped(int v) { return v >= 4; }
 constexpr bool row_variant_ok(int n, int v) {
-    return v >= 0 && v < kNumRowVariants && n * kRowL[v] <= 8192;
+    return v >= 0 && v < kNumRowVariants && n * row_lines(v) <= 8192 &&
+           (!row_swapped(v) || split_n1(n) * split_n1(n) != n);
 }
 
 template <int N>

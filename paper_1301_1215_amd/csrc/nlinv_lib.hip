@@ -1509,8 +1509,9 @@ int tune_class(nlinv_plan_s* p, Class& C, hipStream_t s) {
             float ms = 0.f;
             CHK(timeit([&] { return run_row(p, C, mode, r, s); }, ms));
             if (verbose)
-                std::fprintf(stderr, "nlinv tune n=%d planes=%d %s L=%d: %.1f us\n", C.n, nplanes,
-                             kKClassNames[row_kclass(mode)], kRowL[v], 1e3 * ms);
+                std::fprintf(stderr, "nlinv tune n=%d planes=%d %s L=%d%s: %.1f us\n", C.n, nplanes,
+                             kKClassNames[row_kclass(mode)], row_lines(v), row_swapped(v) ? " split swapped" : "",
+                             1e3 * ms);
             if (ms < best) { best = ms; bestv = v; }
         }
         C.rowv[mode] = bestv;

@@ -31,9 +31,12 @@ __device__ __forceinline__ float sgn(int i) { return (i & 1) ? -1.0f : 1.0f; }
 // the register index (k1 -> k1 + N1/2 on input, k2 -> k2 + N2/2 on output);
 // otherwise the slot keeps its position and the checkerboard sign (-1)^p
 // does the shift (the per-axis sign (-1)^(n/2) cancels on a square grid).
-template <int N>
+// SW: the transposed split N1 <-> N2 (a pass variant the autotuner can
+// choose where N1 != N2); the twiddle table stays the one of the default
+// split (its entry (a, b) is w_N^{ab}, symmetric in a and b).
+template <int N, bool SW = false>
 struct Centre {
-    static constexpr int N1 = split_n1(N), N2 = N / N1;
+    static constexpr int N1 = SW ? N / split_n1(N) : split_n1(N), N2 = N / N1;
     static constexpr bool PERM = (N1 % 2 == 0) && (N2 % 2 == 0);
     // position of stage-1 input slot j2 + N2 k1
     static __device__ __forceinline__ int in_pos(int j2, int k1) {
@@ -761,10 +764,15 @@ struct RowArgs {
     Scalars sc;
 };
 
-template <int N, int L, int MODE, bool HALF>
+template <int N, int L, int MODE, bool HALF, bool SW = false>
 __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
-    using CT = Centre<N>;
+    using CT = Centre<N, SW>;
     constexpr int N1 = CT::N1, N2 = CT::N2;
+    // twiddle w_N^{k1 j2} from the default split's table [N1d][N2d]
+    auto twid = [&](int k1, int j2) -> float2 {
+        if constexpr (SW) return elt(a.tw2, j2 * N1 + k1);
+        else return elt(a.tw2, k1 * N2 + j2);
+    };
     constexpr int NT = pass_threads(N, L);
     constexpr int S2 = N2 + 1;                      // padded stride of [line][k1][j2]
     static_assert(L * N1 <= NT && L * N2 <= NT, "one task per thread");
@@ -818,7 +826,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
             static_for<0, N1>([&](auto K) {
                 constexpr int k1 = K;
                 float2 x = v[k1];
-                if constexpr (k1 > 0) x = cmulc(x, elt(a.tw2, k1 * N2 + j2));
+                if constexpr (k1 > 0) x = cmulc(x, twid(k1, j2));
                 buf[(ll * N1 + k1) * S2 + j2] = x;
             });
         }
@@ -972,7 +980,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
             RegDFT<N1, false>::run(v);
             static_for<0, N1>([&](auto K) {
                 constexpr int k1 = K;
-                if constexpr (k1 > 0) v[k1] = cmul(v[k1], elt(a.tw2, k1 * N2 + j2));
+                if constexpr (k1 > 0) v[k1] = cmul(v[k1], twid(k1, j2));
             });
         }
         __syncthreads();

@@ -115,7 +115,7 @@ def test_every_pass_variant_gives_the_same_operator(n, n_om, J):
     with Plan(n, n_om, J) as pl:
         tried = 0
         for cv in range(4):
-            for rv in range(4):
+            for rv in range(8):
                 try:
                     pl.set_variant(n, cv, rv)
                 except NlinvError:
