@@ -243,15 +243,29 @@ int nlinv_gn_step_vjp(nlinv_plan plan, const nlinv_c32* rho_n, const nlinv_c32* 
  * Time the FFT pass variants (lines per workgroup) of every pass mode for
  * every shape class of the plan on `stream` (which must not be capturing),
  * and keep the fastest per mode.  It overwrites the plan's workspace, so call
- * it between solves.  Results are cached per (device architecture, n, planes)
- * in the text file named by NLINV_TUNE_CACHE, if set; NLINV_TUNE_VERBOSE
- * prints the timings to stderr.  Without this call a fixed default is used. */
+ * it between solves.  It also chooses the form of the normal operator entry
+ * point (nlinv_plan_normal_form).  Results are cached per (device
+ * architecture, n, planes) in the text file named by NLINV_TUNE_CACHE, if
+ * set; NLINV_TUNE_VERBOSE prints the timings to stderr.  Without this call a
+ * fixed default is used. */
 int nlinv_plan_autotune(nlinv_plan plan, void* stream);
 
 /* Choice made for grid size n (NLINV_EINVAL if n is not in the plan): the
  * variant index of the PSF column pass and of the derivative row pass of the
  * CG loop. */
 int nlinv_plan_variant(nlinv_plan plan, int32_t n, int32_t* col_variant, int32_t* row_variant);
+
+/* Form of the normal operator entry point (nlinv_normal) for grid size n:
+ * 0 = the axis passes (the five fused passes of the CG loop), 1 = the
+ * whole-plane kernel: one workgroup per coil plane holds the n x n plane in
+ * LDS and runs all four centred 2D transforms of DF and DF^H (Eq. 2) there,
+ * then a fixed-order coil sum forms the image part; it exists for
+ * 8 <= n <= 64.  nlinv_plan_autotune times both and keeps the faster (the
+ * default is 0).  NLINV_EINVAL if n is not in the plan. */
+int nlinv_plan_normal_form(nlinv_plan plan, int32_t n, int32_t* form);
+/* Force the form for grid size n (for tests): NLINV_EINVAL for a form the
+ * size does not have or an n not in the plan. */
+int nlinv_plan_set_normal_form(nlinv_plan plan, int32_t n, int32_t form);
 
 /* The band of k-space the solves keep of the sensitivities for grid size n:
  * rows and columns [*kb_lo, *kb_lo + *kb).  Outside it every Sobolev weight

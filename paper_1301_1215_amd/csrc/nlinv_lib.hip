@@ -85,6 +85,15 @@ hipError_t row_dispatch(int n, int mode, int variant, const RowArgs& a, hipStrea
     return hipErrorInvalidValue;
 }
 
+hipError_t plane_dispatch(int n, const PlaneArgs& a, hipStream_t s) {
+    switch (n) {
+#define X(N) case N: return launch_plane_normal<N>(a, s);
+        NLINV_FOR_EACH_SIZE(X)
+#undef X
+    }
+    return hipErrorInvalidValue;
+}
+
 bool col_ok(int n, int v) { return col_variant_ok(n, v); }
 bool row_ok(int n, int v) { return row_variant_ok(n, v); }
 
@@ -95,13 +104,14 @@ enum KClass : int {
     KC_ROW_CACHE, KC_ROW_FWD, KC_ROW_DERIV, KC_ROW_ADJ,
     KC_COIL_SUM, KC_VEC_DOT, KC_VEC_OTHER, KC_SCALAR, KC_IMAGE,
     KC_CG_ITER,   // one whole CG iteration (its five launches), bracketed as one
+    KC_PLANE_NORMAL,
     KC_NUM
 };
 const char* kKClassNames[KC_NUM] = {
     "col_winv_ifft", "col_p_ifft", "col_fft_p", "col_resid_p_ifft", "col_psf",
     "col_fft_winv_add", "col_fft_gprod", "col_pupd_winv_ifft", "col_fft_winv_cg_update",
     "row_cache", "row_fwd", "row_deriv", "row_adj",
-    "coil_sum", "vec_dot", "vec_other", "scalar", "image", "cg_iteration"};
+    "coil_sum", "vec_dot", "vec_other", "scalar", "image", "cg_iteration", "plane_normal"};
 
 int col_kclass(int mode) {
     switch (mode) {
@@ -136,6 +146,9 @@ struct Class {
     std::vector<int> J, plane0;
     int colv[kColModes] = {};    // pass variant per column mode
     int rowv[kRowModes] = {};    // and per row mode
+    // the normal operator entry point: 0 the axis passes, 1 the whole-plane
+    // kernel (grids that have one)
+    int normal_form = 0;
 
     int* plane_frame = nullptr;
     int* frame_plane0 = nullptr;
@@ -817,11 +830,49 @@ int seq_cg_iteration(nlinv_plan_s* p, Class& C, int step, int it, int nsteps, in
     return NLINV_OK;
 }
 
-// (drho_out, dchat_out) = (DF^H DF + alpha) (drho, dchat)
+// (drho_out, dchat_out) = (DF^H DF + alpha) (drho, dchat) of one frame in
+// the operator layout (whole grid, row-major) with the whole-plane kernel:
+// one workgroup per coil plane, then the coil sum for the rho part
+int seq_normal_plane(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2* rho, const float2* c,
+                     const float* P, float alpha, const float2* drho, const float2* dchat, float2* drho_out,
+                     float2* dchat_out, hipStream_t s) {
+    if (fr.tiled || fr.kb != C.n || fr.nframes != 1 || !plane_kernel_size(C.n)) return NLINV_EINVAL;
+    PlaneArgs a{};
+    a.rho = rho;
+    a.c = c;
+    a.P = P;
+    a.winv = C.winv;
+    a.drho = drho;
+    a.dchat = dchat;
+    a.dchat_out = dchat_out;
+    a.aux = C.aux;
+    a.tw2 = C.tw;
+    a.alpha = alpha;
+    a.rs = 1.0f / std::sqrt((float)C.n);
+    a.m = C.m;
+    a.lo = C.lo;
+    a.nplanes = fr.nplanes;
+    if (p->dry_run) {
+        CHK(dry_launch(p, rho && c && P && C.winv && drho && dchat && dchat_out && C.aux && C.tw,
+                       KC_PLANE_NORMAL));
+    } else {
+        const int slot = tbegin(p, KC_PLANE_NORMAL, s);
+        const hipError_t e = plane_dispatch(C.n, a, s);
+        tend(p, slot, s);
+        HIPCHK(e);
+    }
+    CoilSumArgs cs = coil_sum_args(C, fr, drho_out, drho, nullptr, nullptr, nullptr, alpha, 0.f, nullptr, 0);
+    return run_coil_sum(p, cs, s);
+}
+
+// (drho_out, dchat_out) = (DF^H DF + alpha) (drho, dchat); with whole_plane
+// (the operator entry point of a plan that chose it) by the whole-plane kernel
 int seq_normal(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2* rho, const float2* c,
                const float* P, long long p_stride, const float* alpha_f, float alpha_c,
                const float2* drho, const float2* dchat, float2* drho_out, float2* dchat_out,
-               hipStream_t s) {
+               hipStream_t s, bool whole_plane = false) {
+    if (whole_plane && C.normal_form == 1 && !alpha_f && p_stride == 0)
+        return seq_normal_plane(p, C, fr, rho, c, P, alpha_c, drho, dchat, drho_out, dchat_out, s);
     CHK(seq_deriv_head(p, C, fr, rho, c, drho, dchat, s));
     ColArgs a = col_args(p, C, fr);
     a.in = C.T;
@@ -1516,6 +1567,25 @@ int tune_class(nlinv_plan_s* p, Class& C, hipStream_t s) {
         }
         C.rowv[mode] = bestv;
     }
+    // the normal operator entry point: the axis passes against the
+    // whole-plane kernel (grids that have one), on the plan's first frame
+    // shape in the operator layout, with full-grid scratch standing in for
+    // the operands
+    C.normal_form = 0;
+    if (plane_kernel_size(C.n) && C.frames.size() > 0 && C.frames[0] == 0) {
+        const Frames fr = single_frame(C, C.J[0]);
+        float ms[2] = {0.f, 0.f};
+        for (int form = 0; form < 2; ++form) {
+            C.normal_form = form;
+            CHK(timeit([&] {
+                return seq_normal(p, C, fr, C.x_r, C.c, C.P, 0, nullptr, 0.5f, C.p_r, C.y, C.q_r, C.q_c, s, true);
+            }, ms[form]));
+            if (verbose)
+                std::fprintf(stderr, "nlinv tune n=%d planes=%d normal %s: %.1f us\n", C.n, C.J[0],
+                             form ? "whole plane" : "axis passes", 1e3 * ms[form]);
+        }
+        C.normal_form = ms[1] < ms[0] ? 1 : 0;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return NLINV_OK;
@@ -1826,7 +1896,7 @@ int nlinv_normal(nlinv_plan p, const nlinv_c32* rho, const nlinv_c32* chat, cons
         cc = C.c;
     }
     return seq_normal(p, C, fr, (const float2*)rho, cc, P, 0, nullptr, alpha, (const float2*)drho,
-                      (const float2*)dchat, (float2*)drho_out, (float2*)dchat_out, s);
+                      (const float2*)dchat, (float2*)drho_out, (float2*)dchat_out, s, true);
 }
 
 int nlinv_mask_gradient(nlinv_plan p, const nlinv_c32* rho, const nlinv_c32* chat, const nlinv_c32* c,
@@ -2143,6 +2213,12 @@ int nlinv_check_launch_args(int32_t n, int32_t n_om, int32_t ncoils, int32_t nfr
         const int s2 = run_row(&pl, K, mode, tune_row_args(K, mode), nullptr);
         if (st == NLINV_OK) st = s2;
     }
+    // the tuner's whole-plane normal operator and its coil sum (grids that have it)
+    if (plane_kernel_size(n)) {
+        const int s2 = seq_normal_plane(&pl, K, single_frame(K, K.J[0]), K.x_r, K.c, K.P, 0.5f, K.p_r, K.y, K.q_r,
+                                        K.q_c, nullptr);
+        if (st == NLINV_OK) st = s2;
+    }
     *launches = pl.dry_launches;
     *first_bad = pl.dry_first_bad;
     return st;
@@ -2154,6 +2230,7 @@ int nlinv_plan_autotune(nlinv_plan p, void* stream) {
     const std::string arch = arch_name(p->device);
     const char* path = std::getenv("NLINV_TUNE_CACHE");
     // cache lines: arch n planes kb <kColModes column variants> <kRowModes row variants>
+    // <normal operator form>
     std::map<std::string, std::vector<int>> cache;
     if (path) {
         std::ifstream in(path);
@@ -2166,7 +2243,7 @@ int nlinv_plan_autotune(nlinv_plan p, void* stream) {
             std::vector<int> v;
             int x;
             while (ls >> x) v.push_back(x);
-            if ((int)v.size() != kColModes + kRowModes) continue;
+            if ((int)v.size() != kColModes + kRowModes + 1) continue;
             std::ostringstream k;
             k << a << ' ' << n << ' ' << np << ' ' << kb;
             cache[k.str()] = v;
@@ -2178,18 +2255,23 @@ int nlinv_plan_autotune(nlinv_plan p, void* stream) {
         k << arch << ' ' << C.n << ' ' << C.nplanes << ' ' << C.kb;
         auto it = cache.find(k.str());
         bool ok = it != cache.end();
-        if (ok)
+        if (ok) {
             for (int i = 0; i < kColModes + kRowModes; ++i)
                 ok = ok && (i < kColModes ? col_ok_cols(C.n, col_mode_on_band(i) ? C.kb : C.n, it->second[i])
                                           : row_ok(C.n, it->second[i]));
+            const int nf = it->second[kColModes + kRowModes];
+            ok = ok && (nf == 0 || (nf == 1 && plane_kernel_size(C.n)));
+        }
         if (ok) {
             for (int i = 0; i < kColModes; ++i) C.colv[i] = it->second[i];
             for (int i = 0; i < kRowModes; ++i) C.rowv[i] = it->second[kColModes + i];
+            C.normal_form = it->second[kColModes + kRowModes];
             continue;
         }
         CHK(tune_class(p, C, s));
         std::vector<int> v(C.colv, C.colv + kColModes);
         v.insert(v.end(), C.rowv, C.rowv + kRowModes);
+        v.push_back(C.normal_form);
         cache[k.str()] = v;
         changed = true;
     }
@@ -2215,6 +2297,28 @@ int nlinv_plan_variant(nlinv_plan p, int32_t n, int32_t* col_variant, int32_t* r
         }
     *col_variant = *row_variant = -1;
     return NLINV_EINVAL;
+}
+
+int nlinv_plan_normal_form(nlinv_plan p, int32_t n, int32_t* form) {
+    if (!p || !form) return NLINV_EINVAL;
+    for (Class& C : p->classes)
+        if (C.n == n) {
+            *form = C.normal_form;
+            return NLINV_OK;
+        }
+    *form = -1;
+    return NLINV_EINVAL;
+}
+
+int nlinv_plan_set_normal_form(nlinv_plan p, int32_t n, int32_t form) {
+    if (!p || form < 0 || form > 1 || (form == 1 && !plane_kernel_size(n))) return NLINV_EINVAL;
+    bool found = false;
+    for (Class& C : p->classes)
+        if (C.n == n) {
+            C.normal_form = form;
+            found = true;
+        }
+    return found ? NLINV_OK : NLINV_EINVAL;
 }
 
 int nlinv_plan_band(nlinv_plan p, int32_t n, int32_t* kb, int32_t* kb_lo) {

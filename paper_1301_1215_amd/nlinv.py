@@ -168,6 +168,13 @@ class Plan:
     def set_variant(self, n, col_variant, row_variant):
         N.nlinv_plan_set_variant(self.handle, n, col_variant, row_variant)
 
+    def normal_form(self, n=None):
+        """0: nlinv_normal runs the axis passes; 1: the whole-plane kernel."""
+        return N.nlinv_plan_normal_form(self.handle, self.dims.n if n is None else n)
+
+    def set_normal_form(self, form, n=None):
+        N.nlinv_plan_set_normal_form(self.handle, self.dims.n if n is None else n, form)
+
     def timing_enable(self, kclass, enable=True):
         N.nlinv_plan_timing_enable(self.handle, kclass, enable)
 

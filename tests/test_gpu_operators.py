@@ -204,8 +204,9 @@ def test_autotune_picks_valid_variants_and_keeps_parity(tmp_path, monkeypatch):
         nr, nc = map(host, pl.normal(dev(rho), dev(chat), dev(P), 0.5, dev(drho), dev(dchat)))
         assert rel(nr, ref[0]) < TOL and rel(nc, ref[1]) < TOL
     line = (tmp_path / "tune.txt").read_text().split()
-    # arch, n, planes, the side of the band the solve keeps (64 at n = 192), 9 + 4 variants
-    assert line[1:4] == ["192", str(J), "64"] and len(line) == 4 + 9 + 4
+    # arch, n, planes, the side of the band the solve keeps (64 at n = 192), 9 + 4 variants,
+    # the normal operator's form (no whole-plane kernel at 192: the axis passes)
+    assert line[1:4] == ["192", str(J), "64"] and len(line) == 4 + 9 + 4 + 1 and line[-1] == "0"
     with Plan(n, n_om, J) as pl2:    # served from the cache file
         pl2.autotune()
         assert pl2.variant(n) == (cv, rv)
@@ -223,3 +224,54 @@ def test_kernel_timing_inside_a_replayed_graph():
         assert cnt == 2 * 4 and ms > 0     # one replay's launches
         cnt2, _ = pl.timing_read()         # graph-owned brackets stay readable
         assert cnt2 == cnt
+
+
+@pytest.mark.parametrize("n,n_om,J", [(8, 4, 2), (12, 6, 2), (16, 16, 3), (24, 12, 3), (24, 10, 2),
+                                      (32, 16, 4), (48, 24, 4), (64, 32, 8), (64, 64, 8)])
+def test_whole_plane_normal_matches_oracle(n, n_om, J):
+    """The whole-plane kernel (one workgroup per coil plane, the four centred
+    2D transforms of DF and DF^H in LDS) against the FP64 oracle and against
+    the axis passes, Omega the centred half, the grid, and an uneven crop."""
+    rng, rho, chat, P = _point(n, n_om, J, 7)
+    drho, dchat = rand_c((n_om, n_om), rng), rand_c((J, n, n), rng)
+    d = O.Dims(n, n_om, J)
+    ref = O.normal(rho, chat, P, 0.5, drho, dchat, d)
+    with Plan(n, n_om, J) as pl:
+        pl.set_normal_form(1)
+        assert pl.normal_form() == 1
+        args = (dev(rho), dev(chat), dev(P), 0.5, dev(drho), dev(dchat))
+        wr, wc = map(host, pl.normal(*args))
+        pl.set_normal_form(0)
+        ar, ac = map(host, pl.normal(*args))
+    assert rel(wr, ref[0]) < TOL and rel(wc, ref[1]) < TOL
+    assert rel(wr, ar) < TOL and rel(wc, ac) < TOL
+
+
+def test_whole_plane_form_only_where_it_exists():
+    from paper_1301_1215_amd._native import NlinvError
+    with Plan(96, 48, 2) as pl:
+        assert pl.normal_form() == 0
+        with pytest.raises(NlinvError):
+            pl.set_normal_form(1)
+
+
+def test_autotune_chooses_the_normal_form_and_keeps_parity(tmp_path, monkeypatch):
+    """At 64 x 64 (8 coils) the autotuner times the axis passes against the
+    whole-plane kernel for nlinv_normal; whichever it keeps, the operator
+    keeps parity and the cache line records the choice."""
+    monkeypatch.setenv("NLINV_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    n, n_om, J = 64, 64, 8
+    rng, rho, chat, P = _point(n, n_om, J, 8)
+    drho, dchat = rand_c((n_om, n_om), rng), rand_c((J, n, n), rng)
+    ref = O.normal(rho, chat, P, 0.5, drho, dchat, O.Dims(n, n_om, J))
+    with Plan(n, n_om, J) as pl:
+        pl.autotune()
+        form = pl.normal_form()
+        assert form in (0, 1)
+        nr, nc = map(host, pl.normal(dev(rho), dev(chat), dev(P), 0.5, dev(drho), dev(dchat)))
+        assert rel(nr, ref[0]) < TOL and rel(nc, ref[1]) < TOL
+    line = (tmp_path / "tune.txt").read_text().split()
+    assert line[1:3] == ["64", str(J)] and line[-1] == str(form)
+    with Plan(n, n_om, J) as pl2:    # served from the cache file
+        pl2.autotune()
+        assert pl2.normal_form() == form
