@@ -244,7 +244,8 @@ int nlinv_gn_step_vjp(nlinv_plan plan, const nlinv_c32* rho_n, const nlinv_c32* 
  * every shape class of the plan on `stream` (which must not be capturing),
  * and keep the fastest per mode.  It overwrites the plan's workspace, so call
  * it between solves.  It also chooses the form of the normal operator entry
- * point (nlinv_plan_normal_form).  Results are cached per (device
+ * point (nlinv_plan_normal_form) and of the solves' CG iteration
+ * (nlinv_plan_cg_form).  Results are cached per (device
  * architecture, n, planes) in the text file named by NLINV_TUNE_CACHE, if
  * set; NLINV_TUNE_VERBOSE prints the timings to stderr.  Without this call a
  * fixed default is used. */
@@ -266,6 +267,20 @@ int nlinv_plan_normal_form(nlinv_plan plan, int32_t n, int32_t* form);
 /* Force the form for grid size n (for tests): NLINV_EINVAL for a form the
  * size does not have or an n not in the plan. */
 int nlinv_plan_set_normal_form(nlinv_plan plan, int32_t n, int32_t form);
+
+/* Form of the solves' CG iteration for grid size n: 0 = the five fused axis
+ * passes, 1 = two launches (8 <= n <= 64): one workgroup per coil plane
+ * updates the direction p = r + beta p and applies the normal operator of
+ * Eq. 3 to it with the whole plane in LDS, then an update launch forms the
+ * step a = <r, r> / Re<p, N p> and applies r -= a N p, x += a p (the image
+ * part through a fixed-order coil sum).  The scalar steps (beta, a,
+ * breakdown, statistics, the components outside the band) are the same in
+ * both forms.  nlinv_plan_autotune times both (default 0).  NLINV_EINVAL if n
+ * is not in the plan. */
+int nlinv_plan_cg_form(nlinv_plan plan, int32_t n, int32_t* form);
+/* Force the CG form for grid size n (for tests; drops a captured graph):
+ * NLINV_EINVAL for a form the size does not have or an n not in the plan. */
+int nlinv_plan_set_cg_form(nlinv_plan plan, int32_t n, int32_t form);
 
 /* The band of k-space the solves keep of the sensitivities for grid size n:
  * rows and columns [*kb_lo, *kb_lo + *kb).  Outside it every Sobolev weight

@@ -22,7 +22,7 @@ EXPORTED = (
     "nlinv_plan_create", "nlinv_plan_create_branched", "nlinv_plan_destroy", "nlinv_coil_maps", "nlinv_forward", "nlinv_deriv",
     "nlinv_adjoint", "nlinv_normal", "nlinv_normal_noalloc", "nlinv_mask_gradient", "nlinv_image", "nlinv_irgnm_solve",
     "nlinv_irgnm_solve_batch", "nlinv_irgnm_solve_series", "nlinv_plan_autotune", "nlinv_plan_variant", "nlinv_plan_band",
-    "nlinv_plan_normal_form", "nlinv_plan_set_normal_form",
+    "nlinv_plan_normal_form", "nlinv_plan_set_normal_form", "nlinv_plan_cg_form", "nlinv_plan_set_cg_form",
     "nlinv_plan_set_variant", "nlinv_plan_timing_enable", "nlinv_plan_timing_read",
     "nlinv_plan_timing_read_class",
     "nlinv_kernel_class_name", "nlinv_status_string", "nlinv_last_hip_error", "nlinv_bandwidth_probe",
@@ -90,6 +90,8 @@ def load(path: str | None = None):
         "nlinv_plan_set_variant": ([vp, i32, i32, i32], C.c_int),
         "nlinv_plan_normal_form": ([vp, i32, C.POINTER(i32)], C.c_int),
         "nlinv_plan_set_normal_form": ([vp, i32, i32], C.c_int),
+        "nlinv_plan_cg_form": ([vp, i32, C.POINTER(i32)], C.c_int),
+        "nlinv_plan_set_cg_form": ([vp, i32, i32], C.c_int),
         "nlinv_plan_band": ([vp, i32, C.POINTER(i32), C.POINTER(i32)], C.c_int),
         "nlinv_plan_timing_enable": ([vp, i32, i32], C.c_int),
         "nlinv_plan_timing_read": ([vp, C.POINTER(i32), C.POINTER(C.c_double)], C.c_int),
@@ -406,6 +408,16 @@ def nlinv_plan_normal_form(plan, n):
 
 def nlinv_plan_set_normal_form(plan, n, form):
     check(load().nlinv_plan_set_normal_form(plan, int(n), int(form)), "nlinv_plan_set_normal_form")
+
+
+def nlinv_plan_cg_form(plan, n):
+    f = C.c_int32()
+    check(load().nlinv_plan_cg_form(plan, int(n), C.byref(f)), "nlinv_plan_cg_form")
+    return f.value
+
+
+def nlinv_plan_set_cg_form(plan, n, form):
+    check(load().nlinv_plan_set_cg_form(plan, int(n), int(form)), "nlinv_plan_set_cg_form")
 
 
 def nlinv_plan_set_variant(plan, n, col_variant, row_variant):

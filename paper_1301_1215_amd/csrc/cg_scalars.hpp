@@ -179,6 +179,19 @@ __device__ __forceinline__ float cg_beta(const ScalarStep& ss, const FrameScalar
     return fs.brk ? 0.f : (float)(tt / fs.rr);
 }
 
+// The CG step a = rr / gamma after the band's total t of Re<p, N p>, or 0
+// on a breakdown (SC_GAMMA records the same value)
+__device__ __forceinline__ bool gamma_breaks(const FrameScalars& fs, double g) {
+    return fs.brk || fs.rr == 0.0 || !(g > 0.0) || !isfinite(fs.rr);
+}
+__device__ __forceinline__ double gamma_total(const ScalarStep& ss, const FrameScalars& fs, double t) {
+    return t + (double)ss.alpha * fs.ipi * fs.ipi * fs.B2;   // alpha |p|^2 outside the band
+}
+__device__ __forceinline__ float cg_step(const ScalarStep& ss, const FrameScalars& fs, double t) {
+    const double g = gamma_total(ss, fs, t);
+    return gamma_breaks(fs, g) ? 0.f : (float)(fs.rr / g);
+}
+
 // The scalar logic for frame f given the total t and the frame's scalars
 // as loaded before (thread 0 only).
 __device__ __forceinline__ void scalar_apply(const ScalarStep& ss, const Scalars& sc, int f, double t,
@@ -209,9 +222,9 @@ __device__ __forceinline__ void scalar_apply(const ScalarStep& ss, const Scalars
         *rr_of(sc, 0, f) = t + B2;
         sc.brk[f] = 0;
     } else if (op == SC_GAMMA) {
-        t += (double)ss.alpha * fs.ipi * fs.ipi * fs.B2;   // alpha |p|^2 outside the band
+        t = gamma_total(ss, fs, t);
         const double rr = fs.rr;
-        if (fs.brk || rr == 0.0 || !(t > 0.0) || !isfinite(rr)) {
+        if (gamma_breaks(fs, t)) {
             if (!fs.brk) {
                 int fl = (int)fs.flags | 1;
                 if (!isfinite(t) || !isfinite(rr)) fl |= 2;

@@ -125,8 +125,25 @@ hipError_t launch_plane_normal(const PlaneArgs& a, hipStream_t s) {
     }
 }
 
+template <int N>
+hipError_t launch_plane_cg(const PlaneCgArgs& a, hipStream_t s) {
+    if constexpr (plane_kernel_size(N)) {
+        if (a.nplanes <= 0) return hipSuccess;
+        if (2 * a.lo + a.m != N || a.m <= 0 || a.kb <= 0 || a.klo < 0 || a.klo + a.kb > N || a.tw <= 0 ||
+            a.kb % a.tw != 0 || a.rseg * kThreads < a.m * a.m)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_plane_cg<N>), dim3(a.nplanes), dim3(plane_threads(N)), 0, s, a);
+        return hipGetLastError();
+    } else {
+        (void)a;
+        (void)s;
+        return hipErrorInvalidValue;
+    }
+}
+
 template hipError_t launch_col<NLINV_SIZE>(int, int, const ColArgs&, int, hipStream_t);
 template hipError_t launch_row<NLINV_SIZE>(int, int, const RowArgs&, hipStream_t);
 template hipError_t launch_plane_normal<NLINV_SIZE>(const PlaneArgs&, hipStream_t);
+template hipError_t launch_plane_cg<NLINV_SIZE>(const PlaneCgArgs&, hipStream_t);
 
 }  // namespace nlinv

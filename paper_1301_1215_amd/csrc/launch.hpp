@@ -36,14 +36,18 @@ template <int N>
 hipError_t launch_col(int mode, int variant, const ColArgs& a, int nplanes, hipStream_t s);
 template <int N>
 hipError_t launch_row(int mode, int variant, const RowArgs& a, hipStream_t s);
-// the whole-plane normal operator (hipErrorInvalidValue where no such kernel exists)
+// the whole-plane normal operator and CG iteration (hipErrorInvalidValue
+// where no such kernel exists)
 template <int N>
 hipError_t launch_plane_normal(const PlaneArgs& a, hipStream_t s);
+template <int N>
+hipError_t launch_plane_cg(const PlaneCgArgs& a, hipStream_t s);
 
 #define NLINV_DECLARE(N)                                                                       \
     extern template hipError_t launch_col<N>(int, int, const ColArgs&, int, hipStream_t);       \
     extern template hipError_t launch_row<N>(int, int, const RowArgs&, hipStream_t);            \
-    extern template hipError_t launch_plane_normal<N>(const PlaneArgs&, hipStream_t);
+    extern template hipError_t launch_plane_normal<N>(const PlaneArgs&, hipStream_t);            \
+    extern template hipError_t launch_plane_cg<N>(const PlaneCgArgs&, hipStream_t);
 NLINV_FOR_EACH_SIZE(NLINV_DECLARE)
 #undef NLINV_DECLARE
 

@@ -94,6 +94,15 @@ hipError_t plane_dispatch(int n, const PlaneArgs& a, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
+hipError_t plane_cg_dispatch(int n, const PlaneCgArgs& a, hipStream_t s) {
+    switch (n) {
+#define X(N) case N: return launch_plane_cg<N>(a, s);
+        NLINV_FOR_EACH_SIZE(X)
+#undef X
+    }
+    return hipErrorInvalidValue;
+}
+
 bool col_ok(int n, int v) { return col_variant_ok(n, v); }
 bool row_ok(int n, int v) { return row_variant_ok(n, v); }
 
@@ -104,14 +113,15 @@ enum KClass : int {
     KC_ROW_CACHE, KC_ROW_FWD, KC_ROW_DERIV, KC_ROW_ADJ,
     KC_COIL_SUM, KC_VEC_DOT, KC_VEC_OTHER, KC_SCALAR, KC_IMAGE,
     KC_CG_ITER,   // one whole CG iteration (its five launches), bracketed as one
-    KC_PLANE_NORMAL,
+    KC_PLANE_NORMAL, KC_PLANE_CG, KC_PLANE_CG_UPDATE,
     KC_NUM
 };
 const char* kKClassNames[KC_NUM] = {
     "col_winv_ifft", "col_p_ifft", "col_fft_p", "col_resid_p_ifft", "col_psf",
     "col_fft_winv_add", "col_fft_gprod", "col_pupd_winv_ifft", "col_fft_winv_cg_update",
     "row_cache", "row_fwd", "row_deriv", "row_adj",
-    "coil_sum", "vec_dot", "vec_other", "scalar", "image", "cg_iteration", "plane_normal"};
+    "coil_sum", "vec_dot", "vec_other", "scalar", "image", "cg_iteration", "plane_normal", "plane_cg",
+    "plane_cg_update"};
 
 int col_kclass(int mode) {
     switch (mode) {
@@ -147,8 +157,10 @@ struct Class {
     int colv[kColModes] = {};    // pass variant per column mode
     int rowv[kRowModes] = {};    // and per row mode
     // the normal operator entry point: 0 the axis passes, 1 the whole-plane
-    // kernel (grids that have one)
+    // kernel (grids that have one); the same choice for the CG iteration of
+    // the solves
     int normal_form = 0;
+    int cg_form = 0;
 
     int* plane_frame = nullptr;
     int* frame_plane0 = nullptr;
@@ -724,7 +736,9 @@ SegGeom rhs_geom(const Class& C) {
 
 // Geometry of the <r, r> partials a CG iteration leaves: column tiles of the
 // CG-update pass per plane, then the segments of its fused coil sum per frame.
+SegGeom plane_rr_geom(const Class& C);
 SegGeom cg_rr_geom(const Class& C) {
+    if (C.cg_form == 1) return plane_rr_geom(C);
     SegGeom g = C.geom;
     const int L = kColL[C.colv[COL_PAD_FFT_WINV_CG_UPD]];
     const int wg = pass_threads(C.n, L);
@@ -830,6 +844,91 @@ int seq_cg_iteration(nlinv_plan_s* p, Class& C, int step, int it, int nsteps, in
     return NLINV_OK;
 }
 
+// Geometry of the partials the whole-plane CG iteration leaves: <r, r> per
+// plane's band, then the rho part in segments of kThreads elements per frame;
+// |DF p|^2 per plane (cseg 1); |p_c|^2 and a share of |p_r|^2 per plane (cseg 2).
+SegGeom plane_rr_geom(const Class& C) {
+    SegGeom g = C.geom;
+    g.cseg = 1;
+    g.rseg = (int)((C.rplane() + kThreads - 1) / kThreads);
+    return g;
+}
+
+// One CG iteration of class C with the whole-plane kernels (two launches;
+// see plane_kernel.hpp): the same scalar steps as the five-pass iteration.
+int seq_cg_iteration_plane(nlinv_plan_s* p, Class& C, int step, int it, int nsteps, int ncg, float alpha,
+                           hipStream_t s) {
+    const int iter_slot = tbegin(p, KC_CG_ITER, s);
+    PlaneCgArgs a{};
+    a.nplanes = C.nplanes;
+    a.nframes = C.nframes;
+    a.plane_frame = C.plane_frame;
+    a.frame_plane0 = C.frame_plane0;
+    a.frame_planes = C.frame_planes;
+    a.m = C.m;
+    a.lo = C.lo;
+    a.kb = C.kb;
+    a.klo = C.kb_lo;
+    a.tw = C.tilew;
+    a.rs = 1.0f / std::sqrt((float)C.n);
+    a.alpha = alpha;
+    a.tw2 = C.tw;
+    a.P = C.P;
+    a.p_stride = C.cplane();
+    a.winv = C.winv_t;
+    a.rho = C.x_r;
+    a.c = C.c;
+    a.r_c = C.r_c;
+    a.p_c = C.p_c;
+    a.q_c = C.q_c;
+    a.x_c = C.x_c;
+    a.r_r = C.r_r;
+    a.p_r = C.p_r;
+    a.dx_r = C.dx_r;
+    a.aux = C.aux;
+    a.part_g = C.part_p;
+    a.part_r = C.partial2;
+    a.rseg = plane_rr_geom(C).rseg;
+    a.first_iter = it == 0;
+    a.fold = it > 0 ? scalar_step(C, SC_RR, plane_rr_geom(C), 0.f, step, it - 1, nsteps, ncg, C.partial2)
+                    : scalar_step(C, SC_RR0, rhs_geom(C), 0.f, step, 0, nsteps, ncg, C.partial);
+    a.fold.alpha = alpha;
+    a.sc = C.sc;
+    const bool ok = a.r_c && a.p_c && a.q_c && a.x_c && a.r_r && a.p_r && a.dx_r && a.aux && a.part_g &&
+                    a.part_r && a.P && a.winv && a.rho && a.c && a.tw2 && a.fold.partial;
+    if (p->dry_run) {
+        CHK(dry_launch(p, ok, KC_PLANE_CG));
+    } else {
+        if (!ok) return NLINV_EINVAL;
+        const int slot = tbegin(p, KC_PLANE_CG, s);
+        const hipError_t e = plane_cg_dispatch(C.n, a, s);
+        tend(p, slot, s);
+        HIPCHK(e);
+    }
+    // the update: a = <r, r> / (|DF p|^2 + alpha |p|^2) from the partials just written
+    SegGeom g = C.geom;
+    g.cseg = 1;
+    g.rseg = 0;
+    a.fold = scalar_step(C, SC_GAMMA, g, 0.f, step, it, nsteps, ncg, C.part_p);
+    a.fold.g2 = C.geom;   // |p_c|^2 and the |p_r|^2 share of each plane
+    a.fold.g2.cseg = 2;
+    a.fold.g2.rseg = 0;
+    a.fold.partial2 = C.part_p + C.nplanes;
+    a.fold.alpha = alpha;
+    if (p->dry_run) {
+        CHK(dry_launch(p, ok, KC_PLANE_CG_UPDATE));
+    } else {
+        const int slot = tbegin(p, KC_PLANE_CG_UPDATE, s);
+        hipLaunchKernelGGL(k_plane_cg_update<kThreads>, dim3(C.nplanes + C.nframes * a.rseg), dim3(kThreads), 0,
+                           s, a);
+        const hipError_t e = hipGetLastError();
+        tend(p, slot, s);
+        HIPCHK(e);
+    }
+    tend(p, iter_slot, s);
+    return NLINV_OK;
+}
+
 // (drho_out, dchat_out) = (DF^H DF + alpha) (drho, dchat) of one frame in
 // the operator layout (whole grid, row-major) with the whole-plane kernel:
 // one workgroup per coil plane, then the coil sum for the rho part
@@ -925,7 +1024,9 @@ int enqueue_class_newton(nlinv_plan_s* p, Class& C, const nlinv_irgnm_params& pr
                 (void)gb;   // the geometry rhs_geom() gives the first CG pass
             }
         }
-        for (int it = 0; it < K; ++it) CHK(seq_cg_iteration(p, C, step, it, N, K, al, s));
+        for (int it = 0; it < K; ++it)
+            CHK(C.cg_form == 1 ? seq_cg_iteration_plane(p, C, step, it, N, K, al, s)
+                               : seq_cg_iteration(p, C, step, it, N, K, al, s));
         // the chat part of the step is already in x; rho += drho happens in
         // the next coil-map pass (dx_r is first written by CG iteration 0)
     }
@@ -1414,7 +1515,8 @@ int build_class(nlinv_plan_s* p, Class& C) {
     const size_t tiles = (size_t)C.nplanes * (C.n / 4) + (size_t)C.nframes * ((rn + 63) / 64);
     CHK(dalloc(p, &C.partial, std::max<size_t>(tiles, (size_t)std::max(nseg(C.geom), nseg(C.geomC)))));
     CHK(dalloc(p, &C.partial2, std::max<size_t>(tiles, (size_t)nseg(C.geom))));
-    CHK(dalloc(p, &C.part_p, (size_t)(C.nplanes + C.nframes) * (C.n / 4)));
+    // (also the whole-plane CG iteration's |DF p|^2 and |p|^2 partials: 3 per plane)
+    CHK(dalloc(p, &C.part_p, std::max<size_t>((size_t)(C.nplanes + C.nframes) * (C.n / 4), (size_t)3 * C.nplanes)));
     CHK(dalloc(p, &C.sc.rr, (size_t)2 * C.nframes));
     CHK(dalloc(p, &C.sc.a, C.nframes));
     CHK(dalloc(p, &C.sc.beta, C.nframes));
@@ -1585,6 +1687,23 @@ int tune_class(nlinv_plan_s* p, Class& C, hipStream_t s) {
                              form ? "whole plane" : "axis passes", 1e3 * ms[form]);
         }
         C.normal_form = ms[1] < ms[0] ? 1 : 0;
+    }
+    // the solves' CG iteration: the five passes against the two whole-plane
+    // launches (CG iteration 1 of 2, with its scalar folds, on scratch state)
+    C.cg_form = 0;
+    if (plane_kernel_size(C.n)) {
+        float ms[2] = {0.f, 0.f};
+        for (int form = 0; form < 2; ++form) {
+            C.cg_form = form;
+            CHK(timeit([&] {
+                return form ? seq_cg_iteration_plane(p, C, 0, 1, 1, 2, 0.5f, s)
+                            : seq_cg_iteration(p, C, 0, 1, 1, 2, 0.5f, s);
+            }, ms[form]));
+            if (verbose)
+                std::fprintf(stderr, "nlinv tune n=%d planes=%d cg_iteration %s: %.1f us\n", C.n, nplanes,
+                             form ? "whole plane" : "axis passes", 1e3 * ms[form]);
+        }
+        C.cg_form = ms[1] < ms[0] ? 1 : 0;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -2213,10 +2332,13 @@ int nlinv_check_launch_args(int32_t n, int32_t n_om, int32_t ncoils, int32_t nfr
         const int s2 = run_row(&pl, K, mode, tune_row_args(K, mode), nullptr);
         if (st == NLINV_OK) st = s2;
     }
-    // the tuner's whole-plane normal operator and its coil sum (grids that have it)
+    // the tuner's whole-plane normal operator and its coil sum, and a
+    // whole-plane CG iteration (grids that have them)
     if (plane_kernel_size(n)) {
-        const int s2 = seq_normal_plane(&pl, K, single_frame(K, K.J[0]), K.x_r, K.c, K.P, 0.5f, K.p_r, K.y, K.q_r,
-                                        K.q_c, nullptr);
+        int s2 = seq_normal_plane(&pl, K, single_frame(K, K.J[0]), K.x_r, K.c, K.P, 0.5f, K.p_r, K.y, K.q_r,
+                                  K.q_c, nullptr);
+        if (st == NLINV_OK) st = s2;
+        s2 = seq_cg_iteration_plane(&pl, K, 0, 1, 1, 2, 0.5f, nullptr);
         if (st == NLINV_OK) st = s2;
     }
     *launches = pl.dry_launches;
@@ -2230,7 +2352,7 @@ int nlinv_plan_autotune(nlinv_plan p, void* stream) {
     const std::string arch = arch_name(p->device);
     const char* path = std::getenv("NLINV_TUNE_CACHE");
     // cache lines: arch n planes kb <kColModes column variants> <kRowModes row variants>
-    // <normal operator form>
+    // <normal operator form> <CG iteration form>
     std::map<std::string, std::vector<int>> cache;
     if (path) {
         std::ifstream in(path);
@@ -2243,7 +2365,7 @@ int nlinv_plan_autotune(nlinv_plan p, void* stream) {
             std::vector<int> v;
             int x;
             while (ls >> x) v.push_back(x);
-            if ((int)v.size() != kColModes + kRowModes + 1) continue;
+            if ((int)v.size() != kColModes + kRowModes + 2) continue;
             std::ostringstream k;
             k << a << ' ' << n << ' ' << np << ' ' << kb;
             cache[k.str()] = v;
@@ -2259,19 +2381,23 @@ int nlinv_plan_autotune(nlinv_plan p, void* stream) {
             for (int i = 0; i < kColModes + kRowModes; ++i)
                 ok = ok && (i < kColModes ? col_ok_cols(C.n, col_mode_on_band(i) ? C.kb : C.n, it->second[i])
                                           : row_ok(C.n, it->second[i]));
-            const int nf = it->second[kColModes + kRowModes];
-            ok = ok && (nf == 0 || (nf == 1 && plane_kernel_size(C.n)));
+            for (int i = 0; i < 2; ++i) {
+                const int nf = it->second[kColModes + kRowModes + i];
+                ok = ok && (nf == 0 || (nf == 1 && plane_kernel_size(C.n)));
+            }
         }
         if (ok) {
             for (int i = 0; i < kColModes; ++i) C.colv[i] = it->second[i];
             for (int i = 0; i < kRowModes; ++i) C.rowv[i] = it->second[kColModes + i];
             C.normal_form = it->second[kColModes + kRowModes];
+            C.cg_form = it->second[kColModes + kRowModes + 1];
             continue;
         }
         CHK(tune_class(p, C, s));
         std::vector<int> v(C.colv, C.colv + kColModes);
         v.insert(v.end(), C.rowv, C.rowv + kRowModes);
         v.push_back(C.normal_form);
+        v.push_back(C.cg_form);
         cache[k.str()] = v;
         changed = true;
     }
@@ -2319,6 +2445,30 @@ int nlinv_plan_set_normal_form(nlinv_plan p, int32_t n, int32_t form) {
             found = true;
         }
     return found ? NLINV_OK : NLINV_EINVAL;
+}
+
+int nlinv_plan_cg_form(nlinv_plan p, int32_t n, int32_t* form) {
+    if (!p || !form) return NLINV_EINVAL;
+    for (Class& C : p->classes)
+        if (C.n == n) {
+            *form = C.cg_form;
+            return NLINV_OK;
+        }
+    *form = -1;
+    return NLINV_EINVAL;
+}
+
+int nlinv_plan_set_cg_form(nlinv_plan p, int32_t n, int32_t form) {
+    if (!p || form < 0 || form > 1 || (form == 1 && !plane_kernel_size(n))) return NLINV_EINVAL;
+    bool found = false;
+    for (Class& C : p->classes)
+        if (C.n == n) {
+            C.cg_form = form;
+            found = true;
+        }
+    if (!found) return NLINV_EINVAL;
+    CHK(drop_graph(p));   // the form is baked into a captured graph
+    return NLINV_OK;
 }
 
 int nlinv_plan_band(nlinv_plan p, int32_t n, int32_t* kb, int32_t* kb_lo) {

@@ -216,4 +216,249 @@ __global__ __launch_bounds__(plane_threads(N)) void k_plane_normal(PlaneArgs a) 
     });
 }
 
+// ---------------------------------------------------------------------------
+// A CG iteration of the solve (Eq. 3) on small grids in two launches:
+// k_plane_cg (one workgroup per coil plane) folds the previous iteration's
+// <r, r> into beta, updates the direction p = r + beta p and applies the
+// whole-plane normal operator to it, writing q = W^{-H} E(conj(rho) v) on the
+// band, the coil products conj(c) v and the partials of |DF p|^2 and |p|^2;
+// k_plane_cg_update then forms the step a = <r, r> / (|DF p|^2 + alpha |p|^2)
+// in every workgroup and applies r -= a N p, x += a p (the rho part through
+// the coil sum), writing the <r, r> partials the next iteration folds.  The
+// scalar logic is the one of the five-pass iteration (cg_scalars.hpp).
+// ---------------------------------------------------------------------------
+
+struct PlaneCgArgs {
+    int nplanes, nframes;
+    const int* plane_frame;     // [planes]
+    const int* frame_plane0;    // [frames]
+    const int* frame_planes;    // [frames]
+    int m, lo;                  // Omega
+    int kb, klo, tw;            // band [klo, klo + kb)^2, its column tile width
+    float rs, alpha;
+    const float2* tw2;          // [N1][N2]
+    const float* P;             // [frames][n][n], column-tiled
+    long long p_stride;
+    const float* winv;          // [kb][kb] band of 1/w, column-tiled
+    const float2* rho;          // [frames][m][m] linearisation point
+    const float2* c;            // [planes][m][m] its coil maps
+    float2* r_c;                // [planes][kb][kb] CG vectors on the band (column-tiled)
+    float2* p_c;
+    float2* q_c;                // W^{-H} E(conj(rho) v) on the band
+    float2* x_c;                // the solution's chat part (takes a p directly)
+    float2* r_r;                // [frames][m][m]
+    float2* p_r;
+    float2* dx_r;
+    float2* aux;                // [planes][m][m]
+    double* part_g;             // k_plane_cg: [planes] |DF p|^2, then per plane |p_c|^2 and its
+                                //   share of the frame's |p_r|^2 ([planes][2])
+    double* part_r;             // update: [planes] |r_c|^2, [frames][rseg] |r_r|^2
+    int rseg;                   // update: segments of a frame's rho part (kThreads elements)
+    int first_iter;             // p = r
+    ScalarStep fold;            // k_plane_cg: SC_RR0 / SC_RR; update: SC_GAMMA
+    Scalars sc;
+};
+
+// the direction p = r + beta p, the same rounding in both kernels
+__device__ __forceinline__ float2 cg_dir(float beta, float2 p, float2 r) {
+    return make_float2(__fmaf_rn(beta, p.x, r.x), __fmaf_rn(beta, p.y, r.y));
+}
+
+template <int N>
+__global__ __launch_bounds__(plane_threads(N)) void k_plane_cg(PlaneCgArgs a) {
+    constexpr int NT = plane_threads(N);
+    using Col = PlaneLines<N, 0>;
+    using Row = PlaneLines<N, 1>;
+    static_assert(plane_kernel_size(N), "whole-plane size");
+    __shared__ float2 A[N * N];
+    __shared__ float2 B[Col::BSIZE];
+    __shared__ float2 TW[N];
+    __shared__ double red[NT / 64];
+    __shared__ float beta_sh;
+    const int plane = blockIdx.x;
+    if (plane >= a.nplanes) return;
+    const int f = a.plane_frame[plane];
+    const bool designated = plane == a.frame_plane0[f];
+    const int m = a.m, lo = a.lo, kb = a.kb, klo = a.klo, tw = a.tw;
+    const float rs = a.rs;
+    const long long kbase = (long long)plane * kb * kb, cb = (long long)plane * m * m, fb = (long long)f * m * m;
+    // the band's operands in flight before the scalar fold
+    constexpr int MAXE = (N * N + NT - 1) / NT;
+    float2 rv[MAXE], pv0[MAXE];
+    float wv[MAXE];
+    static_for<0, MAXE>([&](auto I) {
+        const int e = (int)threadIdx.x + I * NT;
+        if (e < kb * kb) {
+            rv[I] = a.r_c[kbase + e];
+            pv0[I] = a.first_iter ? rv[I] : a.p_c[kbase + e];
+            wv[I] = a.winv[e];
+        }
+    });
+    // beta of this iteration from the previous <r, r> (the frame's first plane records the step)
+    if (threadIdx.x < 64) {
+        const FrameScalars fs = load_frame_scalars(a.fold, a.sc, f);
+        const double t = frame_total_wave(a.fold.g, a.fold.partial, f, a.frame_plane0, a.frame_planes);
+        if (threadIdx.x == 0) {
+            beta_sh = a.first_iter ? 0.f : cg_beta(a.fold, fs, t);
+            if (designated) scalar_apply(a.fold, a.sc, f, t, fs);
+        }
+    }
+    for (int e = threadIdx.x; e < N; e += NT) TW[e] = a.tw2[e];
+    for (int e = threadIdx.x; e < N * N; e += NT) A[e] = make_float2(0.f, 0.f);
+    __syncthreads();
+    const float beta = beta_sh;
+    // p = r + beta p on the band; W^{-1} p into the plane
+    double acc = 0.0;
+    static_for<0, MAXE>([&](auto I) {
+        const int e = (int)threadIdx.x + I * NT;
+        if (e < kb * kb) {
+            const float2 pv = a.first_iter ? rv[I] : cg_dir(beta, pv0[I], rv[I]);
+            a.p_c[kbase + e] = pv;
+            acc += (double)(pv.x * pv.x + pv.y * pv.y);
+            const int col = (e / (kb * tw)) * tw + e % tw, row = (e / tw) % kb;
+            A[(klo + row) * N + klo + col] = cscale(pv, wv[I]);
+        }
+    });
+    auto pr_of = [&](int q) -> float2 {   // the direction's rho part
+        const float2 r = a.r_r[fb + q];
+        return a.first_iter ? r : cg_dir(beta, a.p_r[fb + q], r);
+    };
+    // this plane's share of the frame's |p_r|^2 (p_r itself is written by the update)
+    double ar = 0.0;
+    {
+        const int np = a.frame_planes[f], jj = plane - a.frame_plane0[f];
+        const int chunk = (m * m + np - 1) / np, q1 = min(m * m, (jj + 1) * chunk);
+        for (int q = jj * chunk + (int)threadIdx.x; q < q1; q += NT) {
+            const float2 pv = pr_of(q);
+            ar += (double)(pv.x * pv.x + pv.y * pv.y);
+        }
+    }
+    {
+        const double t = wg_sum<NT>(acc, red);
+        const double tr = wg_sum<NT>(ar, red);
+        if (threadIdx.x == 0) {
+            a.part_g[a.nplanes + 2 * plane] = t;
+            a.part_g[a.nplanes + 2 * plane + 1] = tr;
+        }
+    }
+    auto in_om = [&](int i, int k) { return (unsigned)(i - lo) < (unsigned)m && (unsigned)(k - lo) < (unsigned)m; };
+    auto colA = [&](int col, int row) -> float2& { return A[row * N + col]; };
+    auto rowA = [&](int row, int col) -> float2& { return A[row * N + col]; };
+    Col::template first<true, NT>(B, TW, [&](int col, int row) { return colA(col, row); });
+    __syncthreads();
+    Col::template second<true, NT>(B, rs, [&](int col, int row, float2 v) { colA(col, row) = v; });
+    __syncthreads();
+    Row::template first<true, NT>(B, TW, [&](int row, int col) { return rowA(row, col); });
+    __syncthreads();
+    Row::template middle<true, NT>(B, rs, [&](int row, int col, float2 dc) {
+        if (!in_om(row, col)) return make_float2(0.f, 0.f);
+        const int q = (row - lo) * m + (col - lo);
+        return cadd(cmul(a.c[cb + q], pr_of(q)), cmul(a.rho[fb + q], dc));
+    });
+    __syncthreads();
+    Row::template last<false, NT>(B, TW, rs, [&](int row, int col, float2 v) { rowA(row, col) = v; });
+    __syncthreads();
+    // columns: forward, P^2 with |P K|^2 = |DF p|^2 of the plane, inverse
+    Col::template first<false, NT>(B, TW, [&](int col, int row) { return colA(col, row); });
+    __syncthreads();
+    const float* Pf = a.P + (long long)f * a.p_stride;
+    double accg = 0.0;
+    Col::template middle<false, NT>(B, rs, [&](int col, int row, float2 x) {
+        const float p = Pf[((col / tw) * N + row) * tw + col % tw];
+        accg += (double)(p * p * (x.x * x.x + x.y * x.y));
+        return cscale(x, p * p);
+    });
+    __syncthreads();
+    Col::template last<true, NT>(B, TW, rs, [&](int col, int row, float2 v) { colA(col, row) = v; });
+    __syncthreads();
+    Row::template first<true, NT>(B, TW, [&](int row, int col) { return rowA(row, col); });
+    __syncthreads();
+    Row::template middle<true, NT>(B, rs, [&](int row, int col, float2 v) {
+        if (!in_om(row, col)) return make_float2(0.f, 0.f);
+        const int q = (row - lo) * m + (col - lo);
+        a.aux[cb + q] = cconjmul(a.c[cb + q], v);
+        return cconjmul(a.rho[fb + q], v);
+    });
+    __syncthreads();
+    Row::template last<false, NT>(B, TW, rs, [&](int row, int col, float2 v) { rowA(row, col) = v; });
+    __syncthreads();
+    // columns: forward; q = W^{-H} E(conj(rho) v) on the band
+    Col::template first<false, NT>(B, TW, [&](int col, int row) { return colA(col, row); });
+    __syncthreads();
+    Col::template second<false, NT>(B, rs, [&](int col, int row, float2 v) {
+        const int br = row - klo, bc = col - klo;
+        if ((unsigned)br >= (unsigned)kb || (unsigned)bc >= (unsigned)kb) return;
+        const int e = ((bc / tw) * kb + br) * tw + bc % tw;
+        a.q_c[kbase + e] = cscale(v, a.winv[e]);
+    });
+    const double t = wg_sum<NT>(accg, red);
+    if (threadIdx.x == 0) a.part_g[plane] = t;
+}
+
+// The update: blocks [0, planes) take a plane's band, blocks [planes,
+// planes + frames * rseg) a segment of NT elements of a frame's rho part.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_plane_cg_update(PlaneCgArgs a) {
+    __shared__ double red[NT / 64];
+    __shared__ float a_sh, beta_sh;
+    const int b = blockIdx.x;
+    const bool chat = b < a.nplanes;
+    if (!chat && b >= a.nplanes + a.nframes * a.rseg) return;
+    const int f = chat ? a.plane_frame[b] : (b - a.nplanes) / a.rseg;
+    // a = rr / gamma (every block; the frame's first plane records it)
+    if (threadIdx.x < 64) {
+        const FrameScalars fs = load_frame_scalars(a.fold, a.sc, f);
+        double t = frame_total_wave(a.fold.g, a.fold.partial, f, a.frame_plane0, a.frame_planes);
+        const double t2 = frame_total_wave(a.fold.g2, a.fold.partial2, f, a.frame_plane0, a.frame_planes);
+        if (threadIdx.x == 0) {
+            t += (double)a.fold.alpha * t2;
+            a_sh = cg_step(a.fold, fs, t);
+            beta_sh = a.first_iter ? 0.f : a.sc.beta[f];
+            if (chat && b == a.frame_plane0[f]) scalar_apply(a.fold, a.sc, f, t, fs);
+        }
+    }
+    __syncthreads();
+    const float av = a_sh, beta = beta_sh, al = a.alpha;
+    double acc = 0.0;
+    if (chat) {
+        const long long kbase = (long long)b * a.kb * a.kb;
+        for (int e = threadIdx.x; e < a.kb * a.kb; e += NT) {
+            const float2 pv = a.p_c[kbase + e], qv = a.q_c[kbase + e];
+            const float2 q = make_float2(qv.x + al * pv.x, qv.y + al * pv.y);   // N_alpha p
+            float2 r = a.r_c[kbase + e];
+            r.x -= av * q.x;
+            r.y -= av * q.y;
+            a.r_c[kbase + e] = r;
+            float2 x = a.x_c[kbase + e];
+            x.x += av * pv.x;
+            x.y += av * pv.y;
+            a.x_c[kbase + e] = x;
+            acc += (double)(r.x * r.x + r.y * r.y);
+        }
+    } else {
+        const int k = (b - a.nplanes) % a.rseg;
+        const int E = a.m * a.m, e = k * NT + (int)threadIdx.x;
+        if (e < E) {
+            const long long fo = (long long)f * E;
+            const float2 r0 = a.r_r[fo + e];
+            const float2 pv = a.first_iter ? r0 : cg_dir(beta, a.p_r[fo + e], r0);
+            // q = sum over the frame's coils of conj(c) v, plus alpha p (fixed order)
+            const int p0 = a.frame_plane0[f], np = a.frame_planes[f];
+            float2 s = make_float2(0.f, 0.f);
+            for (int j = 0; j < np; ++j) s = cadd(s, a.aux[(long long)(p0 + j) * E + e]);
+            const float2 q = make_float2(s.x + al * pv.x, s.y + al * pv.y);
+            const float2 r = make_float2(r0.x - av * q.x, r0.y - av * q.y);
+            float2 d = a.first_iter ? make_float2(0.f, 0.f) : a.dx_r[fo + e];
+            d.x += av * pv.x;
+            d.y += av * pv.y;
+            a.p_r[fo + e] = pv;
+            a.r_r[fo + e] = r;
+            a.dx_r[fo + e] = d;
+            acc = (double)(r.x * r.x + r.y * r.y);
+        }
+    }
+    const double t = wg_sum<NT>(acc, red);
+    if (threadIdx.x == 0) a.part_r[chat ? b : a.nplanes + (b - a.nplanes)] = t;
+}
+
 }  // namespace nlinv

@@ -175,6 +175,14 @@ class Plan:
     def set_normal_form(self, form, n=None):
         N.nlinv_plan_set_normal_form(self.handle, self.dims.n if n is None else n, form)
 
+    def cg_form(self, n=None):
+        """0: the solves' CG iteration is the five fused passes; 1: the two
+        whole-plane launches."""
+        return N.nlinv_plan_cg_form(self.handle, self.dims.n if n is None else n)
+
+    def set_cg_form(self, form, n=None):
+        N.nlinv_plan_set_cg_form(self.handle, self.dims.n if n is None else n, form)
+
     def timing_enable(self, kclass, enable=True):
         N.nlinv_plan_timing_enable(self.handle, kclass, enable)
 

@@ -206,7 +206,7 @@ def test_autotune_picks_valid_variants_and_keeps_parity(tmp_path, monkeypatch):
     line = (tmp_path / "tune.txt").read_text().split()
     # arch, n, planes, the side of the band the solve keeps (64 at n = 192), 9 + 4 variants,
     # the normal operator's form (no whole-plane kernel at 192: the axis passes)
-    assert line[1:4] == ["192", str(J), "64"] and len(line) == 4 + 9 + 4 + 1 and line[-1] == "0"
+    assert line[1:4] == ["192", str(J), "64"] and len(line) == 4 + 9 + 4 + 2 and line[-2:] == ["0", "0"]
     with Plan(n, n_om, J) as pl2:    # served from the cache file
         pl2.autotune()
         assert pl2.variant(n) == (cv, rv)
@@ -271,7 +271,7 @@ def test_autotune_chooses_the_normal_form_and_keeps_parity(tmp_path, monkeypatch
         nr, nc = map(host, pl.normal(dev(rho), dev(chat), dev(P), 0.5, dev(drho), dev(dchat)))
         assert rel(nr, ref[0]) < TOL and rel(nc, ref[1]) < TOL
     line = (tmp_path / "tune.txt").read_text().split()
-    assert line[1:3] == ["64", str(J)] and line[-1] == str(form)
+    assert line[1:3] == ["64", str(J)] and line[-2] == str(form) and line[-1] in ("0", "1")
     with Plan(n, n_om, J) as pl2:    # served from the cache file
         pl2.autotune()
         assert pl2.normal_form() == form

@@ -318,3 +318,66 @@ def test_transposed_row_split_solve_matches_oracle():
     got = _variant_solve(fr, 1, 4, 3, 8)
     assert rel(got["image"], ref.image) < NRMSE
     assert rel(got["rho"], ref.rho) < NRMSE
+
+
+def _form_solve(fr, cg_form, newton, cg, use_graph=True):
+    with Plan(fr.n, fr.n_om, fr.ncoils) as pl:
+        pl.set_cg_form(cg_form)
+        assert pl.cg_form() == cg_form
+        out = pl.solve(dev(fr.y), dev(fr.P), Plan.params(newton, cg, use_graph=use_graph))
+        return {k: host(v) for k, v in out.items()}
+
+
+@pytest.mark.parametrize("n,n_om,J,mask", [(64, 64, 8, "cartesian"), (64, 32, 8, "radial"), (48, 24, 4, "radial"),
+                                           (32, 16, 4, "radial"), (24, 12, 3, "radial"), (16, 16, 2, "cartesian"),
+                                           (12, 6, 2, "radial")])
+def test_whole_plane_cg_gives_the_same_solve(n, n_om, J, mask):
+    """The CG iteration in two whole-plane launches (form 1) against the five
+    fused passes (form 0): the same method and scalar steps (beta, a,
+    breakdown, the components outside the band at n >= 48), other summation
+    orders; Omega the grid, its centred half."""
+    fr = synth.make_frame(1, 21, n, n_om, J, mask, spokes=9)
+    ref = _form_solve(fr, 0, 3, 8)
+    got = _form_solve(fr, 1, 3, 8)
+    for k in ("rho", "chat", "image"):
+        assert rel(got[k], ref[k]) < 1e-4, k
+    assert got["stats"][1] == ref["stats"][1]    # the same flags (CG may stop at <r, r> = 0)
+    # the residual norm per Newton step; <r, r> per CG iteration while it is
+    # above the single-precision floor of its Newton step (1e-4 of the step's
+    # first value: below it both forms return rounding noise)
+    np.testing.assert_allclose(got["stats"][2:5], ref["stats"][2:5], rtol=1e-4)
+    rg, rr = got["stats"][5:5 + 3 * 8].reshape(3, 8), ref["stats"][5:5 + 3 * 8].reshape(3, 8)
+    live = rr > 1e-4 * rr[:, :1]
+    np.testing.assert_allclose(rg[live], rr[live], rtol=1e-2)
+
+
+def test_whole_plane_cg_single_frame_64_matches_oracle():
+    """cfg1 (64 x 64, Omega = grid, 8 coils, Cartesian) with the whole-plane
+    CG iteration, eager and graph-replayed: image and rho NRMSE, the residual
+    norms per Newton step and <r, r> per CG iteration against the oracle."""
+    fr = synth.single_frame_64()
+    ref = oracle_solve(fr, 6, 10)
+    for graph in (False, True):
+        got = _form_solve(fr, 1, 6, 10, use_graph=graph)
+        assert rel(got["image"], ref.image) < NRMSE
+        assert rel(got["rho"], ref.rho) < NRMSE
+        st = got["stats"]
+        assert np.allclose(st[2:8], ref.r0_norms, rtol=1e-4)
+        assert np.allclose(st[8:].reshape(6, 10), np.array(ref.cg_rr), rtol=2e-3)
+
+
+def test_whole_plane_cg_in_a_mixed_batch():
+    """A batch with a 64-grid class on the whole-plane CG iteration and a
+    128-grid class on the five passes, against each frame solved alone with
+    the five passes."""
+    frames = [synth.make_frame(3, t, n, n // 2, J, "radial", spokes=11)
+              for t, (n, J) in enumerate([(64, 4), (128, 6), (64, 4)])]
+    prm = Plan.params(3, 6, use_graph=True)
+    with Plan(frames=[(f.n, f.n_om, f.ncoils) for f in frames]) as pl:
+        pl.set_cg_form(1, n=64)
+        assert pl.cg_form(64) == 1 and pl.cg_form(128) == 0
+        outs = pl.solve_batch([(dev(f.y), dev(f.P)) for f in frames], prm)
+        got = [{k: host(v) for k, v in o.items()} for o in outs]
+    for f, g in zip(frames, got):
+        ref = _form_solve(f, 0, 3, 6)
+        assert rel(g["image"], ref["image"]) < 1e-4
