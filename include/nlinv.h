@@ -298,7 +298,8 @@ int nlinv_plan_band(nlinv_plan plan, int32_t n, int32_t* kb, int32_t* kb_lo);
  * returns NLINV_EINVAL for an index that is not valid for n.  Column
  * variants 0-3 are 16, 8, 32 and 4 columns per workgroup; row variants 0-3
  * are 8, 16, 4 and 2 rows per workgroup, 4-7 the same with the line FFT's
- * split N = N1 x N2 transposed (valid where N1 != N2). */
+ * split N = N1 x N2 transposed in the derivative and adjoint row passes of
+ * the CG loop (valid where N1 != N2). */
 int nlinv_plan_set_variant(nlinv_plan plan, int32_t n, int32_t col_variant, int32_t row_variant);
 
 /* ---- kernel timing --------------------------------------------------------

@@ -75,17 +75,21 @@ static hipError_t row_L(int mode, const RowArgs& a, hipStream_t s) {
         return hipErrorInvalidValue;
     const dim3 grid((a.nlines + L - 1) / L), block(pass_threads(N, L));
     const bool half = 2 * a.m == N && 4 * a.lo == N;
-#define NLINV_ROW(MODE)                                                                   \
-    if (half) hipLaunchKernelGGL((k_row<N, L, MODE, true, SW>), grid, block, 0, s, a);     \
-    else hipLaunchKernelGGL((k_row<N, L, MODE, false, SW>), grid, block, 0, s, a)
+    // the transposed split exists for the CG loop's row passes; the others
+    // run the default split under every variant
+#define NLINV_ROW_SPLIT(MODE, S)                                                          \
+    if (half) hipLaunchKernelGGL((k_row<N, L, MODE, true, S>), grid, block, 0, s, a);      \
+    else hipLaunchKernelGGL((k_row<N, L, MODE, false, S>), grid, block, 0, s, a)
+#define NLINV_ROW(MODE) NLINV_ROW_SPLIT(MODE, SW)
     switch (mode) {
-        case ROW_CACHE: NLINV_ROW(ROW_CACHE); break;
-        case ROW_FWD: NLINV_ROW(ROW_FWD); break;
+        case ROW_CACHE: NLINV_ROW_SPLIT(ROW_CACHE, false); break;
+        case ROW_FWD: NLINV_ROW_SPLIT(ROW_FWD, false); break;
         case ROW_DERIV: NLINV_ROW(ROW_DERIV); break;
         case ROW_ADJ: NLINV_ROW(ROW_ADJ); break;
         default: return hipErrorInvalidValue;
     }
 #undef NLINV_ROW
+#undef NLINV_ROW_SPLIT
     return hipGetLastError();
 }
 

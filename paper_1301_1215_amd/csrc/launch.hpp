@@ -24,7 +24,8 @@ constexpr bool col_variant_ok(int n, int v) {
     return v >= 0 && v < kNumColVariants && n % kColL[v] == 0 && n * kColL[v] <= 8192;
 }
 // Row variant v takes kRowL[v & 3] lines per workgroup; v >= 4 also
-// transposes the line FFT's split N1 x N2 (only where N1 != N2).
+// transposes the line FFT's split N1 x N2 (only where N1 != N2) in the CG
+// loop's row passes (the derivative and adjoint passes).
 constexpr int row_lines(int v) { return kRowL[v & 3]; }
 constexpr bool row_swapped(int v) { return v >= 4; }
 constexpr bool row_variant_ok(int n, int v) {

@@ -1658,6 +1658,8 @@ int tune_class(nlinv_plan_s* p, Class& C, hipStream_t s) {
         int bestv = C.rowv[mode];
         for (int v = 0; v < kNumRowVariants; ++v) {
             if (!row_ok(C.n, v)) continue;
+            // the transposed split exists for the CG loop's row passes only
+            if (row_swapped(v) && mode != ROW_DERIV && mode != ROW_ADJ) continue;
             C.rowv[mode] = v;
             float ms = 0.f;
             CHK(timeit([&] { return run_row(p, C, mode, r, s); }, ms));
