@@ -428,6 +428,45 @@ def ragged_bench(a, torch, steps):
                         "{8,12,16,32}, spokes in {11,15,21}, 7 Newton x 10 CG, one batched graph-replayed solve"}
 
 
+def single_64_bench(a, torch, steps=20, applies=200):
+    """The single 64 x 64 frame (8 coils, Cartesian, 6 Newton x 10 CG): frames/s
+    of a graph-replayed solve with each CG form (the five fused passes, the two
+    whole-plane launches) and nlinv_normal applies/s with each normal form."""
+    from paper_1301_1215_amd import Plan, synth
+    fr = synth.single_frame_64()
+    y, P = torch.from_numpy(fr.y).cuda(), torch.from_numpy(fr.P).cuda()
+    prm = Plan.params(6, 10, use_graph=True)
+    rec = {"workload": "single_64: 64x64 grid, Omega = grid, 8 coils, Cartesian 16 central + 25% outer lines, "
+                       "6 Newton x 10 CG, one frame per graph-replayed solve"}
+    with Plan(64, 64, 8) as pl:
+        if not a.no_autotune:
+            pl.autotune()
+        rec["cg_form_chosen"], rec["normal_form_chosen"] = pl.cg_form(), pl.normal_form()
+        outs = [pl._frame_out(pl.dims, prm)]
+        for form, name in ((0, "axis_passes"), (1, "whole_plane")):
+            pl.set_cg_form(form)
+            for _ in range(2):
+                pl.solve_batch([(y, P)], prm, outs)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                pl.solve_batch([(y, P)], prm, outs)
+            torch.cuda.synchronize()
+            rec[f"frames_per_s_{name}"] = steps / (time.perf_counter() - t0)
+        rho, chat = outs[0]["rho"], outs[0]["chat"]
+        c = pl.coil_maps(chat)   # the linearisation's cache, as inside a solve
+        for form, name in ((0, "axis_passes"), (1, "whole_plane")):
+            pl.set_normal_form(form)
+            pl.normal(rho, chat, P, 0.5, rho, chat, c=c)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(applies):
+                pl.normal(rho, chat, P, 0.5, rho, chat, c=c)
+            torch.cuda.synchronize()
+            rec[f"normal_applies_per_s_{name}"] = applies / (time.perf_counter() - t0)
+    return rec
+
+
 # ---------------------------------------------------------------------------
 # profile summaries (host only): rocprofv3 CSV output -> profiles/*.{md,txt}
 # ---------------------------------------------------------------------------
@@ -591,6 +630,7 @@ def main():
         rt = realtime_bench(a, NAT, torch, steps=5)
         other["realtime_384_x4"] = {"frames_per_s": rt["value"], "ms_per_step": rt["ms_per_step"],
                                     "workload": rt["workload"], "cg_iteration_frac": rt["roofline"]["frac"]}
+        other["single_64"] = single_64_bench(a, torch)
         extras["other_workloads"] = other
     if a.stream_probe:
         extras["stream_copy_GBps"] = stream_probe()
