@@ -394,6 +394,8 @@ ColArgs col_args(const nlinv_plan_s* p, const Class& C, const Frames& fr) {
     a.rs = (float)(1.0 / std::sqrt((double)C.n));
     a.tw2 = C.tw;
     a.winv = fr.tiled ? C.winv_t : C.winv;
+    a.frame_plane0 = fr.frame_plane0;
+    a.frame_planes = fr.frame_planes;
     a.fold.op = SC_NONE;
     (void)p;
     return a;
@@ -795,9 +797,9 @@ int seq_cg_iteration(nlinv_plan_s* p, Class& C, int step, int it, int nsteps, in
         ScalarStep ss = scalar_step(C, SC_GAMMA, C.geom, 0.f, step, it, nsteps, ncg, C.partial);
         ss.g.cseg = tg;
         ss.g.rseg = 0;
-        ss.g2 = C.geom;
-        ss.g2.cseg = tp;
-        ss.g2.rseg = tp;
+        ss.g2 = C.geom;            // per plane: |p_c|^2 tiles, then its share of |p_r|^2
+        ss.g2.cseg = 2 * tp;
+        ss.g2.rseg = 0;
         ss.partial2 = C.part_p;
         ss.alpha = alpha;
         r.fold = ss;
@@ -1516,7 +1518,8 @@ int build_class(nlinv_plan_s* p, Class& C) {
     CHK(dalloc(p, &C.partial, std::max<size_t>(tiles, (size_t)std::max(nseg(C.geom), nseg(C.geomC)))));
     CHK(dalloc(p, &C.partial2, std::max<size_t>(tiles, (size_t)nseg(C.geom))));
     // (also the whole-plane CG iteration's |DF p|^2 and |p|^2 partials: 3 per plane)
-    CHK(dalloc(p, &C.part_p, std::max<size_t>((size_t)(C.nplanes + C.nframes) * (C.n / 4), (size_t)3 * C.nplanes)));
+    // (the first CG pass's |p|^2 partials: 2 per plane and column tile)
+    CHK(dalloc(p, &C.part_p, (size_t)(2 * C.nplanes + C.nframes) * (C.n / 4) + (size_t)3 * C.nplanes));
     CHK(dalloc(p, &C.sc.rr, (size_t)2 * C.nframes));
     CHK(dalloc(p, &C.sc.a, C.nframes));
     CHK(dalloc(p, &C.sc.beta, C.nframes));

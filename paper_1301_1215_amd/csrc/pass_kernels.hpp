@@ -197,6 +197,8 @@ struct ColArgs {
     const float* P;           // [frames][n][n] with stride p_stride (0 = shared)
     long long p_stride;
     const int* plane_frame;   // nullable: all planes in frame 0
+    const int* frame_plane0;  // nullable: one frame of nplanes planes
+    const int* frame_planes;
     const float* s1;          // per-frame multiplier of add1 (nullable -> c1)
     const float* s2;
     float c1, c2;
@@ -223,9 +225,10 @@ struct ColArgs {
     const float* cg_a;        // [frames] CG step a
     // FP64 partial sums, one per workgroup at partial[plane * tiles + tile]
     // (tiles = n / L), when non-null:
-    //   COL_PUPD_WINV_IFFT_CROP   |p|^2 of the chat part; the first plane of
-    //                             each frame adds the rho part's |p|^2 at
-    //                             partial[nplanes * tiles + frame * tiles + tile]
+    //   COL_PUPD_WINV_IFFT_CROP   |p|^2 of the chat part at
+    //                             partial[plane * 2 tiles + tile], and of this
+    //                             workgroup's share of the frame's rho part at
+    //                             partial[plane * 2 tiles + tiles + tile]
     //   COL_RESID_P_IFFT          |s y - P . DFT(...)|^2 (the residual's norm)
     //   COL_PAD_FFT_P2_IFFT       |P . DFT(...)|^2 = |DF h|^2 of the plane's coil
     //   COL_PAD_FFT_WINV_ADD      |out|^2
@@ -409,11 +412,14 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
         } else if (a.beta) {
             beta = a.beta[f];
         }
-        // rho part of the direction update, done by the first plane of each frame
-        if (first_plane) {
-            const int E = m * m, ntiles = ncols / L;
-            const int chunk = (E + ntiles - 1) / ntiles;
-            const int e0 = tile * chunk, e1 = min(E, e0 + chunk);
+        // rho part of the direction update, shared by every workgroup of the
+        // frame: chunk (coil, tile) of its J * tiles chunks
+        {
+            const int p0 = a.frame_plane0 ? a.frame_plane0[f] : 0;
+            const int np = a.frame_planes ? a.frame_planes[f] : a.nplanes;
+            const int E = m * m, ntiles = ncols / L, nch = np * ntiles;
+            const int chunk = (E + nch - 1) / nch;
+            const int e0 = min(E, ((plane - p0) * ntiles + tile) * chunk), e1 = min(E, e0 + chunk);
             const float bf = beta;
             float2* pr = a.pr + (long long)f * E;
             const float2* rr = a.rr + (long long)f * E;
@@ -717,12 +723,14 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
         if (a.partial) {   // uniform over the workgroup
             const long long ntiles = ncols / L;
             const double t = wg_sum<NT>(acc, red);
-            if (threadIdx.x == 0) a.partial[(long long)plane * ntiles + tile] = t;
             if constexpr (PUPD) {
-                if (first_plane) {
-                    const double tr = wg_sum<NT>(acc_rho, red);
-                    if (threadIdx.x == 0) a.partial[((long long)a.nplanes + f) * ntiles + tile] = tr;
+                const double tr = wg_sum<NT>(acc_rho, red);
+                if (threadIdx.x == 0) {
+                    a.partial[(long long)plane * 2 * ntiles + tile] = t;
+                    a.partial[(long long)plane * 2 * ntiles + ntiles + tile] = tr;
                 }
+            } else {
+                if (threadIdx.x == 0) a.partial[(long long)plane * ntiles + tile] = t;
             }
         }
     }
