@@ -60,22 +60,24 @@ __device__ __forceinline__ void coil_sum_block(const CoilSumArgs& a, int b, doub
         const float2 u2 = a.add2 ? a.add2[g] : zero;
         float2 r = a.r_upd ? a.r_upd[g] : zero;
         float2 d = (a.r_upd && !a.dx_zero) ? a.dx_upd[g] : zero;
-        // four independent chains over the planes (four loads in flight),
+        // eight independent chains over the planes (eight loads in flight),
         // combined in a fixed order
-        float2 s0 = zero, s1 = zero, s2 = zero, s3 = zero;
+        constexpr int U = 8;
+        float2 sc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) sc[u] = zero;
         int p = 0;
-        for (; p + 3 < np; p += 4) {
-            const float2 v0 = src[(long long)p * a.E], v1 = src[(long long)(p + 1) * a.E];
-            const float2 v2 = src[(long long)(p + 2) * a.E], v3 = src[(long long)(p + 3) * a.E];
-            s0 = cadd(s0, v0);
-            s1 = cadd(s1, v1);
-            s2 = cadd(s2, v2);
-            s3 = cadd(s3, v3);
+        for (; p + U - 1 < np; p += U) {
+            float2 v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = src[(long long)(p + u) * a.E];
+#pragma unroll
+            for (int u = 0; u < U; ++u) sc[u] = cadd(sc[u], v[u]);
         }
-        if (p < np) s0 = cadd(s0, src[(long long)p * a.E]);
-        if (p + 1 < np) s1 = cadd(s1, src[(long long)(p + 1) * a.E]);
-        if (p + 2 < np) s2 = cadd(s2, src[(long long)(p + 2) * a.E]);
-        float2 s = cadd(cadd(s0, s1), cadd(s2, s3));
+#pragma unroll
+        for (int u = 0; u < U - 1; ++u)
+            if (p + u < np) sc[u] = cadd(sc[u], src[(long long)(p + u) * a.E]);
+        float2 s = cadd(cadd(cadd(sc[0], sc[1]), cadd(sc[2], sc[3])), cadd(cadd(sc[4], sc[5]), cadd(sc[6], sc[7])));
         s.x += c1 * u1.x + c2 * u2.x;
         s.y += c1 * u1.y + c2 * u2.y;
         if (a.r_upd) {

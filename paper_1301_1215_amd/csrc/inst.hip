@@ -35,7 +35,8 @@ static hipError_t col_L(int mode, const ColArgs& a, int nplanes, hipStream_t s) 
     const int ncols = chat ? a.kb : N;
     // 1D grid, a multiple of 8 blocks: the kernel deals work items to XCDs
     const int total = (ncols / L) * nplanes;
-    const int extra = mode == COL_PAD_FFT_WINV_CG_UPD ? a.cs_blocks : 0;   // fused coil-sum workgroups
+    // fused coil-sum workgroups, first in the grid (a multiple of 8 blocks)
+    const int extra = mode == COL_PAD_FFT_WINV_CG_UPD ? 8 * ((a.cs_blocks + 7) / 8) : 0;
     const dim3 grid(8 * ((total + 7) / 8) + extra), block(pass_threads(N, L));
     const bool half = 2 * a.m == N && 4 * a.lo == N;
     const bool bandc = chat && a.kb == Band<N>::KB && a.kb_lo == Band<N>::KLO;

@@ -236,9 +236,11 @@ struct ColArgs {
     double* partial;
     int tiled;                // n x n planes, P and 1/w column-tiled (inside a solve)
     // COL_PAD_FFT_WINV_CG_UPD: the rho parts' CG update (a coil sum in its CG
-    // form) runs as cs_blocks extra workgroups of the same launch, after the
-    // column workgroups; it only needs the coil products and a, so it
-    // overlaps the column work instead of taking a launch of its own
+    // form) runs as cs_blocks extra workgroups of the same launch, before the
+    // column workgroups (the grid's first 8 * ceil(cs_blocks / 8) blocks, so
+    // that they are dispatched first and the column tiles keep their XCD
+    // assignment); it only needs the coil products and a, so it overlaps the
+    // column work instead of taking a launch of its own
     CoilSumArgs cs;
     int cs_blocks;
     // COL_PUPD_WINV_IFFT_CROP: the previous iteration's SC_RR step folded in
@@ -258,10 +260,11 @@ struct ColArgs {
 // Work item w = tile * nplanes + plane (planes of a tile adjacent, so the P
 // tile of a frame is reused); blocks are dealt to the 8 XCDs round robin, so
 // block b runs item (b % 8) * per + b / 8: each XCD owns a contiguous range.
-__device__ __forceinline__ bool col_item(int ntiles, int nplanes, int& tile, int& plane) {
+// `first` blocks of the grid (a multiple of 8) come before the work items.
+__device__ __forceinline__ bool col_item(int ntiles, int nplanes, int& tile, int& plane, int first = 0) {
     const int total = ntiles * nplanes;
     const int per = (total + 7) / 8;
-    const int b = blockIdx.x;
+    const int b = (int)blockIdx.x - first;
     const int w = (b & 7) * per + (b >> 3);
     if (w >= total) return false;
     tile = w / nplanes;
@@ -325,15 +328,16 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
             return in_band(r);
         }
     };
+    int first = 0;
     if constexpr (CGU) {
-        const int ncol = 8 * ((ncols / L * a.nplanes + 7) / 8);
-        if ((int)blockIdx.x >= ncol) {
-            coil_sum_block<NT>(a.cs, (int)blockIdx.x - ncol, red);
+        first = 8 * ((a.cs_blocks + 7) / 8);
+        if ((int)blockIdx.x < first) {
+            if ((int)blockIdx.x < a.cs_blocks) coil_sum_block<NT>(a.cs, (int)blockIdx.x, red);
             return;
         }
     }
     int tile, plane;
-    if (!col_item(ncols / L, a.nplanes, tile, plane)) return;
+    if (!col_item(ncols / L, a.nplanes, tile, plane, first)) return;
     const int col0 = tile * L;
     const int f = a.plane_frame ? a.plane_frame[plane] : 0;
     // HALF: Omega is the centred half of the grid (m = n/2, 2x oversampling),
