@@ -963,6 +963,46 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
                 }
             }
             if constexpr (MODE == ROW_CACHE) return;
+            if constexpr (MODE == ROW_DERIV || MODE == ROW_ADJ) {
+                // The forward transform as the adjoint of the inverse's stages
+                // in reverse order: the adjoint of stage 2 (an N2-point DFT)
+                // on this task's registers, back into the slots it read
+                // (v already carries the centring sign of its positions);
+                // then the adjoint of stage 1 (twiddle, N1-point DFT) with
+                // its outputs at the stage-1 input positions, straight to HBM
+                if (act) {
+                    RegDFT<N2, false>::run(v);
+                    static_for<0, N2>([&](auto J) {
+                        constexpr int j2 = J;
+                        buf[(ll * N1 + k1) * S2 + j2] = v[j2];
+                    });
+                }
+                __syncthreads();
+                if (t < L * N2) {
+                    const int lo2 = t / N2, j2 = t % N2;
+                    if (line0 + lo2 < a.nlines) {
+                        float2 w[N1];
+                        static_for<0, N1>([&](auto K) {
+                            constexpr int kk = K;
+                            w[kk] = buf[(lo2 * N1 + kk) * S2 + j2];
+                            if constexpr (kk > 0) w[kk] = cmul(w[kk], twid(kk, j2));
+                        });
+                        RegDFT<N1, false>::run(w);
+                        static_for<0, N1>([&](auto K) {
+                            constexpr int kk = K;
+                            const int pos = CT::in_pos(j2, kk);
+                            const float2 x = cscale(w[kk], CT::sign(pos) * a.rs);
+                            if constexpr (OUT_BAND) {
+                                const int pc = pos - klo;
+                                if ((unsigned)pc < (unsigned)kb) elt(a.out + (long long)line0 * kb, lo2 * kb + pc) = x;
+                            } else {
+                                elt(a.out + (long long)line0 * N, lo2 * N + pos) = x;
+                            }
+                        });
+                    }
+                }
+                return;
+            }
             __syncthreads();
             if (act) {
                 static_for<0, N2>([&](auto K) {
