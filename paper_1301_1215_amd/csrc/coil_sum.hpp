@@ -38,6 +38,8 @@ struct CoilSumArgs {
     float2* dx_upd;          // rho part of dx (in place)
     int dx_zero;             // dx starts from 0 (first CG iteration): not read
     const float* cg_a;       // [frames] CG step a
+    int group;               // > 1: aux holds sums over groups of that many coils,
+                             // [planes / group][E] (frames' plane ranges divisible by it)
 };
 
 // One (frame, segment) of the sum with NT threads (seg_len <= NT); `red`
@@ -46,8 +48,9 @@ template <int NT>
 __device__ __forceinline__ void coil_sum_block(const CoilSumArgs& a, int b, double* red) {
     const int f = b / a.segs, k = b % a.segs;
     const int e = k * a.seg_len + threadIdx.x;
-    const int p0 = a.frame_plane0 ? a.frame_plane0[f] : 0;
-    const int np = a.frame_planes ? a.frame_planes[f] : a.nplanes;
+    const int gs = a.group > 1 ? a.group : 1;
+    const int p0 = (a.frame_plane0 ? a.frame_plane0[f] : 0) / gs;
+    const int np = (a.frame_planes ? a.frame_planes[f] : a.nplanes) / gs;
     double acc = 0.0;
     if (threadIdx.x < a.seg_len && e < a.E) {
         const long long g = (long long)f * a.E + e;
@@ -60,23 +63,35 @@ __device__ __forceinline__ void coil_sum_block(const CoilSumArgs& a, int b, doub
         const float2 u2 = a.add2 ? a.add2[g] : zero;
         float2 r = a.r_upd ? a.r_upd[g] : zero;
         float2 d = (a.r_upd && !a.dx_zero) ? a.dx_upd[g] : zero;
-        // eight independent chains over the planes (eight loads in flight),
-        // combined in a fixed order
+        // The sum's order depends on the frame alone (not on the batch or on
+        // which pass formed the partial sums): a frame whose coil count is a
+        // multiple of 4 sums each group of 4 consecutive coils as
+        // (c0 + c2) + (c1 + c3) (what the adjoint row pass forms when it
+        // groups coils), then the groups; otherwise the coils.  The items
+        // are summed in eight independent chains (eight loads in flight),
+        // combined in a fixed order.
+        const bool quads = gs == 4 || np % 4 == 0;
+        const int nitems = gs == 4 ? np : (quads ? np / 4 : np);
+        auto item = [&](int i) -> float2 {
+            if (gs == 4 || !quads) return src[(long long)i * a.E];
+            const float2* q = src + (long long)4 * i * a.E;
+            return cadd(cadd(q[0], q[2 * (long long)a.E]), cadd(q[a.E], q[3 * (long long)a.E]));
+        };
         constexpr int U = 8;
         float2 sc[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) sc[u] = zero;
-        int p = 0;
-        for (; p + U - 1 < np; p += U) {
+        int i0 = 0;
+        for (; i0 + U - 1 < nitems; i0 += U) {
             float2 v[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) v[u] = src[(long long)(p + u) * a.E];
+            for (int u = 0; u < U; ++u) v[u] = item(i0 + u);
 #pragma unroll
             for (int u = 0; u < U; ++u) sc[u] = cadd(sc[u], v[u]);
         }
 #pragma unroll
         for (int u = 0; u < U - 1; ++u)
-            if (p + u < np) sc[u] = cadd(sc[u], src[(long long)(p + u) * a.E]);
+            if (i0 + u < nitems) sc[u] = cadd(sc[u], item(i0 + u));
         float2 s = cadd(cadd(cadd(sc[0], sc[1]), cadd(sc[2], sc[3])), cadd(cadd(sc[4], sc[5]), cadd(sc[6], sc[7])));
         s.x += c1 * u1.x + c2 * u2.x;
         s.y += c1 * u1.y + c2 * u2.y;

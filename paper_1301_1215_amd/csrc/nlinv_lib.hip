@@ -749,6 +749,22 @@ SegGeom cg_rr_geom(const Class& C) {
     return g;
 }
 
+// Whether the CG loop's adjoint row pass can sum the coil products over
+// groups of 4 coils (RowArgs::cgroup): Omega the centred half with its
+// output slots known at compile time for the pass's split, 4 lines of a row
+// in one wavefront, whole groups of rows per workgroup and whole coil groups
+// per frame.
+bool coil_groups_ok(const Class& C) {
+    const int v = C.rowv[ROW_ADJ], L = row_lines(v), n = C.n;
+    const int d1 = split_n1(n), n1 = row_swapped(v) ? n / d1 : d1, n2 = n / n1;
+    const bool half = 2 * C.m == n && 4 * C.lo == n;
+    const bool half_by_k2 = n1 % 2 == 0 && n2 % 2 == 0 && n2 % 4 == 0 && (n / 4) % n1 == 0;
+    if (!half || !half_by_k2 || L % 4 != 0 || 64 % (4 * n1) != 0 || C.m % (L / 4) != 0) return false;
+    for (int j : C.J)
+        if (j % 4 != 0) return false;
+    return true;
+}
+
 // alpha: the Newton step's regularisation weight (a kernel argument of the
 // passes that need it)
 int seq_cg_iteration(nlinv_plan_s* p, Class& C, int step, int it, int nsteps, int ncg, float alpha,
@@ -809,6 +825,8 @@ int seq_cg_iteration(nlinv_plan_s* p, Class& C, int step, int it, int nsteps, in
     r.drho = nullptr;
     r.in = C.T;
     r.out = TB;
+    const bool groups = coil_groups_ok(C);
+    r.cgroup = groups ? 4 : 0;
     CHK(run_row(p, C, ROW_ADJ, r, s));
     const int tu = col_tiles(C, fr, COL_PAD_FFT_WINV_CG_UPD);
     ColArgs e = col_args(p, C, fr);
@@ -833,6 +851,7 @@ int seq_cg_iteration(nlinv_plan_s* p, Class& C, int step, int it, int nsteps, in
     cs.dx_upd = C.dx_r;
     cs.dx_zero = it == 0;            // dx = a p: no zero fill of dx beforehand
     cs.cg_a = C.sc.a;
+    cs.group = groups ? 4 : 1;       // the adjoint row pass summed groups of 4 coils
     const SegGeom grr = cg_rr_geom(C);
     cs.segs = grr.rseg;
     cs.seg_len = (cs.E + cs.segs - 1) / cs.segs;

@@ -769,6 +769,13 @@ struct RowArgs {
     int kb, kb_lo;
     float rs;
     const float2* tw2;       // [N1][N2]
+    // ROW_ADJ with cgroup = 4 (Omega the centred half with compile-time
+    // slots, L a multiple of 4, the four lines of a row's stage-2 tasks in one
+    // wavefront, every frame's coil count a multiple of 4): a workgroup takes
+    // L/4 rows of 4 consecutive coil planes, and aux receives the sum of the
+    // four coils' products, [planes/4][m][m] (the coil sum then adds planes/4
+    // partials per pixel)
+    int cgroup;
     // ROW_ADJ, ROW_CACHE: a per-frame scalar step folded into the launch (op
     // SC_NONE or partial == nullptr: none), done by the first wavefront of
     // the first workgroups before their lines
@@ -791,10 +798,22 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
     // [line][k1][j2] (padded) for the stage exchange, or [line][pos] between
     // the two transforms: every stage reads into registers, waits, then writes
     __shared__ float2 buf[L * N1 * S2];
-    const int line0 = blockIdx.x * L;
     // HALF: Omega is the centred half of the grid (m = n/2, 2x oversampling),
     // fixed at compile time so that every crop and pad test folds away
     const int m = HALF ? N / 2 : a.m, lo = HALF ? N / 4 : a.lo;
+    // The workgroup's lines: L consecutive global lines (line = plane * m +
+    // row), or with coil groups (RowArgs::cgroup) L/4 rows of 4 consecutive
+    // coil planes, line ll the coil ll % 4 of row ll / 4; line ll sits at
+    // global line line0 + loff(ll)
+    constexpr bool CGROUP = MODE == ROW_ADJ && HALF && CT::HALF_BY_K2 && L % 4 == 0 && 64 % (4 * N1) == 0;
+    const bool cg = CGROUP && a.cgroup == 4;
+    int line0 = blockIdx.x * L, grp = 0;
+    if (cg) {
+        const int wpg = m / (L / 4);     // workgroups per coil group
+        grp = blockIdx.x / wpg;
+        line0 = grp * 4 * m + (blockIdx.x % wpg) * (L / 4);
+    }
+    auto loff = [&](int ll) { return cg ? (ll & 3) * m + (ll >> 2) : ll; };
     const int t = threadIdx.x;
     constexpr bool IN_BAND = MODE == ROW_CACHE || MODE == ROW_DERIV;   // input rows [kb]
     constexpr bool OUT_BAND = MODE == ROW_ADJ;                          // output rows [kb]
@@ -820,7 +839,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
         // inverse transform of the T rows: stage 1 from HBM
         if (t < L * N2) {
             const int ll = t / N2, j2 = t % N2;
-            const int line = line0 + ll;
+            const int line = line0 + loff(ll);
             float2 v[N1];
             static_for<0, N1>([&](auto K) {
                 constexpr int k1 = K;
@@ -829,9 +848,10 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
                 if constexpr (IN_BAND) {
                     const int pc = p - klo;
                     if (line < a.nlines && (unsigned)pc < (unsigned)kb)
-                        v[k1] = cscale(elt(a.in + (long long)line0 * kb, ll * kb + pc), CT::sign(p));
+                        v[k1] = cscale(elt(a.in + (long long)line0 * kb, loff(ll) * kb + pc), CT::sign(p));
                 } else {
-                    if (line < a.nlines) v[k1] = cscale(elt(a.in + (long long)line0 * N, ll * N + p), CT::sign(p));
+                    if (line < a.nlines)
+                        v[k1] = cscale(elt(a.in + (long long)line0 * N, loff(ll) * N + p), CT::sign(p));
                 }
             });
             RegDFT<N1, true>::run(v);
@@ -847,7 +867,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
         {
             const bool act = t < L * N1;
             const int ll = t / N1, k1 = t % N1;
-            const int line = line0 + ll;
+            const int line = line0 + loff(ll);
             float2 v[N2];
             if (act) {
                 static_for<0, N2>([&](auto J) {
@@ -915,7 +935,20 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
                         });
                     });
                     if constexpr (MODE == ROW_ADJ) {
-                        if (live) {
+                        if (CGROUP && cg) {
+                            // the group's four coils sit N1 lanes apart in this
+                            // wavefront: (c0 + c2) + (c1 + c3), stored by coil 0
+                            float2* arow = a.aux + ((long long)grp * m + i) * m;
+                            static_for<0, NO>([&](auto O) {
+                                constexpr int k2 = CT::half_k2_at(O);
+                                float2 x = aux[O];
+                                x.x += __shfl_down(x.x, 2 * N1, 64);
+                                x.y += __shfl_down(x.y, 2 * N1, 64);
+                                x.x += __shfl_down(x.x, N1, 64);
+                                x.y += __shfl_down(x.y, N1, 64);
+                                if ((ll & 3) == 0 && live) elt(arow, CT::out_pos(k1, k2) - lo) = x;
+                            });
+                        } else if (live) {
                             static_for<0, NO>([&](auto O) {
                                 constexpr int k2 = CT::half_k2_at(O);
                                 elt(a.aux + (long long)line0 * m, cofs + (CT::out_pos(k1, k2) - lo)) = aux[O];
@@ -980,7 +1013,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
                 __syncthreads();
                 if (t < L * N2) {
                     const int lo2 = t / N2, j2 = t % N2;
-                    if (line0 + lo2 < a.nlines) {
+                    if (line0 + loff(lo2) < a.nlines) {
                         float2 w[N1];
                         static_for<0, N1>([&](auto K) {
                             constexpr int kk = K;
@@ -994,9 +1027,10 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
                             const float2 x = cscale(w[kk], CT::sign(pos) * a.rs);
                             if constexpr (OUT_BAND) {
                                 const int pc = pos - klo;
-                                if ((unsigned)pc < (unsigned)kb) elt(a.out + (long long)line0 * kb, lo2 * kb + pc) = x;
+                                if ((unsigned)pc < (unsigned)kb)
+                                    elt(a.out + (long long)line0 * kb, loff(lo2) * kb + pc) = x;
                             } else {
-                                elt(a.out + (long long)line0 * N, lo2 * N + pos) = x;
+                                elt(a.out + (long long)line0 * N, loff(lo2) * N + pos) = x;
                             }
                         });
                     }
