@@ -671,6 +671,25 @@ int seq_deriv_head(nlinv_plan_s* p, const Class& C, const Frames& fr, const floa
     return run_row(p, C, ROW_DERIV, r, s);
 }
 
+// Whether the adjoint row pass can sum the coil products over
+// groups of 4 coils (RowArgs::cgroup): Omega the centred half with its
+// output slots known at compile time for the pass's split, 4 lines of a row
+// in one wavefront, whole groups of rows per workgroup and whole coil groups
+// per frame.
+bool coil_groups_ok(const Class& C, const Frames& fr) {
+    // every frame's coil count known and a multiple of 4 (a class without
+    // its frame list, as the allocation-free entry point builds, never groups)
+    if (C.J.empty() || fr.nplanes % 4 != 0) return false;
+    const int v = C.rowv[ROW_ADJ], L = row_lines(v), n = C.n;
+    const int d1 = split_n1(n), n1 = row_swapped(v) ? n / d1 : d1, n2 = n / n1;
+    const bool half = 2 * C.m == n && 4 * C.lo == n;
+    const bool half_by_k2 = n1 % 2 == 0 && n2 % 2 == 0 && n2 % 4 == 0 && (n / 4) % n1 == 0;
+    if (!half || !half_by_k2 || L % 4 != 0 || 64 % (4 * n1) != 0 || C.m % (L / 4) != 0) return false;
+    for (int j : C.J)
+        if (j % 4 != 0) return false;
+    return true;
+}
+
 // from T = crop_rows(IDFT_0(...)): u = crop(IDFT_1(T)); aux = conj(c) u;
 // dchat_out = W^{-H} E(conj(rho) u) + s1 add1 + s2 add2;
 // drho_out = sum_j aux + s1 add1r + s2 add2r
@@ -692,6 +711,8 @@ int seq_adjoint_tail(nlinv_plan_s* p, const Class& C, const Frames& fr, const fl
     }
     r.plane_frame = fr.plane_frame;
     r.nlines = fr.nplanes * C.m;
+    const bool groups = coil_groups_ok(C, fr);
+    r.cgroup = groups ? 4 : 0;
     CHK(run_row(p, C, ROW_ADJ, r, s));
     ColArgs a = col_args(p, C, fr);
     a.in = band_T(C, fr);
@@ -709,6 +730,7 @@ int seq_adjoint_tail(nlinv_plan_s* p, const Class& C, const Frames& fr, const fl
     CoilSumArgs cs = coil_sum_args(C, fr, drho_out, add1r, add2r, s1, s2, c1, c2, partial,
                                    (long long)fr.nplanes * nt);
     cs.self_dot = partial != nullptr;
+    cs.group = groups ? 4 : 1;   // the adjoint row pass summed groups of 4 coils
     if (g) {
         *g = C.geom;
         g->cseg = nt;
@@ -747,22 +769,6 @@ SegGeom cg_rr_geom(const Class& C) {
     g.cseg = col_tiles(C, class_frames(C), COL_PAD_FFT_WINV_CG_UPD);
     g.rseg = (int)((C.rplane() + wg - 1) / wg);
     return g;
-}
-
-// Whether the CG loop's adjoint row pass can sum the coil products over
-// groups of 4 coils (RowArgs::cgroup): Omega the centred half with its
-// output slots known at compile time for the pass's split, 4 lines of a row
-// in one wavefront, whole groups of rows per workgroup and whole coil groups
-// per frame.
-bool coil_groups_ok(const Class& C) {
-    const int v = C.rowv[ROW_ADJ], L = row_lines(v), n = C.n;
-    const int d1 = split_n1(n), n1 = row_swapped(v) ? n / d1 : d1, n2 = n / n1;
-    const bool half = 2 * C.m == n && 4 * C.lo == n;
-    const bool half_by_k2 = n1 % 2 == 0 && n2 % 2 == 0 && n2 % 4 == 0 && (n / 4) % n1 == 0;
-    if (!half || !half_by_k2 || L % 4 != 0 || 64 % (4 * n1) != 0 || C.m % (L / 4) != 0) return false;
-    for (int j : C.J)
-        if (j % 4 != 0) return false;
-    return true;
 }
 
 // alpha: the Newton step's regularisation weight (a kernel argument of the
@@ -825,7 +831,7 @@ int seq_cg_iteration(nlinv_plan_s* p, Class& C, int step, int it, int nsteps, in
     r.drho = nullptr;
     r.in = C.T;
     r.out = TB;
-    const bool groups = coil_groups_ok(C);
+    const bool groups = coil_groups_ok(C, fr);
     r.cgroup = groups ? 4 : 0;
     CHK(run_row(p, C, ROW_ADJ, r, s));
     const int tu = col_tiles(C, fr, COL_PAD_FFT_WINV_CG_UPD);
