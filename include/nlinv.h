@@ -242,8 +242,10 @@ int nlinv_gn_step_vjp(nlinv_plan plan, const nlinv_c32* rho_n, const nlinv_c32* 
 /* ---- autotuning -----------------------------------------------------------
  * Time the FFT pass variants (lines per workgroup) of every pass mode for
  * every shape class of the plan on `stream` (which must not be capturing),
- * and keep the fastest per mode.  It overwrites the plan's workspace, so call
- * it between solves.  It also chooses the form of the normal operator entry
+ * and keep the fastest per mode; then refine the five passes of the CG loop
+ * by timing whole CG iterations, one pass mode at a time over all its
+ * variants (where an iteration takes at least 40 us).  It overwrites the
+ * plan's workspace, so call it between solves.  It also chooses the form of the normal operator entry
  * point (nlinv_plan_normal_form) and of the solves' CG iteration
  * (nlinv_plan_cg_form).  Results are cached per (device
  * architecture, n, planes) in the text file named by NLINV_TUNE_CACHE, if

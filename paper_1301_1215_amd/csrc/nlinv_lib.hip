@@ -1699,6 +1699,81 @@ int tune_class(nlinv_plan_s* p, Class& C, hipStream_t s) {
         }
         C.rowv[mode] = bestv;
     }
+    // The CG loop's five passes, refined inside whole CG iterations: timed
+    // alone, a pass re-reads its own input warm from the caches, while in the
+    // loop it reads what the pass before it wrote, so the fastest variant
+    // alone is not always the fastest in the loop.  One mode at a time, every
+    // valid variant (narrow ones included: splitting cache lines between
+    // workgroups is priced here); a change is kept only if the iteration
+    // gets at least 0.3 % faster (each time is the best of two).  Only where
+    // the iteration is long enough (≥ 40 µs of passes) for the host's eager
+    // launches to stay ahead of the GPU.
+    {
+        float pass_sum = 0.f;
+        {
+            const ColArgs ap = tune_col_args(p, C, COL_PUPD_WINV_IFFT_CROP);
+            const int cm[] = {COL_PUPD_WINV_IFFT_CROP, COL_PAD_FFT_P2_IFFT, COL_PAD_FFT_WINV_CG_UPD};
+            for (int mode : cm) {
+                float ms = 0.f;
+                const ColArgs a = mode == COL_PUPD_WINV_IFFT_CROP ? ap : tune_col_args(p, C, mode);
+                CHK(timeit([&] { return run_col(p, C, mode, a, nplanes, s); }, ms));
+                pass_sum += ms;
+            }
+            const int rm[] = {ROW_DERIV, ROW_ADJ};
+            for (int mode : rm) {
+                float ms = 0.f;
+                const RowArgs r = tune_row_args(C, mode);
+                CHK(timeit([&] { return run_row(p, C, mode, r, s); }, ms));
+                pass_sum += ms;
+            }
+        }
+        if (pass_sum >= 0.040f) {
+            auto time_cg = [&](float& best) -> int {
+                best = 1e30f;
+                for (int k = 0; k < 2; ++k) {
+                    float ms = 0.f;
+                    CHK(timeit([&] { return seq_cg_iteration(p, C, 0, 1, 1, 2, 0.5f, s); }, ms));
+                    best = std::min(best, ms);
+                }
+                return NLINV_OK;
+            };
+            float cur = 0.f;
+            CHK(time_cg(cur));
+            const int cm[] = {COL_PUPD_WINV_IFFT_CROP, COL_PAD_FFT_P2_IFFT, COL_PAD_FFT_WINV_CG_UPD};
+            for (int mode : cm) {
+                const int keep = C.colv[mode];
+                int bestv = keep;
+                for (int v = 0; v < kNumColVariants; ++v) {
+                    if (v == keep || !col_ok_cols(C.n, col_mode_on_band(mode) ? C.kb : C.n, v)) continue;
+                    C.colv[mode] = v;
+                    float ms = 0.f;
+                    CHK(time_cg(ms));
+                    if (verbose)
+                        std::fprintf(stderr, "nlinv tune n=%d planes=%d cg_iteration with %s L=%d: %.1f us (now %.1f)\n",
+                                     C.n, nplanes, kKClassNames[col_kclass(mode)], kColL[v], 1e3 * ms, 1e3 * cur);
+                    if (ms < 0.997f * cur) { cur = ms; bestv = v; }
+                }
+                C.colv[mode] = bestv;
+            }
+            const int rm[] = {ROW_DERIV, ROW_ADJ};
+            for (int mode : rm) {
+                const int keep = C.rowv[mode];
+                int bestv = keep;
+                for (int v = 0; v < kNumRowVariants; ++v) {
+                    if (v == keep || !row_ok(C.n, v)) continue;
+                    C.rowv[mode] = v;
+                    float ms = 0.f;
+                    CHK(time_cg(ms));
+                    if (verbose)
+                        std::fprintf(stderr, "nlinv tune n=%d planes=%d cg_iteration with %s L=%d%s: %.1f us (now %.1f)\n",
+                                     C.n, nplanes, kKClassNames[row_kclass(mode)], row_lines(v),
+                                     row_swapped(v) ? " split swapped" : "", 1e3 * ms, 1e3 * cur);
+                    if (ms < 0.997f * cur) { cur = ms; bestv = v; }
+                }
+                C.rowv[mode] = bestv;
+            }
+        }
+    }
     // the normal operator entry point: the axis passes against the
     // whole-plane kernel (grids that have one), on the plan's first frame
     // shape in the operator layout, with full-grid scratch standing in for

@@ -312,6 +312,31 @@ def test_transposed_row_split_gives_the_same_solve(n, J):
     assert np.allclose(got["stats"], ref["stats"], rtol=1e-4)
 
 
+# column variants 0-3: 16, 8, 32 and 4 columns per workgroup; 4 is narrower
+# than the solve layout's 8-column tiles, which the autotuner's in-loop
+# refinement may choose
+COL_LINES = (16, 8, 32, 4)
+
+
+@pytest.mark.parametrize("n,J", [(128, 4), (192, 4), (512, 8)])
+def test_every_column_variant_gives_the_same_solve(n, J):
+    """Every column pass of a graph-replayed solve (the band-side passes on
+    the column-tiled band, the PSF and residual passes on the grid) under each
+    valid lines-per-workgroup variant against the default one."""
+    fr = synth.make_frame(2, 13, n, n // 2, J, "radial", spokes=13)
+    ref = _variant_solve(fr, 1, 0, 2, 6)
+    tried = 0
+    for cv, L in enumerate(COL_LINES):
+        if cv == 1 or n % L or n * L > 8192:
+            continue
+        got = _variant_solve(fr, cv, 0, 2, 6)
+        for k in ("rho", "chat", "image"):
+            assert rel(got[k], ref[k]) < 1e-5, (L, k)
+        assert np.allclose(got["stats"], ref["stats"], rtol=1e-4), L
+        tried += 1
+    assert tried >= 2
+
+
 def test_transposed_row_split_solve_matches_oracle():
     fr = synth.make_frame(2, 12, 192, 96, 4, "radial", spokes=13)
     ref = oracle_solve(fr, 3, 8)
