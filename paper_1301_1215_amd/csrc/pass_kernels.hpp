@@ -358,6 +358,8 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
     constexpr int CHP = PUPD ? (BANDC ? N1 : pointwise_chunk(N1)) : 1;
     float2 rv0[CHP], pv0[CHP];
     float w0[CHP];
+    int rho_e0 = 0, rho_e1 = 0;                    // PUPD: the rho-part chunk
+    float2 rho_r0 = make_float2(0.f, 0.f), rho_p0 = rho_r0;   // and its first operands
     if constexpr (MODE == COL_WINV_IFFT_CROP) {
         if (a.rho_acc && (plane == 0 || (a.plane_frame && a.plane_frame[plane - 1] != f))) {
             const int E = m * m, ntiles = ncols / L;
@@ -374,6 +376,21 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
         const bool fold_rr = a.fold.partial && (a.fold.op == SC_RR || a.fold.op == SC_RR0);
         has_beta = fold_rr ? a.fold.op == SC_RR : a.beta != nullptr;
         static_assert(L * N2 <= NT, "one stage-1 task per thread");
+        // this workgroup's chunk of the frame's rho part (see below) and the
+        // operands of its first element per thread, also loaded before the fold
+        {
+            const int p0 = a.frame_plane0 ? a.frame_plane0[f] : 0;
+            const int np = a.frame_planes ? a.frame_planes[f] : a.nplanes;
+            const int E = m * m, ntiles = ncols / L, nch = np * ntiles;
+            const int chunk = (E + nch - 1) / nch;
+            rho_e0 = min(E, ((plane - p0) * ntiles + tile) * chunk);
+            rho_e1 = min(E, rho_e0 + chunk);
+            const int e = rho_e0 + (int)threadIdx.x;
+            if (e < rho_e1) {
+                rho_r0 = a.rr[(long long)f * E + e];
+                rho_p0 = has_beta ? a.pr[(long long)f * E + e] : make_float2(0.f, 0.f);
+            }
+        }
         if ((int)threadIdx.x < L * N2) {
             const int l = threadIdx.x % L, j2 = threadIdx.x / L, col = col0 + l;
             static_for<0, CHP>([&](auto I) {
@@ -419,17 +436,15 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
         // rho part of the direction update, shared by every workgroup of the
         // frame: chunk (coil, tile) of its J * tiles chunks
         {
-            const int p0 = a.frame_plane0 ? a.frame_plane0[f] : 0;
-            const int np = a.frame_planes ? a.frame_planes[f] : a.nplanes;
-            const int E = m * m, ntiles = ncols / L, nch = np * ntiles;
-            const int chunk = (E + nch - 1) / nch;
-            const int e0 = min(E, ((plane - p0) * ntiles + tile) * chunk), e1 = min(E, e0 + chunk);
+            const int E = m * m;
             const float bf = beta;
             float2* pr = a.pr + (long long)f * E;
             const float2* rr = a.rr + (long long)f * E;
-            for (int e = e0 + threadIdx.x; e < e1; e += NT) {
-                const float2 r = rr[e];
-                const float2 pv = has_beta ? make_float2(r.x + bf * pr[e].x, r.y + bf * pr[e].y) : r;
+            for (int e = rho_e0 + threadIdx.x; e < rho_e1; e += NT) {
+                const bool pre = e - rho_e0 < NT;   // operands loaded before the fold
+                const float2 r = pre ? rho_r0 : rr[e];
+                const float2 po = has_beta ? (pre ? rho_p0 : pr[e]) : make_float2(0.f, 0.f);
+                const float2 pv = has_beta ? make_float2(r.x + bf * po.x, r.y + bf * po.y) : r;
                 pr[e] = pv;
                 acc_rho += (double)(pv.x * pv.x + pv.y * pv.y);
             }
@@ -809,7 +824,7 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
     const bool cg = CGROUP && a.cgroup == 4;
     int line0 = blockIdx.x * L, grp = 0;
     if (cg) {
-        const int wpg = m / (L / 4);     // workgroups per coil group
+        const int wpg = m / (L >= 4 ? L / 4 : 1);     // workgroups per coil group
         grp = blockIdx.x / wpg;
         line0 = grp * 4 * m + (blockIdx.x % wpg) * (L / 4);
     }
