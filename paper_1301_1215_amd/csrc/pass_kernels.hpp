@@ -150,6 +150,15 @@ __device__ __forceinline__ T& elt(T* base, int i) {
     return *reinterpret_cast<T*>(reinterpret_cast<B*>(base) + (unsigned)i * (unsigned)sizeof(T));
 }
 
+// Store of an intermediate that the next pass reads (element i, as elt):
+// non-temporal, so that it streams out instead of waiting dirty in this
+// XCD's L2 for the write-back at the end of the kernel.
+__device__ __forceinline__ void st_stream(float2* base, int i, float2 v) {
+    using V = float __attribute__((ext_vector_type(2)));
+    const V w = {v.x, v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<V*>(&elt(base, i)));
+}
+
 // Outputs per chunk of a pointwise stage (a divisor of the stage length,
 // at most cmax): the operands of a chunk are loaded together.
 constexpr int pointwise_chunk(int n2, int cmax = 8) {
@@ -623,10 +632,10 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                 constexpr int k1 = K;
                 const int r = CT::in_pos(j2, k1);
                 if constexpr (HALF && CT::HALF_BY_K1) {
-                    if constexpr (CT::half_k1(k1)) elt(a.out + obase, (r - lo) * ncols + col) = cscale(v[k1], CT::sign(r));
+                    if constexpr (CT::half_k1(k1)) st_stream(a.out + obase, (r - lo) * ncols + col, cscale(v[k1], CT::sign(r)));
                 } else {
                     const int ri = r - lo;
-                    if (ri >= 0 && ri < m) elt(a.out + obase, ri * ncols + col) = cscale(v[k1], CT::sign(r));
+                    if (ri >= 0 && ri < m) st_stream(a.out + obase, ri * ncols + col, cscale(v[k1], CT::sign(r)));
                 }
             });
         }
@@ -656,8 +665,8 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                     const int rp = CT::out_pos(k1, k2);
                     const int ri = rp - lo;
                     if (ri >= 0 && ri < m) {
-                        elt(a.out + (long long)plane * m * ncols, ri * ncols + col) =
-                            cscale(v[k2], CT::sign(rp) * a.rs);
+                        st_stream(a.out + (long long)plane * m * ncols, ri * ncols + col,
+                                  cscale(v[k2], CT::sign(rp) * a.rs));
                     }
                 }
             });
