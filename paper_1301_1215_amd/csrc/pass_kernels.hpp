@@ -159,6 +159,14 @@ __device__ __forceinline__ void st_stream(float2* base, int i, float2 v) {
     __builtin_nontemporal_store(w, reinterpret_cast<V*>(&elt(base, i)));
 }
 
+// Load of an intermediate that this pass reads once (element i, as elt):
+// non-temporal, so that it does not displace reused operands from the L2.
+__device__ __forceinline__ float2 ld_stream(const float2* base, int i) {
+    using V = float __attribute__((ext_vector_type(2)));
+    const V w = __builtin_nontemporal_load(reinterpret_cast<const V*>(&elt(base, i)));
+    return make_float2(w.x, w.y);
+}
+
 // Outputs per chunk of a pointwise stage (a divisor of the stage length,
 // at most cmax): the operands of a chunk are loaded together.
 constexpr int pointwise_chunk(int n2, int cmax = 8) {
@@ -520,10 +528,10 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                 float2 x = make_float2(0.f, 0.f);
                 if constexpr (IN_CROP && HALF && CT::HALF_BY_K1) {
                     // Omega rows by slot, known at compile time
-                    if constexpr (CT::half_k1(k1)) x = cscale(elt(src, (r - lo) * ncols + col), CT::sign(r));
+                    if constexpr (CT::half_k1(k1)) x = cscale(ld_stream(src, (r - lo) * ncols + col), CT::sign(r));
                 } else if constexpr (IN_CROP) {
                     const int ri = r - lo;
-                    if (ri >= 0 && ri < m) x = cscale(elt(src, ri * ncols + col), CT::sign(r));
+                    if (ri >= 0 && ri < m) x = cscale(ld_stream(src, ri * ncols + col), CT::sign(r));
                 } else if constexpr (WINV_IN) {
                     if (in_band_k1(std::integral_constant<int, k1>{}, r)) {
                         const int o = cidx(r, col);
@@ -872,10 +880,10 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
                 if constexpr (IN_BAND) {
                     const int pc = p - klo;
                     if (line < a.nlines && (unsigned)pc < (unsigned)kb)
-                        v[k1] = cscale(elt(a.in + (long long)line0 * kb, loff(ll) * kb + pc), CT::sign(p));
+                        v[k1] = cscale(ld_stream(a.in + (long long)line0 * kb, loff(ll) * kb + pc), CT::sign(p));
                 } else {
                     if (line < a.nlines)
-                        v[k1] = cscale(elt(a.in + (long long)line0 * N, loff(ll) * N + p), CT::sign(p));
+                        v[k1] = cscale(ld_stream(a.in + (long long)line0 * N, loff(ll) * N + p), CT::sign(p));
                 }
             });
             RegDFT<N1, true>::run(v);
