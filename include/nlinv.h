@@ -243,8 +243,8 @@ int nlinv_gn_step_vjp(nlinv_plan plan, const nlinv_c32* rho_n, const nlinv_c32* 
  * Time the FFT pass variants (lines per workgroup) of every pass mode for
  * every shape class of the plan on `stream` (which must not be capturing),
  * and keep the fastest per mode; then refine the five passes of the CG loop
- * by timing whole CG iterations, one pass mode at a time over all its
- * variants (where an iteration takes at least 40 us).  It overwrites the
+ * by timing whole CG iterations, captured and replayed as a graph as the
+ * solves do, one pass mode at a time over all its variants.  It overwrites the
  * plan's workspace, so call it between solves.  It also chooses the form of the normal operator entry
  * point (nlinv_plan_normal_form) and of the solves' CG iteration
  * (nlinv_plan_cg_form).  Results are cached per (device
@@ -283,6 +283,20 @@ int nlinv_plan_cg_form(nlinv_plan plan, int32_t n, int32_t* form);
 /* Force the CG form for grid size n (for tests; drops a captured graph):
  * NLINV_EINVAL for a form the size does not have or an n not in the plan. */
 int nlinv_plan_set_cg_form(nlinv_plan plan, int32_t n, int32_t form);
+
+/* Access policy of the pass intermediates for grid size n (*on = 0 or 1):
+ * with 1, every column and row pass loads its input T or T2 (the previous
+ * pass's output, read once) non-temporally, and the column passes store
+ * theirs so: they then do not displace the operands every CG iteration
+ * re-reads (coil maps, P, 1/w) from the L2, which pays where the
+ * intermediates exceed the L2s; where they fit, plain accesses are faster.
+ * Results are identical either way.  The plan sets 1 where one intermediate
+ * ([planes][m][n] complex) exceeds 30 MiB, just under the eight XCDs' L2s
+ * together (32 MB).  NLINV_EINVAL if n is not in the plan. */
+int nlinv_plan_streaming(nlinv_plan plan, int32_t n, int32_t* on);
+/* Force the policy for grid size n (for tests; drops a captured graph):
+ * NLINV_EINVAL for on outside {0, 1} or an n not in the plan. */
+int nlinv_plan_set_streaming(nlinv_plan plan, int32_t n, int32_t on);
 
 /* The band of k-space the solves keep of the sensitivities for grid size n:
  * rows and columns [*kb_lo, *kb_lo + *kb).  Outside it every Sobolev weight

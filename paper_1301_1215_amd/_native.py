@@ -23,6 +23,7 @@ EXPORTED = (
     "nlinv_adjoint", "nlinv_normal", "nlinv_normal_noalloc", "nlinv_mask_gradient", "nlinv_image", "nlinv_irgnm_solve",
     "nlinv_irgnm_solve_batch", "nlinv_irgnm_solve_series", "nlinv_plan_autotune", "nlinv_plan_variant", "nlinv_plan_band",
     "nlinv_plan_normal_form", "nlinv_plan_set_normal_form", "nlinv_plan_cg_form", "nlinv_plan_set_cg_form",
+    "nlinv_plan_streaming", "nlinv_plan_set_streaming",
     "nlinv_plan_set_variant", "nlinv_plan_timing_enable", "nlinv_plan_timing_read",
     "nlinv_plan_timing_read_class",
     "nlinv_kernel_class_name", "nlinv_status_string", "nlinv_last_hip_error", "nlinv_bandwidth_probe",
@@ -92,6 +93,8 @@ def load(path: str | None = None):
         "nlinv_plan_set_normal_form": ([vp, i32, i32], C.c_int),
         "nlinv_plan_cg_form": ([vp, i32, C.POINTER(i32)], C.c_int),
         "nlinv_plan_set_cg_form": ([vp, i32, i32], C.c_int),
+        "nlinv_plan_streaming": ([vp, i32, C.POINTER(i32)], C.c_int),
+        "nlinv_plan_set_streaming": ([vp, i32, i32], C.c_int),
         "nlinv_plan_band": ([vp, i32, C.POINTER(i32), C.POINTER(i32)], C.c_int),
         "nlinv_plan_timing_enable": ([vp, i32, i32], C.c_int),
         "nlinv_plan_timing_read": ([vp, C.POINTER(i32), C.POINTER(C.c_double)], C.c_int),
@@ -418,6 +421,16 @@ def nlinv_plan_cg_form(plan, n):
 
 def nlinv_plan_set_cg_form(plan, n, form):
     check(load().nlinv_plan_set_cg_form(plan, int(n), int(form)), "nlinv_plan_set_cg_form")
+
+
+def nlinv_plan_streaming(plan, n):
+    f = C.c_int32()
+    check(load().nlinv_plan_streaming(plan, int(n), C.byref(f)), "nlinv_plan_streaming")
+    return f.value
+
+
+def nlinv_plan_set_streaming(plan, n, on):
+    check(load().nlinv_plan_set_streaming(plan, int(n), int(on)), "nlinv_plan_set_streaming")
 
 
 def nlinv_plan_set_variant(plan, n, col_variant, row_variant):

@@ -161,6 +161,10 @@ struct Class {
     // the solves
     int normal_form = 0;
     int cg_form = 0;
+    // the passes load the intermediates T and T2 non-temporally and the
+    // column passes store them so (ColArgs::stream): where T exceeds what the
+    // eight XCDs' L2s hold between two passes (stream_by_size)
+    int stream = 0;
 
     int* plane_frame = nullptr;
     int* frame_plane0 = nullptr;
@@ -396,6 +400,7 @@ ColArgs col_args(const nlinv_plan_s* p, const Class& C, const Frames& fr) {
     a.winv = fr.tiled ? C.winv_t : C.winv;
     a.frame_plane0 = fr.frame_plane0;
     a.frame_planes = fr.frame_planes;
+    a.stream = C.stream;
     a.fold.op = SC_NONE;
     (void)p;
     return a;
@@ -409,6 +414,7 @@ RowArgs row_args(const Class& C, const Frames& fr) {
     a.kb_lo = fr.kb_lo;
     a.rs = (float)(1.0 / std::sqrt((double)C.n));
     a.tw2 = C.tw;
+    a.stream = C.stream;
     a.fold.op = SC_NONE;
     return a;
 }
@@ -1498,8 +1504,18 @@ int band_half(int n, double a, double l) {
     return 2 * h >= n ? n / 2 : h;
 }
 
+// Whether the passes should stream their intermediates: T ([planes][m][n]
+// complex) larger than 30 MiB, just under the 32 MB of the eight XCDs' L2s
+// together.  Measured in graph-replayed solves: 32 planes of 256 x 512
+// (32 MiB) 0.8 % faster streamed; 48 planes of 192 x 384 (27 MiB) 2.3 %
+// slower.  (Timing whole CG iterations alone misjudges the first case.)
+int stream_by_size(const Class& C) {
+    return (double)C.nplanes * C.m * C.n * sizeof(float2) > 30.0 * 1024 * 1024 ? 1 : 0;
+}
+
 int build_class(nlinv_plan_s* p, Class& C) {
     C.tilew = plane_tile_width(C.n);
+    C.stream = stream_by_size(C);
     {
         const int h = band_half(C.n, (double)p->sob_a, 2.0 * (double)p->sob_hl);
         C.kb = 2 * h;
@@ -1658,6 +1674,44 @@ int tune_class(nlinv_plan_s* p, Class& C, hipStream_t s) {
         ms /= reps;
         return NLINV_OK;
     };
+    // ms per call of `launch` (a sequence that depends only on the plan's
+    // state), `reps` calls captured as one graph and replayed, as the solves
+    // replay theirs: the best of two replays after a warm-up one.  Kernel
+    // timing brackets stay out of the capture.
+    auto time_graph = [&](auto&& launch, float& best) -> int {
+        bool saved[KC_NUM];
+        for (int k = 0; k < KC_NUM; ++k) {
+            saved[k] = p->timing[k];
+            p->timing[k] = false;
+        }
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+        int st = NLINV_OK;
+        if (e == hipSuccess) {
+            p->capturing = true;
+            for (int r = 0; r < reps && st == NLINV_OK; ++r) st = launch(p->cap_stream);
+            e = hipStreamEndCapture(p->cap_stream, &g);
+            p->capturing = false;
+        }
+        for (int k = 0; k < KC_NUM; ++k) p->timing[k] = saved[k];
+        hipGraphExec_t x = nullptr;
+        if (st == NLINV_OK && e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        best = 1e30f;
+        for (int k = 0; k < 3 && st == NLINV_OK && e == hipSuccess; ++k) {
+            float ms = 0.f;
+            e = hipEventRecord(e0, s);
+            if (e == hipSuccess) e = hipGraphLaunch(x, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (k > 0) best = std::min(best, ms / reps);
+        }
+        if (x) (void)hipGraphExecDestroy(x);
+        CHK(st);
+        HIPCHK(e);
+        return NLINV_OK;
+    };
     const int col_modes[] = {COL_WINV_IFFT_CROP, COL_PUPD_WINV_IFFT_CROP, COL_P_IFFT_CROP, COL_PAD_FFT_P,
                              COL_RESID_P_IFFT, COL_PAD_FFT_P2_IFFT, COL_PAD_FFT_WINV_ADD,
                              COL_PAD_FFT_WINV_CG_UPD};
@@ -1699,43 +1753,18 @@ int tune_class(nlinv_plan_s* p, Class& C, hipStream_t s) {
         }
         C.rowv[mode] = bestv;
     }
-    // The CG loop's five passes, refined inside whole CG iterations: timed
-    // alone, a pass re-reads its own input warm from the caches, while in the
-    // loop it reads what the pass before it wrote, so the fastest variant
-    // alone is not always the fastest in the loop.  One mode at a time, every
-    // valid variant (narrow ones included: splitting cache lines between
-    // workgroups is priced here); a change is kept only if the iteration
-    // gets at least 0.3 % faster (each time is the best of two).  Only where
-    // the iteration is long enough (≥ 40 µs of passes) for the host's eager
-    // launches to stay ahead of the GPU.
+    // The CG loop's five passes, refined inside whole CG iterations captured
+    // and replayed as in a solve: timed alone, a pass re-reads its own input
+    // warm from the caches, while in the loop it reads what the pass before
+    // it wrote, so the fastest variant alone is not always the fastest in the
+    // loop (and eager launches, with their gaps, change what the caches hold
+    // between passes).  One mode at a time, every valid variant (narrow ones
+    // included: splitting cache lines between workgroups is priced here); a
+    // change is kept only if the iteration gets at least 0.3 % faster.
     {
-        float pass_sum = 0.f;
         {
-            const ColArgs ap = tune_col_args(p, C, COL_PUPD_WINV_IFFT_CROP);
-            const int cm[] = {COL_PUPD_WINV_IFFT_CROP, COL_PAD_FFT_P2_IFFT, COL_PAD_FFT_WINV_CG_UPD};
-            for (int mode : cm) {
-                float ms = 0.f;
-                const ColArgs a = mode == COL_PUPD_WINV_IFFT_CROP ? ap : tune_col_args(p, C, mode);
-                CHK(timeit([&] { return run_col(p, C, mode, a, nplanes, s); }, ms));
-                pass_sum += ms;
-            }
-            const int rm[] = {ROW_DERIV, ROW_ADJ};
-            for (int mode : rm) {
-                float ms = 0.f;
-                const RowArgs r = tune_row_args(C, mode);
-                CHK(timeit([&] { return run_row(p, C, mode, r, s); }, ms));
-                pass_sum += ms;
-            }
-        }
-        if (pass_sum >= 0.040f) {
             auto time_cg = [&](float& best) -> int {
-                best = 1e30f;
-                for (int k = 0; k < 2; ++k) {
-                    float ms = 0.f;
-                    CHK(timeit([&] { return seq_cg_iteration(p, C, 0, 1, 1, 2, 0.5f, s); }, ms));
-                    best = std::min(best, ms);
-                }
-                return NLINV_OK;
+                return time_graph([&](hipStream_t cs) { return seq_cg_iteration(p, C, 0, 1, 1, 2, 0.5f, cs); }, best);
             };
             float cur = 0.f;
             CHK(time_cg(cur));
@@ -1794,15 +1823,16 @@ int tune_class(nlinv_plan_s* p, Class& C, hipStream_t s) {
         C.normal_form = ms[1] < ms[0] ? 1 : 0;
     }
     // the solves' CG iteration: the five passes against the two whole-plane
-    // launches (CG iteration 1 of 2, with its scalar folds, on scratch state)
+    // launches (CG iteration 1 of 2, with its scalar folds, on scratch state;
+    // captured and replayed, as in a solve)
     C.cg_form = 0;
     if (plane_kernel_size(C.n)) {
         float ms[2] = {0.f, 0.f};
         for (int form = 0; form < 2; ++form) {
             C.cg_form = form;
-            CHK(timeit([&] {
-                return form ? seq_cg_iteration_plane(p, C, 0, 1, 1, 2, 0.5f, s)
-                            : seq_cg_iteration(p, C, 0, 1, 1, 2, 0.5f, s);
+            CHK(time_graph([&](hipStream_t cs) {
+                return form ? seq_cg_iteration_plane(p, C, 0, 1, 1, 2, 0.5f, cs)
+                            : seq_cg_iteration(p, C, 0, 1, 1, 2, 0.5f, cs);
             }, ms[form]));
             if (verbose)
                 std::fprintf(stderr, "nlinv tune n=%d planes=%d cg_iteration %s: %.1f us\n", C.n, nplanes,
@@ -2457,7 +2487,7 @@ int nlinv_plan_autotune(nlinv_plan p, void* stream) {
     const std::string arch = arch_name(p->device);
     const char* path = std::getenv("NLINV_TUNE_CACHE");
     // cache lines: arch n planes kb <kColModes column variants> <kRowModes row variants>
-    // <normal operator form> <CG iteration form>
+    // <normal operator form> <CG iteration form> <streaming intermediates>
     std::map<std::string, std::vector<int>> cache;
     if (path) {
         std::ifstream in(path);
@@ -2470,7 +2500,7 @@ int nlinv_plan_autotune(nlinv_plan p, void* stream) {
             std::vector<int> v;
             int x;
             while (ls >> x) v.push_back(x);
-            if ((int)v.size() != kColModes + kRowModes + 2) continue;
+            if ((int)v.size() != kColModes + kRowModes + 3) continue;
             std::ostringstream k;
             k << a << ' ' << n << ' ' << np << ' ' << kb;
             cache[k.str()] = v;
@@ -2490,12 +2520,15 @@ int nlinv_plan_autotune(nlinv_plan p, void* stream) {
                 const int nf = it->second[kColModes + kRowModes + i];
                 ok = ok && (nf == 0 || (nf == 1 && plane_kernel_size(C.n)));
             }
+            const int st = it->second[kColModes + kRowModes + 2];
+            ok = ok && (st == 0 || st == 1);
         }
         if (ok) {
             for (int i = 0; i < kColModes; ++i) C.colv[i] = it->second[i];
             for (int i = 0; i < kRowModes; ++i) C.rowv[i] = it->second[kColModes + i];
             C.normal_form = it->second[kColModes + kRowModes];
             C.cg_form = it->second[kColModes + kRowModes + 1];
+            C.stream = it->second[kColModes + kRowModes + 2];
             continue;
         }
         CHK(tune_class(p, C, s));
@@ -2503,6 +2536,7 @@ int nlinv_plan_autotune(nlinv_plan p, void* stream) {
         v.insert(v.end(), C.rowv, C.rowv + kRowModes);
         v.push_back(C.normal_form);
         v.push_back(C.cg_form);
+        v.push_back(C.stream);
         cache[k.str()] = v;
         changed = true;
     }
@@ -2573,6 +2607,30 @@ int nlinv_plan_set_cg_form(nlinv_plan p, int32_t n, int32_t form) {
         }
     if (!found) return NLINV_EINVAL;
     CHK(drop_graph(p));   // the form is baked into a captured graph
+    return NLINV_OK;
+}
+
+int nlinv_plan_streaming(nlinv_plan p, int32_t n, int32_t* on) {
+    if (!p || !on) return NLINV_EINVAL;
+    for (Class& C : p->classes)
+        if (C.n == n) {
+            *on = C.stream;
+            return NLINV_OK;
+        }
+    *on = -1;
+    return NLINV_EINVAL;
+}
+
+int nlinv_plan_set_streaming(nlinv_plan p, int32_t n, int32_t on) {
+    if (!p || on < 0 || on > 1) return NLINV_EINVAL;
+    bool found = false;
+    for (Class& C : p->classes)
+        if (C.n == n) {
+            C.stream = on;
+            found = true;
+        }
+    if (!found) return NLINV_EINVAL;
+    CHK(drop_graph(p));   // the launch arguments are baked into a captured graph
     return NLINV_OK;
 }
 

@@ -150,21 +150,28 @@ __device__ __forceinline__ T& elt(T* base, int i) {
     return *reinterpret_cast<T*>(reinterpret_cast<B*>(base) + (unsigned)i * (unsigned)sizeof(T));
 }
 
-// Store of an intermediate that the next pass reads (element i, as elt):
-// non-temporal, so that it streams out instead of waiting dirty in this
-// XCD's L2 for the write-back at the end of the kernel.
-__device__ __forceinline__ void st_stream(float2* base, int i, float2 v) {
+// Load and store of an intermediate of the passes (T, T2; element i, as
+// elt), read once by the pass that follows its producer.  With nt (the
+// shape class's choice, made by the autotuner) both are non-temporal: the
+// loads do not displace the operands that every iteration re-reads (coil
+// maps, P, 1/w) from the L2, and the column passes' stores stream out
+// instead of waiting dirty in one XCD's L2 for the write-back at the end of
+// the kernel.  Where the intermediates are small enough to stay in the L2s
+// between two passes, plain accesses are faster.
+__device__ __forceinline__ float2 ld_mid(const float2* base, int i, bool nt) {
     using V = float __attribute__((ext_vector_type(2)));
-    const V w = {v.x, v.y};
-    __builtin_nontemporal_store(w, reinterpret_cast<V*>(&elt(base, i)));
-}
-
-// Load of an intermediate that this pass reads once (element i, as elt):
-// non-temporal, so that it does not displace reused operands from the L2.
-__device__ __forceinline__ float2 ld_stream(const float2* base, int i) {
-    using V = float __attribute__((ext_vector_type(2)));
+    if (!nt) return elt(base, i);
     const V w = __builtin_nontemporal_load(reinterpret_cast<const V*>(&elt(base, i)));
     return make_float2(w.x, w.y);
+}
+__device__ __forceinline__ void st_mid(float2* base, int i, float2 v, bool nt) {
+    using V = float __attribute__((ext_vector_type(2)));
+    if (!nt) {
+        elt(base, i) = v;
+        return;
+    }
+    const V w = {v.x, v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<V*>(&elt(base, i)));
 }
 
 // Outputs per chunk of a pointwise stage (a divisor of the stage length,
@@ -227,6 +234,7 @@ struct ColArgs {
     // kb = n, kb_lo = 0 is the whole grid.
     int kb, kb_lo;
     int nplanes;
+    int stream;               // intermediates T, T2 accessed non-temporally (ld_mid, st_mid)
     float rs;                 // 1/sqrt(n)
     const float2* tw2;        // [N1][N2]: exp(-2 pi i k1 j2 / n)
     const float* winv;        // [kb][kb]: 1/w, the inverse Sobolev weight on the band
@@ -528,10 +536,10 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                 float2 x = make_float2(0.f, 0.f);
                 if constexpr (IN_CROP && HALF && CT::HALF_BY_K1) {
                     // Omega rows by slot, known at compile time
-                    if constexpr (CT::half_k1(k1)) x = cscale(ld_stream(src, (r - lo) * ncols + col), CT::sign(r));
+                    if constexpr (CT::half_k1(k1)) x = cscale(ld_mid(src, (r - lo) * ncols + col, a.stream), CT::sign(r));
                 } else if constexpr (IN_CROP) {
                     const int ri = r - lo;
-                    if (ri >= 0 && ri < m) x = cscale(ld_stream(src, ri * ncols + col), CT::sign(r));
+                    if (ri >= 0 && ri < m) x = cscale(ld_mid(src, ri * ncols + col, a.stream), CT::sign(r));
                 } else if constexpr (WINV_IN) {
                     if (in_band_k1(std::integral_constant<int, k1>{}, r)) {
                         const int o = cidx(r, col);
@@ -640,10 +648,10 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                 constexpr int k1 = K;
                 const int r = CT::in_pos(j2, k1);
                 if constexpr (HALF && CT::HALF_BY_K1) {
-                    if constexpr (CT::half_k1(k1)) st_stream(a.out + obase, (r - lo) * ncols + col, cscale(v[k1], CT::sign(r)));
+                    if constexpr (CT::half_k1(k1)) st_mid(a.out + obase, (r - lo) * ncols + col, cscale(v[k1], CT::sign(r)), a.stream);
                 } else {
                     const int ri = r - lo;
-                    if (ri >= 0 && ri < m) st_stream(a.out + obase, ri * ncols + col, cscale(v[k1], CT::sign(r)));
+                    if (ri >= 0 && ri < m) st_mid(a.out + obase, ri * ncols + col, cscale(v[k1], CT::sign(r)), a.stream);
                 }
             });
         }
@@ -673,8 +681,8 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
                     const int rp = CT::out_pos(k1, k2);
                     const int ri = rp - lo;
                     if (ri >= 0 && ri < m) {
-                        st_stream(a.out + (long long)plane * m * ncols, ri * ncols + col,
-                                  cscale(v[k2], CT::sign(rp) * a.rs));
+                        st_mid(a.out + (long long)plane * m * ncols, ri * ncols + col,
+                               cscale(v[k2], CT::sign(rp) * a.rs), a.stream);
                     }
                 }
             });
@@ -799,6 +807,7 @@ struct RowArgs {
     // ROW_CACHE and ROW_DERIV read only those columns of their input (the
     // rest is zero), ROW_ADJ writes only those of its output
     int kb, kb_lo;
+    int stream;              // the input T or T2 loaded non-temporally (ld_mid)
     float rs;
     const float2* tw2;       // [N1][N2]
     // ROW_ADJ with cgroup = 4 (Omega the centred half with compile-time
@@ -880,10 +889,10 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
                 if constexpr (IN_BAND) {
                     const int pc = p - klo;
                     if (line < a.nlines && (unsigned)pc < (unsigned)kb)
-                        v[k1] = cscale(ld_stream(a.in + (long long)line0 * kb, loff(ll) * kb + pc), CT::sign(p));
+                        v[k1] = cscale(ld_mid(a.in + (long long)line0 * kb, loff(ll) * kb + pc, a.stream), CT::sign(p));
                 } else {
                     if (line < a.nlines)
-                        v[k1] = cscale(ld_stream(a.in + (long long)line0 * N, loff(ll) * N + p), CT::sign(p));
+                        v[k1] = cscale(ld_mid(a.in + (long long)line0 * N, loff(ll) * N + p, a.stream), CT::sign(p));
                 }
             });
             RegDFT<N1, true>::run(v);

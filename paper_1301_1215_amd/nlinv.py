@@ -183,6 +183,13 @@ class Plan:
     def set_cg_form(self, form, n=None):
         N.nlinv_plan_set_cg_form(self.handle, self.dims.n if n is None else n, form)
 
+    def streaming(self, n=None):
+        """1: the passes access the intermediates T and T2 non-temporally."""
+        return N.nlinv_plan_streaming(self.handle, self.dims.n if n is None else n)
+
+    def set_streaming(self, on, n=None):
+        N.nlinv_plan_set_streaming(self.handle, self.dims.n if n is None else n, 1 if on else 0)
+
     def timing_enable(self, kclass, enable=True):
         N.nlinv_plan_timing_enable(self.handle, kclass, enable)
 

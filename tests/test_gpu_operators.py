@@ -205,11 +205,28 @@ def test_autotune_picks_valid_variants_and_keeps_parity(tmp_path, monkeypatch):
         assert rel(nr, ref[0]) < TOL and rel(nc, ref[1]) < TOL
     line = (tmp_path / "tune.txt").read_text().split()
     # arch, n, planes, the side of the band the solve keeps (64 at n = 192), 9 + 4 variants,
-    # the normal operator's form (no whole-plane kernel at 192: the axis passes)
-    assert line[1:4] == ["192", str(J), "64"] and len(line) == 4 + 9 + 4 + 2 and line[-2:] == ["0", "0"]
+    # the normal operator's and the CG iteration's forms (no whole-plane kernel at 192: the
+    # axis passes), the intermediates' access policy
+    assert line[1:4] == ["192", str(J), "64"] and len(line) == 4 + 9 + 4 + 3 and line[-3:-1] == ["0", "0"]
+    assert line[-1] in ("0", "1")
     with Plan(n, n_om, J) as pl2:    # served from the cache file
         pl2.autotune()
         assert pl2.variant(n) == (cv, rv)
+        assert pl2.streaming() == int(line[-1])
+
+
+def test_streaming_policy_follows_the_intermediate_size():
+    """The pass intermediates are streamed where one of them ([planes][m][n]
+    complex) exceeds 30 MiB: 32 planes of 256 x 512 (32 MiB) yes, four
+    12-coil frames of 192 x 384 (27 MiB) and small grids no."""
+    with Plan(512, 256, 32) as pl:
+        assert pl.streaming() == 1
+    with Plan(frames=[(384, 192, 12)] * 4) as pl:
+        assert pl.streaming(384) == 0
+    with Plan(64, 32, 8) as pl:
+        assert pl.streaming() == 0
+        pl.set_streaming(1)
+        assert pl.streaming() == 1
 
 
 def test_kernel_timing_inside_a_replayed_graph():
@@ -271,7 +288,7 @@ def test_autotune_chooses_the_normal_form_and_keeps_parity(tmp_path, monkeypatch
         nr, nc = map(host, pl.normal(dev(rho), dev(chat), dev(P), 0.5, dev(drho), dev(dchat)))
         assert rel(nr, ref[0]) < TOL and rel(nc, ref[1]) < TOL
     line = (tmp_path / "tune.txt").read_text().split()
-    assert line[1:3] == ["64", str(J)] and line[-2] == str(form) and line[-1] in ("0", "1")
+    assert line[1:3] == ["64", str(J)] and line[-3] == str(form) and line[-2] in ("0", "1")
     with Plan(n, n_om, J) as pl2:    # served from the cache file
         pl2.autotune()
         assert pl2.normal_form() == form

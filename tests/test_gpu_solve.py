@@ -337,6 +337,22 @@ def test_every_column_variant_gives_the_same_solve(n, J):
     assert tried >= 2
 
 
+@pytest.mark.parametrize("n,J", [(96, 3), (512, 8)])
+def test_streaming_intermediates_give_the_identical_solve(n, J):
+    """The non-temporal access policy of the pass intermediates changes only
+    how the caches hold them: the graph-replayed solve is bitwise the same."""
+    fr = synth.make_frame(2, 14, n, n // 2, J, "radial", spokes=13)
+    out = []
+    for on in (0, 1):
+        with Plan(fr.n, fr.n_om, fr.ncoils) as pl:
+            pl.set_streaming(on)
+            assert pl.streaming() == on
+            got = pl.solve(dev(fr.y), dev(fr.P), Plan.params(2, 6, use_graph=True))
+            out.append({k: host(v) for k, v in got.items()})
+    for k in ("rho", "chat", "image", "stats"):
+        assert np.array_equal(out[0][k], out[1][k]), k
+
+
 def test_transposed_row_split_solve_matches_oracle():
     fr = synth.make_frame(2, 12, 192, 96, 4, "radial", spokes=13)
     ref = oracle_solve(fr, 3, 8)
