@@ -449,7 +449,7 @@ bool col_operands_ok(int mode, const ColArgs& a) {
 bool row_operands_ok(int mode, const RowArgs& a) {
     if (!a.tw2 || (mode != ROW_FWD && !a.in) || (mode != ROW_CACHE && !a.out)) return false;
     switch (mode) {
-        case ROW_CACHE: return a.c_out;
+        case ROW_CACHE: return a.c_out && (!a.out || a.rho);
         case ROW_FWD: return a.rho && a.c;
         case ROW_DERIV: return a.rho && a.c && a.drho;
         case ROW_ADJ: return a.rho && a.c && a.aux;
@@ -585,11 +585,18 @@ CoilSumArgs coil_sum_args(const Class& C, const Frames& fr, float2* out, const f
     return cs;
 }
 
+// Whether the coil-map row pass can go on into the forward model's first
+// pass (RowArgs::c_out): Omega the centred half on compile-time slots.
+bool coil_maps_fwd_ok(const Class& C) { return 2 * C.m == C.n && 4 * C.lo == C.n && half_slots_k2(C.n); }
+
 // c = E^H W^{-1} chat
 // (inside a solve, optionally with the previous Newton step's rho update
-// and its last CG scalar step folded into the two passes)
+// and its last CG scalar step folded into the two passes; with fwd_out, the
+// row pass also writes fwd_out = T of rho . c, the forward model's first
+// pass, where coil_maps_fwd_ok)
 int seq_coil_maps(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2* chat, float2* c_out,
-                  hipStream_t s, bool rho_update = false, const ScalarStep* fold = nullptr) {
+                  hipStream_t s, bool rho_update = false, const ScalarStep* fold = nullptr,
+                  float2* fwd_out = nullptr, const float2* rho = nullptr) {
     ColArgs a = col_args(p, C, fr);
     a.in = chat;
     a.out = band_T(C, fr);
@@ -607,6 +614,11 @@ int seq_coil_maps(nlinv_plan_s* p, const Class& C, const Frames& fr, const float
     if (fold) {
         r.fold = *fold;
         r.sc = C.sc;
+    }
+    if (fwd_out) {
+        if (!coil_maps_fwd_ok(C)) return NLINV_EINVAL;
+        r.out = fwd_out;
+        r.rho = rho;
     }
     return run_row(p, C, ROW_CACHE, r, s);
 }
@@ -632,16 +644,19 @@ int seq_forward(nlinv_plan_s* p, const Class& C, const Frames& fr, const float2*
 
 // Newton step: T = crop_rows(IDFT_0(P . r0)) with the residual
 // r0 = s y - P . DFT(E(rho . c)) never stored (the first step of DF^H r0);
-// |r0|^2 partials into `partial`, `g` receives their geometry.
+// |r0|^2 partials into `partial`, `g` receives their geometry.  With
+// row_done, the row pass of rho . c is already in T (seq_coil_maps).
 int seq_residual_head(nlinv_plan_s* p, const Class& C, const Frames& fr, double* partial, SegGeom* g,
-                      hipStream_t s) {
-    RowArgs r = row_args(C, fr);
-    r.c = C.c;
-    r.rho = C.x_r;
-    r.out = C.T;
-    r.plane_frame = fr.plane_frame;
-    r.nlines = fr.nplanes * C.m;
-    CHK(run_row(p, C, ROW_FWD, r, s));
+                      hipStream_t s, bool row_done = false) {
+    if (!row_done) {
+        RowArgs r = row_args(C, fr);
+        r.c = C.c;
+        r.rho = C.x_r;
+        r.out = C.T;
+        r.plane_frame = fr.plane_frame;
+        r.nlines = fr.nplanes * C.m;
+        CHK(run_row(p, C, ROW_FWD, r, s));
+    }
     ColArgs a = col_args(p, C, fr);
     a.in = C.T;
     a.out = C.T;
@@ -1036,16 +1051,20 @@ int enqueue_class_newton(nlinv_plan_s* p, Class& C, const nlinv_irgnm_params& pr
             const long long ps = C.cplane();
             // linearisation cache c at x_n (with the previous step's rho
             // update and its last CG step's stats folded in)
+            // (the coil-map row pass goes on into the forward model's row
+            // pass where the geometry allows)
+            const bool fused = coil_maps_fwd_ok(C);
+            float2* fwd = fused ? C.T : nullptr;
             if (step > 0 && K > 0) {
                 ScalarStep last = scalar_step(C, SC_RR, cg_rr_geom(C), 0.f, step - 1, K - 1, N, K, C.partial2);
                 last.alpha = alpha_of(prm, step - 1);
-                CHK(seq_coil_maps(p, C, fr, C.x_c, C.c, s, true, &last));
+                CHK(seq_coil_maps(p, C, fr, C.x_c, C.c, s, true, &last, fwd, C.x_r));
             } else {
-                CHK(seq_coil_maps(p, C, fr, C.x_c, C.c, s));
+                CHK(seq_coil_maps(p, C, fr, C.x_c, C.c, s, false, nullptr, fwd, C.x_r));
             }
             // r0 = s y - F(x_n) (its norm) and the first step of DF^H r0
             SegGeom g0{};
-            CHK(seq_residual_head(p, C, fr, C.partial, &g0, s));
+            CHK(seq_residual_head(p, C, fr, C.partial, &g0, s, fused));
             // b = DF^H r0 - alpha (x_n - x_ref) into r; ||r0|| recorded inside
             // its adjoint row pass, <b, b> inside the first CG pass
             {

@@ -34,6 +34,13 @@ __device__ __forceinline__ float sgn(int i) { return (i & 1) ? -1.0f : 1.0f; }
 // SW: the transposed split N1 <-> N2 (a pass variant the autotuner can
 // choose where N1 != N2); the twiddle table stays the one of the default
 // split (its entry (a, b) is w_N^{ab}, symmetric in a and b).
+// Whether the default split of an n-point line puts the stage-2 outputs of
+// the centred half on compile-time slots (Centre<n>::HALF_BY_K2).
+constexpr bool half_slots_k2(int n) {
+    const int n1 = split_n1(n), n2 = n / n1;
+    return n1 % 2 == 0 && n2 % 2 == 0 && n2 % 4 == 0 && (n / 4) % n1 == 0;
+}
+
 template <int N, bool SW = false>
 struct Centre {
     static constexpr int N1 = SW ? N / split_n1(N) : split_n1(N), N2 = N / N1;
@@ -53,6 +60,7 @@ struct Centre {
     // [N2/4, 3 N2/4): which outputs fall in Omega = the centred half is then
     // known at compile time.
     static constexpr bool HALF_BY_K2 = PERM && N2 % 4 == 0 && (N / 4) % N1 == 0;
+    static_assert(SW || HALF_BY_K2 == half_slots_k2(N), "host predicate");
     static constexpr bool half_k2(int k2) {
         const int k = (k2 + N2 / 2) % N2;
         return k >= N2 / 4 && k < 3 * N2 / 4;
@@ -785,7 +793,8 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_col(ColArgs a) {
 // ---------------------------------------------------------------------------
 
 enum RowMode : int {
-    ROW_CACHE = 0,   // c = crop_cols(IDFT_1(T))  (may fold a scalar step, see RowArgs)
+    ROW_CACHE = 0,   // c = crop_cols(IDFT_1(T))  (may fold a scalar step, see RowArgs); with out
+                     // set also out = DFT_1(pad_cols(rho . c)) (as ROW_FWD), see RowArgs
     ROW_FWD = 1,     // T = DFT_1(pad_cols(rho . c))
     ROW_DERIV = 2,   // dc = crop_cols(IDFT_1(T)); T = DFT_1(pad_cols(drho . c + rho . dc))
     ROW_ADJ = 3,     // u = crop_cols(IDFT_1(T)); aux = conj(c) . u; T = DFT_1(pad_cols(conj(rho) . u))
@@ -797,6 +806,11 @@ struct RowArgs {
                              // in when both have the same row length
     const float2* c;         // [planes][m][m]
     float2* c_out;           // ROW_CACHE output
+    // ROW_CACHE with out set (Omega the centred half with compile-time slots,
+    // half_slots_k2(n), the default split only): the pass continues as
+    // ROW_FWD on the coil maps it has just formed, out = T of rho . c, so
+    // that the forward model's first pass needs neither a launch of its own
+    // nor a second read of c
     const float2* rho;       // [frames][m][m]
     const float2* drho;      // [frames][m][m]
     float2* aux;             // [planes][m][m]
@@ -932,6 +946,27 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
                                     cscale(v[k2], CT::sign(pos) * a.rs);
                         }
                     });
+                    if constexpr (HALF && CT::HALF_BY_K2) {
+                        if (a.out) {   // fused forward: v = sign . rho . c on Omega, zero elsewhere
+                            constexpr int NO = N2 / 2;
+                            const float2* rrow = a.rho + ((long long)f * m + i) * m;
+                            float2 rv[NO];
+                            static_for<0, NO>([&](auto O) {
+                                constexpr int k2 = CT::half_k2_at(O);
+                                rv[O] = elt(rrow, CT::out_pos(k1, k2) - lo);
+                            });
+                            static_for<0, N2>([&](auto K) {
+                                constexpr int k2 = K;
+                                if constexpr (!CT::half_k2(k2)) v[k2] = make_float2(0.f, 0.f);
+                            });
+                            static_for<0, NO>([&](auto O) {
+                                constexpr int k2 = CT::half_k2_at(O);
+                                const int pos = CT::out_pos(k1, k2);
+                                const float2 u = cscale(v[k2], CT::sign(pos) * a.rs);
+                                v[k2] = live ? cscale(cmul(rv[O], u), CT::sign(pos)) : make_float2(0.f, 0.f);
+                            });
+                        }
+                    }
                 } else if constexpr (HALF && CT::HALF_BY_K2) {
                     // Omega = the centred half, its output slots known at
                     // compile time (N2/2 of them): their operands are loaded
@@ -1036,8 +1071,10 @@ __global__ __launch_bounds__(pass_threads(N, L)) void k_row(RowArgs a) {
                     });
                 }
             }
-            if constexpr (MODE == ROW_CACHE) return;
-            if constexpr (MODE == ROW_DERIV || MODE == ROW_ADJ) {
+            if constexpr (MODE == ROW_CACHE) {
+                if (!(HALF && CT::HALF_BY_K2) || !a.out) return;   // uniform over the workgroup
+            }
+            if constexpr (MODE == ROW_DERIV || MODE == ROW_ADJ || MODE == ROW_CACHE) {
                 // The forward transform as the adjoint of the inverse's stages
                 // in reverse order: the adjoint of stage 2 (an N2-point DFT)
                 // on this task's registers, back into the slots it read
