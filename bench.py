@@ -47,7 +47,7 @@ TIMING_STRIDE = 7
 # the five kernel classes of one CG iteration (q = N_alpha p with p = r + beta p
 # in the first and r -= a q, x += a p in the last)
 CG_CLASSES = ("col_pupd_winv_ifft", "row_deriv", "col_psf", "row_adj", "col_fft_winv_cg_update")
-MAX_WORKERS = 16   # host threads for the oracle's FFTs (the GPU machine's CPU share)
+MAX_WORKERS = 16   # host threads for the oracle's FFTs (at most one GPU's share of a 16-threads-per-GPU host)
 
 WORKLOADS = {
     # name: (n, n_om, J, description)
@@ -609,7 +609,7 @@ def main():
         return
 
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported (how the path "
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {a.gpus} is not supported (how the path "
               f"would shard across GPUs is a design, not built)", file=sys.stderr)
         sys.exit(2)
 
