@@ -353,6 +353,26 @@ def test_streaming_intermediates_give_the_identical_solve(n, J):
         assert np.array_equal(out[0][k], out[1][k]), k
 
 
+@pytest.mark.parametrize("n,n_om,J", [(128, 64, 4), (96, 96, 3)])
+def test_data_outside_the_sampling_pattern(n, n_om, J):
+    """Data also outside the sampling pattern (which the method's P . r0
+    never sees, but the data scale from ||y|| and the residual norms do): the
+    scale, the residual norms and the image match the oracle."""
+    import dataclasses
+    fr = synth.make_frame(2, 15, n, n_om, J, "radial", spokes=11)
+    rng = np.random.default_rng(15)
+    extra = (rng.standard_normal(fr.y.shape) + 1j * rng.standard_normal(fr.y.shape)).astype(np.complex64)
+    scale = 0.5 * np.abs(fr.y[:, fr.P > 0]).mean()
+    y = np.where(fr.P[None] > 0, fr.y, scale * extra).astype(np.complex64)
+    fr = dataclasses.replace(fr, y=y)
+    ref = oracle_solve(fr, 3, 6)
+    got = gpu_solve(fr, 3, 6, use_graph=True)
+    st = got["stats"]
+    assert abs(st[0] - ref.scale) / ref.scale < 1e-6 and st[1] == 0
+    np.testing.assert_allclose(st[2:5], ref.r0_norms, rtol=1e-4)
+    assert rel(got["image"], ref.image) < NRMSE
+
+
 def test_transposed_row_split_solve_matches_oracle():
     fr = synth.make_frame(2, 12, 192, 96, 4, "radial", spokes=13)
     ref = oracle_solve(fr, 3, 8)
