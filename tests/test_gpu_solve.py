@@ -337,11 +337,12 @@ def test_every_column_variant_gives_the_same_solve(n, J):
     assert tried >= 2
 
 
-@pytest.mark.parametrize("n,J", [(96, 3), (512, 8)])
-def test_streaming_intermediates_give_the_identical_solve(n, J):
+@pytest.mark.parametrize("n,n_om,J", [(96, 48, 3), (512, 256, 8), (64, 64, 4), (96, 40, 3)])
+def test_streaming_intermediates_give_the_identical_solve(n, n_om, J):
     """The non-temporal access policy of the pass intermediates changes only
-    how the caches hold them: the graph-replayed solve is bitwise the same."""
-    fr = synth.make_frame(2, 14, n, n // 2, J, "radial", spokes=13)
+    how the caches hold them: the graph-replayed solve is bitwise the same
+    (Omega the centred half, the whole grid, and another crop)."""
+    fr = synth.make_frame(2, 14, n, n_om, J, "radial", spokes=13)
     out = []
     for on in (0, 1):
         with Plan(fr.n, fr.n_om, fr.ncoils) as pl:
