@@ -580,6 +580,51 @@ def summarize_pmc(fetch_dir: str, write_dir: str, out_txt: str, workload: str, c
     print(out_txt)
 
 
+def summarize_sq(dir_a: str, dir_b: str, out_txt: str, workload: str, commands):
+    """Per-wave instruction counts and wait / VALU-issue shares of the
+    workload's grid-size passes from two SQ counter runs (dir_a: SQ_WAVES,
+    SQ_WAVE_CYCLES, SQ_INSTS_VALU, SQ_INSTS_LDS, SQ_ACTIVE_INST_VALU,
+    SQ_LDS_BANK_CONFLICT; dir_b: SQ_WAIT_ANY, SQ_INSTS_VMEM), averaged over
+    the dispatches of each kernel."""
+    import csv
+    from collections import defaultdict
+
+    def load(d):
+        acc, disp = defaultdict(lambda: defaultdict(float)), defaultdict(set)
+        for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
+            acc[r["Kernel_Name"]][r["Counter_Name"]] += float(r["Counter_Value"])
+            disp[r["Kernel_Name"]].add(r["Dispatch_Id"])
+        return {k: {c: v / len(disp[k]) for c, v in cs.items()} for k, cs in acc.items()}, disp
+    a, da = load(dir_a)
+    b, _ = load(dir_b)
+    n = WORKLOADS[workload][0]
+    lines = [f"# SQ counters of the {n}x{n} passes -- {workload}",
+             "# Commands (repo root, MI355X, ROCm 7.2; the first run autotunes and saves the pass variants):"] + [
+             "#   " + c for c in commands] + [
+             "# Per dispatch, averaged over the dispatches of each kernel (counter values summed over the chip):",
+             "#   VALU, LDS, VMEM = SQ_INSTS_VALU, SQ_INSTS_LDS, SQ_INSTS_VMEM per wave (SQ_WAVES);",
+             "#   wait = SQ_WAIT_ANY / SQ_WAVE_CYCLES (share of the waves' resident cycles spent waiting on anything);",
+             "#   valu_busy = SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES (share of those cycles issuing VALU work);",
+             "#   bank = SQ_LDS_BANK_CONFLICT per dispatch.",
+             "# class  kernel  dispatches  waves  VALU  LDS  VMEM  wait  valu_busy  bank"]
+    recs = []
+    for name, A in a.items():
+        kc, _ = kernel_class_of(name)
+        if kc is None or f"<{n}," not in name.replace(" ", "") or not A.get("SQ_WAVES"):
+            continue
+        B = b.get(name, {})
+        w, cyc = A["SQ_WAVES"], max(A.get("SQ_WAVE_CYCLES", 0.0), 1.0)
+        short = name.replace("void nlinv::", "").split("(")[0].replace(" ", "")
+        recs.append((len(da[name]), f"{kc}  {short}  {len(da[name])}  {w:.0f}  {A.get('SQ_INSTS_VALU', 0) / w:.0f}  "
+                     f"{A.get('SQ_INSTS_LDS', 0) / w:.0f}  {B.get('SQ_INSTS_VMEM', 0) / w:.0f}  "
+                     f"{B.get('SQ_WAIT_ANY', 0) / cyc:.3f}  {A.get('SQ_ACTIVE_INST_VALU', 0) / cyc:.3f}  "
+                     f"{A.get('SQ_LDS_BANK_CONFLICT', 0):.0f}"))
+    recs.sort(key=lambda r: -r[0])
+    lines += [r[1] for r in recs]
+    open(out_txt, "w").write("\n".join(lines) + "\n")
+    print(out_txt)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -598,6 +643,8 @@ def main():
                     help="write a kernel-trace summary (no GPU needed) and exit")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_TXT"),
                     help="write a FETCH_SIZE / WRITE_SIZE traffic summary (no GPU needed) and exit")
+    ap.add_argument("--summarize-sq", nargs=3, metavar=("DIR_A", "DIR_B", "OUT_TXT"),
+                    help="write an SQ counter summary (no GPU needed) and exit")
     ap.add_argument("--command", action="append", default=[], help="command lines to record in a summary")
     a = ap.parse_args()
 
@@ -606,6 +653,9 @@ def main():
         return
     if a.summarize_pmc:
         summarize_pmc(*a.summarize_pmc, workload=a.workload, commands=a.command)
+        return
+    if a.summarize_sq:
+        summarize_sq(*a.summarize_sq, workload=a.workload, commands=a.command)
         return
 
     if a.gpus != 1:
